@@ -1,0 +1,564 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each check compares the oracle with something other than itself: values
+computed by hand (tests/golden), closed forms, library routines (scipy graph
+algorithms, numpy pooling), brute force on tiny inputs, or invariants.
+"""
+
+import itertools
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import connected_components, minimum_spanning_tree, shortest_path
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def rng_img(seed, H, W, lo=0, hi=256):
+    return np.random.default_rng(seed).integers(lo, hi, size=(H, W, 3)).astype(np.uint8)
+
+
+def grid_edges(H, W):
+    """(id, p, q) of the 4-connected grid, id 2p right, 2p+1 down."""
+    out = []
+    for y in range(H):
+        for x in range(W):
+            p = y * W + x
+            if x + 1 < W:
+                out.append((2 * p, p, p + 1))
+            if y + 1 < H:
+                out.append((2 * p + 1, p, p + W))
+    return out
+
+
+def forest_graph(H, W, in_tree, weights=None):
+    N = H * W
+    rows, cols, vals = [], [], []
+    for e, p, q in grid_edges(H, W):
+        if in_tree[e]:
+            rows.append(p); cols.append(q)
+            vals.append(1.0 if weights is None else weights[e])
+    return sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()
+
+
+# --- pyramid (Section 2.1) ---------------------------------------------------
+
+def test_pyramid_golden(orc):
+    g = load("pyramid_3x3.json")
+    img = np.array(g["image_rgb_rows"], np.uint8)
+    lv = orc.pyramid(img, g["S"], g["L"])
+    assert lv[1].shape == (2, 2, 3) and lv[2].shape == (1, 1, 3)
+    np.testing.assert_array_equal(lv[1], np.array(g["level1_rgb_rows"]))
+    np.testing.assert_array_equal(lv[2], np.array(g["level2_rgb_rows"]))
+
+
+def test_pyramid_even_size_is_average_pooling(orc):
+    img = rng_img(1, 16, 24)
+    lv = orc.pyramid(img, 2, 3)
+    ref = img.astype(np.float64)
+    for l in range(1, 4):
+        h, w = ref.shape[0] // 2, ref.shape[1] // 2
+        ref = ref.reshape(h, 2, w, 2, 3).mean(axis=(1, 3))
+        np.testing.assert_array_equal(lv[l], ref)
+
+
+def test_pyramid_dims_and_constant_image(orc):
+    Hs, Ws, ds = orc.level_dims(1104, 1344, 255, 2, 3)
+    assert Hs == [1104, 552, 276, 138] and Ws == [1344, 672, 336, 168] and ds == [255, 127, 63, 31]
+    Hs, Ws, ds = orc.level_dims(375, 1242, 191, 2, 2)
+    assert Hs == [375, 188, 94] and Ws == [1242, 621, 311] and ds == [191, 95, 47]
+    img = np.full((7, 5, 3), 77, np.uint8)
+    for lvl in orc.pyramid(img, 2, 3):
+        assert np.all(lvl == 77.0)
+
+
+def test_pyramid_levels_are_dyadic(orc):
+    # S=2: every level-l value is a multiple of 4^-l (exact edge keys rely on it)
+    img = rng_img(5, 13, 11)
+    for l, lvl in enumerate(orc.pyramid(img, 2, 3)):
+        scaled = lvl * 4 ** l
+        assert np.all(scaled == np.round(scaled))
+
+
+# --- matching cost (Section 3.3, eq. E) ---------------------------------------
+
+def test_cost_golden(orc):
+    g = load("cost_4x3.json")
+    H, W = g["H"], g["W"]
+    L = np.zeros((H, W, 3)); R = np.zeros((H, W, 3))
+    L[1] = np.array(g["left_row1"]); R[1] = np.array(g["right_row1"])
+    for c in g["cases"]:
+        num, _, den = c["cost"].partition("/")
+        want = float(Fraction(num) / Fraction(den or "1"))
+        got = orc.matching_cost(L, R, c["x"], c["y"], c["d"], g["params"])
+        assert abs(got - want) < 1e-12, c
+
+
+def test_cost_volume_nan_outside_interval(orc):
+    img_l = rng_img(2, 5, 9).astype(np.float64); img_r = rng_img(3, 5, 9).astype(np.float64)
+    lo = np.random.default_rng(0).integers(0, 4, size=(5, 9)); hi = lo + 3
+    vol = orc.cost_volume(img_l, img_r, 7, lo, hi)
+    full = orc.cost_volume(img_l, img_r, 7)
+    for p in range(45):
+        for d in range(8):
+            if lo.ravel()[p] <= d <= hi.ravel()[p]:
+                assert vol[p, d] == full[p, d]
+            else:
+                assert np.isnan(vol[p, d])
+    # bounded by the saturated value, non-negative
+    assert np.all(full >= 0) and np.all(full <= 0.89 * 7 + 0.11 * 2 + 1e-12)
+
+
+def test_cost_identical_images_zero_disparity_is_zero(orc):
+    img = rng_img(9, 6, 8).astype(np.float64)
+    vol = orc.cost_volume(img, img, 3)
+    assert np.all(vol[:, 0] == 0.0)
+
+
+# --- edge keys (eq. weight) -------------------------------------------------
+
+def test_edge_keys_golden(orc):
+    g = load("pyramid_3x3.json")
+    lv = orc.pyramid(np.array(g["image_rgb_rows"], np.uint8), 2, 2)
+    np.testing.assert_array_equal(orc.edge_keys(lv[1], 1), g["level1_edge_keys"]["keys"])
+
+
+# --- MST (Section 1, Section 3.2 Rules 1-2) ------------------------------------
+
+def mst_of(orc, img, level=0):
+    H, W = img.shape[:2]
+    key = orc.edge_keys(img.astype(np.float64), level)
+    in_tree, _, _, n = orc.kruskal(H, W, key)
+    return key, in_tree, n
+
+
+def k64(key, e):
+    return (int(key[e]) << 32) | e
+
+
+@pytest.mark.parametrize("seed,H,W", [(0, 9, 13), (1, 17, 5), (2, 1, 30), (3, 24, 24)])
+def test_mst_matches_scipy(orc, seed, H, W):
+    # narrow intensity range => many equal weights; the (key, id) order decides
+    img = rng_img(seed, H, W, 100, 104)
+    key, in_tree, n = mst_of(orc, img)
+    assert n == H * W - 1
+    N = H * W
+    rows, cols, vals = [], [], []
+    for e, p, q in grid_edges(H, W):
+        rows.append(p); cols.append(q); vals.append(float(k64(key, e) + 1))
+    G = sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()
+    T = minimum_spanning_tree(G).tocoo()
+    ref = set()
+    for p, q, v in zip(T.row, T.col, T.data):
+        ref.add(int(v) - 1 & 0xFFFFFFFF)
+    got = {e for e in range(2 * N) if in_tree[e]}
+    assert got == ref
+
+
+def test_mst_cycle_property_bruteforce(orc):
+    H, W = 6, 7
+    img = rng_img(11, H, W, 0, 6)
+    key, in_tree, n = mst_of(orc, img)
+    N = H * W
+    adj = [[] for _ in range(N)]
+    for e, p, q in grid_edges(H, W):
+        if in_tree[e]:
+            adj[p].append((q, e)); adj[q].append((p, e))
+
+    def path_edges(a, b):
+        prev = {a: None}
+        stack = [a]
+        while stack:
+            v = stack.pop()
+            for q, e in adj[v]:
+                if q not in prev:
+                    prev[q] = (v, e); stack.append(q)
+        out, v = [], b
+        while prev[v] is not None:
+            v, e = prev[v][0], prev[v][1]
+            out.append(e)
+        return out
+
+    for e, p, q in grid_edges(H, W):
+        if in_tree[e]:
+            continue
+        assert all(k64(key, f) < k64(key, e) for f in path_edges(p, q))
+
+
+def test_mst_exhaustive_3x3(orc):
+    H, W = 3, 3
+    img = rng_img(4, H, W, 0, 3)
+    key, in_tree, n = mst_of(orc, img)
+    edges = grid_edges(H, W)
+    best = None
+    for sub in itertools.combinations(edges, H * W - 1):
+        par = list(range(H * W))
+
+        def find(v):
+            while par[v] != v:
+                v = par[v]
+            return v
+        ok = True
+        for e, p, q in sub:
+            a, b = find(p), find(q)
+            if a == b:
+                ok = False; break
+            par[a] = b
+        if not ok:
+            continue
+        tot = sum(k64(key, e) for e, _, _ in sub)
+        if best is None or tot < best[0]:
+            best = (tot, {e for e, _, _ in sub})
+    assert {e for e in range(2 * H * W) if in_tree[e]} == best[1]
+
+
+# --- rooting and level order ---------------------------------------------------
+
+def test_root_forest_invariants(orc):
+    H, W = 11, 14
+    img = rng_img(6, H, W)
+    key = orc.edge_keys(img.astype(np.float64), 0)
+    lo = np.random.default_rng(1).integers(0, 3, size=(H, W)) * 2
+    in_tree, tlo, thi, _ = orc.kruskal(H, W, key, lo, lo + 1)
+    f = orc.root_forest(H, W, in_tree, key, 0)
+    N = H * W
+    ncomp, lab = connected_components(forest_graph(H, W, in_tree), directed=False)
+    # root = smallest id of each component
+    for c in range(ncomp):
+        members = np.flatnonzero(lab == c)
+        assert f["tree"][members].min() == members.min() and np.all(f["tree"][members] == members.min())
+        assert f["parent"][members.min()] == -1
+    # every forest edge is a parent link, depth grows by one along it
+    links = set()
+    for v in range(N):
+        p = f["parent"][v]
+        if p >= 0:
+            assert f["depth"][v] == f["depth"][p] + 1
+            links.add((min(v, p), max(v, p)))
+    assert links == {(p, q) for e, p, q in grid_edges(H, W) if in_tree[e]}
+    # level order: permutation sorted by (depth, id)
+    order = f["order"]
+    assert sorted(order.tolist()) == list(range(N))
+    keys = [(f["depth"][v], v) for v in order]
+    assert keys == sorted(keys)
+    lp = f["level_ptr"]
+    assert lp[0] == 0 and lp[-1] == N and len(lp) == f["n_levels"] + 1
+    for k in range(f["n_levels"]):
+        assert np.all(f["depth"][order[lp[k]:lp[k + 1]]] == k)
+
+
+# --- disparity forest (Section 3.2: DT-Rule 1, DT-Rule 2) --------------------------
+
+def msf_equal_intervals(H, W, key, lo, hi):
+    """Independent: scipy MSF of the grid restricted to equal-interval edges."""
+    N = H * W
+    rows, cols, vals = [], [], []
+    lo = lo.ravel(); hi = hi.ravel()
+    for e, p, q in grid_edges(H, W):
+        if lo[p] == lo[q] and hi[p] == hi[q]:
+            rows.append(p); cols.append(q); vals.append(float(k64(key, e) + 1))
+    G = sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()
+    T = minimum_spanning_tree(G).tocoo()
+    return {int(v) - 1 & 0xFFFFFFFF for v in T.data}
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_hdpf_regime_equals_filtered_msf(orc, seed):
+    # widths <= 10 and beta = 19/20 > 9/10: only equal intervals can merge
+    rng = np.random.default_rng(100 + seed)
+    H, W = 12, 15
+    img = rng_img(200 + seed, H, W, 90, 110)
+    key = orc.edge_keys(img.astype(np.float64), 0)
+    blocks = rng.integers(0, 3, size=(H // 3 + 1, W // 3 + 1))
+    i = np.kron(blocks, np.ones((3, 3), int))[:H, :W]
+    lo = np.clip(2 * i - 4, 0, 15); hi = np.clip(2 * i + 5, 0, 15)
+    in_tree, tlo, thi, n = orc.kruskal(H, W, key, lo, hi, beta=(19, 20))
+    assert {e for e in range(2 * H * W) if in_tree[e]} == msf_equal_intervals(H, W, key, lo, hi)
+    # intervals never widen in the regime
+    np.testing.assert_array_equal(tlo, lo.ravel()); np.testing.assert_array_equal(thi, hi.ravel())
+
+
+def test_hdpf_full_intervals_is_mst(orc):
+    H, W = 10, 12
+    img = rng_img(31, H, W)
+    key = orc.edge_keys(img.astype(np.float64), 0)
+    mst, _, _, _ = orc.kruskal(H, W, key)
+    full_lo = np.zeros((H, W), np.int32); full_hi = np.full((H, W), 15, np.int32)
+    hd, tlo, thi, _ = orc.kruskal(H, W, key, full_lo, full_hi, beta=(19, 20))
+    np.testing.assert_array_equal(mst, hd)
+
+
+@pytest.mark.parametrize("beta", [(3, 5), (1, 2), (19, 20)])
+def test_hdpf_rules_hold_outside_regime(orc, beta):
+    """Literal process with wide random intervals: DT-Rule 1 on every forest edge,
+    tree interval = union of member pixel intervals and an interval (contiguity),
+    and every merge satisfied DT-Rule 2 (checked: the final tree interval of a
+    tree that holds an edge is at least as wide as both pixel intervals)."""
+    rng = np.random.default_rng(7)
+    H, W = 9, 10
+    img = rng_img(8, H, W)
+    key = orc.edge_keys(img.astype(np.float64), 0)
+    lo = rng.integers(0, 20, size=(H, W)); hi = lo + rng.integers(0, 12, size=(H, W))
+    in_tree, tlo, thi, _ = orc.kruskal(H, W, key, lo, hi, beta=beta)
+    lo = lo.ravel(); hi = hi.ravel()
+    for e, p, q in grid_edges(H, W):
+        if in_tree[e]:
+            assert max(lo[p], lo[q]) <= min(hi[p], hi[q])  # DT-Rule 1
+    ncomp, lab = connected_components(forest_graph(H, W, in_tree), directed=False)
+    for c in range(ncomp):
+        m = np.flatnonzero(lab == c)
+        covered = np.zeros(40, bool)
+        for v in m:
+            covered[lo[v]:hi[v] + 1] = True
+        idx = np.flatnonzero(covered)
+        assert idx.max() - idx.min() + 1 == len(idx)  # union is an interval
+        assert np.all(tlo[m] == idx.min()) and np.all(thi[m] == idx.max())
+
+
+def test_hdpf_dt_rule2_bruteforce_two_pixels(orc):
+    # 1x2 image: the single edge merges iff IoU >= beta (exact rational test)
+    key = np.array([5, -1, -1, -1], np.int64)
+    for a0, a1, b0, b1 in itertools.product(range(4), range(4), range(4), range(4)):
+        if a1 < a0 or b1 < b0:
+            continue
+        lo = np.array([[a0, b0]]); hi = np.array([[a1, b1]])
+        inter = max(0, min(a1, b1) - max(a0, b0) + 1)
+        uni = len(set(range(a0, a1 + 1)) | set(range(b0, b1 + 1)))
+        for beta in [(1, 2), (2, 3), (19, 20)]:
+            in_tree, _, _, _ = orc.kruskal(1, 2, key, lo, hi, beta=beta)
+            want = inter > 0 and Fraction(inter, uni) >= Fraction(*beta)
+            assert bool(in_tree[0]) == want
+
+
+# --- aggregation (eq. aggre, eq. W, eq. S, eq. C) --------------------------------
+
+def tree_setup(orc, seed, H, W, level=0, lo=None, hi=None):
+    img = rng_img(seed, H, W)
+    key = orc.edge_keys(img.astype(np.float64), level)
+    in_tree, tlo, thi, _ = orc.kruskal(H, W, key, lo, hi)
+    ew = orc.edge_weights(key, level)
+    f = orc.root_forest(H, W, in_tree, key, level)
+    return key, in_tree, ew, f
+
+
+def test_aggregate_direct_equals_dense_shortest_path(orc):
+    H, W, D, sigma = 8, 9, 5, 0.1
+    key, in_tree, ew, f = tree_setup(orc, 41, H, W)
+    cost = np.random.default_rng(3).random((H * W, D))
+    G = forest_graph(H, W, in_tree, np.nan_to_num(ew) + 0.0)
+    # zero-weight edges would vanish from a sparse matrix: shift by a tiny amount
+    G.data = G.data + 1e-300
+    Dist = shortest_path(G, directed=False)
+    A = np.where(np.isinf(Dist), 0.0, np.exp(-Dist / sigma))
+    ref = A @ cost
+    got = orc.aggregate_direct(H, W, in_tree, ew, sigma, cost)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=0)
+
+
+def test_aggregate_chain_is_two_sided_exponential_filter(orc):
+    # 1 x N image: the tree is the chain, D(i,j) = |t_i - t_j| with t the cumulative weight
+    W, D, sigma = 40, 3, 0.2
+    img = rng_img(5, 1, W)
+    key = orc.edge_keys(img.astype(np.float64), 0)
+    in_tree, _, _, n = orc.kruskal(1, W, key)
+    assert n == W - 1
+    w = np.array([key[2 * x] / 255.0 for x in range(W - 1)])
+    t = np.concatenate([[0.0], np.cumsum(w)])
+    cost = np.random.default_rng(1).random((W, D))
+    ref = np.exp(-np.abs(t[:, None] - t[None, :]) / sigma) @ cost
+    got = orc.aggregate_direct(1, W, in_tree, orc.edge_weights(key, 0), sigma, cost)
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
+    f = orc.root_forest(1, W, in_tree, key, 0)
+    np.testing.assert_allclose(orc.aggregate_twopass(f["parent"], f["wgt"], f["order"], sigma, cost),
+                               ref, rtol=1e-12)
+
+
+def test_aggregate_limits(orc):
+    H, W, D = 7, 8, 4
+    lo = np.random.default_rng(2).integers(0, 2, size=(H, W)) * 3
+    key, in_tree, ew, f = tree_setup(orc, 43, H, W, 0, lo, lo + 2)
+    cost = np.random.default_rng(4).random((H * W, D))
+    ncomp, lab = connected_components(forest_graph(H, W, in_tree), directed=False)
+    # sigma -> infinity: every weight is 1, each pixel gets the sum over its tree
+    big = orc.aggregate_twopass(f["parent"], f["wgt"], f["order"], 1e30, cost)
+    ref = np.zeros_like(cost)
+    for c in range(ncomp):
+        m = lab == c
+        ref[m] = cost[m].sum(axis=0)
+    np.testing.assert_allclose(big, ref, rtol=1e-12)
+    # sigma -> 0 with positive edge weights: identity
+    pos = np.all(f["wgt"][f["parent"] >= 0] > 0)
+    if pos:
+        np.testing.assert_allclose(
+            orc.aggregate_twopass(f["parent"], f["wgt"], f["order"], 1e-9, cost), cost, rtol=1e-12)
+
+
+def test_aggregate_operator_symmetric(orc):
+    H, W, sigma = 5, 6, 0.15
+    key, in_tree, ew, f = tree_setup(orc, 44, H, W)
+    N = H * W
+    M = orc.aggregate_twopass(f["parent"], f["wgt"], f["order"], sigma, np.eye(N))
+    np.testing.assert_allclose(M, M.T, rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_twopass_equals_direct(orc, seed):
+    H, W, D, sigma = 13, 11, 6, 0.1
+    lo = np.random.default_rng(seed).integers(0, 3, size=(H, W)) * 2
+    key, in_tree, ew, f = tree_setup(orc, 50 + seed, H, W, 0, lo, lo + 4)
+    cost = np.random.default_rng(seed).random((H * W, D))
+    a = orc.aggregate_twopass(f["parent"], f["wgt"], f["order"], sigma, cost)
+    b = orc.aggregate_direct(H, W, in_tree, ew, sigma, cost)
+    np.testing.assert_allclose(a, b, rtol=1e-12)
+
+
+# --- WTA (Section 3.3) ---------------------------------------------------------------
+
+def test_wta_hand_cases(orc):
+    agg = np.array([[3.0, 1.0, 1.0, 2.0],
+                    [5.0, 4.0, 3.0, 0.0],
+                    [2.0, 2.0, 2.0, 2.0]])
+    lo = np.array([0, 1, 1]); hi = np.array([3, 2, 3])
+    disp, c1, c2 = orc.wta(agg, lo, hi)
+    assert disp.tolist() == [1, 2, 1]
+    assert c1.tolist() == [1.0, 3.0, 2.0] and c2.tolist() == [1.0, 4.0, 2.0]
+
+
+# --- interval prediction (Section 3.1) -------------------------------------------------
+
+def test_predict_range_golden(orc):
+    g = load("predict_range.json")
+    lo, hi = orc.predict_range(np.array(g["disp_up"]), g["H"], g["W"], g["S"], g["window"],
+                               g["dmax_l"])
+    for c in g["cases"]:
+        assert (lo[c["y"], c["x"]], hi[c["y"], c["x"]]) == (c["lo"], c["hi"])
+
+
+def test_predict_range_properties(orc):
+    rng = np.random.default_rng(0)
+    for S, w, dl in [(2, 4, 255), (2, 6, 191), (2, 0, 31), (2, 4, 7)]:
+        du = dl // S
+        up = rng.integers(0, du + 1, size=(6, 7))
+        lo, hi = orc.predict_range(up, 12, 13, S, w, dl)
+        i = np.kron(up, np.ones((S, S), int))[:12, :13]
+        assert np.all(lo <= S * i) and np.all(hi >= np.minimum(S * i + S - 1, dl))
+        assert np.all(hi - lo + 1 <= S + 2 * w) and np.all(lo >= 0) and np.all(hi <= dl)
+
+
+# --- one layer and the HDP loop ----------------------------------------------------------
+
+def test_stereo_level_matches_stage_composition(orc):
+    H, W, dmax, sigma = 12, 16, 7, 0.1
+    L = rng_img(60, H, W).astype(np.float64); R = rng_img(61, H, W).astype(np.float64)
+    r = orc.stereo_level(L, R, dmax, 0, sigma=sigma, sample_d=[0, 3, 7])
+    key = orc.edge_keys(L, 0)
+    in_tree, _, _, _ = orc.kruskal(H, W, key)
+    f = orc.root_forest(H, W, in_tree, key, 0)
+    cost = orc.cost_volume(L, R, dmax)
+    agg = orc.aggregate_direct(H, W, in_tree, orc.edge_weights(key, 0), sigma, cost)
+    disp, c1, c2 = orc.wta(agg)
+    np.testing.assert_allclose(r["sample_agg"], agg[:, [0, 3, 7]].T, rtol=1e-12)
+    gap = (c2 - c1) / c1
+    ok = gap > 1e-9
+    assert np.array_equal(r["disp"].ravel()[ok], disp[ok])
+    np.testing.assert_array_equal(r["parent"], f["parent"])
+    np.testing.assert_array_equal(r["order"], f["order"])
+
+
+def test_hdp_restriction_equals_full_range_over_same_forest(orc):
+    """Aggregation is independent per label, so HDP aggregation at (p, x) equals
+    full-range aggregation over the same forest, for x in the tree interval."""
+    H, W, dmax, sigma = 16, 20, 15, 0.1
+    L = rng_img(70, H, W).astype(np.float64); R = rng_img(71, H, W).astype(np.float64)
+    up = np.random.default_rng(3).integers(0, 8, size=(8, 10))
+    lo, hi = orc.predict_range(up, H, W, 2, 2, dmax)
+    r = orc.stereo_level(L, R, dmax, 0, lo, hi, sigma=sigma, sample_d=list(range(16)))
+    key = orc.edge_keys(L, 0)
+    in_tree, tlo, thi, _ = orc.kruskal(H, W, key, lo, hi)
+    full = orc.cost_volume(L, R, dmax)
+    agg = orc.aggregate_direct(H, W, in_tree, orc.edge_weights(key, 0), sigma, full)
+    inside = (np.arange(16)[:, None] >= tlo[None, :]) & (np.arange(16)[:, None] <= thi[None, :])
+    np.testing.assert_allclose(r["sample_agg"][inside], agg.T[inside], rtol=1e-12)
+    assert np.all(np.isnan(r["sample_agg"][~inside]))
+    # winners agree wherever the full-range winner over this forest is inside the interval
+    dfull = np.argmin(agg, axis=1)
+    ok = (dfull >= tlo) & (dfull <= thi)
+    assert np.array_equal(r["disp"].ravel()[ok], dfull[ok])
+
+
+def test_hdp_wide_window_equals_full_range(orc):
+    # window >= dmax: every interval is [0, d_l], the forest is the MST
+    from paper_1509_08197_amd import scenes
+    pair = scenes.small_scene(5, 24, 32, 15)
+    res = orc.hdp_stereo(pair.left, pair.right, 15, S=2, L=2, window=64, want_forest=True)
+    lv = orc.pyramid(pair.left, 2, 2); rv = orc.pyramid(pair.right, 2, 2)
+    for l in range(2):
+        ds = 15 >> l
+        full = orc.stereo_level(lv[l], rv[l], ds, l)
+        np.testing.assert_array_equal(res[l]["disp"], full["disp"])
+        np.testing.assert_array_equal(res[l]["parent"], full["parent"])
+
+
+# --- gradients ----------------------------------------------------------------------------
+
+def test_grad_dense_matches_finite_differences(orc):
+    H, W, D, sigma = 4, 5, 3, 0.2
+    key, in_tree, ew, f = tree_setup(orc, 80, H, W)
+    N = H * W
+    rng = np.random.default_rng(5)
+    cost = rng.random((N, D)); g = rng.normal(size=(N, D))
+
+    def loss(c, ew_, s):
+        return float(np.sum(g * orc.aggregate_direct(H, W, in_tree, ew_, s, c)))
+
+    dC, dw, ds = orc.aggregate_grad_dense(H, W, in_tree, ew, sigma, cost, g)
+    h = 1e-6
+    for (p, x) in [(0, 0), (7, 2), (19, 1)]:
+        cp = cost.copy(); cp[p, x] += h; cm = cost.copy(); cm[p, x] -= h
+        assert abs((loss(cp, ew, sigma) - loss(cm, ew, sigma)) / (2 * h) - dC[p, x]) < 1e-7
+    fd = (loss(cost, ew, sigma + h) - loss(cost, ew, sigma - h)) / (2 * h)
+    assert abs(fd - ds) < 1e-6 * max(1, abs(ds))
+    for e in [e for e in range(2 * N) if in_tree[e]][:6]:
+        ep = ew.copy(); ep[e] += h; em = ew.copy(); em[e] -= h
+        fd = (loss(cost, ep, sigma) - loss(cost, em, sigma)) / (2 * h)
+        assert abs(fd - dw[e]) < 1e-6 * max(1, abs(dw[e]))
+
+
+def test_grad_twopass_matches_dense(orc):
+    H, W, D, sigma = 7, 9, 4, 0.1
+    lo = np.random.default_rng(9).integers(0, 2, size=(H, W)) * 5
+    key, in_tree, ew, f = tree_setup(orc, 81, H, W, 0, lo, lo + 3)
+    N = H * W
+    rng = np.random.default_rng(6)
+    cost = rng.random((N, D)); g = rng.normal(size=(N, D))
+    dC, dw, ds = orc.aggregate_grad_dense(H, W, in_tree, ew, sigma, cost, g)
+    tC, tw, ts = orc.aggregate_backward_twopass(f["parent"], f["wgt"], f["order"], sigma, cost, g)
+    np.testing.assert_allclose(tC, dC, rtol=1e-10, atol=1e-12)
+    assert abs(ts - ds) <= 1e-9 * max(1.0, abs(ds))
+    # per-node edge gradient vs per-edge-id dense gradient
+    for v in range(N):
+        p = f["parent"][v]
+        if p < 0:
+            continue
+        a, b = min(v, p), max(v, p)
+        e = 2 * a if b == a + 1 else 2 * a + 1
+        assert abs(tw[v] - dw[e]) <= 1e-9 * max(1.0, abs(dw[e]))
+
+
+def test_edge_keys_constant_and_scaled(orc):
+    # identical neighbours weigh 0; a unit step of one channel weighs 4^l at level l
+    img = np.full((3, 4, 3), 50.0)
+    k = orc.edge_keys(img, 0)
+    assert set(k.tolist()) == {0, -1}
+    img[:, 2:, 1] = 50.25
+    k2 = orc.edge_keys(img, 2)
+    assert k2[2 * 1] == 4 and k2[2 * 0] == 0 and k2[2 * 5] == 4 and k2[2 * 2] == 0
