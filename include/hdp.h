@@ -1,0 +1,259 @@
+/*
+ * hdp.h -- C ABI of the MI355X hot path of hierarchical-disparity-prediction
+ * (HDP) stereo matching (Luo et al., "Fast Non-local Stereo Matching based on
+ * Hierarchical Disparity Prediction").
+ *
+ * One layer of the method (Section 3) is
+ *     hdp_predict_range  -> pixel intervals        (Section 3.1)
+ *     hdp_build_tree     -> disparity forest       (Section 3.2)
+ *     hdp_cost_volume    -> restricted cost E      (Section 3.3, eq. E)
+ *     hdp_aggregate      -> aggregated cost C      (eq. W, eq. S, eq. C)
+ *     hdp_wta            -> disparity map          (Section 3.3)
+ * run top-down over the graph pyramid built by hdp_pyramid (Section 2.1).
+ *
+ * General rules
+ *  - Every pointer argument is a DEVICE pointer unless stated otherwise; every
+ *    call is asynchronous on `stream` (a hipStream_t, NULL = default stream).
+ *  - The caller owns all memory.  No entry point allocates device memory;
+ *    scratch space comes from a caller-provided workspace whose size is given
+ *    by the matching *_workspace_bytes query.
+ *  - A batch of `n_pairs` image pairs is processed by one call.  The pixels of
+ *    the pairs are concatenated in pair order (pair p starts at the sum of
+ *    H*W of the pairs before it); pixel (x, y) of a pair is at y*W + x.
+ *    `shapes` is a HOST array of n_pairs entries, 1 <= n_pairs <= HDP_MAX_PAIRS.
+ *  - Arguments are validated on the host before anything is enqueued; a call
+ *    that returns an error has enqueued nothing.  A HIP runtime error seen
+ *    while enqueueing is returned as HDP_EHIP.  No C++ exception crosses the
+ *    ABI.
+ *  - Labels are 0..dmax inclusive.
+ */
+#ifndef HDP_H_
+#define HDP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HDP_API __attribute__((visibility("default")))
+
+#define HDP_MAX_PAIRS 64
+#define HDP_MAX_LABELS 256   /* dmax + 1 <= 256 */
+#define HDP_MAX_PHASES 40    /* bound on the chain phases of a forest */
+#define HDP_INFO_WORDS 16
+
+typedef enum {
+    HDP_OK = 0,
+    HDP_EINVAL = -1,      /* null pointer or out-of-range scalar */
+    HDP_ESHAPE = -2,      /* bad image shape, dmax, or batch size */
+    HDP_EWORKSPACE = -3,  /* workspace smaller than required */
+    HDP_EREGIME = -4,     /* beta / interval width outside the exact regime */
+    HDP_EHIP = -5         /* HIP runtime error */
+} hdp_status;
+
+typedef struct {
+    int32_t H, W;   /* image size in pixels */
+    int32_t dmax;   /* largest label; labels are 0..dmax */
+} hdp_shape;
+
+typedef struct {
+    float a_c, tau_c;   /* weight and truncation of the colour term */
+    float a_g, tau_g;   /* weight and truncation of the gradient term */
+} hdp_cost_params;
+
+/* Indices into hdp_forest.info (device int32 words written by hdp_build_tree). */
+enum {
+    HDP_INFO_N_LEVELS = 0,   /* 1 + largest depth */
+    HDP_INFO_N_PHASES = 1,   /* number of chain phases (1 + largest light depth) */
+    HDP_INFO_N_TREES = 2,    /* number of trees in the forest */
+    HDP_INFO_WIDTH = 3,      /* row width of the volume layout (labels per row) */
+    HDP_INFO_MST_ROUNDS = 4, /* hooking rounds the spanning-forest build used */
+    HDP_INFO_RANK_ROUNDS = 5,/* pointer-jumping rounds of the tour ranking */
+    HDP_INFO_BAD_INTERVAL = 6,/* pixels whose interval was empty or wider than allowed */
+    HDP_INFO_ERROR = 7       /* nonzero if an internal consistency guard tripped */
+};
+
+/*
+ * Disparity forest of one pyramid layer for a batch (Section 3.2), plus the
+ * schedule that hdp_aggregate walks.  All arrays live inside ONE device
+ * buffer owned by the caller: size it with hdp_forest_bytes(n) and carve it
+ * with hdp_forest_bind (host-only, no GPU work).  n = total pixels of the
+ * batch at this layer.
+ *
+ * Per pixel (pixel order):
+ *   parent  parent pixel id, -1 at a root.  Each tree is rooted at its
+ *           smallest pixel id.
+ *   depth   edges from the root.
+ *   tree    root pixel id of the pixel's tree.
+ *   wgt     weight of the edge to the parent (max-channel |dI| / 255), 0 at
+ *           roots.
+ *   lo, hi  tree interval TreeIntv of the pixel's tree (labels).
+ *   row     row of the pixel in the volume layout below.
+ * Level order (canonical; not used by the aggregation schedule):
+ *   order   pixel ids sorted by (depth, id); level_ptr[k] = first position of
+ *           depth k, level_ptr[n_levels] = n.  level_ptr has n + 1 entries.
+ * Volume layout: a cost or aggregated volume is float[n][width]; row r holds
+ * the labels lo(v) .. hi(v) of pixel v = node[r] at columns 0 .. hi-lo,
+ * columns beyond are padding.  Rows are grouped in chain phases (heavy-path
+ * decomposition): phase k = rows phase_ptr[k] .. phase_ptr[k+1]-1 hold the
+ * pixels with k light edges on their root path; inside a phase every heavy
+ * path is a contiguous run of rows, root side first.
+ *   node    row -> pixel id.
+ *   prow    row of the parent, -1 at roots.
+ *   heavy   1 if the row's pixel is its parent's heavy child (same chain).
+ *   lc      [3][n] rows of the light children, -1 where absent.
+ *   rw      weight of the row's edge to its parent (= wgt[node]).
+ *   phase_ptr  HDP_MAX_PHASES + 1 entries.
+ *   info    HDP_INFO_WORDS device scalars (see HDP_INFO_*).
+ */
+typedef struct {
+    int64_t n;
+    int32_t *parent, *depth, *tree, *lo, *hi, *row;
+    float *wgt;
+    int32_t *order, *level_ptr;
+    int32_t *node, *prow, *lc;
+    uint8_t *heavy;
+    float *rw;
+    int32_t *phase_ptr, *info;
+} hdp_forest;
+
+/* Bytes of the single device buffer that holds a forest of n pixels. */
+HDP_API size_t hdp_forest_bytes(int64_t n);
+
+/* Point the fields of *f into buf (host-only).  buf must be 256-byte aligned
+ * and at least hdp_forest_bytes(n) long. */
+HDP_API hdp_status hdp_forest_bind(void *buf, size_t bytes, int64_t n, hdp_forest *f);
+
+/* Level shapes of the graph pyramid (Section 2.1): H_{l+1} = ceil(H_l / S),
+ * W_{l+1} = ceil(W_l / S), d_{l+1} = floor(d_l / S).  out (HOST) receives
+ * (L+1)*n_pairs shapes, level-major. */
+HDP_API hdp_status hdp_level_shapes(const hdp_shape *shapes, int32_t n_pairs, int32_t S, int32_t L,
+                            hdp_shape *out);
+
+/*
+ * Graph pyramid (Section 2.1) of one image per pair, S = 2 only.
+ *   rgb     uint8 [n0][3] (interleaved RGB, the batch's pixels).
+ *   levels  float [sum over l of n_l][4]: levels 0..L back to back; each
+ *           pixel holds (R, G, B, gx) where R, G, B is the mean of the S x S
+ *           nodes of the layer below that exist (exact in FP32 for S = 2) and
+ *           gx = (R+G+B)(x+1) - (R+G+B)(x-1) with replicated borders, the
+ *           numerator of the horizontal gray gradient used by the cost.
+ */
+HDP_API hdp_status hdp_pyramid(const uint8_t *rgb, const hdp_shape *shapes, int32_t n_pairs,
+                       int32_t S, int32_t L, float *levels, void *stream);
+
+/* Bytes of scratch space hdp_build_tree needs for n pixels. */
+HDP_API size_t hdp_build_tree_workspace_bytes(int64_t n);
+
+/*
+ * Spanning tree (pix_lo == NULL: minimum spanning tree, Section 1 and
+ * Rules 1-2 of Section 3.2) or disparity forest (DT-Rule 1 eq. cri1, DT-Rule 2
+ * eq. DTrules) of one layer, with edge weight of eq. weight taken as the
+ * largest channel difference.  Edges are ordered by (weight, edge id), edge id
+ * 2p = right neighbour of p, 2p+1 = pixel below.
+ *   img       level images as written by hdp_pyramid for this layer, [n][4].
+ *   shapes    HOST shapes of this layer; level = pyramid layer (weights are
+ *             exact integers at 4^level scale).
+ *   pix_lo/hi pixel intervals PixelIntv (int32 [n]) or NULL for [0, dmax].
+ *   max_width upper bound the caller guarantees on hi - lo + 1 (ignored when
+ *             pix_lo is NULL).  The forest is built exactly (the same forest
+ *             as the sequential Kruskal process with both DT rules) when
+ *             beta_num / beta_den > (max_width - 1) / max_width: then DT-Rule 2
+ *             admits only equal intervals and the forest is the minimum
+ *             spanning forest of the equal-interval edges.  Otherwise the call
+ *             returns HDP_EREGIME.  Pixels that break the bound are counted in
+ *             info[HDP_INFO_BAD_INTERVAL].
+ *   width     row width of the volume layout to prepare: at least the widest
+ *             tree interval (dmax + 1 for the full range).
+ */
+HDP_API hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int32_t n_pairs,
+                          int32_t level, const int32_t *pix_lo, const int32_t *pix_hi,
+                          int32_t max_width, int32_t beta_num, int32_t beta_den,
+                          int32_t width, const hdp_forest *f, void *ws, size_t ws_bytes,
+                          void *stream);
+
+/* Host copy of the forest's phase table and scalars (synchronises `stream`). */
+HDP_API hdp_status hdp_forest_read_info(const hdp_forest *f, int32_t *info_host,
+                                int32_t *phase_ptr_host, void *stream);
+
+/*
+ * Restricted matching cost E (eq. E) of one layer.
+ *   left/right  level images of the two views, [n][4] as written by
+ *               hdp_pyramid.
+ *   f           forest: cost is written in the forest's volume layout
+ *               float[n][width] (width from hdp_build_tree);
+ *               NULL: dense float[n][dmax+1] in pixel order, width = the
+ *               largest dmax + 1 of the batch (a pair with a smaller range
+ *               leaves its extra columns at 0).
+ *   Entry (v, x) = a_c*min(mean_c |L_c(x,y) - R_c(x-d,y)|, tau_c)
+ *                + a_g*min(|gx_L - gx_R| / 6, tau_g),
+ *   and a_c*tau_c + a_g*tau_g where x - d < 0.  Padding columns are 0.
+ */
+HDP_API hdp_status hdp_cost_volume(const float *left, const float *right, const hdp_shape *shapes,
+                           int32_t n_pairs, const hdp_forest *f, int32_t width,
+                           const hdp_cost_params *p, float *cost, void *stream);
+
+/* Bytes of scratch space hdp_aggregate / hdp_aggregate_backward need. */
+HDP_API size_t hdp_aggregate_workspace_bytes(int64_t n, int32_t width);
+
+/*
+ * Tree aggregation (eq. W, eq. S, eq. C):
+ *   agg(v, x) = sum over u in the tree of v of exp(-W(v,u)/sigma) * cost(u, x)
+ * with W the sum of edge weights on the tree path, computed exactly by a
+ * leaf-to-root and a root-to-leaf pass over the forest's chain phases.
+ *   cost, agg   float[n][width] in the forest's volume layout.
+ *   up          optional (NULL) float[n][width]: receives the leaf-to-root
+ *               sums U(v, x) = cost(v,x) + sum_children s_c U(c,x), which
+ *               hdp_aggregate_backward can reuse instead of recomputing.
+ *   phase_ptr_host / n_phases  the forest's phase table on the HOST (from
+ *               hdp_forest_read_info).
+ */
+HDP_API hdp_status hdp_aggregate(const hdp_forest *f, int32_t width, const int32_t *phase_ptr_host,
+                         int32_t n_phases, const float *cost, float sigma, float *agg,
+                         float *up, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Adjoint of hdp_aggregate for L = sum g(v,x) agg(v,x), g = grad_agg:
+ *   grad_cost = A^T g = A g (the aggregation operator is symmetric),
+ *   grad_w[v] = dL/dw of the edge (v, parent(v)) (0 at roots; NULL skips),
+ *   grad_sigma (device, 1 float; NULL skips) = dL/dsigma.
+ * cost/agg are the forward's input and output; up = the forward's U or NULL
+ * (then it is recomputed).  Same layout and phase table as hdp_aggregate.
+ */
+HDP_API hdp_status hdp_aggregate_backward(const hdp_forest *f, int32_t width,
+                                  const int32_t *phase_ptr_host, int32_t n_phases,
+                                  const float *cost, const float *agg, const float *up,
+                                  const float *grad_agg, float sigma, float *grad_cost,
+                                  float *grad_w, float *grad_sigma, void *ws, size_t ws_bytes,
+                                  void *stream);
+
+/*
+ * Winner-takes-all (Section 3.3): disp[v] = the label of least aggregated cost
+ * in [lo(v), hi(v)], lowest label on ties.
+ *   f == NULL: agg is dense float[n][width] in pixel order, labels 0..dmax of
+ *   each pair.  disp: int32 [n] in pixel order.
+ */
+HDP_API hdp_status hdp_wta(const hdp_forest *f, const hdp_shape *shapes, int32_t n_pairs,
+                   int32_t width, const float *agg, int32_t *disp, void *stream);
+
+/*
+ * Pixel interval prediction (Section 3.1) for layer l from the disparity map
+ * of layer l+1:
+ *   PixelIntv(x, y) = [S*i - window, S*i + S - 1 + window] intersected with
+ *   [0, dmax_l], i = disp_upper at (floor(x/S), floor(y/S)).
+ * upper/lower are HOST shapes of layers l+1 and l (same pairs).
+ * pix_lo/pix_hi: int32 [n_l].
+ */
+HDP_API hdp_status hdp_predict_range(const int32_t *disp_upper, const hdp_shape *upper,
+                             const hdp_shape *lower, int32_t n_pairs, int32_t S,
+                             int32_t window, int32_t *pix_lo, int32_t *pix_hi, void *stream);
+
+HDP_API const char *hdp_status_str(hdp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDP_H_ */

@@ -1,0 +1,315 @@
+// C ABI of the HDP library: host-side validation, batch geometry and dispatch
+// to the HIP launchers.  Nothing here allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "hdp.h"
+#include "kernels.hpp"
+
+using hdp::LevelGeom;
+
+namespace {
+
+constexpr int64_t kMaxPixels = (int64_t(1) << 30);  // tour slots 4n fit in int32
+constexpr int64_t kMaxPairPixels = (int64_t(1) << 22) - 1;  // packed depth field
+
+hdp_status last_hip() {
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? HDP_OK : HDP_EHIP;
+}
+
+hdp_status make_geom(const hdp_shape *shapes, int32_t n_pairs, int32_t level, LevelGeom *g) {
+    if (!shapes) return HDP_EINVAL;
+    if (n_pairs < 1 || n_pairs > HDP_MAX_PAIRS) return HDP_ESHAPE;
+    std::memset(g, 0, sizeof(*g));
+    g->n_pairs = n_pairs;
+    g->level = level;
+    int64_t off = 0;
+    for (int i = 0; i < n_pairs; ++i) {
+        const hdp_shape &s = shapes[i];
+        if (s.H < 1 || s.W < 1 || s.dmax < 0 || s.dmax >= HDP_MAX_LABELS) return HDP_ESHAPE;
+        int64_t px = (int64_t)s.H * s.W;
+        if (px > kMaxPairPixels) return HDP_ESHAPE;
+        g->off[i] = (int32_t)off;
+        g->H[i] = s.H;
+        g->W[i] = s.W;
+        g->dmax[i] = s.dmax;
+        off += px;
+        if (off > kMaxPixels) return HDP_ESHAPE;
+    }
+    g->off[n_pairs] = (int32_t)off;
+    return HDP_OK;
+}
+
+int64_t total_pixels(const LevelGeom &g) { return g.off[g.n_pairs]; }
+
+int max_dmax(const LevelGeom &g) {
+    int m = 0;
+    for (int i = 0; i < g.n_pairs; ++i) m = g.dmax[i] > m ? g.dmax[i] : m;
+    return m;
+}
+
+struct FLayout {
+    size_t parent, depth, tree, lo, hi, row, wgt, order, level_ptr, node, prow, lc, heavy, rw,
+        phase_ptr, info, end;
+};
+
+FLayout forest_layout(int64_t n) {
+    FLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~size_t(255);
+        size_t at = off;
+        off += bytes;
+        return at;
+    };
+    L.parent = take(4 * n);
+    L.depth = take(4 * n);
+    L.tree = take(4 * n);
+    L.lo = take(4 * n);
+    L.hi = take(4 * n);
+    L.row = take(4 * n);
+    L.wgt = take(4 * n);
+    L.order = take(4 * n);
+    L.level_ptr = take(4 * (n + 1));
+    L.node = take(4 * n);
+    L.prow = take(4 * n);
+    L.lc = take(4 * 3 * n);
+    L.heavy = take(n);
+    L.rw = take(4 * n);
+    L.phase_ptr = take(4 * (HDP_MAX_PHASES + 1));
+    L.info = take(4 * HDP_INFO_WORDS);
+    L.end = (off + 255) & ~size_t(255);
+    return L;
+}
+
+bool forest_ok(const hdp_forest *f, int64_t n) {
+    return f && f->n == n && f->parent && f->depth && f->tree && f->lo && f->hi && f->row &&
+           f->wgt && f->order && f->level_ptr && f->node && f->prow && f->lc && f->heavy &&
+           f->rw && f->phase_ptr && f->info;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hdp_forest_bytes(int64_t n) { return n < 1 ? 0 : forest_layout(n).end; }
+
+hdp_status hdp_forest_bind(void *buf, size_t bytes, int64_t n, hdp_forest *f) {
+    if (!buf || !f || n < 1) return HDP_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(buf) & 255) != 0) return HDP_EINVAL;
+    FLayout L = forest_layout(n);
+    if (bytes < L.end) return HDP_EWORKSPACE;
+    char *b = reinterpret_cast<char *>(buf);
+    f->n = n;
+    f->parent = reinterpret_cast<int32_t *>(b + L.parent);
+    f->depth = reinterpret_cast<int32_t *>(b + L.depth);
+    f->tree = reinterpret_cast<int32_t *>(b + L.tree);
+    f->lo = reinterpret_cast<int32_t *>(b + L.lo);
+    f->hi = reinterpret_cast<int32_t *>(b + L.hi);
+    f->row = reinterpret_cast<int32_t *>(b + L.row);
+    f->wgt = reinterpret_cast<float *>(b + L.wgt);
+    f->order = reinterpret_cast<int32_t *>(b + L.order);
+    f->level_ptr = reinterpret_cast<int32_t *>(b + L.level_ptr);
+    f->node = reinterpret_cast<int32_t *>(b + L.node);
+    f->prow = reinterpret_cast<int32_t *>(b + L.prow);
+    f->lc = reinterpret_cast<int32_t *>(b + L.lc);
+    f->heavy = reinterpret_cast<uint8_t *>(b + L.heavy);
+    f->rw = reinterpret_cast<float *>(b + L.rw);
+    f->phase_ptr = reinterpret_cast<int32_t *>(b + L.phase_ptr);
+    f->info = reinterpret_cast<int32_t *>(b + L.info);
+    return HDP_OK;
+}
+
+hdp_status hdp_level_shapes(const hdp_shape *shapes, int32_t n_pairs, int32_t S, int32_t L,
+                            hdp_shape *out) {
+    if (!shapes || !out) return HDP_EINVAL;
+    if (n_pairs < 1 || n_pairs > HDP_MAX_PAIRS || S < 2 || L < 0 || L > 8) return HDP_ESHAPE;
+    for (int i = 0; i < n_pairs; ++i) {
+        hdp_shape s = shapes[i];
+        if (s.H < 1 || s.W < 1 || s.dmax < 0) return HDP_ESHAPE;
+        for (int l = 0; l <= L; ++l) {
+            out[(size_t)l * n_pairs + i] = s;
+            s.H = (s.H + S - 1) / S;
+            s.W = (s.W + S - 1) / S;
+            s.dmax = s.dmax / S;
+        }
+    }
+    return HDP_OK;
+}
+
+hdp_status hdp_pyramid(const uint8_t *rgb, const hdp_shape *shapes, int32_t n_pairs, int32_t S,
+                       int32_t L, float *levels, void *stream) {
+    if (!rgb || !levels) return HDP_EINVAL;
+    if (S != 2 || L < 0 || L > 8) return HDP_EINVAL;
+    hdp_shape ls[(8 + 1) * HDP_MAX_PAIRS];
+    hdp_status st = hdp_level_shapes(shapes, n_pairs, S, L, ls);
+    if (st != HDP_OK) return st;
+    LevelGeom geoms[9];
+    for (int l = 0; l <= L; ++l) {
+        st = make_geom(ls + (size_t)l * n_pairs, n_pairs, l, &geoms[l]);
+        if (st != HDP_OK) return st;
+    }
+    (void)hipGetLastError();
+    hdp::launch_pyramid(rgb, geoms, L, S, levels, (hipStream_t)stream);
+    return last_hip();
+}
+
+size_t hdp_build_tree_workspace_bytes(int64_t n) {
+    return n < 1 ? 0 : hdp::tree_workspace_bytes(n);
+}
+
+hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int32_t n_pairs,
+                          int32_t level, const int32_t *pix_lo, const int32_t *pix_hi,
+                          int32_t max_width, int32_t beta_num, int32_t beta_den, int32_t width,
+                          const hdp_forest *f, void *ws, size_t ws_bytes, void *stream) {
+    if (!img || !ws) return HDP_EINVAL;
+    if ((pix_lo == nullptr) != (pix_hi == nullptr)) return HDP_EINVAL;
+    if (level < 0 || level > 8) return HDP_EINVAL;
+    LevelGeom g;
+    hdp_status st = make_geom(shapes, n_pairs, level, &g);
+    if (st != HDP_OK) return st;
+    int64_t n = total_pixels(g);
+    if (!forest_ok(f, n)) return HDP_EINVAL;
+    if (width < 1 || width > HDP_MAX_LABELS) return HDP_EINVAL;
+    if (pix_lo) {
+        if (max_width < 1 || width < max_width) return HDP_EINVAL;
+        // exact regime: two distinct intervals of width <= w have IoU <= (w-1)/w < beta
+        if (beta_num < 1 || beta_den < 1 || beta_num > beta_den) return HDP_EINVAL;
+        if ((int64_t)beta_num * max_width <= (int64_t)beta_den * (max_width - 1))
+            return HDP_EREGIME;
+    } else if (width < max_dmax(g) + 1) {
+        return HDP_EINVAL;
+    }
+    if (ws_bytes < hdp::tree_workspace_bytes(n)) return HDP_EWORKSPACE;
+    (void)hipGetLastError();
+    hdp::launch_build_tree(img, g, pix_lo, pix_hi, max_width, width, *f, ws, (hipStream_t)stream);
+    return last_hip();
+}
+
+hdp_status hdp_forest_read_info(const hdp_forest *f, int32_t *info_host, int32_t *phase_ptr_host,
+                                void *stream) {
+    if (!f || !f->info || !f->phase_ptr) return HDP_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (info_host &&
+        hipMemcpyAsync(info_host, f->info, 4 * HDP_INFO_WORDS, hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
+        return HDP_EHIP;
+    if (phase_ptr_host && hipMemcpyAsync(phase_ptr_host, f->phase_ptr, 4 * (HDP_MAX_PHASES + 1),
+                                         hipMemcpyDeviceToHost, st) != hipSuccess)
+        return HDP_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return HDP_EHIP;
+    return HDP_OK;
+}
+
+hdp_status hdp_cost_volume(const float *left, const float *right, const hdp_shape *shapes,
+                           int32_t n_pairs, const hdp_forest *f, int32_t width,
+                           const hdp_cost_params *p, float *cost, void *stream) {
+    if (!left || !right || !p || !cost) return HDP_EINVAL;
+    LevelGeom g;
+    hdp_status st = make_geom(shapes, n_pairs, 0, &g);
+    if (st != HDP_OK) return st;
+    int64_t n = total_pixels(g);
+    if (f && !forest_ok(f, n)) return HDP_EINVAL;
+    if (width < 1 || width > HDP_MAX_LABELS) return HDP_EINVAL;
+    if (!f && width < max_dmax(g) + 1) return HDP_EINVAL;
+    (void)hipGetLastError();
+    hdp::launch_cost_volume(left, right, g, f ? f->node : nullptr, f ? f->lo : nullptr,
+                            f ? f->hi : nullptr, width, *p, cost, (hipStream_t)stream);
+    return last_hip();
+}
+
+size_t hdp_aggregate_workspace_bytes(int64_t n, int32_t width) {
+    if (n < 1 || width < 1) return 0;
+    return hdp::aggregate_workspace_bytes(n, width);
+}
+
+static hdp_status check_phases(const hdp_forest *f, int32_t width, const int32_t *pp, int32_t np) {
+    if (!f || !pp) return HDP_EINVAL;
+    if (width < 1 || width > HDP_MAX_LABELS) return HDP_EINVAL;
+    if (np < 1 || np > HDP_MAX_PHASES) return HDP_EINVAL;
+    if (pp[0] != 0 || pp[np] != f->n) return HDP_EINVAL;
+    for (int k = 0; k < np; ++k)
+        if (pp[k + 1] < pp[k]) return HDP_EINVAL;
+    return HDP_OK;
+}
+
+hdp_status hdp_aggregate(const hdp_forest *f, int32_t width, const int32_t *phase_ptr_host,
+                         int32_t n_phases, const float *cost, float sigma, float *agg, float *up,
+                         void *ws, size_t ws_bytes, void *stream) {
+    hdp_status st = check_phases(f, width, phase_ptr_host, n_phases);
+    if (st != HDP_OK) return st;
+    if (!cost || !agg || !ws || !(sigma > 0.f)) return HDP_EINVAL;
+    if (ws_bytes < hdp::aggregate_workspace_bytes(f->n, width)) return HDP_EWORKSPACE;
+    (void)hipGetLastError();
+    hdp::launch_aggregate(*f, width, phase_ptr_host, n_phases, cost, sigma, agg, up, ws,
+                          (hipStream_t)stream);
+    return last_hip();
+}
+
+hdp_status hdp_aggregate_backward(const hdp_forest *f, int32_t width,
+                                  const int32_t *phase_ptr_host, int32_t n_phases,
+                                  const float *cost, const float *agg, const float *up,
+                                  const float *grad_agg, float sigma, float *grad_cost,
+                                  float *grad_w, float *grad_sigma, void *ws, size_t ws_bytes,
+                                  void *stream) {
+    hdp_status st = check_phases(f, width, phase_ptr_host, n_phases);
+    if (st != HDP_OK) return st;
+    if (!cost || !agg || !grad_agg || !grad_cost || !ws || !(sigma > 0.f)) return HDP_EINVAL;
+    if (ws_bytes < hdp::aggregate_workspace_bytes(f->n, width)) return HDP_EWORKSPACE;
+    (void)hipGetLastError();
+    hdp::launch_aggregate_backward(*f, width, phase_ptr_host, n_phases, cost, agg, up, grad_agg,
+                                   sigma, grad_cost, grad_w, grad_sigma, ws, (hipStream_t)stream);
+    return last_hip();
+}
+
+hdp_status hdp_wta(const hdp_forest *f, const hdp_shape *shapes, int32_t n_pairs, int32_t width,
+                   const float *agg, int32_t *disp, void *stream) {
+    if (!agg || !disp) return HDP_EINVAL;
+    LevelGeom g;
+    hdp_status st = make_geom(shapes, n_pairs, 0, &g);
+    if (st != HDP_OK) return st;
+    int64_t n = total_pixels(g);
+    if (f && !forest_ok(f, n)) return HDP_EINVAL;
+    if (width < 1 || width > HDP_MAX_LABELS) return HDP_EINVAL;
+    if (!f && width < max_dmax(g) + 1) return HDP_EINVAL;
+    (void)hipGetLastError();
+    hdp::launch_wta(g, f ? f->node : nullptr, f ? f->lo : nullptr, f ? f->hi : nullptr, width, agg,
+                    disp, (hipStream_t)stream);
+    return last_hip();
+}
+
+hdp_status hdp_predict_range(const int32_t *disp_upper, const hdp_shape *upper,
+                             const hdp_shape *lower, int32_t n_pairs, int32_t S, int32_t window,
+                             int32_t *pix_lo, int32_t *pix_hi, void *stream) {
+    if (!disp_upper || !pix_lo || !pix_hi) return HDP_EINVAL;
+    if (S < 2 || window < 0) return HDP_EINVAL;
+    LevelGeom gu, gl;
+    hdp_status st = make_geom(upper, n_pairs, 1, &gu);
+    if (st != HDP_OK) return st;
+    st = make_geom(lower, n_pairs, 0, &gl);
+    if (st != HDP_OK) return st;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (gu.H[i] != (gl.H[i] + S - 1) / S || gu.W[i] != (gl.W[i] + S - 1) / S ||
+            gu.dmax[i] != gl.dmax[i] / S)
+            return HDP_ESHAPE;
+    }
+    (void)hipGetLastError();
+    hdp::launch_predict_range(disp_upper, gu, gl, S, window, pix_lo, pix_hi, (hipStream_t)stream);
+    return last_hip();
+}
+
+const char *hdp_status_str(hdp_status s) {
+    switch (s) {
+    case HDP_OK: return "ok";
+    case HDP_EINVAL: return "invalid argument";
+    case HDP_ESHAPE: return "invalid shape or batch";
+    case HDP_EWORKSPACE: return "workspace too small";
+    case HDP_EREGIME: return "beta and interval width outside the exact disparity-forest regime";
+    case HDP_EHIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+// Shared device-side definitions of the HDP library (gfx950 / CDNA4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hdp.h"
+
+namespace hdp {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wavefronts of 64)
+
+// Geometry of one pyramid layer of a batch, passed to kernels by value.
+struct LevelGeom {
+    int32_t n_pairs;
+    int32_t level;                    // pyramid layer (edge keys scale by 4^level)
+    int32_t off[HDP_MAX_PAIRS + 1];   // first pixel of each pair, off[n_pairs] = n
+    int32_t H[HDP_MAX_PAIRS];
+    int32_t W[HDP_MAX_PAIRS];
+    int32_t dmax[HDP_MAX_PAIRS];
+};
+
+// Pair that holds global pixel v (binary search over the offsets).
+__device__ __forceinline__ int pair_of(const LevelGeom &g, int v) {
+    int lo = 0, hi = g.n_pairs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (g.off[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct PixelPos {
+    int pair, x, y, W, H, base;
+};
+
+__device__ __forceinline__ PixelPos pixel_pos(const LevelGeom &g, int v) {
+    PixelPos p;
+    p.pair = pair_of(g, v);
+    p.base = g.off[p.pair];
+    p.W = g.W[p.pair];
+    p.H = g.H[p.pair];
+    int local = v - p.base;
+    p.y = local / p.W;
+    p.x = local - p.y * p.W;
+    return p;
+}
+
+__device__ __forceinline__ int64_t gtid() {
+    return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+}
+
+inline unsigned grid_for(int64_t n, int per_block = kBlock) {
+    int64_t b = (n + per_block - 1) / per_block;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace hdp

@@ -1,0 +1,110 @@
+// Restricted matching cost E (Section 3.3, eq. E) and winner-takes-all.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace hdp {
+
+struct CostParams {
+    float a_c, tau_c, a_g, tau_g;
+};
+
+// M(v, label): colour term from the channel differences, gradient term from
+// the difference of the gx numerators (gray gradient = gx / 6).
+__device__ __forceinline__ float match_cost(float4 L, const float4 *__restrict__ right, int v,
+                                            int x, int label, const CostParams &c) {
+    if (x - label < 0) return c.a_c * c.tau_c + c.a_g * c.tau_g;
+    float4 R = right[v - label];
+    float col = (fabsf(L.x - R.x) + fabsf(L.y - R.y) + fabsf(L.z - R.z)) / 3.0f;
+    float gd = fabsf(L.w - R.w) / 6.0f;
+    return c.a_c * fminf(col, c.tau_c) + c.a_g * fminf(gd, c.tau_g);
+}
+
+// One thread per (row, column) entry of the volume.  node == NULL: rows are
+// pixels and the interval is [0, dmax of the pair].
+__global__ void k_cost_volume(const float4 *__restrict__ left, const float4 *__restrict__ right,
+                              LevelGeom g, const int32_t *__restrict__ node,
+                              const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
+                              int width, CostParams cp, float *__restrict__ cost, int64_t total) {
+    int64_t e = gtid();
+    if (e >= total) return;
+    int64_t r = e / width;
+    int j = (int)(e - r * width);
+    int v = node ? node[r] : (int)r;
+    PixelPos p = pixel_pos(g, v);
+    int a = node ? lo[v] : 0;
+    int b = node ? hi[v] : g.dmax[p.pair];
+    int label = a + j;
+    float out = 0.f;
+    if (label <= b) out = match_cost(left[v], right, v, p.x, label, cp);
+    cost[e] = out;
+}
+
+// Winner-takes-all, one thread per row (narrow rows).
+__global__ void k_wta_thread(LevelGeom g, const int32_t *__restrict__ node,
+                             const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
+                             int width, const float *__restrict__ agg, int32_t *__restrict__ disp,
+                             int64_t n) {
+    int64_t r = gtid();
+    if (r >= n) return;
+    int v = node ? node[r] : (int)r;
+    int a = node ? lo[v] : 0;
+    int b = node ? hi[v] : g.dmax[pair_of(g, v)];
+    const float *row = agg + r * width;
+    int nl = b - a + 1 < width ? b - a + 1 : width;
+    float best = row[0];
+    int bj = 0;
+    for (int j = 1; j < nl; ++j) {
+        float x = row[j];
+        if (x < best) { best = x; bj = j; }
+    }
+    disp[v] = a + bj;
+}
+
+// Winner-takes-all, one wavefront per row (wide rows).
+__global__ void k_wta_wave(LevelGeom g, const int32_t *__restrict__ node,
+                           const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
+                           int width, const float *__restrict__ agg, int32_t *__restrict__ disp,
+                           int64_t n) {
+    int64_t r = gtid() >> 6;
+    int lane = threadIdx.x & 63;
+    if (r >= n) return;
+    int v = node ? node[r] : (int)r;
+    int a = node ? lo[v] : 0;
+    int b = node ? hi[v] : g.dmax[pair_of(g, v)];
+    int nl = b - a + 1 < width ? b - a + 1 : width;
+    const float *row = agg + r * width;
+    float best = __builtin_inff();
+    int bj = 0x7fffffff;
+    for (int j = lane; j < nl; j += 64) {
+        float x = row[j];
+        if (x < best) { best = x; bj = j; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        float ob = __shfl_xor(best, off, 64);
+        int oj = __shfl_xor(bj, off, 64);
+        if (ob < best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+    }
+    if (lane == 0) disp[v] = a + bj;
+}
+
+void launch_cost_volume(const float *left, const float *right, const LevelGeom &g,
+                        const int32_t *node, const int32_t *lo, const int32_t *hi, int width,
+                        const hdp_cost_params &p, float *cost, hipStream_t st) {
+    int64_t n = g.off[g.n_pairs];
+    int64_t total = n * width;
+    CostParams cp{p.a_c, p.tau_c, p.a_g, p.tau_g};
+    k_cost_volume<<<grid_for(total), kBlock, 0, st>>>(
+        reinterpret_cast<const float4 *>(left), reinterpret_cast<const float4 *>(right), g, node,
+        lo, hi, width, cp, cost, total);
+}
+
+void launch_wta(const LevelGeom &g, const int32_t *node, const int32_t *lo, const int32_t *hi,
+                int width, const float *agg, int32_t *disp, hipStream_t st) {
+    int64_t n = g.off[g.n_pairs];
+    if (width >= 64)
+        k_wta_wave<<<grid_for(n * 64), kBlock, 0, st>>>(g, node, lo, hi, width, agg, disp, n);
+    else
+        k_wta_thread<<<grid_for(n), kBlock, 0, st>>>(g, node, lo, hi, width, agg, disp, n);
+}
+
+}  // namespace hdp

@@ -1,0 +1,30 @@
+// Host-side launchers of the HDP kernels (one translation unit per stage).
+#pragma once
+
+#include "common.hpp"
+
+namespace hdp {
+
+void launch_pyramid(const uint8_t *rgb, const LevelGeom *geoms, int L, int S, float *levels,
+                    hipStream_t st);
+void launch_predict_range(const int32_t *disp_up, const LevelGeom &gu, const LevelGeom &gl, int S,
+                          int window, int32_t *lo, int32_t *hi, hipStream_t st);
+void launch_cost_volume(const float *left, const float *right, const LevelGeom &g,
+                        const int32_t *node, const int32_t *lo, const int32_t *hi, int width,
+                        const hdp_cost_params &p, float *cost, hipStream_t st);
+void launch_wta(const LevelGeom &g, const int32_t *node, const int32_t *lo, const int32_t *hi,
+                int width, const float *agg, int32_t *disp, hipStream_t st);
+size_t tree_workspace_bytes(int64_t n);
+void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
+                       const int32_t *phi, int max_width, int width, const hdp_forest &f,
+                       void *ws, hipStream_t st);
+size_t aggregate_workspace_bytes(int64_t n, int width);
+void launch_aggregate(const hdp_forest &f, int width, const int32_t *phase_ptr, int n_phases,
+                      const float *cost, float sigma, float *agg, float *up, void *ws,
+                      hipStream_t st);
+void launch_aggregate_backward(const hdp_forest &f, int width, const int32_t *phase_ptr,
+                               int n_phases, const float *cost, const float *agg, const float *up,
+                               const float *grad_agg, float sigma, float *grad_cost, float *grad_w,
+                               float *grad_sigma, void *ws, hipStream_t st);
+
+}  // namespace hdp

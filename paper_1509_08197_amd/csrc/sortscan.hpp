@@ -1,0 +1,178 @@
+// Device-wide prefix scans and stable counting sorts used by the tree builder.
+// Deterministic (integer arithmetic only), no memsets, fixed launch shapes.
+#pragma once
+
+#include "common.hpp"
+
+namespace hdp {
+
+constexpr int kScanPerThread = 4;
+constexpr int kScanTile = kBlock * kScanPerThread;  // 1024 elements per workgroup
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Inclusive scan of one value per lane across a 64-wide wavefront.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+    int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread across the 256-thread workgroup.
+// Returns the exclusive prefix; *total receives the workgroup sum.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T *total) {
+    __shared__ T wsum[kBlock / 64];
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    T inc = wave_incl_scan(x);
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    T base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        T s = wsum[w];
+        if (w < wv) base += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - x;
+}
+
+template <typename T>
+__global__ void k_scan_reduce(const T *__restrict__ in, int64_t n, T *__restrict__ partial) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i)
+        if (base + i < n) s += in[base + i];
+    T tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the per-tile partial sums, by one workgroup.
+template <typename T>
+__global__ void k_scan_partials(T *__restrict__ partial, int64_t nb, T *__restrict__ grand) {
+    T carry = 0;
+    for (int64_t c = 0; c < nb; c += kBlock) {
+        int64_t i = c + threadIdx.x;
+        T x = i < nb ? partial[i] : (T)0;
+        T tot;
+        T ex = block_excl_scan(x, &tot);
+        if (i < nb) partial[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && grand) *grand = carry;
+}
+
+template <typename T>
+__global__ void k_scan_apply(const T *__restrict__ in, T *__restrict__ out, int64_t n,
+                             const T *__restrict__ partial, int inclusive) {
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
+    T v[kScanPerThread];
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) {
+        v[i] = base + i < n ? in[base + i] : (T)0;
+        s += v[i];
+    }
+    T tot;
+    T ex = block_excl_scan(s, &tot) + partial[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) {
+        T nx = ex + v[i];
+        if (base + i < n) out[base + i] = inclusive ? nx : ex;
+        ex = nx;
+    }
+}
+
+inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+// out[i] = sum of in[0..i-1] (exclusive) or in[0..i] (inclusive); in == out allowed.
+// partial: scratch of scan_tiles(n) elements; grand (device, may be NULL) = total.
+template <typename T>
+inline void device_scan(const T *in, T *out, int64_t n, T *partial, T *grand, bool inclusive,
+                        hipStream_t st) {
+    int64_t nb = scan_tiles(n);
+    if (nb < 1) nb = 1;
+    k_scan_reduce<T><<<(unsigned)nb, kBlock, 0, st>>>(in, n, partial);
+    k_scan_partials<T><<<1, kBlock, 0, st>>>(partial, nb, grand);
+    k_scan_apply<T><<<(unsigned)nb, kBlock, 0, st>>>(in, out, n, partial, inclusive ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Stable counting sort of the sequence src[0..n) by a small key (< NB <= 256).
+// key_of(i, x) gives the key of element x = src[i].  Histogram per tile of
+// 1024 elements (bin-major so that one exclusive scan gives every tile's base),
+// then a stable scatter that ranks equal keys with wavefront ballots.
+
+template <int NB, typename KeyFn>
+__global__ void k_count_hist(const int32_t *__restrict__ src, int64_t n, KeyFn key_of,
+                             int32_t *__restrict__ hist, int64_t ntiles) {
+    __shared__ int32_t h[NB];
+    for (int k = threadIdx.x; k < NB; k += kBlock) h[k] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int i = threadIdx.x; i < kScanTile; i += kBlock) {
+        int64_t e = base + i;
+        if (e < n) atomicAdd(&h[key_of(e, src[e])], 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < NB; k += kBlock) hist[(int64_t)k * ntiles + blockIdx.x] = h[k];
+}
+
+template <int NB, int NBITS, typename KeyFn>
+__global__ void k_count_scatter(const int32_t *__restrict__ src, int64_t n, KeyFn key_of,
+                                const int32_t *__restrict__ offs, int64_t ntiles,
+                                int32_t *__restrict__ dst, int32_t *__restrict__ pos_of) {
+    __shared__ int32_t run[NB];
+    __shared__ int32_t wcnt[kBlock / 64][NB];
+    int wv = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < NB; k += kBlock) {
+        run[k] = offs[(int64_t)k * ntiles + blockIdx.x];
+        for (int w = 0; w < kBlock / 64; ++w) wcnt[w][k] = 0;
+    }
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    for (int step = 0; step < kScanPerThread; ++step) {
+        int64_t e = base + step * kBlock + threadIdx.x;
+        bool valid = e < n;
+        int32_t x = valid ? src[e] : 0;
+        int key = valid ? key_of(e, x) : 0;
+        uint64_t m = __ballot(valid);
+        if (!valid) m = ~m;
+#pragma unroll
+        for (int b = 0; b < NBITS; ++b) {
+            bool bit = (key >> b) & 1;
+            uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        int rnk = __popcll(m & lanemask_lt());
+        if (valid && rnk == 0) wcnt[wv][key] = __popcll(m);
+        __syncthreads();
+        if (valid) {
+            int p = run[key] + rnk;
+            for (int w = 0; w < wv; ++w) p += wcnt[w][key];
+            dst[p] = x;
+            if (pos_of) pos_of[x] = p;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < NB; k += kBlock) {
+            int add = 0;
+            for (int w = 0; w < kBlock / 64; ++w) { add += wcnt[w][k]; wcnt[w][k] = 0; }
+            run[k] += add;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace hdp

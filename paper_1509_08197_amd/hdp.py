@@ -1,0 +1,388 @@
+"""Thin Python binding of ``libhdp.so`` (argument marshalling only).
+
+Every step runs in the HIP kernels behind the C ABI declared in
+``include/hdp.h``; torch is used for device memory and streams.  There is no
+CPU fallback: if the library is missing or no HIP device is present the calls
+raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdp.so")
+
+MAX_PAIRS = 64
+MAX_LABELS = 256
+MAX_PHASES = 40
+INFO_WORDS = 16
+INFO = dict(n_levels=0, n_phases=1, n_trees=2, width=3, mst_rounds=4, rank_rounds=5,
+            bad_interval=6, error=7)
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "invalid shape or batch",
+          -3: "workspace too small", -4: "outside the exact disparity-forest regime",
+          -5: "HIP runtime error"}
+
+
+class HdpError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed: {STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+class Shape(C.Structure):
+    _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("dmax", C.c_int32)]
+
+
+class CostParams(C.Structure):
+    _fields_ = [("a_c", C.c_float), ("tau_c", C.c_float), ("a_g", C.c_float),
+                ("tau_g", C.c_float)]
+
+
+class ForestStruct(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in (
+        "parent", "depth", "tree", "lo", "hi", "row", "wgt", "order", "level_ptr", "node",
+        "prow", "lc", "heavy", "rw", "phase_ptr", "info")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhdp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_1509_08197_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _declare(L):
+    P, I32, I64, F, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
+    L.hdp_forest_bytes.argtypes = [I64]; L.hdp_forest_bytes.restype = SZ
+    L.hdp_forest_bind.argtypes = [P, SZ, I64, C.POINTER(ForestStruct)]
+    L.hdp_level_shapes.argtypes = [P, I32, I32, I32, P]
+    L.hdp_pyramid.argtypes = [P, P, I32, I32, I32, P, P]
+    L.hdp_build_tree_workspace_bytes.argtypes = [I64]; L.hdp_build_tree_workspace_bytes.restype = SZ
+    L.hdp_build_tree.argtypes = [P, P, I32, I32, P, P, I32, I32, I32, I32,
+                                 C.POINTER(ForestStruct), P, SZ, P]
+    L.hdp_forest_read_info.argtypes = [C.POINTER(ForestStruct), P, P, P]
+    L.hdp_cost_volume.argtypes = [P, P, P, I32, C.POINTER(ForestStruct), I32,
+                                  C.POINTER(CostParams), P, P]
+    L.hdp_aggregate_workspace_bytes.argtypes = [I64, I32]
+    L.hdp_aggregate_workspace_bytes.restype = SZ
+    L.hdp_aggregate.argtypes = [C.POINTER(ForestStruct), I32, P, I32, P, F, P, P, P, SZ, P]
+    L.hdp_aggregate_backward.argtypes = [C.POINTER(ForestStruct), I32, P, I32, P, P, P, P, F,
+                                         P, P, P, P, SZ, P]
+    L.hdp_wta.argtypes = [C.POINTER(ForestStruct), P, I32, I32, P, P, P]
+    L.hdp_predict_range.argtypes = [P, P, P, I32, I32, I32, P, P, P]
+    L.hdp_status_str.argtypes = [I32]; L.hdp_status_str.restype = C.c_char_p
+    for name in ("hdp_forest_bind", "hdp_level_shapes", "hdp_pyramid", "hdp_build_tree",
+                 "hdp_forest_read_info", "hdp_cost_volume", "hdp_aggregate",
+                 "hdp_aggregate_backward", "hdp_wta", "hdp_predict_range"):
+        getattr(L, name).restype = I32
+
+
+def _check(fn, code):
+    if code != 0:
+        raise HdpError(fn, code)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _shapes(shapes: Sequence[Tuple[int, int, int]]):
+    arr = (Shape * len(shapes))()
+    for i, (H, W, d) in enumerate(shapes):
+        arr[i].H, arr[i].W, arr[i].dmax = int(H), int(W), int(d)
+    return arr
+
+
+def n_pixels(shapes) -> int:
+    return int(sum(int(H) * int(W) for H, W, _ in shapes))
+
+
+def level_shapes(shapes, S: int, L: int) -> List[List[Tuple[int, int, int]]]:
+    """Per level l = 0..L, the list of (H, W, dmax) of every pair (Section 2.1)."""
+    n = len(shapes)
+    out = (Shape * (n * (L + 1)))()
+    _check("hdp_level_shapes", lib().hdp_level_shapes(_shapes(shapes), n, S, L, out))
+    return [[(out[l * n + i].H, out[l * n + i].W, out[l * n + i].dmax) for i in range(n)]
+            for l in range(L + 1)]
+
+
+def _empty(nbytes, device):
+    # 256-byte aligned device buffer (torch's allocator aligns to 512 B)
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# --- pyramid ---------------------------------------------------------------------
+
+def pyramid(rgb: torch.Tensor, shapes, S: int = 2, L: int = 3) -> List[torch.Tensor]:
+    """rgb: uint8 [n0, 3] on the GPU (pairs concatenated).  Returns per level a
+    float32 [n_l, 4] view (R, G, B, gx)."""
+    assert rgb.is_cuda and rgb.dtype == torch.uint8 and rgb.is_contiguous()
+    lv = level_shapes(shapes, S, L)
+    ns = [n_pixels(s) for s in lv]
+    out = torch.empty((sum(ns), 4), dtype=torch.float32, device=rgb.device)
+    _check("hdp_pyramid", lib().hdp_pyramid(_ptr(rgb), _shapes(shapes), len(shapes), S, L,
+                                            _ptr(out), _stream()))
+    views, off = [], 0
+    for n in ns:
+        views.append(out[off:off + n]); off += n
+    return views
+
+
+# --- forest ----------------------------------------------------------------------
+
+@dataclass
+class Forest:
+    buf: torch.Tensor
+    st: ForestStruct
+    n: int
+    width: int
+    shapes: list
+    level: int
+    info: Optional[List[int]] = None
+    phase_ptr: Optional[List[int]] = None
+
+    def _view(self, name, count, dtype):
+        base = self.buf.data_ptr()
+        off = getattr(self.st, name) - base
+        esz = torch.tensor([], dtype=dtype).element_size()
+        return self.buf[off:off + count * esz].view(dtype)
+
+    def array(self, name):
+        n = self.n
+        if name in ("parent", "depth", "tree", "lo", "hi", "row", "order", "node", "prow"):
+            return self._view(name, n, torch.int32)
+        if name in ("wgt", "rw"):
+            return self._view(name, n, torch.float32)
+        if name == "heavy":
+            return self._view(name, n, torch.uint8)
+        if name == "lc":
+            return self._view(name, 3 * n, torch.int32).view(3, n)
+        if name == "level_ptr":
+            return self._view(name, n + 1, torch.int32)
+        if name == "phase_ptr":
+            return self._view(name, MAX_PHASES + 1, torch.int32)
+        if name == "info":
+            return self._view(name, INFO_WORDS, torch.int32)
+        raise KeyError(name)
+
+    def read_info(self):
+        """Host copy of the scalars and the phase table (synchronises)."""
+        info = (C.c_int32 * INFO_WORDS)()
+        pp = (C.c_int32 * (MAX_PHASES + 1))()
+        _check("hdp_forest_read_info",
+               lib().hdp_forest_read_info(C.byref(self.st), info, pp, _stream()))
+        self.info = list(info)
+        npz = self.info[INFO["n_phases"]]
+        self.phase_ptr = list(pp)[:npz + 1]
+        return self.info
+
+
+def alloc_forest(n: int, device) -> Tuple[torch.Tensor, ForestStruct]:
+    nbytes = lib().hdp_forest_bytes(n)
+    buf = _empty(nbytes, device)
+    st = ForestStruct()
+    _check("hdp_forest_bind", lib().hdp_forest_bind(_ptr(buf), nbytes, n, C.byref(st)))
+    return buf, st
+
+
+class Workspace:
+    """Grow-only scratch buffer reused across calls (no allocation when large enough)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes, device):
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != torch.device(device):
+            self.buf = _empty(nbytes, device)
+        return self.buf
+
+
+_ws_tree = Workspace()
+_ws_agg = Workspace()
+
+
+def build_tree(img: torch.Tensor, shapes, level: int, pix_lo=None, pix_hi=None,
+               max_width: int = 0, beta=(19, 20), width: Optional[int] = None,
+               read_info: bool = True, forest: Optional[Forest] = None, ws=None) -> Forest:
+    """Minimum spanning tree (pix_lo None) or disparity forest of one layer."""
+    n = n_pixels(shapes)
+    assert img.shape == (n, 4) and img.dtype == torch.float32 and img.is_contiguous()
+    if width is None:
+        width = max_width if pix_lo is not None else max(d for _, _, d in shapes) + 1
+    dev = img.device
+    if forest is None:
+        buf, st = alloc_forest(n, dev)
+        forest = Forest(buf=buf, st=st, n=n, width=width, shapes=list(shapes), level=level)
+    else:
+        forest.width = width
+        forest.shapes = list(shapes)
+        forest.level = level
+    wsb = lib().hdp_build_tree_workspace_bytes(n)
+    w = (ws or _ws_tree).get(wsb, dev)
+    _check("hdp_build_tree", lib().hdp_build_tree(
+        _ptr(img), _shapes(shapes), len(shapes), level, _ptr(pix_lo), _ptr(pix_hi), int(max_width),
+        int(beta[0]), int(beta[1]), int(width), C.byref(forest.st), _ptr(w), wsb, _stream()))
+    if read_info:
+        forest.read_info()
+    return forest
+
+
+# --- cost, aggregation, WTA ---------------------------------------------------------
+
+def cost_params(a_c=0.89, tau_c=7.0, a_g=0.11, tau_g=2.0) -> CostParams:
+    return CostParams(a_c, tau_c, a_g, tau_g)
+
+
+def cost_volume(left: torch.Tensor, right: torch.Tensor, shapes, forest: Optional[Forest] = None,
+                width: Optional[int] = None, params: Optional[CostParams] = None,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    n = n_pixels(shapes)
+    if width is None:
+        width = forest.width if forest is not None else max(d for _, _, d in shapes) + 1
+    if out is None:
+        out = torch.empty((n, width), dtype=torch.float32, device=left.device)
+    p = params or cost_params()
+    _check("hdp_cost_volume", lib().hdp_cost_volume(
+        _ptr(left), _ptr(right), _shapes(shapes), len(shapes),
+        C.byref(forest.st) if forest is not None else None, int(width), C.byref(p), _ptr(out),
+        _stream()))
+    return out
+
+
+def _phase_args(forest: Forest):
+    if forest.phase_ptr is None:
+        forest.read_info()
+    pp = (C.c_int32 * len(forest.phase_ptr))(*forest.phase_ptr)
+    return pp, len(forest.phase_ptr) - 1
+
+
+def aggregate(forest: Forest, cost: torch.Tensor, sigma: float = 0.1, keep_up: bool = False,
+              out: Optional[torch.Tensor] = None, up: Optional[torch.Tensor] = None, ws=None):
+    """agg(v,x) = sum_u exp(-W(v,u)/sigma) cost(u,x) over the forest (eq. C).
+    Returns agg, or (agg, U) with keep_up."""
+    n, width = forest.n, forest.width
+    assert cost.shape == (n, width) and cost.dtype == torch.float32 and cost.is_contiguous()
+    if out is None:
+        out = torch.empty_like(cost)
+    if keep_up and up is None:
+        up = torch.empty_like(cost)
+    pp, npz = _phase_args(forest)
+    wsb = lib().hdp_aggregate_workspace_bytes(n, width)
+    w = (ws or _ws_agg).get(wsb, cost.device)
+    _check("hdp_aggregate", lib().hdp_aggregate(
+        C.byref(forest.st), width, pp, npz, _ptr(cost), float(sigma), _ptr(out), _ptr(up),
+        _ptr(w), wsb, _stream()))
+    return (out, up) if keep_up else out
+
+
+def aggregate_backward(forest: Forest, cost, agg, grad_agg, sigma=0.1, up=None,
+                       want_w=True, want_sigma=True, ws=None):
+    """Returns (grad_cost, grad_w per pixel or None, grad_sigma tensor or None)."""
+    n, width = forest.n, forest.width
+    gc = torch.empty_like(cost)
+    gw = torch.zeros(n, dtype=torch.float32, device=cost.device) if want_w else None
+    gs = torch.zeros(1, dtype=torch.float32, device=cost.device) if want_sigma else None
+    pp, npz = _phase_args(forest)
+    wsb = lib().hdp_aggregate_workspace_bytes(n, width)
+    w = (ws or _ws_agg).get(wsb, cost.device)
+    _check("hdp_aggregate_backward", lib().hdp_aggregate_backward(
+        C.byref(forest.st), width, pp, npz, _ptr(cost), _ptr(agg), _ptr(up),
+        _ptr(grad_agg.contiguous()), float(sigma), _ptr(gc), _ptr(gw), _ptr(gs), _ptr(w), wsb,
+        _stream()))
+    return gc, gw, gs
+
+
+def wta(agg: torch.Tensor, shapes, forest: Optional[Forest] = None,
+        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    n = n_pixels(shapes)
+    width = agg.shape[1]
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=agg.device)
+    _check("hdp_wta", lib().hdp_wta(C.byref(forest.st) if forest is not None else None,
+                                    _shapes(shapes), len(shapes), int(width), _ptr(agg), _ptr(out),
+                                    _stream()))
+    return out
+
+
+def predict_range(disp_upper: torch.Tensor, upper_shapes, lower_shapes, S: int = 2,
+                  window: int = 4, out=None):
+    n = n_pixels(lower_shapes)
+    if out is None:
+        lo = torch.empty(n, dtype=torch.int32, device=disp_upper.device)
+        hi = torch.empty(n, dtype=torch.int32, device=disp_upper.device)
+    else:
+        lo, hi = out
+    _check("hdp_predict_range", lib().hdp_predict_range(
+        _ptr(disp_upper), _shapes(upper_shapes), _shapes(lower_shapes), len(lower_shapes), S,
+        window, _ptr(lo), _ptr(hi), _stream()))
+    return lo, hi
+
+
+# --- the method ----------------------------------------------------------------------
+
+@dataclass
+class LevelResult:
+    level: int
+    shapes: list
+    forest: Forest
+    disp: torch.Tensor
+    pix_lo: Optional[torch.Tensor] = None
+    pix_hi: Optional[torch.Tensor] = None
+    cost: Optional[torch.Tensor] = None
+    agg: Optional[torch.Tensor] = None
+
+
+def stereo_level(left_img, right_img, shapes, level, pix_lo=None, pix_hi=None, max_width=0,
+                 beta=(19, 20), sigma=0.1, params=None, keep=False) -> LevelResult:
+    """One layer (Section 3): forest, restricted cost, aggregation, WTA."""
+    f = build_tree(left_img, shapes, level, pix_lo, pix_hi, max_width=max_width, beta=beta)
+    cost = cost_volume(left_img, right_img, shapes, f, params=params)
+    agg = aggregate(f, cost, sigma)
+    disp = wta(agg, shapes, f)
+    return LevelResult(level=level, shapes=list(shapes), forest=f, disp=disp, pix_lo=pix_lo,
+                       pix_hi=pix_hi, cost=cost if keep else None, agg=agg if keep else None)
+
+
+def hdp_stereo(left_rgb: torch.Tensor, right_rgb: torch.Tensor, shapes, S=2, L=3, window=4,
+               beta=(19, 20), sigma=0.1, params=None, keep=False) -> List[LevelResult]:
+    """Top-down HDP (Section 3): layer L over [0, d_L] with the MST, then for
+    l = L-1..0 interval prediction -> disparity forest -> cost -> aggregation
+    -> WTA.  left_rgb/right_rgb: uint8 [n0, 3].  Returns results indexed by layer."""
+    lv = level_shapes(shapes, S, L)
+    lp = pyramid(left_rgb, shapes, S, L)
+    rp = pyramid(right_rgb, shapes, S, L)
+    res: List[Optional[LevelResult]] = [None] * (L + 1)
+    res[L] = stereo_level(lp[L], rp[L], lv[L], L, sigma=sigma, params=params, keep=keep)
+    for l in range(L - 1, -1, -1):
+        lo, hi = predict_range(res[l + 1].disp, lv[l + 1], lv[l], S, window)
+        mw = min(S + 2 * window, max(d for _, _, d in lv[l]) + 1)
+        res[l] = stereo_level(lp[l], rp[l], lv[l], l, lo, hi, max_width=mw, beta=beta,
+                              sigma=sigma, params=params, keep=keep)
+    return res
+
+
+def full_range(left_rgb, right_rgb, shapes, sigma=0.1, params=None, keep=False) -> LevelResult:
+    """Full-range MST aggregation + WTA at the input resolution (the baseline
+    the method speeds up)."""
+    lp = pyramid(left_rgb, shapes, 2, 0)
+    rp = pyramid(right_rgb, shapes, 2, 0)
+    return stereo_level(lp[0], rp[0], shapes, 0, sigma=sigma, params=params, keep=keep)

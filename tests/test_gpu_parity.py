@@ -1,0 +1,319 @@
+"""GPU parity: every stage of the HIP path against the FP64 oracle on the same
+seeded inputs.  Trees, level order and ranges must match bit for bit; costs and
+aggregated costs within 1e-5 relative of FP64; WTA labels identical except at
+pixels whose two best oracle costs are within that tolerance (near-ties, counted).
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1509_08197_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1509_08197_amd import hdp
+    hdp.lib()
+    return hdp
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def rgb_dev(*imgs):
+    return dev(np.concatenate([im.reshape(-1, 3) for im in imgs]))
+
+
+def assert_rel(got, ref, rel=REL, what=""):
+    got = np.asarray(got, np.float64); ref = np.asarray(ref, np.float64)
+    bad = np.abs(got - ref) > rel * np.abs(ref)
+    if bad.any():
+        i = np.flatnonzero(bad.ravel())[:5]
+        raise AssertionError(f"{what}: {bad.sum()} of {bad.size} outside {rel} rel; "
+                             f"got {got.ravel()[i]} ref {ref.ravel()[i]}")
+
+
+def forest_np(f):
+    keys = ("parent", "depth", "tree", "lo", "hi", "row", "wgt", "order", "node", "prow",
+            "heavy", "lc", "rw", "level_ptr")
+    torch.cuda.synchronize()
+    out = {k: f.array(k).cpu().numpy() for k in keys}
+    out["info"] = f.read_info()
+    return out
+
+
+def volume_to_pixels(vol, F, D):
+    """[n][width] rows of the forest layout -> [n][D] by pixel and label (NaN elsewhere)."""
+    n, width = vol.shape
+    out = np.full((n, D), np.nan)
+    node = F["node"]
+    for j in range(width):
+        lab = F["lo"][node] + j
+        ok = lab <= F["hi"][node]
+        out[node[ok], lab[ok]] = vol[ok, j]
+    return out
+
+
+def check_forest(F, ref, n, what):
+    info = F["info"]
+    assert info[7] == 0, f"{what}: consistency guard tripped ({info[7]})"
+    np.testing.assert_array_equal(F["parent"], ref["parent"], err_msg=f"{what} parent")
+    np.testing.assert_array_equal(F["depth"], ref["depth"], err_msg=f"{what} depth")
+    np.testing.assert_array_equal(F["tree"], ref["tree"], err_msg=f"{what} tree")
+    np.testing.assert_array_equal(F["order"], ref["order"], err_msg=f"{what} order")
+    nl = ref["n_levels"]
+    assert info[0] == nl
+    np.testing.assert_array_equal(F["level_ptr"][:nl + 1], ref["level_ptr"])
+    assert_rel(F["wgt"], ref["wgt"], 1e-6, f"{what} wgt")
+    # schedule invariants: rows are a permutation, chains contiguous, phases ordered
+    node, row = F["node"], F["row"]
+    assert np.array_equal(np.sort(node), np.arange(n))
+    assert np.array_equal(row[node], np.arange(n))
+    par_row = np.where(F["parent"][node] >= 0, row[np.maximum(F["parent"][node], 0)], -1)
+    np.testing.assert_array_equal(F["prow"], par_row)
+    hv = F["heavy"].astype(bool)
+    assert np.all(F["prow"][hv] == np.flatnonzero(hv) - 1)
+
+
+def run_level_oracle(orc, Lf, Rf, dmax, level, lo=None, hi=None, sigma=0.1, sample=None):
+    """Oracle forest + full restricted volume + aggregated volume at one layer."""
+    Hh, Ww = Lf.shape[:2]
+    key = orc.edge_keys(Lf, level)
+    in_tree, tlo, thi, _ = orc.kruskal(Hh, Ww, key, lo, hi)
+    ref = orc.root_forest(Hh, Ww, in_tree, key, level)
+    if lo is None:
+        tlo = np.zeros(Hh * Ww, np.int32); thi = np.full(Hh * Ww, dmax, np.int32)
+    cost = orc.cost_volume(Lf, Rf, dmax, tlo, thi)
+    agg = orc.aggregate_twopass(ref["parent"], ref["wgt"], ref["order"], sigma,
+                                np.nan_to_num(cost, nan=0.0))
+    agg[np.isnan(cost)] = np.nan
+    return dict(ref=ref, in_tree=in_tree, tlo=tlo, thi=thi, cost=cost, agg=agg, key=key)
+
+
+def check_wta(disp, agg_ref, tlo, thi, what):
+    import oracle.oracle as O
+    d_ref, c1, c2 = O.wta(np.nan_to_num(agg_ref, nan=np.inf), tlo, thi)
+    mism = disp != d_ref
+    near = (c2 - c1) <= REL * np.abs(c1)
+    assert np.all(near[mism]), f"{what}: {int((mism & ~near).sum())} WTA mismatches off near-ties"
+    return int(mism.sum()), int(near.sum())
+
+
+# --- pyramid -----------------------------------------------------------------------
+
+@pytest.mark.parametrize("Hh,Ww", [(120, 160), (37, 53), (1, 9), (9, 1), (1, 1)])
+def test_pyramid_exact(H, orc, Hh, Ww):
+    img = np.random.default_rng(Hh * 1000 + Ww).integers(0, 256, (Hh, Ww, 3)).astype(np.uint8)
+    L = 3
+    lv = H.pyramid(rgb_dev(img), [(Hh, Ww, 15)], 2, L)
+    ref = orc.pyramid(img, 2, L)
+    for l in range(L + 1):
+        got = lv[l].cpu().numpy()[:, :3].reshape(ref[l].shape)
+        np.testing.assert_array_equal(got, ref[l].astype(np.float32))
+
+
+# --- trees -------------------------------------------------------------------------
+
+@pytest.mark.parametrize("Hh,Ww,seed", [(120, 160, 1), (31, 47, 2), (1, 64, 3), (64, 1, 4),
+                                        (1, 1, 5), (2, 2, 6), (200, 300, 7)])
+def test_mst_bit_exact(H, orc, Hh, Ww, seed):
+    pair = scenes.small_scene(seed, Hh, Ww, 15)
+    lv = H.pyramid(rgb_dev(pair.left), [(Hh, Ww, 15)], 2, 0)
+    f = H.build_tree(lv[0], [(Hh, Ww, 15)], 0)
+    F = forest_np(f)
+    key = orc.edge_keys(pair.left.astype(np.float64), 0)
+    in_tree, _, _, _ = orc.kruskal(Hh, Ww, key)
+    ref = orc.root_forest(Hh, Ww, in_tree, key, 0)
+    check_forest(F, ref, Hh * Ww, f"MST {Hh}x{Ww}")
+    assert F["info"][2] == 1  # one tree
+
+
+@pytest.mark.parametrize("level", [1, 2, 3])
+def test_mst_upper_levels_bit_exact(H, orc, level):
+    pair = scenes.small_scene(11, 97, 131, 31)
+    lv = H.pyramid(rgb_dev(pair.left), [(97, 131, 31)], 2, 3)
+    shp = H.level_shapes([(97, 131, 31)], 2, 3)[level]
+    f = H.build_tree(lv[level], shp, level)
+    F = forest_np(f)
+    ref_img = orc.pyramid(pair.left, 2, 3)[level]
+    key = orc.edge_keys(ref_img, level)
+    in_tree, _, _, _ = orc.kruskal(shp[0][0], shp[0][1], key)
+    ref = orc.root_forest(shp[0][0], shp[0][1], in_tree, key, level)
+    check_forest(F, ref, shp[0][0] * shp[0][1], f"MST level {level}")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_hdpf_bit_exact(H, orc, seed):
+    Hh, Ww, dmax, S, w = 96, 128, 63, 2, 4
+    pair = scenes.small_scene(20 + seed, Hh, Ww, dmax)
+    up = np.random.default_rng(seed).integers(0, dmax // 2 + 1, ((Hh + 1) // 2, (Ww + 1) // 2))
+    # blocky parent labels so that equal-interval regions are large
+    up = np.kron(up[::4, ::4], np.ones((4, 4), int))[:up.shape[0], :up.shape[1]]
+    lo, hi = orc.predict_range(up, Hh, Ww, S, w, dmax)
+    lv = H.pyramid(rgb_dev(pair.left), [(Hh, Ww, dmax)], 2, 0)
+    f = H.build_tree(lv[0], [(Hh, Ww, dmax)], 0, dev(lo.ravel(), torch.int32),
+                     dev(hi.ravel(), torch.int32), max_width=S + 2 * w, beta=(19, 20))
+    F = forest_np(f)
+    key = orc.edge_keys(pair.left.astype(np.float64), 0)
+    in_tree, tlo, thi, _ = orc.kruskal(Hh, Ww, key, lo, hi, beta=(19, 20))
+    ref = orc.root_forest(Hh, Ww, in_tree, key, 0)
+    check_forest(F, ref, Hh * Ww, "HDPF")
+    np.testing.assert_array_equal(F["lo"], tlo)
+    np.testing.assert_array_equal(F["hi"], thi)
+    assert F["info"][6] == 0
+
+
+def test_regime_rejected(H):
+    lv = H.pyramid(rgb_dev(np.zeros((8, 8, 3), np.uint8)), [(8, 8, 63)], 2, 0)
+    lo = dev(np.zeros(64, np.int32)); hi = dev(np.full(64, 9, np.int32))
+    with pytest.raises(H.HdpError) as e:
+        H.build_tree(lv[0], [(8, 8, 63)], 0, lo, hi, max_width=10, beta=(3, 5))
+    assert e.value.code == -4
+
+
+# --- cost, aggregation, WTA ------------------------------------------------------------
+
+@pytest.mark.parametrize("Hh,Ww,dmax,seed", [(120, 160, 15, 1001), (45, 70, 31, 7),
+                                             (33, 257, 255, 8), (17, 5, 0, 9)])
+def test_full_range_layer(H, orc, Hh, Ww, dmax, seed):
+    pair = scenes.small_scene(seed, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lp = H.pyramid(rgb_dev(pair.left), shapes, 2, 0)
+    rp = H.pyramid(rgb_dev(pair.right), shapes, 2, 0)
+    f = H.build_tree(lp[0], shapes, 0)
+    cost = H.cost_volume(lp[0], rp[0], shapes, f)
+    agg = H.aggregate(f, cost, 0.1)
+    disp = H.wta(agg, shapes, f)
+    F = forest_np(f)
+    o = run_level_oracle(orc, pair.left.astype(np.float64), pair.right.astype(np.float64),
+                         dmax, 0)
+    check_forest(F, o["ref"], Hh * Ww, "full-range tree")
+    D = dmax + 1
+    assert_rel(volume_to_pixels(cost.cpu().numpy(), F, D), o["cost"], REL, "cost")
+    assert_rel(volume_to_pixels(agg.cpu().numpy(), F, D), o["agg"], REL, "aggregate")
+    nm, nt = check_wta(disp.cpu().numpy(), o["agg"], o["tlo"], o["thi"], "WTA")
+    print(f"WTA mismatches {nm} (near-ties {nt})")
+
+
+def test_dense_cost_and_wta(H, orc):
+    Hh, Ww, dmax = 40, 60, 23
+    pair = scenes.small_scene(31, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lp = H.pyramid(rgb_dev(pair.left), shapes, 2, 0)
+    rp = H.pyramid(rgb_dev(pair.right), shapes, 2, 0)
+    cost = H.cost_volume(lp[0], rp[0], shapes).cpu().numpy()
+    ref = orc.cost_volume(pair.left.astype(np.float64), pair.right.astype(np.float64), dmax)
+    assert_rel(cost, ref, REL, "dense cost")
+    disp = H.wta(dev(cost), shapes).cpu().numpy()
+    d_ref, c1, c2 = orc.wta(cost.astype(np.float64))
+    np.testing.assert_array_equal(disp, d_ref)
+
+
+@pytest.mark.parametrize("level,seed", [(0, 1), (1, 2), (2, 3)])
+def test_hdp_layer_stagewise(H, orc, level, seed):
+    """Layer l of HDP with the ORACLE's layer-(l+1) disparities as input."""
+    Hh, Ww, dmax, S, w, L = 96, 128, 63, 2, 4, 3
+    pair = scenes.small_scene(40 + seed, Hh, Ww, dmax)
+    ores = orc.hdp_stereo(pair.left, pair.right, dmax, S=S, L=L, window=w, want_forest=True)
+    lvs = H.level_shapes([(Hh, Ww, dmax)], S, L)
+    lp = H.pyramid(rgb_dev(pair.left), [(Hh, Ww, dmax)], S, L)
+    rp = H.pyramid(rgb_dev(pair.right), [(Hh, Ww, dmax)], S, L)
+    up = dev(ores[level + 1]["disp"].ravel(), torch.int32)
+    lo, hi = H.predict_range(up, lvs[level + 1], lvs[level], S, w)
+    np.testing.assert_array_equal(lo.cpu().numpy(), ores[level]["pix_lo"].ravel())
+    np.testing.assert_array_equal(hi.cpu().numpy(), ores[level]["pix_hi"].ravel())
+    dl = lvs[level][0][2]
+    r = H.stereo_level(lp[level], rp[level], lvs[level], level, lo, hi,
+                       max_width=min(S + 2 * w, dl + 1), keep=True)
+    F = forest_np(r.forest)
+    assert F["info"][7] == 0
+    np.testing.assert_array_equal(F["parent"], ores[level]["parent"])
+    np.testing.assert_array_equal(F["order"], ores[level]["order"])
+    np.testing.assert_array_equal(F["lo"], ores[level]["tree_lo"])
+    np.testing.assert_array_equal(F["hi"], ores[level]["tree_hi"])
+    Lf = orc.pyramid(pair.left, S, L)[level]; Rf = orc.pyramid(pair.right, S, L)[level]
+    o = run_level_oracle(orc, Lf, Rf, dl, level, ores[level]["pix_lo"], ores[level]["pix_hi"])
+    assert_rel(volume_to_pixels(r.agg.cpu().numpy(), F, dl + 1), o["agg"], REL, "HDP aggregate")
+    nm, nt = check_wta(r.disp.cpu().numpy(), o["agg"], o["tlo"], o["thi"], "HDP WTA")
+    print(f"level {level}: WTA mismatches {nm} (near-ties {nt})")
+
+
+def test_hdp_end_to_end_small(H, orc):
+    """Whole loop on the GPU vs the whole loop in the oracle (config-1 sized)."""
+    pair = scenes.workload(1)
+    Hh, Ww = pair.shape
+    res = H.hdp_stereo(rgb_dev(pair.left), rgb_dev(pair.right), [(Hh, Ww, 15)], S=2, L=2,
+                       window=2)
+    ores = orc.hdp_stereo(pair.left, pair.right, 15, S=2, L=2, window=2)
+    for l in (2, 1, 0):
+        g = res[l].disp.cpu().numpy(); o = ores[l]["disp"].ravel()
+        gap = (ores[l]["c2"] - ores[l]["c1"]) / ores[l]["c1"]
+        mism = g != o
+        # a mismatch must come from a near-tie here or from a different interval upstream
+        if l < 2:
+            same_int = ((res[l].pix_lo.cpu().numpy() == ores[l]["pix_lo"].ravel()) &
+                        (res[l].pix_hi.cpu().numpy() == ores[l]["pix_hi"].ravel()))
+        else:
+            same_int = np.ones_like(mism)
+        assert np.all(gap[mism & same_int] <= REL), f"layer {l}: unexplained mismatches"
+        print(f"layer {l}: {int(mism.sum())} label mismatches, {int((gap <= REL).sum())} near-ties")
+
+
+def test_batched_matches_single(H):
+    """Two uneven pairs in one call give the per-pair results of single calls."""
+    shapes = [(50, 70, 31), (33, 41, 15)]
+    pairs = [scenes.small_scene(60 + i, h, w, d) for i, (h, w, d) in enumerate(shapes)]
+    rb = H.hdp_stereo(rgb_dev(*[p.left for p in pairs]), rgb_dev(*[p.right for p in pairs]),
+                      shapes, S=2, L=2, window=2)
+    off = 0
+    for p, (h, w, d) in zip(pairs, shapes):
+        rs = H.hdp_stereo(rgb_dev(p.left), rgb_dev(p.right), [(h, w, d)], S=2, L=2, window=2)
+        np.testing.assert_array_equal(rb[0].disp.cpu().numpy()[off:off + h * w],
+                                      rs[0].disp.cpu().numpy())
+        off += h * w
+
+
+# --- adjoint --------------------------------------------------------------------------
+
+def test_adjoint_matches_oracle(H, orc):
+    Hh, Ww, dmax, sigma = 32, 48, 7, 0.1
+    pair = scenes.small_scene(77, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lp = H.pyramid(rgb_dev(pair.left), shapes, 2, 0)
+    rp = H.pyramid(rgb_dev(pair.right), shapes, 2, 0)
+    f = H.build_tree(lp[0], shapes, 0)
+    cost = H.cost_volume(lp[0], rp[0], shapes, f)
+    agg, up = H.aggregate(f, cost, sigma, keep_up=True)
+    g = torch.from_numpy(np.random.default_rng(3).normal(size=cost.shape).astype(np.float32)).cuda()
+    gc, gw, gs = H.aggregate_backward(f, cost, agg, g, sigma, up=up)
+    gc2, gw2, gs2 = H.aggregate_backward(f, cost, agg, g, sigma, up=None)
+    F = forest_np(f)
+    node = F["node"]
+    # oracle on the same pixel-ordered inputs (cost from the oracle itself)
+    key = orc.edge_keys(pair.left.astype(np.float64), 0)
+    in_tree, _, _, _ = orc.kruskal(Hh, Ww, key)
+    ref = orc.root_forest(Hh, Ww, in_tree, key, 0)
+    C = orc.cost_volume(pair.left.astype(np.float64), pair.right.astype(np.float64), dmax)
+    Gp = np.zeros_like(C); Gp[node] = g.cpu().numpy().astype(np.float64)
+    dC, dw, ds = orc.aggregate_backward_twopass(ref["parent"], ref["wgt"], ref["order"], sigma, C, Gp)
+    got = np.zeros_like(C); got[node] = gc.cpu().numpy()
+    scale = np.abs(dC).max()
+    assert np.all(np.abs(got - dC) <= REL * np.maximum(np.abs(dC), 1e-3 * scale))
+    gwn = gw.cpu().numpy()
+    sw = np.abs(dw).max()
+    assert np.all(np.abs(gwn - dw) <= 1e-4 * np.maximum(np.abs(dw), 1e-2 * sw)), \
+        np.abs(gwn - dw).max() / sw
+    assert abs(float(gs.cpu()) - ds) <= 1e-4 * abs(ds)
+    np.testing.assert_allclose(gc2.cpu().numpy(), gc.cpu().numpy(), rtol=1e-6)
