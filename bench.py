@@ -30,6 +30,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="both", choices=["both", "hdp", "full"],
+                    help="profiling aid: time only the HDP loop or only the full-range path")
     return ap.parse_args()
 
 
@@ -70,8 +72,9 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    t_hdp = timed(hdp_step, args.steps, args.warmup)
-    t_full = timed(full_step, max(2, args.steps // 4), 1)
+    t_hdp = timed(hdp_step, args.steps, args.warmup) if args.mode != "full" else float("nan")
+    t_full = (timed(full_step, max(2, args.steps // 4), 1) if args.mode != "hdp"
+              else float("nan"))
 
     res = hdp_step()
     torch.cuda.synchronize()

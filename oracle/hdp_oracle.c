@@ -334,11 +334,12 @@ OR_API void or_aggregate_direct(int H, int W, const uint8_t *in_tree, const doub
  * U(v) collects the subtree of v; A(parent) - s_v U(v) is what the parent
  * receives from outside that subtree, so A(v) = U(v) + s_v (A(p) - s_v U(v)),
  * the same sum as the plain definition.  cost/agg are [N][D]; NaN entries are
- * carried through (they only meet entries of the same tree). */
+ * carried through (they only meet entries of the same tree).  up (may be NULL)
+ * receives U. */
 
 OR_API void or_aggregate_twopass(int N, const int32_t *parent, const double *wgt,
                                  const int32_t *order, double sigma, int D,
-                                 const double *cost, double *agg) {
+                                 const double *cost, double *agg, double *up) {
     double *U = (double *)malloc(sizeof(double) * (size_t)N * D);
     memcpy(U, cost, sizeof(double) * (size_t)N * D);
     for (int i = N - 1; i >= 0; --i) {
@@ -357,6 +358,7 @@ OR_API void or_aggregate_twopass(int N, const int32_t *parent, const double *wgt
         for (int d = 0; d < D; ++d)
             agg[(size_t)v * D + d] = s * agg[(size_t)p * D + d] + (1.0 - s * s) * U[(size_t)v * D + d];
     }
+    if (up) memcpy(up, U, sizeof(double) * (size_t)N * D);
     free(U);
 }
 

@@ -63,7 +63,7 @@ def _declare(L):
     L.or_root_forest.argtypes = [I, I, P, P, I, P, P, P, P, P, P]
     L.or_root_forest.restype = I
     L.or_aggregate_direct.argtypes = [I, I, P, P, D, I, P, P, I, P]
-    L.or_aggregate_twopass.argtypes = [I, P, P, P, D, I, P, P]
+    L.or_aggregate_twopass.argtypes = [I, P, P, P, D, I, P, P, P]
     L.or_wta.argtypes = [I, I, P, P, P, P, P, P]
     L.or_predict_range.argtypes = [P, I, I, I, I, I, I, I, P, P]
     L.or_stereo_level.argtypes = [P, P, I, I, I, I, P, P, I, I, D, P,
@@ -181,13 +181,15 @@ def aggregate_direct(H, W, in_tree, edge_w, sigma, cost, pixels=None):
     return out
 
 
-def aggregate_twopass(parent, wgt, order, sigma, cost):
+def aggregate_twopass(parent, wgt, order, sigma, cost, want_up=False):
     cost = _c(cost, np.float64)
     N, Dn = cost.shape
     out = np.zeros_like(cost)
+    up = np.zeros_like(cost) if want_up else None
     lib().or_aggregate_twopass(N, _p(_c(parent, np.int32)), _p(_c(wgt, np.float64)),
-                               _p(_c(order, np.int32)), float(sigma), Dn, _p(cost), _p(out))
-    return out
+                               _p(_c(order, np.int32)), float(sigma), Dn, _p(cost), _p(out),
+                               _p(up))
+    return (out, up) if want_up else out
 
 
 def wta(agg, lo=None, hi=None):

@@ -18,12 +18,14 @@
 // affine maps over a contiguous range of rows, independent per label column:
 // tile reduce -> carry scan over tiles -> tile apply.  Rows are row-major
 // [row][width] (labels fastest); arithmetic is FP64 in registers, storage FP32.
+#include <cstdlib>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace hdp {
 
-constexpr int kRowsPerGroup = 16;
+constexpr int kRowsPerGroup = 8;
 
 struct AggTileGeom {
     int width;   // labels per row (<= 256)
@@ -71,27 +73,30 @@ struct PassArgs {
     double *Pt, *Xt, *Ct;    // per tile: coefficient product, zero-input result, carry-in
 };
 
-// Affine map of one row: x -> a x + b for column j.
+// Coefficient of row r: zero where a chain starts (scan order), so the value
+// carried in from the previous row is dropped there.
 template <bool UP>
-__device__ __forceinline__ void row_map(const PassArgs &A, int64_t r, int j, double &a, double &b) {
+__device__ __forceinline__ double row_coef(const PassArgs &A, int64_t r) {
+    if (UP) return (r + 1 < A.r1 && A.heavy[r + 1]) ? A.s[r + 1] : 0.0;
+    return A.heavy[r] ? A.s[r] : 0.0;
+}
+
+// Constant term of row r for column j.
+template <bool UP>
+__device__ __forceinline__ double row_b(const PassArgs &A, int64_t r, int j) {
     if (UP) {
-        a = (r + 1 < A.r1 && A.heavy[r + 1]) ? A.s[r + 1] : 0.0;
         double x = (double)A.src[r * A.width + j];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             int c = A.lc[(int64_t)k * A.n + r];
             if (c >= 0) x += A.s[c] * (double)A.aux[(int64_t)c * A.width + j];
         }
-        b = x;
-    } else {
-        bool hv = A.heavy[r];
-        double s = A.s[r];
-        a = hv ? s : 0.0;
-        double x = A.om[r] * (double)A.src[r * A.width + j];
-        int p = A.prow[r];
-        if (!hv && p >= 0) x += s * (double)A.aux[(int64_t)p * A.width + j];
-        b = x;
+        return x;
     }
+    double x = A.om[r] * (double)A.src[r * A.width + j];
+    int p = A.prow[r];
+    if (!A.heavy[r] && p >= 0) x += A.s[r] * (double)A.aux[(int64_t)p * A.width + j];
+    return x;
 }
 
 // Physical row of logical position li of tile t (logical order = scan order).
@@ -100,10 +105,69 @@ __device__ __forceinline__ int64_t tile_row(const PassArgs &A, int t, int li) {
     return UP ? (int64_t)A.r1 - 1 - ((int64_t)t * A.rows + li) : (int64_t)A.r0 + (int64_t)t * A.rows + li;
 }
 
-// APPLY = false: per-tile (P, X) with zero input.  APPLY = true: outputs from
-// the tile's carry-in.
-template <bool UP, bool APPLY>
-__global__ void __launch_bounds__(kBlock) k_tile(PassArgs A) {
+// Tile reduce: the affine map of the whole tile applied to 0 (X) and the
+// product of its coefficients (P).  Only the rows after the tile's last chain
+// start matter for X (the coefficient there is 0), so only those are read.
+template <bool UP>
+__global__ void __launch_bounds__(kBlock) k_tile_reduce(PassArgs A) {
+    __shared__ double sP[kBlock];
+    __shared__ double sX[kBlock];
+    __shared__ int sZ[kBlock];
+    int t = blockIdx.x;
+    if (t >= A.ntiles) return;
+    int tid = threadIdx.x;
+    int g = tid / A.width, j = tid - g * A.width;
+    bool active = g < A.groups;
+    double av[kRowsPerGroup];
+    double P = 1.0;
+    int z = -1;
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < kRowsPerGroup; ++i) {
+            int li = g * kRowsPerGroup + i;
+            int64_t r = tile_row<UP>(A, t, li);
+            bool in = UP ? r >= A.r0 : r < A.r1;
+            double a = in ? row_coef<UP>(A, r) : 1.0;
+            av[i] = a;
+            P = a * P;
+            if (a == 0.0) z = li;
+        }
+    }
+    sZ[tid] = z;
+    __syncthreads();
+    int zt = -1;
+    for (int q = 0; q < A.groups; ++q) {
+        int zq = sZ[q * A.width];
+        zt = zq > zt ? zq : zt;
+    }
+    double X = 0.0;
+    if (active && g * kRowsPerGroup + kRowsPerGroup - 1 >= zt) {
+#pragma unroll
+        for (int i = 0; i < kRowsPerGroup; ++i) {
+            int li = g * kRowsPerGroup + i;
+            int64_t r = tile_row<UP>(A, t, li);
+            bool in = UP ? r >= A.r0 : r < A.r1;
+            if (in && li >= zt) X = av[i] * X + row_b<UP>(A, r, j);
+        }
+    }
+    sP[tid] = P;
+    sX[tid] = X;
+    __syncthreads();
+    if (active && g == 0) {
+        double Pc = 1.0, Xc = 0.0;
+        for (int q = 0; q < A.groups; ++q) {
+            double pq = sP[q * A.width + j], xq = sX[q * A.width + j];
+            Xc = pq * Xc + xq;
+            Pc = pq * Pc;
+        }
+        A.Xt[(int64_t)t * A.width + j] = Xc;
+        if (j == 0) A.Pt[t] = Pc;
+    }
+}
+
+// Tile apply: outputs of the tile from its carry-in.
+template <bool UP>
+__global__ void __launch_bounds__(kBlock) k_tile_apply(PassArgs A) {
     __shared__ double sP[kBlock];
     __shared__ double sX[kBlock];
     int t = blockIdx.x;
@@ -122,7 +186,10 @@ __global__ void __launch_bounds__(kBlock) k_tile(PassArgs A) {
             bool in = UP ? r >= A.r0 : r < A.r1;
             rr[i] = in ? r : -1;
             double a = 1.0, b = 0.0;  // identity map past the end of the phase
-            if (in) row_map<UP>(A, r, j, a, b);
+            if (in) {
+                a = row_coef<UP>(A, r);
+                b = row_b<UP>(A, r, j);
+            }
             av[i] = a;
             bv[i] = b;
             X = a * X + b;
@@ -132,19 +199,6 @@ __global__ void __launch_bounds__(kBlock) k_tile(PassArgs A) {
     sP[tid] = P;
     sX[tid] = X;
     __syncthreads();
-    if (!APPLY) {
-        if (active && g == 0) {
-            double Pc = 1.0, Xc = 0.0;
-            for (int q = 0; q < A.groups; ++q) {
-                double pq = sP[q * A.width + j], xq = sX[q * A.width + j];
-                Xc = pq * Xc + xq;
-                Pc = pq * Pc;
-            }
-            A.Xt[(int64_t)t * A.width + j] = Xc;
-            if (j == 0) A.Pt[t] = Pc;
-        }
-        return;
-    }
     if (!active) return;
     double c = A.Ct[(int64_t)t * A.width + j];
     for (int q = 0; q < g; ++q) c = sP[q * A.width + j] * c + sX[q * A.width + j];
@@ -192,9 +246,226 @@ __global__ void __launch_bounds__(kBlock) k_carry(PassArgs A) {
     }
 }
 
+// ---------------------------------------------------------------------------------
+// Single-launch pass.  Tiles of all phases are taken in ticket order (phase by
+// phase in scan order, tiles in scan order inside a phase).  A tile only waits
+// for tiles with smaller tickets, which are already running, so the launch
+// always drains:
+//   - before reading rows of the previous phase (light children's U in the up
+//     pass, parents' A in the down pass) it waits for that phase's completion
+//     counter;
+//   - its carry-in (a chain that crosses the tile boundary) comes from a
+//     decoupled look-back over the preceding tiles' published maps.
+// Every wait is bounded; on timeout an error word is set and the pass goes on
+// (wrong values, never a hang).
+
+struct PassPlan {
+    int n_phases;
+    int total_tiles;
+    int32_t row0[HDP_MAX_PHASES + 1];   // rows of phase k: row0[k] .. row0[k+1]-1
+    int32_t tile0[HDP_MAX_PHASES + 1];  // first ticket of the q-th processed phase
+};
+
+struct PassSync {
+    int32_t *ticket;   // [1]
+    int32_t *done;     // [HDP_MAX_PHASES] completed tiles per processed phase
+    int32_t *flag;     // [tiles] 0 nothing, 1 map published, 2 final value published
+    double *tP;        // [tiles] product of the tile's coefficients
+    double *tX;        // [tiles][width] tile map applied to 0
+    double *tI;        // [tiles][width] value after the tile's last row
+    int32_t *err;      // nonzero: a bounded wait timed out
+};
+
+// Data that crosses workgroups inside one launch (published tile maps, rows of
+// the previous phase, flags) is read and written with device-scope relaxed
+// atomics (device-coherent loads/stores); a publisher waits for its stores to
+// complete before it raises the flag.  No cache-wide flush or invalidate is
+// issued.
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T *p) {
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dev(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0); }
+
+constexpr int64_t kSpinLimit = int64_t(1) << 24;
+
+// Bounded wait (one lane) until *p >= target.
+__device__ void wait_at_least(const int32_t *p, int32_t target, int32_t *err, int code) {
+    int64_t it = 0;
+    while (ld_dev(p) < target) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++it > kSpinLimit) {
+            atomicMax(err, code);
+            break;
+        }
+    }
+}
+
+__global__ void k_pass_init(PassSync sy, int total_tiles) {
+    int64_t i = gtid();
+    if (i < total_tiles) sy.flag[i] = 0;
+    if (i < HDP_MAX_PHASES) sy.done[i] = 0;
+    if (i == 0) sy.ticket[0] = 0;
+}
+
+template <bool UP>
+__global__ void __launch_bounds__(kBlock) k_agg_pass(PassArgs A, PassPlan pl, PassSync sy) {
+    __shared__ double sP[kBlock];
+    __shared__ double sX[kBlock];
+    __shared__ int s_ticket, s_flag;
+    __shared__ double s_first;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_ticket = atomicAdd(sy.ticket, 1);
+    __syncthreads();
+    const int T = s_ticket;
+    if (T >= pl.total_tiles) return;
+    int q = 0;
+    while (q + 1 < pl.n_phases && pl.tile0[q + 1] <= T) ++q;
+    const int k = UP ? pl.n_phases - 1 - q : q;
+    const int tl = T - pl.tile0[q];
+    A.r0 = pl.row0[k];
+    A.r1 = pl.row0[k + 1];
+    const int g = tid / A.width, j = tid - g * A.width;
+    const bool active = g < A.groups;
+    const int w = A.width;
+
+    // stage 1: loads that do not depend on other tiles
+    double av[kRowsPerGroup], bv[kRowsPerGroup];
+    int32_t rr[kRowsPerGroup];
+    int32_t x0[kRowsPerGroup], x1[kRowsPerGroup], x2[kRowsPerGroup];
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < kRowsPerGroup; ++i) {
+            int li = g * kRowsPerGroup + i;
+            int r = UP ? A.r1 - 1 - (tl * A.rows + li) : A.r0 + tl * A.rows + li;
+            bool in = UP ? r >= A.r0 : r < A.r1;
+            rr[i] = in ? r : -1;
+            av[i] = 1.0;
+            bv[i] = 0.0;
+            x0[i] = x1[i] = x2[i] = -1;
+            if (!in) continue;
+            av[i] = row_coef<UP>(A, r);
+            if (UP) {
+                bv[i] = (double)A.src[r * w + j];
+                x0[i] = A.lc[r];
+                x1[i] = A.lc[(int)A.n + r];
+                x2[i] = A.lc[2 * (int)A.n + r];
+            } else {
+                bv[i] = A.om[r] * (double)A.src[r * w + j];
+                x0[i] = A.heavy[r] ? -1 : A.prow[r];
+            }
+        }
+    }
+    // the previous phase must be complete before its rows are read
+    if (q > 0) {
+        if (tid == 0) wait_at_least(&sy.done[q - 1], pl.tile0[q] - pl.tile0[q - 1], sy.err, 16);
+        __syncthreads();
+    }
+    // stage 2: rows of the previous phase (light children / parent)
+    double P = 1.0, X = 0.0;
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < kRowsPerGroup; ++i) {
+            if (UP) {
+                if (x0[i] >= 0) bv[i] += A.s[x0[i]] * (double)ld_dev(&A.aux[x0[i] * w + j]);
+                if (x1[i] >= 0) bv[i] += A.s[x1[i]] * (double)ld_dev(&A.aux[x1[i] * w + j]);
+                if (x2[i] >= 0) bv[i] += A.s[x2[i]] * (double)ld_dev(&A.aux[x2[i] * w + j]);
+            } else if (x0[i] >= 0) {
+                bv[i] += A.s[rr[i]] * (double)ld_dev(&A.aux[x0[i] * w + j]);
+            }
+            X = av[i] * X + bv[i];
+            P = av[i] * P;
+        }
+    }
+    if (tid == 0) s_first = av[0];
+    sP[tid] = P;
+    sX[tid] = X;
+    __syncthreads();
+    // map of the whole tile for column j (P is the same in every column)
+    double Pt = 1.0, Xt = 0.0;
+    if (active) {
+        for (int q2 = 0; q2 < A.groups; ++q2) {
+            double pq = sP[q2 * A.width + j];
+            Xt = pq * Xt + sX[q2 * A.width + j];
+            Pt = pq * Pt;
+        }
+    }
+    const bool incl_now = tl == 0 || Pt == 0.0;
+    if (active && g == 0) {
+        if (incl_now) {
+            st_dev(&sy.tI[T * w + j], Xt);
+        } else {
+            st_dev(&sy.tX[T * w + j], Xt);
+            if (j == 0) st_dev(&sy.tP[T], Pt);
+        }
+    }
+    stores_complete();
+    __syncthreads();
+    if (tid == 0) st_dev(&sy.flag[T], incl_now ? 2 : 1);
+
+    // carry-in (decoupled look-back), needed when the first row continues a chain
+    double carry = 0.0;
+    if (tl > 0 && s_first != 0.0) {
+        double mP = 1.0, mX = 0.0;
+        int kk = T - 1;
+        for (;;) {
+            if (tid == 0) {
+                int64_t it = 0;
+                int f;
+                while ((f = ld_dev(&sy.flag[kk])) == 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++it > kSpinLimit) {
+                        atomicMax(sy.err, 17);
+                        f = 2;
+                        break;
+                    }
+                }
+                s_flag = f;
+            }
+            __syncthreads();
+            int f = s_flag;
+            if (f == 2) {
+                if (active) carry = mP * ld_dev(&sy.tI[kk * w + j]) + mX;
+                break;
+            }
+            if (active) {
+                double pk = ld_dev(&sy.tP[kk]);
+                mX = mP * ld_dev(&sy.tX[kk * w + j]) + mX;
+                mP = mP * pk;
+            }
+            --kk;
+            __syncthreads();
+            if (kk < pl.tile0[q]) break;  // unreachable: a phase's first tile publishes its value
+        }
+    }
+
+    // apply and store
+    if (active) {
+        double c = carry;
+        for (int q2 = 0; q2 < g; ++q2) c = sP[q2 * A.width + j] * c + sX[q2 * A.width + j];
+#pragma unroll
+        for (int i = 0; i < kRowsPerGroup; ++i) {
+            c = av[i] * c + bv[i];
+            if (rr[i] >= 0) st_dev(&A.dst[rr[i] * w + j], (float)c);
+        }
+        if (!incl_now && g == A.groups - 1) st_dev(&sy.tI[T * w + j], c);
+    }
+    stores_complete();
+    __syncthreads();
+    if (tid == 0) {
+        if (!incl_now) st_dev(&sy.flag[T], 2);
+        atomicAdd(&sy.done[q], 1);
+    }
+}
+
 // --- workspace --------------------------------------------------------------------
 
 struct AggWs {
+    int32_t *flag, *done, *ticket;
     double *s, *om, *Pt, *Xt, *Ct;
     float *up;      // U when the caller does not keep it
     float *ug;      // U of the gradient (backward)
@@ -217,6 +488,9 @@ static AggWs carve_agg_ws(void *ws, int64_t n, int width, size_t *bytes) {
     };
     int64_t nt = max_tiles(n, width);
     AggWs a;
+    a.flag = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * nt));
+    a.done = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * HDP_MAX_PHASES));
+    a.ticket = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * 4));
     a.s = reinterpret_cast<double *>(take(sizeof(double) * n));
     a.om = reinterpret_cast<double *>(take(sizeof(double) * n));
     a.Pt = reinterpret_cast<double *>(take(sizeof(double) * nt));
@@ -239,9 +513,40 @@ template <bool UP>
 static void run_pass(PassArgs A, hipStream_t st) {
     if (A.r1 <= A.r0) return;
     A.ntiles = (int)(((int64_t)A.r1 - A.r0 + A.rows - 1) / A.rows);
-    k_tile<UP, false><<<A.ntiles, kBlock, 0, st>>>(A);
+    k_tile_reduce<UP><<<A.ntiles, kBlock, 0, st>>>(A);
     k_carry<<<A.width, kBlock, 0, st>>>(A);
-    k_tile<UP, true><<<A.ntiles, kBlock, 0, st>>>(A);
+    k_tile_apply<UP><<<A.ntiles, kBlock, 0, st>>>(A);
+}
+
+static int schedule_mode() {
+    static int mode = -1;
+    if (mode < 0) {
+        const char *e = getenv("HDP_AGG_SCHEDULE");
+        mode = (e && e[0] == '3') ? 3 : 1;  // 1: one launch per pass, 3: three launches per phase
+    }
+    return mode;
+}
+
+template <bool UP>
+static void run_pass_single(PassArgs A, const int32_t *phase_ptr, int n_phases, const AggWs &w,
+                            int32_t *err, hipStream_t st) {
+    PassPlan pl{};
+    pl.n_phases = n_phases;
+    int tot = 0;
+    for (int q = 0; q < n_phases; ++q) {
+        int k = UP ? n_phases - 1 - q : q;
+        int rows = phase_ptr[k + 1] - phase_ptr[k];
+        pl.tile0[q] = tot;
+        tot += (rows + A.rows - 1) / A.rows;
+    }
+    pl.tile0[n_phases] = tot;
+    for (int k = 0; k <= n_phases; ++k) pl.row0[k] = phase_ptr[k];
+    pl.total_tiles = tot;
+    if (tot == 0) return;
+    PassSync sy{w.ticket, w.done, w.flag, w.Pt, w.Xt, w.Ct, err};
+    int64_t init_n = tot > HDP_MAX_PHASES ? tot : HDP_MAX_PHASES;
+    k_pass_init<<<grid_for(init_n), kBlock, 0, st>>>(sy, tot);
+    k_agg_pass<UP><<<tot, kBlock, 0, st>>>(A, pl, sy);
 }
 
 // Two passes of `src` over the forest: U -> up, A -> out.
@@ -261,6 +566,13 @@ static void two_pass(const hdp_forest &f, int width, const int32_t *phase_ptr, i
     A.Pt = w.Pt;
     A.Xt = w.Xt;
     A.Ct = w.Ct;
+    if (schedule_mode() == 1) {
+        A.src = src; A.aux = up; A.dst = up;
+        run_pass_single<true>(A, phase_ptr, n_phases, w, f.info + HDP_INFO_ERROR, st);
+        A.src = up; A.aux = out; A.dst = out;
+        run_pass_single<false>(A, phase_ptr, n_phases, w, f.info + HDP_INFO_ERROR, st);
+        return;
+    }
     for (int k = n_phases - 1; k >= 0; --k) {
         A.r0 = phase_ptr[k];
         A.r1 = phase_ptr[k + 1];
@@ -359,10 +671,14 @@ void launch_aggregate_backward(const hdp_forest &f, int width, const int32_t *ph
         A.n = f.n; A.width = width; A.rows = tg.rows; A.groups = tg.groups;
         A.s = w.s; A.om = w.om; A.heavy = f.heavy; A.prow = f.prow; A.lc = f.lc;
         A.Pt = w.Pt; A.Xt = w.Xt; A.Ct = w.Ct;
-        for (int k = n_phases - 1; k >= 0; --k) {
-            A.r0 = phase_ptr[k]; A.r1 = phase_ptr[k + 1];
-            A.src = cost; A.aux = w.up; A.dst = w.up;
-            run_pass<true>(A, st);
+        A.src = cost; A.aux = w.up; A.dst = w.up;
+        if (schedule_mode() == 1) {
+            run_pass_single<true>(A, phase_ptr, n_phases, w, f.info + HDP_INFO_ERROR, st);
+        } else {
+            for (int k = n_phases - 1; k >= 0; --k) {
+                A.r0 = phase_ptr[k]; A.r1 = phase_ptr[k + 1];
+                run_pass<true>(A, st);
+            }
         }
         uc = w.up;
     }

@@ -228,6 +228,7 @@ size_t hdp_aggregate_workspace_bytes(int64_t n, int32_t width) {
 static hdp_status check_phases(const hdp_forest *f, int32_t width, const int32_t *pp, int32_t np) {
     if (!f || !pp) return HDP_EINVAL;
     if (width < 1 || width > HDP_MAX_LABELS) return HDP_EINVAL;
+    if (f->n * (int64_t)width >= (int64_t(1) << 31)) return HDP_ESHAPE;  // 32-bit volume offsets
     if (np < 1 || np > HDP_MAX_PHASES) return HDP_EINVAL;
     if (pp[0] != 0 || pp[np] != f->n) return HDP_EINVAL;
     for (int k = 0; k < np; ++k)

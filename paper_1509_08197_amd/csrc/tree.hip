@@ -149,10 +149,22 @@ __global__ void k_bv_compress(int round, const int32_t *__restrict__ flags,
 
 // --- 3. roots -------------------------------------------------------------------
 
+// Smallest pixel id of every component.  Lanes of a wavefront that share a
+// component (the common case: components are large and pixels contiguous)
+// combine first, so one atomic per wavefront and component reaches memory.
 __global__ void k_rootmin(const int32_t *__restrict__ comp, int32_t *__restrict__ mn, int64_t n) {
     int64_t v = gtid();
-    if (v >= n) return;
-    atomicMin(&mn[comp[v]], (int32_t)v);
+    bool valid = v < n;
+    int c = valid ? comp[v] : -1;
+    int c0 = __shfl(c, 0, 64);
+    uint64_t same = __ballot(c == c0);
+    uint64_t act = __ballot(valid);
+    if (same == act) {
+        // every active lane has component c0; lane 0 holds the smallest v
+        if ((threadIdx.x & 63) == 0 && valid && mn[c0] > (int32_t)v) atomicMin(&mn[c0], (int32_t)v);
+        return;
+    }
+    if (valid && mn[c] > (int32_t)v) atomicMin(&mn[c], (int32_t)v);
 }
 
 __global__ void k_set_tree(const int32_t *__restrict__ comp, const int32_t *__restrict__ mn,
@@ -335,6 +347,15 @@ __global__ void k_tour_scatter(LevelGeom g, const uint8_t *__restrict__ adj,
     tourval[pos] = val;
 }
 
+// Maximum over the active lanes of a wavefront, then one atomicMax.
+__device__ __forceinline__ void wave_max_to(int32_t *dst, int32_t x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        int32_t y = __shfl_xor(x, off, 64);
+        x = y > x ? y : x;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(dst, x);
+}
+
 __global__ void k_node_order(LevelGeom g, const uint8_t *__restrict__ adj,
                              const int32_t *__restrict__ tree, const int32_t *__restrict__ parent,
                              const uint64_t *__restrict__ pr, const uint64_t *__restrict__ rootoff,
@@ -342,46 +363,42 @@ __global__ void k_node_order(LevelGeom g, const uint8_t *__restrict__ adj,
                              int32_t *__restrict__ depth, int32_t *__restrict__ ld,
                              int32_t *__restrict__ gpre, int32_t *__restrict__ info) {
     int64_t w = gtid();
-    if (w >= g.off[g.n_pairs]) return;
-    int64_t root = tree[w];
-    uint64_t ro = rootoff[root];
-    uint32_t toff = (uint32_t)ro, noff = (uint32_t)(ro >> 32);
-    if (root == w) {
-        depth[w] = 0;
-        ld[w] = 0;
-        gpre[w] = (int32_t)noff;
-        return;
+    int32_t dep = 0, l = 0;  // every lane reaches the wavefront maxima below
+    if (w < g.off[g.n_pairs]) {
+        int64_t root = tree[w];
+        uint64_t ro = rootoff[root];
+        uint32_t toff = (uint32_t)ro, noff = (uint32_t)(ro >> 32);
+        int32_t pre = (int32_t)noff;
+        if (root != w) {
+            int64_t p = parent[w];
+            int W = g.W[pair_of(g, (int)w)];
+            // direction of the edge p -> w (a one-pixel-wide image has vertical edges only)
+            int d = W == 1 ? (w > p ? 1 : 3) : w == p + 1 ? 0 : w == p + W ? 1 : w == p - 1 ? 2 : 3;
+            int64_t tlen = 2 * (int64_t)(size[root] - 1);
+            int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rank_of(pr, 4 * p + d));
+            if (pos < toff || pos >= (int64_t)toff + tlen) {
+                info[HDP_INFO_ERROR] = 3;
+                pre = 0;
+            } else {
+                uint64_t P = tourscan[pos];
+                dep = (int32_t)(P & ((1ull << kDepthBits) - 1));
+                l = (int32_t)((P >> kLdShift) & 63);
+                uint64_t down = P >> kDownShift;
+                uint32_t tidx = noff - (toff >> 1);  // trees before this one
+                pre = (int32_t)(down + tidx);
+            }
+        }
+        depth[w] = dep;
+        ld[w] = l;
+        gpre[w] = pre;
     }
-    int64_t p = parent[w];
-    int W = g.W[pair_of(g, (int)w)];
-    // direction of the edge p -> w (a one-pixel-wide image has vertical edges only)
-    int d = W == 1 ? (w > p ? 1 : 3) : w == p + 1 ? 0 : w == p + W ? 1 : w == p - 1 ? 2 : 3;
-    int64_t tlen = 2 * (int64_t)(size[root] - 1);
-    int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rank_of(pr, 4 * p + d));
-    if (pos < toff || pos >= (int64_t)toff + tlen) {
-        info[HDP_INFO_ERROR] = 3;
-        depth[w] = 0; ld[w] = 0; gpre[w] = 0;
-        return;
-    }
-    uint64_t P = tourscan[pos];
-    int32_t dep = (int32_t)(P & ((1ull << kDepthBits) - 1));
-    int32_t l = (int32_t)((P >> kLdShift) & 63);
-    uint64_t down = P >> kDownShift;
-    uint32_t tidx = noff - (toff >> 1);  // trees before this one
-    depth[w] = dep;
-    ld[w] = l;
-    gpre[w] = (int32_t)(down + tidx);
-    atomicMax(&info[HDP_INFO_N_LEVELS], dep + 1);
-    atomicMax(&info[HDP_INFO_N_PHASES], l + 1);
+    wave_max_to(&info[HDP_INFO_N_LEVELS], dep + 1);
+    wave_max_to(&info[HDP_INFO_N_PHASES], l + 1);
 }
 
 __global__ void k_scatter_seq(const int32_t *__restrict__ gpre, int32_t *__restrict__ seq,
                               int64_t n, int32_t *__restrict__ info) {
     int64_t v = gtid();
-    if (v == 0) {
-        atomicMax(&info[HDP_INFO_N_LEVELS], 1);
-        atomicMax(&info[HDP_INFO_N_PHASES], 1);
-    }
     if (v >= n) return;
     int32_t q = gpre[v];
     if (q < 0 || q >= n) {
@@ -462,17 +479,15 @@ __global__ void k_iota(int32_t *__restrict__ a, int64_t n) {
     if (i < n) a[i] = (int32_t)i;
 }
 
-__global__ void k_depth_hist(const int32_t *__restrict__ depth, int32_t *__restrict__ cnt,
-                             int64_t n) {
-    int64_t v = gtid();
-    if (v >= n) return;
-    int d = depth[v];
-    atomicAdd(&cnt[d < 0 ? 0 : d > n ? n : d], 1);
-}
-
-__global__ void k_zero_i32(int32_t *__restrict__ a, int64_t n) {
+// level_ptr[k] = first position of depth k in the level order: every
+// position where the depth steps up from d' to d writes the entries d'+1..d.
+__global__ void k_level_ptr(const int32_t *__restrict__ order, const int32_t *__restrict__ depth,
+                            int64_t n, int32_t *__restrict__ level_ptr) {
     int64_t i = gtid();
-    if (i < n) a[i] = 0;
+    if (i > n) return;
+    int d = i < n ? depth[order[i]] : depth[order[n - 1]] + 1;
+    int dp = i > 0 ? depth[order[i - 1]] : -1;
+    for (int k = dp + 1; k <= d; ++k) level_ptr[k] = (int32_t)i;
 }
 
 __global__ void k_finish_info(const int32_t *__restrict__ flags, int32_t *__restrict__ info,
@@ -630,9 +645,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         src = out;
         dst = (out == t.sortB) ? t.sortA : t.sortB;
     }
-    k_zero_i32<<<grid_for(n + 1), kBlock, 0, st>>>(t.cnt, n + 1);
-    k_depth_hist<<<gn, kBlock, 0, st>>>(f.depth, t.cnt, n);
-    device_scan<int32_t>(t.cnt, f.level_ptr, n + 1, t.partial32, nullptr, false, st);
+    k_level_ptr<<<grid_for(n + 1), kBlock, 0, st>>>(f.order, f.depth, n, f.level_ptr);
     k_finish_info<<<1, 64, 0, st>>>(t.flags, f.info, width);
 }
 
