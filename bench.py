@@ -3,13 +3,15 @@
 Workload: one synthetic 1344x1104 RGB pair with labels 0..255 (slanted planes,
 shaped like the paper's full-size benchmark images), HDP with a 4-layer graph
 pyramid (S=2, L=3), +-4 predicted window, beta=19/20, sigma=0.1.  One step =
-the whole top-down loop: pyramid, then per layer interval prediction,
-disparity forest, restricted cost, two-pass aggregation and WTA.
+the whole top-down loop, captured once as a HIP graph and replayed: pyramid,
+then per layer interval prediction, disparity forest, restricted cost,
+two-pass aggregation and WTA.  Inputs are resident in HBM before timing.
 
 Prints one JSON line.  `value` is the full-range-equivalent throughput
 N*(dmax+1)/step_time in Mpix*disp/s (the rate at which disparity maps of this
-size and range are produced); the full-range MST baseline on the same pair is
-reported beside it.
+size and range are produced); the full-range MST path on the same pair, the
+algorithmic HDP rate, the roofline of the dominant kernel and the FP64 CPU
+oracle timed on the host are reported beside it.
 """
 
 from __future__ import annotations
@@ -23,6 +25,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -35,12 +39,25 @@ def parse():
     return ap.parse_args()
 
 
+def pass_bytes(forest, up: bool) -> float:
+    """Algorithmic HBM bytes of one aggregation pass over a forest: read the
+    source volume and write the result (8 B per entry), read the previous-phase
+    row of every chain head (4 B per label), and the per-row coefficients and
+    links (21 B per row, plus 8 B per light child in the up pass)."""
+    import torch
+    n, w = forest.n, forest.width
+    heavy = forest.array("heavy")
+    prow = forest.array("prow")
+    heads = int(torch.count_nonzero((heavy == 0) & (prow >= 0)).item())
+    return 8.0 * n * w + 4.0 * heads * w + 21.0 * n + (8.0 * heads if up else 0.0)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (one pair per GPU; "
+                                   "--gpus must be 1)"}))
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_1509_08197_amd import hdp, scenes
@@ -55,12 +72,12 @@ def main():
     R_rgb = torch.from_numpy(pair.right.reshape(-1, 3).copy()).cuda()
     N = Hh * Ww
 
-    def hdp_step():
+    def hdp_eager(ws=None):
         return hdp.hdp_stereo(L_rgb, R_rgb, shapes, S=P["S"], L=P["L"], window=P["window"],
-                              beta=P["beta"])
+                              beta=P["beta"], ws=ws)
 
-    def full_step():
-        return hdp.full_range(L_rgb, R_rgb, shapes)
+    def full_eager(ws=None):
+        return hdp.full_range(L_rgb, R_rgb, shapes, ws=ws)
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -72,33 +89,71 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    t_hdp = timed(hdp_step, args.steps, args.warmup) if args.mode != "full" else float("nan")
-    t_full = (timed(full_step, max(2, args.steps // 4), 1) if args.mode != "hdp"
-              else float("nan"))
+    nan = float("nan")
+    out = {"metric": "aggregated Mpix*disp/s (full-range-equivalent, HDP single pair)",
+           "value": nan, "unit": "Mpix*disp/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": nan, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "single pair 1344x1104 RGB, labels 0..255, HDP pyramid "
+                                  "L=3 S=2, window 4, beta 19/20, sigma 0.1",
+                      "global_batch": 1}}
 
-    res = hdp_step()
-    torch.cuda.synchronize()
-    alg_entries = sum(r.forest.n * r.forest.width for r in res)
-    out = {
-        "metric": "aggregated Mpix*disp/s (full-range-equivalent, HDP single pair)",
-        "value": N * (dmax + 1) / t_hdp / 1e6,
-        "unit": "Mpix*disp/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": t_hdp * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "single pair 1344x1104, labels 0..255, HDP L=3 S=2 w=4 beta=19/20",
-                   "global_batch": 1},
-        "full_range": {"ms_per_step": t_full * 1e3,
-                       "value": N * (dmax + 1) / t_full / 1e6,
-                       "speedup_hdp_over_full": t_full / t_hdp},
-        "hdp_algorithmic_entries": int(alg_entries),
-    }
+    if args.mode != "full":
+        # the timed step is a whole-step HIP graph replay (captured once)
+        step = hdp.CapturedStep(hdp_eager)
+        t_hdp = timed(step.replay, args.steps, args.warmup)
+        res = hdp_eager()
+        torch.cuda.synchronize()
+        alg = sum(r.forest.n * r.forest.width for r in res)
+        out["value"] = N * (dmax + 1) / t_hdp / 1e6
+        out["ms_per_step"] = t_hdp * 1e3
+        out["hdp_algorithmic"] = {"entries_per_step": int(alg),
+                                  "Mpix_disp_per_s": alg / t_hdp / 1e6,
+                                  "search_ratio_vs_full": alg / (N * (dmax + 1))}
+        # roofline of the dominant kernel: the aggregation passes (eager runs of
+        # the same step; HIP events around every pass launch on its stream)
+        rl = {}
+        for cls, up in (("up_pass", True), ("down_pass", False)):
+            reps = 5
+            hdp.timer_arm(cls)
+            for _ in range(reps):
+                r = hdp_eager()
+            ms, launches = hdp.timer_read()
+            hdp.timer_arm(None)
+            byts = reps * sum(pass_bytes(x.forest, up) for x in r)
+            rl[cls] = (byts, ms * 1e-3, launches)
+        byts = sum(v[0] for v in rl.values())
+        secs = sum(v[1] for v in rl.values())
+        launches = sum(v[2] for v in rl.values())
+        achieved = byts / secs / 1e9
+        out["roofline"] = {"kernel": "k_pass (two-pass aggregation, up and down)",
+                           "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "launches": launches, "avg_launch_us": secs / launches * 1e6,
+                           "algorithmic_bytes_per_launch": byts / launches}
+        del step
+
+    if args.mode != "hdp":
+        fstep = hdp.CapturedStep(full_eager)
+        t_full = timed(fstep.replay, max(2, args.steps // 4), 1)
+        out["full_range"] = {"ms_per_step": t_full * 1e3,
+                             "value": N * (dmax + 1) / t_full / 1e6}
+        if args.mode == "both":
+            out["full_range"]["speedup_hdp_over_full"] = t_full / (out["ms_per_step"] * 1e-3)
+        del fstep
+
+    if not args.no_cpu_baseline and args.mode == "both":
+        from oracle import oracle
+        t0 = time.perf_counter()
+        oracle.hdp_stereo(pair.left, pair.right, dmax, S=P["S"], L=P["L"], window=P["window"],
+                          beta=P["beta"])
+        t_cpu = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": N * (dmax + 1) / t_cpu / 1e6, "unit": "Mpix*disp/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "one whole HDP step of the same 1344x1104 pair "
+                                         "(FP64, single-threaded C)",
+                               "seconds": t_cpu,
+                               "host_cores_available": len(os.sched_getaffinity(0))}
     print(json.dumps(out))
 
 

@@ -174,7 +174,9 @@ HDP_API hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int
                           int32_t width, const hdp_forest *f, void *ws, size_t ws_bytes,
                           void *stream);
 
-/* Host copy of the forest's phase table and scalars (synchronises `stream`). */
+/* Host copy of the forest's scalars and phase table (synchronises `stream`;
+ * diagnostics only, nothing on the hot path needs it).  Either pointer may be
+ * NULL; phase_ptr_host receives HDP_MAX_PHASES + 1 entries. */
 HDP_API hdp_status hdp_forest_read_info(const hdp_forest *f, int32_t *info_host,
                                 int32_t *phase_ptr_host, void *stream);
 
@@ -202,32 +204,35 @@ HDP_API size_t hdp_aggregate_workspace_bytes(int64_t n, int32_t width);
  * Tree aggregation (eq. W, eq. S, eq. C):
  *   agg(v, x) = sum over u in the tree of v of exp(-W(v,u)/sigma) * cost(u, x)
  * with W the sum of edge weights on the tree path, computed exactly by a
- * leaf-to-root and a root-to-leaf pass over the forest's chain phases.
- *   cost, agg   float[n][width] in the forest's volume layout.
+ * leaf-to-root and a root-to-leaf pass over the forest's chain phases (two
+ * kernel launches; the phase table is read on the device, so the call never
+ * synchronises with the host and can be captured in a HIP graph).
+ *   cost, agg   float[n][width] in the forest's volume layout; width as given
+ *               to hdp_build_tree (n * width < 2^31).
  *   up          optional (NULL) float[n][width]: receives the leaf-to-root
  *               sums U(v, x) = cost(v,x) + sum_children s_c U(c,x), which
  *               hdp_aggregate_backward can reuse instead of recomputing.
- *   phase_ptr_host / n_phases  the forest's phase table on the HOST (from
- *               hdp_forest_read_info).
+ *   sigma       > 0, the smoothing constant (sigma of eq. aggre / gamma of eq. S).
+ * Internal consistency failures (never expected) set info[HDP_INFO_ERROR].
  */
-HDP_API hdp_status hdp_aggregate(const hdp_forest *f, int32_t width, const int32_t *phase_ptr_host,
-                         int32_t n_phases, const float *cost, float sigma, float *agg,
-                         float *up, void *ws, size_t ws_bytes, void *stream);
+HDP_API hdp_status hdp_aggregate(const hdp_forest *f, int32_t width, const float *cost,
+                                 float sigma, float *agg, float *up, void *ws, size_t ws_bytes,
+                                 void *stream);
 
 /*
  * Adjoint of hdp_aggregate for L = sum g(v,x) agg(v,x), g = grad_agg:
  *   grad_cost = A^T g = A g (the aggregation operator is symmetric),
- *   grad_w[v] = dL/dw of the edge (v, parent(v)) (0 at roots; NULL skips),
+ *   grad_w[v] = dL/dw of the edge (v, parent(v)) in pixel order (0 at roots;
+ *               NULL skips),
  *   grad_sigma (device, 1 float; NULL skips) = dL/dsigma.
  * cost/agg are the forward's input and output; up = the forward's U or NULL
- * (then it is recomputed).  Same layout and phase table as hdp_aggregate.
+ * (then it is recomputed from cost).  Same layout as hdp_aggregate.
  */
-HDP_API hdp_status hdp_aggregate_backward(const hdp_forest *f, int32_t width,
-                                  const int32_t *phase_ptr_host, int32_t n_phases,
-                                  const float *cost, const float *agg, const float *up,
-                                  const float *grad_agg, float sigma, float *grad_cost,
-                                  float *grad_w, float *grad_sigma, void *ws, size_t ws_bytes,
-                                  void *stream);
+HDP_API hdp_status hdp_aggregate_backward(const hdp_forest *f, int32_t width, const float *cost,
+                                          const float *agg, const float *up,
+                                          const float *grad_agg, float sigma, float *grad_cost,
+                                          float *grad_w, float *grad_sigma, void *ws,
+                                          size_t ws_bytes, void *stream);
 
 /*
  * Winner-takes-all (Section 3.3): disp[v] = the label of least aggregated cost
@@ -251,6 +256,17 @@ HDP_API hdp_status hdp_predict_range(const int32_t *disp_upper, const hdp_shape 
                              int32_t window, int32_t *pix_lo, int32_t *pix_hi, void *stream);
 
 HDP_API const char *hdp_status_str(hdp_status s);
+
+/*
+ * Diagnostics (not for use under graph capture): time every launch of one
+ * kernel class with a pair of HIP events recorded on the launch's stream.
+ * hdp_timer_arm(c) selects class c (or -1: off) and clears the record (at most
+ * 1024 launches are kept); hdp_timer_read waits for the recorded events and
+ * returns the summed kernel time in milliseconds and the number of launches.
+ */
+enum { HDP_TIMER_UP_PASS = 0, HDP_TIMER_DOWN_PASS = 1, HDP_TIMER_COST = 2 };
+HDP_API hdp_status hdp_timer_arm(int32_t kernel_class);
+HDP_API hdp_status hdp_timer_read(float *total_ms, int32_t *launches);
 
 #ifdef __cplusplus
 }

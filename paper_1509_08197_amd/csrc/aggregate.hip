@@ -11,13 +11,16 @@
 // decomposition, at most log2(n)+1 phases).  Along a heavy path both passes are
 // first-order linear recurrences with a scalar coefficient per row,
 //   up:   U_r = b_r + a_r U_{r+1},  a_r = s_{r+1} if row r+1 is r's heavy child
-//         b_r = C_r + sum over light children c of s_c U_c (earlier phase)
+//         b_r = C_r + sum over light children c of s_c U_c (previous phase)
 //   down: A_r = a_r A_{r-1} + b_r,  a_r = s_r if r is a heavy child
 //         b_r = (1 - s_r^2) U_r + (r heads a chain ? s_r A_parent : 0)
-// and a zero coefficient ends a chain.  So each phase is ONE segmented scan of
-// affine maps over a contiguous range of rows, independent per label column:
-// tile reduce -> carry scan over tiles -> tile apply.  Rows are row-major
-// [row][width] (labels fastest); arithmetic is FP64 in registers, storage FP32.
+// and a zero coefficient ends a chain.  Each pass is ONE launch: tiles of
+// consecutive rows are taken in ticket order (phase by phase in scan order),
+// a tile waits only for the tiles that produced the previous-phase rows it
+// reads, and the carry of a chain that crosses tile boundaries comes from a
+// decoupled look-back over the preceding tiles' affine maps (64 tiles per
+// step).  Rows are row-major [row][width] (labels fastest); arithmetic is FP64
+// in registers, storage FP32.
 #include <cstdlib>
 
 #include "common.hpp"
@@ -25,20 +28,34 @@
 
 namespace hdp {
 
-constexpr int kRowsPerGroup = 8;
+constexpr int kRPG = 8;  // rows per thread group of a tile
 
-struct AggTileGeom {
-    int width;   // labels per row (<= 256)
-    int groups;  // row groups per tile = 256 / width
-    int rows;    // rows per tile = groups * kRowsPerGroup
+// Layout of the device-side pass plan (int32 words).
+enum {
+    P_NPH = 0,      // number of phases K
+    P_TOT_UP = 1,   // tiles of the up pass
+    P_TOT_DN = 2,   // tiles of the down pass
+    P_ROWS = 3,     // rows per tile
+    P_ROW0 = 4,     // [K+1] first row of phase k
+    P_T0UP = 48,    // [K+1] first ticket of the q-th phase processed by the up pass
+    P_T0DN = 96,    // [K+1] same for the down pass
+    P_WORDS = 144
 };
 
-static AggTileGeom tile_geom(int width) {
-    AggTileGeom t;
-    t.width = width;
-    t.groups = kBlock / width;
+struct TileGeom {
+    int cpt;     // labels per thread (4, 2 or 1)
+    int lpr;     // threads per row
+    int groups;  // row groups per tile
+    int rows;    // rows per tile
+};
+
+static TileGeom tile_geom(int width) {
+    TileGeom t;
+    t.cpt = (width >= 64 && width % 4 == 0) ? 4 : (width % 2 == 0 && width >= 8) ? 2 : 1;
+    t.lpr = (width + t.cpt - 1) / t.cpt;
+    t.groups = kBlock / t.lpr;
     if (t.groups < 1) t.groups = 1;
-    t.rows = t.groups * kRowsPerGroup;
+    t.rows = t.groups * kRPG;
     return t;
 }
 
@@ -56,230 +73,52 @@ __global__ void k_coef(int64_t n, const float *__restrict__ rw, const int32_t *_
     }
 }
 
+// Ticket layout of both passes from the forest's phase table.
+__global__ void k_make_plan(const int32_t *__restrict__ phase_ptr, const int32_t *__restrict__ info,
+                            int rows, int32_t *__restrict__ plan) {
+    if (threadIdx.x != 0) return;
+    int K = info[HDP_INFO_N_PHASES];
+    if (K < 1) K = 1;
+    if (K > HDP_MAX_PHASES) K = HDP_MAX_PHASES;
+    plan[P_NPH] = K;
+    plan[P_ROWS] = rows;
+    for (int k = 0; k <= K; ++k) plan[P_ROW0 + k] = phase_ptr[k];
+    int tu = 0, td = 0;
+    for (int q = 0; q < K; ++q) {
+        int ku = K - 1 - q;
+        plan[P_T0UP + q] = tu;
+        tu += (phase_ptr[ku + 1] - phase_ptr[ku] + rows - 1) / rows;
+        plan[P_T0DN + q] = td;
+        td += (phase_ptr[q + 1] - phase_ptr[q] + rows - 1) / rows;
+    }
+    plan[P_T0UP + K] = tu;
+    plan[P_T0DN + K] = td;
+    plan[P_TOT_UP] = tu;
+    plan[P_TOT_DN] = td;
+}
+
 struct PassArgs {
-    int64_t n;
-    int32_t r0, r1;          // rows of the phase
-    int width;
-    int rows;                // rows per tile
-    int groups;
-    int ntiles;
+    int n;
+    int width, lpr, groups, rows;
     const double *s, *om;
     const uint8_t *heavy;
-    const int32_t *prow;
-    const int32_t *lc;       // [3][n]
-    const float *src;        // up: cost C;  down: U
-    const float *aux;        // up: U (light children, earlier phase);  down: A (parents)
-    float *dst;              // up: U;  down: A
-    double *Pt, *Xt, *Ct;    // per tile: coefficient product, zero-input result, carry-in
-};
-
-// Coefficient of row r: zero where a chain starts (scan order), so the value
-// carried in from the previous row is dropped there.
-template <bool UP>
-__device__ __forceinline__ double row_coef(const PassArgs &A, int64_t r) {
-    if (UP) return (r + 1 < A.r1 && A.heavy[r + 1]) ? A.s[r + 1] : 0.0;
-    return A.heavy[r] ? A.s[r] : 0.0;
-}
-
-// Constant term of row r for column j.
-template <bool UP>
-__device__ __forceinline__ double row_b(const PassArgs &A, int64_t r, int j) {
-    if (UP) {
-        double x = (double)A.src[r * A.width + j];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            int c = A.lc[(int64_t)k * A.n + r];
-            if (c >= 0) x += A.s[c] * (double)A.aux[(int64_t)c * A.width + j];
-        }
-        return x;
-    }
-    double x = A.om[r] * (double)A.src[r * A.width + j];
-    int p = A.prow[r];
-    if (!A.heavy[r] && p >= 0) x += A.s[r] * (double)A.aux[(int64_t)p * A.width + j];
-    return x;
-}
-
-// Physical row of logical position li of tile t (logical order = scan order).
-template <bool UP>
-__device__ __forceinline__ int64_t tile_row(const PassArgs &A, int t, int li) {
-    return UP ? (int64_t)A.r1 - 1 - ((int64_t)t * A.rows + li) : (int64_t)A.r0 + (int64_t)t * A.rows + li;
-}
-
-// Tile reduce: the affine map of the whole tile applied to 0 (X) and the
-// product of its coefficients (P).  Only the rows after the tile's last chain
-// start matter for X (the coefficient there is 0), so only those are read.
-template <bool UP>
-__global__ void __launch_bounds__(kBlock) k_tile_reduce(PassArgs A) {
-    __shared__ double sP[kBlock];
-    __shared__ double sX[kBlock];
-    __shared__ int sZ[kBlock];
-    int t = blockIdx.x;
-    if (t >= A.ntiles) return;
-    int tid = threadIdx.x;
-    int g = tid / A.width, j = tid - g * A.width;
-    bool active = g < A.groups;
-    double av[kRowsPerGroup];
-    double P = 1.0;
-    int z = -1;
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < kRowsPerGroup; ++i) {
-            int li = g * kRowsPerGroup + i;
-            int64_t r = tile_row<UP>(A, t, li);
-            bool in = UP ? r >= A.r0 : r < A.r1;
-            double a = in ? row_coef<UP>(A, r) : 1.0;
-            av[i] = a;
-            P = a * P;
-            if (a == 0.0) z = li;
-        }
-    }
-    sZ[tid] = z;
-    __syncthreads();
-    int zt = -1;
-    for (int q = 0; q < A.groups; ++q) {
-        int zq = sZ[q * A.width];
-        zt = zq > zt ? zq : zt;
-    }
-    double X = 0.0;
-    if (active && g * kRowsPerGroup + kRowsPerGroup - 1 >= zt) {
-#pragma unroll
-        for (int i = 0; i < kRowsPerGroup; ++i) {
-            int li = g * kRowsPerGroup + i;
-            int64_t r = tile_row<UP>(A, t, li);
-            bool in = UP ? r >= A.r0 : r < A.r1;
-            if (in && li >= zt) X = av[i] * X + row_b<UP>(A, r, j);
-        }
-    }
-    sP[tid] = P;
-    sX[tid] = X;
-    __syncthreads();
-    if (active && g == 0) {
-        double Pc = 1.0, Xc = 0.0;
-        for (int q = 0; q < A.groups; ++q) {
-            double pq = sP[q * A.width + j], xq = sX[q * A.width + j];
-            Xc = pq * Xc + xq;
-            Pc = pq * Pc;
-        }
-        A.Xt[(int64_t)t * A.width + j] = Xc;
-        if (j == 0) A.Pt[t] = Pc;
-    }
-}
-
-// Tile apply: outputs of the tile from its carry-in.
-template <bool UP>
-__global__ void __launch_bounds__(kBlock) k_tile_apply(PassArgs A) {
-    __shared__ double sP[kBlock];
-    __shared__ double sX[kBlock];
-    int t = blockIdx.x;
-    if (t >= A.ntiles) return;
-    int tid = threadIdx.x;
-    int g = tid / A.width, j = tid - g * A.width;
-    bool active = g < A.groups;
-    double av[kRowsPerGroup], bv[kRowsPerGroup];
-    int64_t rr[kRowsPerGroup];
-    double P = 1.0, X = 0.0;
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < kRowsPerGroup; ++i) {
-            int li = g * kRowsPerGroup + i;
-            int64_t r = tile_row<UP>(A, t, li);
-            bool in = UP ? r >= A.r0 : r < A.r1;
-            rr[i] = in ? r : -1;
-            double a = 1.0, b = 0.0;  // identity map past the end of the phase
-            if (in) {
-                a = row_coef<UP>(A, r);
-                b = row_b<UP>(A, r, j);
-            }
-            av[i] = a;
-            bv[i] = b;
-            X = a * X + b;
-            P = a * P;
-        }
-    }
-    sP[tid] = P;
-    sX[tid] = X;
-    __syncthreads();
-    if (!active) return;
-    double c = A.Ct[(int64_t)t * A.width + j];
-    for (int q = 0; q < g; ++q) c = sP[q * A.width + j] * c + sX[q * A.width + j];
-#pragma unroll
-    for (int i = 0; i < kRowsPerGroup; ++i) {
-        c = av[i] * c + bv[i];
-        if (rr[i] >= 0) A.dst[rr[i] * A.width + j] = (float)c;
-    }
-}
-
-// Carry-in of every tile, one workgroup per label column: exclusive scan of
-// the tiles' affine maps (composition in scan order), starting from 0.
-__global__ void __launch_bounds__(kBlock) k_carry(PassArgs A) {
-    __shared__ double sP[kBlock];
-    __shared__ double sX[kBlock];
-    int j = blockIdx.x;
-    int tid = threadIdx.x;
-    int chunk = (A.ntiles + kBlock - 1) / kBlock;
-    int t0 = tid * chunk, t1 = t0 + chunk < A.ntiles ? t0 + chunk : A.ntiles;
-    double P = 1.0, X = 0.0;
-    for (int t = t0; t < t1; ++t) {
-        double p = A.Pt[t];
-        X = p * X + A.Xt[(int64_t)t * A.width + j];
-        P = p * P;
-    }
-    sP[tid] = P;
-    sX[tid] = X;
-    __syncthreads();
-    // inclusive Hillis-Steele scan of maps: combine(earlier e, later l) = (l.P e.P, l.P e.X + l.X)
-    for (int off = 1; off < kBlock; off <<= 1) {
-        double pe = 1.0, xe = 0.0;
-        if (tid >= off) { pe = sP[tid - off]; xe = sX[tid - off]; }
-        __syncthreads();
-        if (tid >= off) {
-            double pl = sP[tid], xl = sX[tid];
-            sP[tid] = pl * pe;
-            sX[tid] = pl * xe + xl;
-        }
-        __syncthreads();
-    }
-    double c = tid > 0 ? sX[tid - 1] : 0.0;
-    for (int t = t0; t < t1; ++t) {
-        A.Ct[(int64_t)t * A.width + j] = c;
-        c = A.Pt[t] * c + A.Xt[(int64_t)t * A.width + j];
-    }
-}
-
-// ---------------------------------------------------------------------------------
-// Single-launch pass.  Tiles of all phases are taken in ticket order (phase by
-// phase in scan order, tiles in scan order inside a phase).  A tile only waits
-// for tiles with smaller tickets, which are already running, so the launch
-// always drains:
-//   - before reading rows of the previous phase (light children's U in the up
-//     pass, parents' A in the down pass) it waits for that phase's completion
-//     counter;
-//   - its carry-in (a chain that crosses the tile boundary) comes from a
-//     decoupled look-back over the preceding tiles' published maps.
-// Every wait is bounded; on timeout an error word is set and the pass goes on
-// (wrong values, never a hang).
-
-struct PassPlan {
-    int n_phases;
-    int total_tiles;
-    int32_t row0[HDP_MAX_PHASES + 1];   // rows of phase k: row0[k] .. row0[k+1]-1
-    int32_t tile0[HDP_MAX_PHASES + 1];  // first ticket of the q-th processed phase
-};
-
-struct PassSync {
-    int32_t *ticket;   // [1]
-    int32_t *done;     // [HDP_MAX_PHASES] completed tiles per processed phase
-    int32_t *flag;     // [tiles] 0 nothing, 1 map published, 2 final value published
-    double *tP;        // [tiles] product of the tile's coefficients
-    double *tX;        // [tiles][width] tile map applied to 0
-    double *tI;        // [tiles][width] value after the tile's last row
-    int32_t *err;      // nonzero: a bounded wait timed out
+    const int32_t *prow, *lc;
+    const float *src;    // up: cost C;  down: U
+    float *dst;          // up: U;  down: A  (rows of the previous phase are read back from it)
+    const int32_t *plan;
+    int32_t *ticket;     // [1]
+    int32_t *flag;       // [tiles] 0 nothing, 1 map published, 2 final value published
+    int32_t *flagw;      // [tiles] 1 once the tile's rows are stored
+    double *tP;          // [tiles] product of the tile's coefficients
+    double *tX;          // [tiles][width] tile map applied to 0
+    double *tI;          // [tiles][width] value after the tile's last row
+    int32_t *err;        // nonzero: a bounded wait timed out / inconsistent input
 };
 
 // Data that crosses workgroups inside one launch (published tile maps, rows of
 // the previous phase, flags) is read and written with device-scope relaxed
-// atomics (device-coherent loads/stores); a publisher waits for its stores to
-// complete before it raises the flag.  No cache-wide flush or invalidate is
+// atomics (device-coherent loads and stores); a publisher waits for its stores
+// to complete before it raises a flag.  No cache-wide flush or invalidate is
 // issued.
 template <typename T>
 __device__ __forceinline__ T ld_dev(const T *p) {
@@ -293,188 +132,310 @@ __device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0
 
 constexpr int64_t kSpinLimit = int64_t(1) << 24;
 
-// Bounded wait (one lane) until *p >= target.
-__device__ void wait_at_least(const int32_t *p, int32_t target, int32_t *err, int code) {
+__device__ __forceinline__ int wait_nonzero(const int32_t *p, int32_t *err, int code) {
+    int f = ld_dev(p);
     int64_t it = 0;
-    while (ld_dev(p) < target) {
-        __builtin_amdgcn_s_sleep(2);
+    while (f == 0) {
+        __builtin_amdgcn_s_sleep(1);
+        f = ld_dev(p);
         if (++it > kSpinLimit) {
             atomicMax(err, code);
-            break;
+            return 2;
+        }
+    }
+    return f;
+}
+
+// CPT consecutive labels of one row: plain vector load (data of an earlier launch).
+template <int CPT>
+__device__ __forceinline__ void load_cols(const float *p, float *v) {
+    if (CPT == 4) {
+        float4 x = *reinterpret_cast<const float4 *>(p);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    } else if (CPT == 2) {
+        float2 x = *reinterpret_cast<const float2 *>(p);
+        v[0] = x.x; v[1] = x.y;
+    } else {
+        v[0] = *p;
+    }
+}
+
+// Device-coherent load / store of CPT consecutive labels (64-bit words).
+template <int CPT>
+__device__ __forceinline__ void load_cols_dev(const float *p, float *v) {
+    if (CPT == 1) {
+        v[0] = ld_dev(p);
+    } else {
+#pragma unroll
+        for (int h = 0; h < CPT / 2; ++h) {
+            uint64_t u = ld_dev(reinterpret_cast<const uint64_t *>(p) + h);
+            v[2 * h] = __uint_as_float((uint32_t)u);
+            v[2 * h + 1] = __uint_as_float((uint32_t)(u >> 32));
         }
     }
 }
 
-__global__ void k_pass_init(PassSync sy, int total_tiles) {
-    int64_t i = gtid();
-    if (i < total_tiles) sy.flag[i] = 0;
-    if (i < HDP_MAX_PHASES) sy.done[i] = 0;
-    if (i == 0) sy.ticket[0] = 0;
+template <int CPT>
+__device__ __forceinline__ void store_cols_dev(float *p, const double *c) {
+    if (CPT == 1) {
+        st_dev(p, (float)c[0]);
+    } else {
+#pragma unroll
+        for (int h = 0; h < CPT / 2; ++h) {
+            uint64_t u = (uint64_t)__float_as_uint((float)c[2 * h]) |
+                         ((uint64_t)__float_as_uint((float)c[2 * h + 1]) << 32);
+            st_dev(reinterpret_cast<uint64_t *>(p) + h, u);
+        }
+    }
 }
 
-template <bool UP>
-__global__ void __launch_bounds__(kBlock) k_agg_pass(PassArgs A, PassPlan pl, PassSync sy) {
+template <bool UP, int CPT>
+__global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
     __shared__ double sP[kBlock];
-    __shared__ double sX[kBlock];
-    __shared__ int s_ticket, s_flag;
+    __shared__ double sX[kBlock * CPT];
+    __shared__ int s_ticket;
+    __shared__ int s_win[64];
     __shared__ double s_first;
     const int tid = threadIdx.x;
-    if (tid == 0) s_ticket = atomicAdd(sy.ticket, 1);
+    if (tid == 0) s_ticket = atomicAdd(A.ticket, 1);
     __syncthreads();
     const int T = s_ticket;
-    if (T >= pl.total_tiles) return;
+    const int K = A.plan[P_NPH];
+    const int total = A.plan[UP ? P_TOT_UP : P_TOT_DN];
+    if (T >= total) return;
+    const int32_t *t0 = A.plan + (UP ? P_T0UP : P_T0DN);
+    const int32_t *row0 = A.plan + P_ROW0;
     int q = 0;
-    while (q + 1 < pl.n_phases && pl.tile0[q + 1] <= T) ++q;
-    const int k = UP ? pl.n_phases - 1 - q : q;
-    const int tl = T - pl.tile0[q];
-    A.r0 = pl.row0[k];
-    A.r1 = pl.row0[k + 1];
-    const int g = tid / A.width, j = tid - g * A.width;
+    while (q + 1 < K && t0[q + 1] <= T) ++q;
+    const int k = UP ? K - 1 - q : q;
+    const int tl = T - t0[q];
+    const int r0 = row0[k], r1 = row0[k + 1];
+    // the previous processed phase produced the rows gathered below
+    const int kp = UP ? k + 1 : k - 1;
+    const int pr0 = q > 0 ? row0[kp] : 0, pr1 = q > 0 ? row0[kp + 1] : 0;
+    const int pt0 = q > 0 ? t0[q - 1] : 0, pt1 = t0[q];
+    const int w = A.width, rows = A.rows;
+    const int g = tid / A.lpr, jl = tid - g * A.lpr;
+    const int j0 = jl * CPT;
     const bool active = g < A.groups;
-    const int w = A.width;
 
-    // stage 1: loads that do not depend on other tiles
-    double av[kRowsPerGroup], bv[kRowsPerGroup];
-    int32_t rr[kRowsPerGroup];
-    int32_t x0[kRowsPerGroup], x1[kRowsPerGroup], x2[kRowsPerGroup];
-    if (active) {
+    // stage 1: loads that do not depend on other tiles of this launch
+    double av[kRPG];
+    double bv[kRPG][CPT];
+    int rr[kRPG], x0[kRPG], x1[kRPG], x2[kRPG];
 #pragma unroll
-        for (int i = 0; i < kRowsPerGroup; ++i) {
-            int li = g * kRowsPerGroup + i;
-            int r = UP ? A.r1 - 1 - (tl * A.rows + li) : A.r0 + tl * A.rows + li;
-            bool in = UP ? r >= A.r0 : r < A.r1;
-            rr[i] = in ? r : -1;
-            av[i] = 1.0;
-            bv[i] = 0.0;
-            x0[i] = x1[i] = x2[i] = -1;
-            if (!in) continue;
-            av[i] = row_coef<UP>(A, r);
-            if (UP) {
-                bv[i] = (double)A.src[r * w + j];
-                x0[i] = A.lc[r];
-                x1[i] = A.lc[(int)A.n + r];
-                x2[i] = A.lc[2 * (int)A.n + r];
-            } else {
-                bv[i] = A.om[r] * (double)A.src[r * w + j];
-                x0[i] = A.heavy[r] ? -1 : A.prow[r];
-            }
+    for (int i = 0; i < kRPG; ++i) {
+        int li = g * kRPG + i;
+        int r = UP ? r1 - 1 - (tl * rows + li) : r0 + tl * rows + li;
+        bool in = active && (UP ? r >= r0 : r < r1);
+        rr[i] = in ? r : -1;
+        av[i] = 1.0;
+        x0[i] = x1[i] = x2[i] = -1;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) bv[i][c] = 0.0;
+        if (!in) continue;
+        float v[CPT];
+        load_cols<CPT>(A.src + (int64_t)r * w + j0, v);
+        if (UP) {
+            av[i] = (r + 1 < r1 && A.heavy[r + 1]) ? A.s[r + 1] : 0.0;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) bv[i][c] = (double)v[c];
+            x0[i] = A.lc[r];
+            x1[i] = A.lc[A.n + r];
+            x2[i] = A.lc[2 * A.n + r];
+        } else {
+            bool hv = A.heavy[r];
+            av[i] = hv ? A.s[r] : 0.0;
+            double o = A.om[r];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) bv[i][c] = o * (double)v[c];
+            x0[i] = hv ? -1 : A.prow[r];
         }
     }
-    // the previous phase must be complete before its rows are read
-    if (q > 0) {
-        if (tid == 0) wait_at_least(&sy.done[q - 1], pl.tile0[q] - pl.tile0[q - 1], sy.err, 16);
-        __syncthreads();
-    }
-    // stage 2: rows of the previous phase (light children / parent)
-    double P = 1.0, X = 0.0;
-    if (active) {
-#pragma unroll
-        for (int i = 0; i < kRowsPerGroup; ++i) {
-            if (UP) {
-                if (x0[i] >= 0) bv[i] += A.s[x0[i]] * (double)ld_dev(&A.aux[x0[i] * w + j]);
-                if (x1[i] >= 0) bv[i] += A.s[x1[i]] * (double)ld_dev(&A.aux[x1[i] * w + j]);
-                if (x2[i] >= 0) bv[i] += A.s[x2[i]] * (double)ld_dev(&A.aux[x2[i] * w + j]);
-            } else if (x0[i] >= 0) {
-                bv[i] += A.s[rr[i]] * (double)ld_dev(&A.aux[x0[i] * w + j]);
-            }
-            X = av[i] * X + bv[i];
-            P = av[i] * P;
+
+    // stage 2: wait for the producing tiles of the gathered rows, then gather
+    auto wait_row = [&](int x) {
+        if (x < 0) return;
+        if (x < pr0 || x >= pr1) {  // not in the previous phase: inconsistent forest
+            atomicMax(A.err, 18);
+            return;
         }
+        int tk = pt0 + (UP ? (pr1 - 1 - x) / rows : (x - pr0) / rows);
+        if (tk >= pt0 && tk < pt1) wait_nonzero(&A.flagw[tk], A.err, 16);
+    };
+#pragma unroll
+    for (int i = 0; i < kRPG; ++i) {
+        wait_row(x0[i]);
+        if (UP) {
+            wait_row(x1[i]);
+            wait_row(x2[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kRPG; ++i) {
+        float v[CPT];
+        if (UP) {
+            if (x0[i] >= 0) {
+                double sc = A.s[x0[i]];
+                load_cols_dev<CPT>(A.dst + (int64_t)x0[i] * w + j0, v);
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
+            }
+            if (x1[i] >= 0) {
+                double sc = A.s[x1[i]];
+                load_cols_dev<CPT>(A.dst + (int64_t)x1[i] * w + j0, v);
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
+            }
+            if (x2[i] >= 0) {
+                double sc = A.s[x2[i]];
+                load_cols_dev<CPT>(A.dst + (int64_t)x2[i] * w + j0, v);
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
+            }
+        } else if (x0[i] >= 0) {
+            double sc = A.s[rr[i]];
+            load_cols_dev<CPT>(A.dst + (int64_t)x0[i] * w + j0, v);
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
+        }
+    }
+
+    // map of this thread's rows, then of the whole tile
+    double P = 1.0, X[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) X[c] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kRPG; ++i) {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) X[c] = av[i] * X[c] + bv[i][c];
+        P *= av[i];
     }
     if (tid == 0) s_first = av[0];
     sP[tid] = P;
-    sX[tid] = X;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) sX[tid * CPT + c] = X[c];
     __syncthreads();
-    // map of the whole tile for column j (P is the same in every column)
-    double Pt = 1.0, Xt = 0.0;
+    double Pt = 1.0, Xt[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) Xt[c] = 0.0;
     if (active) {
         for (int q2 = 0; q2 < A.groups; ++q2) {
-            double pq = sP[q2 * A.width + j];
-            Xt = pq * Xt + sX[q2 * A.width + j];
-            Pt = pq * Pt;
+            int o = q2 * A.lpr + jl;
+            double pq = sP[o];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) Xt[c] = pq * Xt[c] + sX[o * CPT + c];
+            Pt *= pq;
         }
     }
     const bool incl_now = tl == 0 || Pt == 0.0;
     if (active && g == 0) {
-        if (incl_now) {
-            st_dev(&sy.tI[T * w + j], Xt);
-        } else {
-            st_dev(&sy.tX[T * w + j], Xt);
-            if (j == 0) st_dev(&sy.tP[T], Pt);
-        }
+        double *dstp = incl_now ? A.tI : A.tX;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) st_dev(&dstp[(int64_t)T * w + j0 + c], Xt[c]);
+        if (!incl_now && jl == 0) st_dev(&A.tP[T], Pt);
     }
     stores_complete();
     __syncthreads();
-    if (tid == 0) st_dev(&sy.flag[T], incl_now ? 2 : 1);
+    if (tid == 0) st_dev(&A.flag[T], incl_now ? 2 : 1);
 
-    // carry-in (decoupled look-back), needed when the first row continues a chain
-    double carry = 0.0;
+    // carry-in by decoupled look-back, 64 predecessors per step
+    double carry[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) carry[c] = 0.0;
     if (tl > 0 && s_first != 0.0) {
-        double mP = 1.0, mX = 0.0;
-        int kk = T - 1;
+        double mP = 1.0, mX[CPT];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) mX[c] = 0.0;
+        const int lim = t0[q];
+        int base = T - 1;
         for (;;) {
-            if (tid == 0) {
-                int64_t it = 0;
-                int f;
-                while ((f = ld_dev(&sy.flag[kk])) == 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++it > kSpinLimit) {
-                        atomicMax(sy.err, 17);
-                        f = 2;
-                        break;
-                    }
-                }
-                s_flag = f;
-            }
+            int cnt = base - lim + 1;
+            cnt = cnt < 64 ? cnt : 64;
+            if (tid < cnt) s_win[tid] = wait_nonzero(&A.flag[base - tid], A.err, 17);
             __syncthreads();
-            int f = s_flag;
-            if (f == 2) {
-                if (active) carry = mP * ld_dev(&sy.tI[kk * w + j]) + mX;
+            int m = -1;
+            for (int L = 0; L < cnt; ++L)
+                if (s_win[L] == 2) { m = L; break; }
+            int upto = m >= 0 ? m : cnt;
+            if (active) {
+                for (int L = 0; L < upto; ++L) {
+                    int tk = base - L;
+                    double pk = ld_dev(&A.tP[tk]);
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c)
+                        mX[c] = mP * ld_dev(&A.tX[(int64_t)tk * w + j0 + c]) + mX[c];
+                    mP *= pk;
+                }
+                if (m >= 0) {
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c)
+                        carry[c] = mP * ld_dev(&A.tI[(int64_t)(base - m) * w + j0 + c]) + mX[c];
+                }
+            }
+            if (m >= 0) break;
+            base -= cnt;
+            __syncthreads();
+            if (base < lim) {  // a phase's first tile always publishes its value
+                atomicMax(A.err, 19);
                 break;
             }
-            if (active) {
-                double pk = ld_dev(&sy.tP[kk]);
-                mX = mP * ld_dev(&sy.tX[kk * w + j]) + mX;
-                mP = mP * pk;
-            }
-            --kk;
-            __syncthreads();
-            if (kk < pl.tile0[q]) break;  // unreachable: a phase's first tile publishes its value
         }
     }
 
     // apply and store
     if (active) {
-        double c = carry;
-        for (int q2 = 0; q2 < g; ++q2) c = sP[q2 * A.width + j] * c + sX[q2 * A.width + j];
+        double cv[CPT];
 #pragma unroll
-        for (int i = 0; i < kRowsPerGroup; ++i) {
-            c = av[i] * c + bv[i];
-            if (rr[i] >= 0) st_dev(&A.dst[rr[i] * w + j], (float)c);
+        for (int c = 0; c < CPT; ++c) cv[c] = carry[c];
+        for (int q2 = 0; q2 < g; ++q2) {
+            int o = q2 * A.lpr + jl;
+            double pq = sP[o];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) cv[c] = pq * cv[c] + sX[o * CPT + c];
         }
-        if (!incl_now && g == A.groups - 1) st_dev(&sy.tI[T * w + j], c);
+#pragma unroll
+        for (int i = 0; i < kRPG; ++i) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) cv[c] = av[i] * cv[c] + bv[i][c];
+            if (rr[i] >= 0) store_cols_dev<CPT>(A.dst + (int64_t)rr[i] * w + j0, cv);
+        }
+        if (!incl_now && g == A.groups - 1) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) st_dev(&A.tI[(int64_t)T * w + j0 + c], cv[c]);
+        }
     }
     stores_complete();
     __syncthreads();
     if (tid == 0) {
-        if (!incl_now) st_dev(&sy.flag[T], 2);
-        atomicAdd(&sy.done[q], 1);
+        if (!incl_now) st_dev(&A.flag[T], 2);
+        st_dev(&A.flagw[T], 1);
     }
+}
+
+__global__ void k_pass_init(int32_t *__restrict__ flag, int32_t *__restrict__ flagw,
+                            int32_t *__restrict__ ticket, int64_t tiles) {
+    int64_t i = gtid();
+    if (i < tiles) {
+        flag[i] = 0;
+        flagw[i] = 0;
+    }
+    if (i == 0) ticket[0] = 0;
 }
 
 // --- workspace --------------------------------------------------------------------
 
 struct AggWs {
-    int32_t *flag, *done, *ticket;
-    double *s, *om, *Pt, *Xt, *Ct;
+    int32_t *plan, *ticket, *flag, *flagw;
+    double *s, *om, *tP, *tX, *tI;
     float *up;      // U when the caller does not keep it
     float *ug;      // U of the gradient (backward)
     double *red;    // per-block partial sums (backward)
+    int64_t tiles;
 };
 
 static int64_t max_tiles(int64_t n, int width) {
-    AggTileGeom tg = tile_geom(width);
-    return n / tg.rows + HDP_MAX_PHASES + 2;
+    return n / tile_geom(width).rows + HDP_MAX_PHASES + 2;
 }
 
 static AggWs carve_agg_ws(void *ws, int64_t n, int width, size_t *bytes) {
@@ -488,14 +449,16 @@ static AggWs carve_agg_ws(void *ws, int64_t n, int width, size_t *bytes) {
     };
     int64_t nt = max_tiles(n, width);
     AggWs a;
-    a.flag = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * nt));
-    a.done = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * HDP_MAX_PHASES));
+    a.tiles = nt;
+    a.plan = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * P_WORDS));
     a.ticket = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * 4));
+    a.flag = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * nt));
+    a.flagw = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * nt));
     a.s = reinterpret_cast<double *>(take(sizeof(double) * n));
     a.om = reinterpret_cast<double *>(take(sizeof(double) * n));
-    a.Pt = reinterpret_cast<double *>(take(sizeof(double) * nt));
-    a.Xt = reinterpret_cast<double *>(take(sizeof(double) * nt * width));
-    a.Ct = reinterpret_cast<double *>(take(sizeof(double) * nt * width));
+    a.tP = reinterpret_cast<double *>(take(sizeof(double) * nt));
+    a.tX = reinterpret_cast<double *>(take(sizeof(double) * nt * width));
+    a.tI = reinterpret_cast<double *>(take(sizeof(double) * nt * width));
     a.up = reinterpret_cast<float *>(take(sizeof(float) * n * width));
     a.ug = reinterpret_cast<float *>(take(sizeof(float) * n * width));
     a.red = reinterpret_cast<double *>(take(sizeof(double) * (n / 4 + 64)));
@@ -509,95 +472,69 @@ size_t aggregate_workspace_bytes(int64_t n, int width) {
     return b;
 }
 
-template <bool UP>
-static void run_pass(PassArgs A, hipStream_t st) {
-    if (A.r1 <= A.r0) return;
-    A.ntiles = (int)(((int64_t)A.r1 - A.r0 + A.rows - 1) / A.rows);
-    k_tile_reduce<UP><<<A.ntiles, kBlock, 0, st>>>(A);
-    k_carry<<<A.width, kBlock, 0, st>>>(A);
-    k_tile_apply<UP><<<A.ntiles, kBlock, 0, st>>>(A);
-}
-
-static int schedule_mode() {
-    static int mode = -1;
-    if (mode < 0) {
-        const char *e = getenv("HDP_AGG_SCHEDULE");
-        mode = (e && e[0] == '3') ? 3 : 1;  // 1: one launch per pass, 3: three launches per phase
-    }
-    return mode;
+template <bool UP, int CPT>
+static void launch_pass(const PassArgs &A, const AggWs &w, hipStream_t st) {
+    k_pass_init<<<grid_for(w.tiles), kBlock, 0, st>>>(w.flag, w.flagw, w.ticket, w.tiles);
+    timer_before(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
+    k_pass<UP, CPT><<<(unsigned)w.tiles, kBlock, 0, st>>>(A);
+    timer_after(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
 }
 
 template <bool UP>
-static void run_pass_single(PassArgs A, const int32_t *phase_ptr, int n_phases, const AggWs &w,
-                            int32_t *err, hipStream_t st) {
-    PassPlan pl{};
-    pl.n_phases = n_phases;
-    int tot = 0;
-    for (int q = 0; q < n_phases; ++q) {
-        int k = UP ? n_phases - 1 - q : q;
-        int rows = phase_ptr[k + 1] - phase_ptr[k];
-        pl.tile0[q] = tot;
-        tot += (rows + A.rows - 1) / A.rows;
-    }
-    pl.tile0[n_phases] = tot;
-    for (int k = 0; k <= n_phases; ++k) pl.row0[k] = phase_ptr[k];
-    pl.total_tiles = tot;
-    if (tot == 0) return;
-    PassSync sy{w.ticket, w.done, w.flag, w.Pt, w.Xt, w.Ct, err};
-    int64_t init_n = tot > HDP_MAX_PHASES ? tot : HDP_MAX_PHASES;
-    k_pass_init<<<grid_for(init_n), kBlock, 0, st>>>(sy, tot);
-    k_agg_pass<UP><<<tot, kBlock, 0, st>>>(A, pl, sy);
+static void run_pass(const PassArgs &A, const AggWs &w, int cpt, hipStream_t st) {
+    if (cpt == 4) launch_pass<UP, 4>(A, w, st);
+    else if (cpt == 2) launch_pass<UP, 2>(A, w, st);
+    else launch_pass<UP, 1>(A, w, st);
 }
 
-// Two passes of `src` over the forest: U -> up, A -> out.
-static void two_pass(const hdp_forest &f, int width, const int32_t *phase_ptr, int n_phases,
-                     const float *src, float *up, float *out, const AggWs &w, hipStream_t st) {
-    AggTileGeom tg = tile_geom(width);
+static PassArgs pass_args(const hdp_forest &f, int width, const AggWs &w, const TileGeom &tg) {
     PassArgs A{};
-    A.n = f.n;
+    A.n = (int)f.n;
     A.width = width;
-    A.rows = tg.rows;
+    A.lpr = tg.lpr;
     A.groups = tg.groups;
+    A.rows = tg.rows;
     A.s = w.s;
     A.om = w.om;
     A.heavy = f.heavy;
     A.prow = f.prow;
     A.lc = f.lc;
-    A.Pt = w.Pt;
-    A.Xt = w.Xt;
-    A.Ct = w.Ct;
-    if (schedule_mode() == 1) {
-        A.src = src; A.aux = up; A.dst = up;
-        run_pass_single<true>(A, phase_ptr, n_phases, w, f.info + HDP_INFO_ERROR, st);
-        A.src = up; A.aux = out; A.dst = out;
-        run_pass_single<false>(A, phase_ptr, n_phases, w, f.info + HDP_INFO_ERROR, st);
-        return;
-    }
-    for (int k = n_phases - 1; k >= 0; --k) {
-        A.r0 = phase_ptr[k];
-        A.r1 = phase_ptr[k + 1];
-        A.src = src;
-        A.aux = up;
-        A.dst = up;
-        run_pass<true>(A, st);
-    }
-    for (int k = 0; k < n_phases; ++k) {
-        A.r0 = phase_ptr[k];
-        A.r1 = phase_ptr[k + 1];
-        A.src = up;
-        A.aux = out;
-        A.dst = out;
-        run_pass<false>(A, st);
-    }
+    A.plan = w.plan;
+    A.ticket = w.ticket;
+    A.flag = w.flag;
+    A.flagw = w.flagw;
+    A.tP = w.tP;
+    A.tX = w.tX;
+    A.tI = w.tI;
+    A.err = f.info + HDP_INFO_ERROR;
+    return A;
 }
 
-void launch_aggregate(const hdp_forest &f, int width, const int32_t *phase_ptr, int n_phases,
-                      const float *cost, float sigma, float *agg, float *up, void *ws,
-                      hipStream_t st) {
+// Coefficients and the plan of both passes (device side, no host sync).
+static void prologue(const hdp_forest &f, int width, float sigma, const AggWs &w, hipStream_t st) {
+    k_coef<<<grid_for(f.n), kBlock, 0, st>>>(f.n, f.rw, f.prow, 1.0 / (double)sigma, w.s, w.om);
+    k_make_plan<<<1, 64, 0, st>>>(f.phase_ptr, f.info, tile_geom(width).rows, w.plan);
+}
+
+// Two passes of `src` over the forest: U -> up, A -> out.
+static void two_pass(const hdp_forest &f, int width, const float *src, float *up, float *out,
+                     const AggWs &w, hipStream_t st) {
+    TileGeom tg = tile_geom(width);
+    PassArgs A = pass_args(f, width, w, tg);
+    A.src = src;
+    A.dst = up;
+    run_pass<true>(A, w, tg.cpt, st);
+    A.src = up;
+    A.dst = out;
+    run_pass<false>(A, w, tg.cpt, st);
+}
+
+void launch_aggregate(const hdp_forest &f, int width, const float *cost, float sigma, float *agg,
+                      float *up, void *ws, hipStream_t st) {
     size_t bytes;
     AggWs w = carve_agg_ws(ws, f.n, width, &bytes);
-    k_coef<<<grid_for(f.n), kBlock, 0, st>>>(f.n, f.rw, f.prow, 1.0 / (double)sigma, w.s, w.om);
-    two_pass(f, width, phase_ptr, n_phases, cost, up ? up : w.up, agg, w, st);
+    prologue(f, width, sigma, w, st);
+    two_pass(f, width, cost, up ? up : w.up, agg, w, st);
 }
 
 // --- adjoint ----------------------------------------------------------------------------
@@ -657,32 +594,23 @@ __global__ void k_sum_red(const double *__restrict__ red, int64_t nb, float *__r
     if (threadIdx.x == 0) *out = (float)sh[0];
 }
 
-void launch_aggregate_backward(const hdp_forest &f, int width, const int32_t *phase_ptr,
-                               int n_phases, const float *cost, const float *agg, const float *up,
-                               const float *grad_agg, float sigma, float *grad_cost, float *grad_w,
-                               float *grad_sigma, void *ws, hipStream_t st) {
+void launch_aggregate_backward(const hdp_forest &f, int width, const float *cost, const float *agg,
+                               const float *up, const float *grad_agg, float sigma,
+                               float *grad_cost, float *grad_w, float *grad_sigma, void *ws,
+                               hipStream_t st) {
     size_t bytes;
     AggWs w = carve_agg_ws(ws, f.n, width, &bytes);
-    k_coef<<<grid_for(f.n), kBlock, 0, st>>>(f.n, f.rw, f.prow, 1.0 / (double)sigma, w.s, w.om);
+    prologue(f, width, sigma, w, st);
     const float *uc = up;
-    if (!uc) {  // recompute the up pass of the cost (the down pass output is discarded)
-        AggTileGeom tg = tile_geom(width);
-        PassArgs A{};
-        A.n = f.n; A.width = width; A.rows = tg.rows; A.groups = tg.groups;
-        A.s = w.s; A.om = w.om; A.heavy = f.heavy; A.prow = f.prow; A.lc = f.lc;
-        A.Pt = w.Pt; A.Xt = w.Xt; A.Ct = w.Ct;
-        A.src = cost; A.aux = w.up; A.dst = w.up;
-        if (schedule_mode() == 1) {
-            run_pass_single<true>(A, phase_ptr, n_phases, w, f.info + HDP_INFO_ERROR, st);
-        } else {
-            for (int k = n_phases - 1; k >= 0; --k) {
-                A.r0 = phase_ptr[k]; A.r1 = phase_ptr[k + 1];
-                run_pass<true>(A, st);
-            }
-        }
+    if (!uc) {  // recompute the up pass of the cost
+        TileGeom tg = tile_geom(width);
+        PassArgs A = pass_args(f, width, w, tg);
+        A.src = cost;
+        A.dst = w.up;
+        run_pass<true>(A, w, tg.cpt, st);
         uc = w.up;
     }
-    two_pass(f, width, phase_ptr, n_phases, grad_agg, w.ug, grad_cost, w, st);
+    two_pass(f, width, grad_agg, w.ug, grad_cost, w, st);
     if (grad_w || grad_sigma) {
         int64_t nb = (f.n * 64 + kBlock - 1) / kBlock;
         k_edge_grad<<<(unsigned)nb, kBlock, 0, st>>>(f.n, width, f.prow, f.node, f.rw, w.s, uc, agg,

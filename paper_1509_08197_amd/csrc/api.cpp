@@ -9,6 +9,27 @@
 
 using hdp::LevelGeom;
 
+namespace hdp {
+namespace {
+constexpr int kTimerSlots = 1024;
+int g_timer_class = -1;
+int g_timer_n = 0;
+hipEvent_t g_ev[kTimerSlots][2];
+bool g_ev_made = false;
+}  // namespace
+
+void timer_before(int kernel_class, hipStream_t st) {
+    if (kernel_class != g_timer_class || g_timer_n >= kTimerSlots) return;
+    (void)hipEventRecord(g_ev[g_timer_n][0], st);
+}
+
+void timer_after(int kernel_class, hipStream_t st) {
+    if (kernel_class != g_timer_class || g_timer_n >= kTimerSlots) return;
+    (void)hipEventRecord(g_ev[g_timer_n][1], st);
+    ++g_timer_n;
+}
+}  // namespace hdp
+
 namespace {
 
 constexpr int64_t kMaxPixels = (int64_t(1) << 30);  // tour slots 4n fit in int32
@@ -225,43 +246,35 @@ size_t hdp_aggregate_workspace_bytes(int64_t n, int32_t width) {
     return hdp::aggregate_workspace_bytes(n, width);
 }
 
-static hdp_status check_phases(const hdp_forest *f, int32_t width, const int32_t *pp, int32_t np) {
-    if (!f || !pp) return HDP_EINVAL;
+static hdp_status check_agg(const hdp_forest *f, int32_t width) {
+    if (!f || !f->phase_ptr || !f->info || f->n < 1) return HDP_EINVAL;
     if (width < 1 || width > HDP_MAX_LABELS) return HDP_EINVAL;
     if (f->n * (int64_t)width >= (int64_t(1) << 31)) return HDP_ESHAPE;  // 32-bit volume offsets
-    if (np < 1 || np > HDP_MAX_PHASES) return HDP_EINVAL;
-    if (pp[0] != 0 || pp[np] != f->n) return HDP_EINVAL;
-    for (int k = 0; k < np; ++k)
-        if (pp[k + 1] < pp[k]) return HDP_EINVAL;
     return HDP_OK;
 }
 
-hdp_status hdp_aggregate(const hdp_forest *f, int32_t width, const int32_t *phase_ptr_host,
-                         int32_t n_phases, const float *cost, float sigma, float *agg, float *up,
-                         void *ws, size_t ws_bytes, void *stream) {
-    hdp_status st = check_phases(f, width, phase_ptr_host, n_phases);
+hdp_status hdp_aggregate(const hdp_forest *f, int32_t width, const float *cost, float sigma,
+                         float *agg, float *up, void *ws, size_t ws_bytes, void *stream) {
+    hdp_status st = check_agg(f, width);
     if (st != HDP_OK) return st;
     if (!cost || !agg || !ws || !(sigma > 0.f)) return HDP_EINVAL;
     if (ws_bytes < hdp::aggregate_workspace_bytes(f->n, width)) return HDP_EWORKSPACE;
     (void)hipGetLastError();
-    hdp::launch_aggregate(*f, width, phase_ptr_host, n_phases, cost, sigma, agg, up, ws,
-                          (hipStream_t)stream);
+    hdp::launch_aggregate(*f, width, cost, sigma, agg, up, ws, (hipStream_t)stream);
     return last_hip();
 }
 
-hdp_status hdp_aggregate_backward(const hdp_forest *f, int32_t width,
-                                  const int32_t *phase_ptr_host, int32_t n_phases,
-                                  const float *cost, const float *agg, const float *up,
-                                  const float *grad_agg, float sigma, float *grad_cost,
-                                  float *grad_w, float *grad_sigma, void *ws, size_t ws_bytes,
-                                  void *stream) {
-    hdp_status st = check_phases(f, width, phase_ptr_host, n_phases);
+hdp_status hdp_aggregate_backward(const hdp_forest *f, int32_t width, const float *cost,
+                                  const float *agg, const float *up, const float *grad_agg,
+                                  float sigma, float *grad_cost, float *grad_w, float *grad_sigma,
+                                  void *ws, size_t ws_bytes, void *stream) {
+    hdp_status st = check_agg(f, width);
     if (st != HDP_OK) return st;
     if (!cost || !agg || !grad_agg || !grad_cost || !ws || !(sigma > 0.f)) return HDP_EINVAL;
     if (ws_bytes < hdp::aggregate_workspace_bytes(f->n, width)) return HDP_EWORKSPACE;
     (void)hipGetLastError();
-    hdp::launch_aggregate_backward(*f, width, phase_ptr_host, n_phases, cost, agg, up, grad_agg,
-                                   sigma, grad_cost, grad_w, grad_sigma, ws, (hipStream_t)stream);
+    hdp::launch_aggregate_backward(*f, width, cost, agg, up, grad_agg, sigma, grad_cost, grad_w,
+                                   grad_sigma, ws, (hipStream_t)stream);
     return last_hip();
 }
 
@@ -299,6 +312,34 @@ hdp_status hdp_predict_range(const int32_t *disp_upper, const hdp_shape *upper,
     (void)hipGetLastError();
     hdp::launch_predict_range(disp_upper, gu, gl, S, window, pix_lo, pix_hi, (hipStream_t)stream);
     return last_hip();
+}
+
+hdp_status hdp_timer_arm(int32_t kernel_class) {
+    using namespace hdp;
+    if (kernel_class >= 0 && !g_ev_made) {
+        for (int i = 0; i < kTimerSlots; ++i)
+            for (int k = 0; k < 2; ++k)
+                if (hipEventCreate(&g_ev[i][k]) != hipSuccess) return HDP_EHIP;
+        g_ev_made = true;
+    }
+    g_timer_class = kernel_class;
+    g_timer_n = 0;
+    return HDP_OK;
+}
+
+hdp_status hdp_timer_read(float *total_ms, int32_t *launches) {
+    using namespace hdp;
+    if (!total_ms || !launches) return HDP_EINVAL;
+    float tot = 0.f;
+    for (int i = 0; i < g_timer_n; ++i) {
+        if (hipEventSynchronize(g_ev[i][1]) != hipSuccess) return HDP_EHIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g_ev[i][0], g_ev[i][1]) != hipSuccess) return HDP_EHIP;
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = g_timer_n;
+    return HDP_OK;
 }
 
 const char *hdp_status_str(hdp_status s) {

@@ -50,6 +50,10 @@ __device__ __forceinline__ int64_t gtid() {
     return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 }
 
+// Diagnostic launch timer (HIP events around the launches of one kernel class).
+void timer_before(int kernel_class, hipStream_t st);
+void timer_after(int kernel_class, hipStream_t st);
+
 inline unsigned grid_for(int64_t n, int per_block = kBlock) {
     int64_t b = (n + per_block - 1) / per_block;
     return (unsigned)(b < 1 ? 1 : b);

@@ -93,9 +93,11 @@ void launch_cost_volume(const float *left, const float *right, const LevelGeom &
     int64_t n = g.off[g.n_pairs];
     int64_t total = n * width;
     CostParams cp{p.a_c, p.tau_c, p.a_g, p.tau_g};
+    timer_before(HDP_TIMER_COST, st);
     k_cost_volume<<<grid_for(total), kBlock, 0, st>>>(
         reinterpret_cast<const float4 *>(left), reinterpret_cast<const float4 *>(right), g, node,
         lo, hi, width, cp, cost, total);
+    timer_after(HDP_TIMER_COST, st);
 }
 
 void launch_wta(const LevelGeom &g, const int32_t *node, const int32_t *lo, const int32_t *hi,

@@ -19,12 +19,11 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
                        const int32_t *phi, int max_width, int width, const hdp_forest &f,
                        void *ws, hipStream_t st);
 size_t aggregate_workspace_bytes(int64_t n, int width);
-void launch_aggregate(const hdp_forest &f, int width, const int32_t *phase_ptr, int n_phases,
-                      const float *cost, float sigma, float *agg, float *up, void *ws,
-                      hipStream_t st);
-void launch_aggregate_backward(const hdp_forest &f, int width, const int32_t *phase_ptr,
-                               int n_phases, const float *cost, const float *agg, const float *up,
-                               const float *grad_agg, float sigma, float *grad_cost, float *grad_w,
-                               float *grad_sigma, void *ws, hipStream_t st);
+void launch_aggregate(const hdp_forest &f, int width, const float *cost, float sigma, float *agg,
+                      float *up, void *ws, hipStream_t st);
+void launch_aggregate_backward(const hdp_forest &f, int width, const float *cost, const float *agg,
+                               const float *up, const float *grad_agg, float sigma,
+                               float *grad_cost, float *grad_w, float *grad_sigma, void *ws,
+                               hipStream_t st);
 
 }  // namespace hdp

@@ -88,18 +88,23 @@ __global__ void k_info_clear(int32_t *__restrict__ info) {
 }
 
 __global__ void k_bv_minedge(int round, const int32_t *__restrict__ flags, LevelGeom g,
-                             const uint32_t *__restrict__ key, const int32_t *__restrict__ comp,
+                             uint32_t *__restrict__ key, const int32_t *__restrict__ comp,
                              uint64_t *__restrict__ best) {
     if (round > 0 && flags[FLAG_BV + round - 1] == 0) return;
     int64_t v = gtid();
     if (v >= g.off[g.n_pairs]) return;
+    uint2 kk = reinterpret_cast<const uint2 *>(key)[v];
+    if (kk.x == kNoKey && kk.y == kNoKey) return;
     int cu = comp[v];
     for (int dir = 0; dir < 2; ++dir) {
-        uint32_t k = key[2 * v + dir];
+        uint32_t k = dir == 0 ? kk.x : kk.y;
         if (k == kNoKey) continue;
         int64_t q = dir == 0 ? v + 1 : v + g.W[pair_of(g, (int)v)];
         int cq = comp[q];
-        if (cq == cu) continue;
+        if (cq == cu) {  // both ends already in one component: never needed again
+            key[2 * v + dir] = kNoKey;
+            continue;
+        }
         uint64_t k64 = ((uint64_t)k << 32) | (uint64_t)(2 * v + dir);
         if (best[cu] > k64) atomicMin((unsigned long long *)&best[cu], (unsigned long long)k64);
         if (best[cq] > k64) atomicMin((unsigned long long *)&best[cq], (unsigned long long)k64);
@@ -153,14 +158,23 @@ __global__ void k_bv_compress(int round, const int32_t *__restrict__ flags,
 // component (the common case: components are large and pixels contiguous)
 // combine first, so one atomic per wavefront and component reaches memory.
 __global__ void k_rootmin(const int32_t *__restrict__ comp, int32_t *__restrict__ mn, int64_t n) {
+    __shared__ int s_c0, s_diff;
     int64_t v = gtid();
     bool valid = v < n;
     int c = valid ? comp[v] : -1;
+    if (threadIdx.x == 0) { s_c0 = c; s_diff = 0; }
+    __syncthreads();
+    if (valid && c != s_c0) s_diff = 1;
+    __syncthreads();
+    if (!s_diff) {
+        // the whole workgroup lies in one component; thread 0 holds the smallest id
+        if (threadIdx.x == 0 && valid && mn[c] > (int32_t)v) atomicMin(&mn[c], (int32_t)v);
+        return;
+    }
     int c0 = __shfl(c, 0, 64);
     uint64_t same = __ballot(c == c0);
     uint64_t act = __ballot(valid);
     if (same == act) {
-        // every active lane has component c0; lane 0 holds the smallest v
         if ((threadIdx.x & 63) == 0 && valid && mn[c0] > (int32_t)v) atomicMin(&mn[c0], (int32_t)v);
         return;
     }
@@ -244,8 +258,10 @@ __device__ __forceinline__ uint32_t rank_of(const uint64_t *pr, int64_t s) {
 }
 
 // parent, subtree size and edge weight of the child side of every tree edge.
+// (edge weights are recomputed from the image: the key array no longer holds
+// the keys of edges that became internal during the spanning-forest rounds)
 __global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
-                         const uint32_t *__restrict__ key, const uint64_t *__restrict__ pr,
+                         const float4 *__restrict__ img, const uint64_t *__restrict__ pr,
                          int32_t *__restrict__ parent, int32_t *__restrict__ size,
                          float *__restrict__ wgt) {
     int64_t v = gtid();
@@ -262,9 +278,12 @@ __global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
         uint32_t sz;
         if (rv > rw) { child = w; par = v; sz = (rv - rw + 1) >> 1; }
         else { child = v; par = w; sz = (rw - rv + 1) >> 1; }
+        float4 a = img[v], b = img[w];
+        float m = fmaxf(fmaxf(fabsf(a.x - b.x), fabsf(a.y - b.y)), fabsf(a.z - b.z));
+        float k = (float)__float2uint_rn(m * ldexpf(1.0f, 2 * g.level));
         parent[child] = (int32_t)par;
         size[child] = (int32_t)sz;
-        wgt[child] = (float)key[e] * inv;
+        wgt[child] = k * inv;
     }
 }
 
@@ -363,7 +382,7 @@ __global__ void k_node_order(LevelGeom g, const uint8_t *__restrict__ adj,
                              int32_t *__restrict__ depth, int32_t *__restrict__ ld,
                              int32_t *__restrict__ gpre, int32_t *__restrict__ info) {
     int64_t w = gtid();
-    int32_t dep = 0, l = 0;  // every lane reaches the wavefront maxima below
+    int32_t dep = 0, l = 0;
     if (w < g.off[g.n_pairs]) {
         int64_t root = tree[w];
         uint64_t ro = rootoff[root];
@@ -392,8 +411,6 @@ __global__ void k_node_order(LevelGeom g, const uint8_t *__restrict__ adj,
         ld[w] = l;
         gpre[w] = pre;
     }
-    wave_max_to(&info[HDP_INFO_N_LEVELS], dep + 1);
-    wave_max_to(&info[HDP_INFO_N_PHASES], l + 1);
 }
 
 __global__ void k_scatter_seq(const int32_t *__restrict__ gpre, int32_t *__restrict__ seq,
@@ -420,10 +437,14 @@ struct DigitKey {
 };
 
 __global__ void k_phase_ptr(const int32_t *__restrict__ offs, int64_t ntiles, int64_t n,
-                            int32_t *__restrict__ phase_ptr) {
+                            int32_t *__restrict__ phase_ptr, int32_t *__restrict__ info) {
     int k = threadIdx.x;
     if (k > HDP_MAX_PHASES) return;
-    phase_ptr[k] = offs[(int64_t)k * ntiles];  // rows with light depth < k
+    int32_t v = offs[(int64_t)k * ntiles];  // rows with light depth < k
+    phase_ptr[k] = v;
+    // phases = 1 + largest light depth present: the first k with all rows below it
+    int32_t prev = k > 0 ? offs[(int64_t)(k - 1) * ntiles] : 0;
+    if (k > 0 && v == n && prev < n) info[HDP_INFO_N_PHASES] = k;
 }
 
 // --- 7. rows of the volume layout ---------------------------------------------------
@@ -482,12 +503,14 @@ __global__ void k_iota(int32_t *__restrict__ a, int64_t n) {
 // level_ptr[k] = first position of depth k in the level order: every
 // position where the depth steps up from d' to d writes the entries d'+1..d.
 __global__ void k_level_ptr(const int32_t *__restrict__ order, const int32_t *__restrict__ depth,
-                            int64_t n, int32_t *__restrict__ level_ptr) {
+                            int64_t n, int32_t *__restrict__ level_ptr,
+                            int32_t *__restrict__ info) {
     int64_t i = gtid();
     if (i > n) return;
     int d = i < n ? depth[order[i]] : depth[order[n - 1]] + 1;
     int dp = i > 0 ? depth[order[i - 1]] : -1;
     for (int k = dp + 1; k <= d; ++k) level_ptr[k] = (int32_t)i;
+    if (i == n) info[HDP_INFO_N_LEVELS] = d;
 }
 
 __global__ void k_finish_info(const int32_t *__restrict__ flags, int32_t *__restrict__ info,
@@ -607,7 +630,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     int rk_rounds = ceil_log2(2 * n) + 2;
     if (rk_rounds > 63) rk_rounds = 63;
     for (int r = 0; r < rk_rounds; ++r) k_rank_round<<<gn4, kBlock, 0, st>>>(r, t.flags, t.pr, 4 * n);
-    k_parent<<<gn, kBlock, 0, st>>>(g, t.intree, t.key, t.pr, f.parent, t.size, f.wgt);
+    k_parent<<<gn, kBlock, 0, st>>>(g, t.intree, im, t.pr, f.parent, t.size, f.wgt);
     k_root_info<<<gn, kBlock, 0, st>>>(n, f.tree, t.adj, t.pr, f.parent, t.size, f.wgt, t.rootval);
     // 5: heavy child
     k_heavy<<<gn, kBlock, 0, st>>>(g, t.adj, f.parent, t.size, t.heavy_child);
@@ -627,7 +650,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         LdKey key{t.ld};
         k_count_hist<64><<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles);
         device_scan<int32_t>(t.hist, t.hist, 64 * ntiles, t.partial32, nullptr, false, st);
-        k_phase_ptr<<<1, 64, 0, st>>>(t.hist, ntiles, n, f.phase_ptr);
+        k_phase_ptr<<<1, 64, 0, st>>>(t.hist, ntiles, n, f.phase_ptr, f.info);
         k_count_scatter<64, 6><<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles,
                                                                     f.node, f.row);
     }
@@ -645,7 +668,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         src = out;
         dst = (out == t.sortB) ? t.sortA : t.sortB;
     }
-    k_level_ptr<<<grid_for(n + 1), kBlock, 0, st>>>(f.order, f.depth, n, f.level_ptr);
+    k_level_ptr<<<grid_for(n + 1), kBlock, 0, st>>>(f.order, f.depth, n, f.level_ptr, f.info);
     k_finish_info<<<1, 64, 0, st>>>(t.flags, f.info, width);
 }
 

@@ -80,12 +80,14 @@ def _declare(L):
                                   C.POINTER(CostParams), P, P]
     L.hdp_aggregate_workspace_bytes.argtypes = [I64, I32]
     L.hdp_aggregate_workspace_bytes.restype = SZ
-    L.hdp_aggregate.argtypes = [C.POINTER(ForestStruct), I32, P, I32, P, F, P, P, P, SZ, P]
-    L.hdp_aggregate_backward.argtypes = [C.POINTER(ForestStruct), I32, P, I32, P, P, P, P, F,
+    L.hdp_aggregate.argtypes = [C.POINTER(ForestStruct), I32, P, F, P, P, P, SZ, P]
+    L.hdp_aggregate_backward.argtypes = [C.POINTER(ForestStruct), I32, P, P, P, P, F,
                                          P, P, P, P, SZ, P]
     L.hdp_wta.argtypes = [C.POINTER(ForestStruct), P, I32, I32, P, P, P]
     L.hdp_predict_range.argtypes = [P, P, P, I32, I32, I32, P, P, P]
     L.hdp_status_str.argtypes = [I32]; L.hdp_status_str.restype = C.c_char_p
+    L.hdp_timer_arm.argtypes = [I32]; L.hdp_timer_arm.restype = I32
+    L.hdp_timer_read.argtypes = [P, P]; L.hdp_timer_read.restype = I32
     for name in ("hdp_forest_bind", "hdp_level_shapes", "hdp_pyramid", "hdp_build_tree",
                  "hdp_forest_read_info", "hdp_cost_volume", "hdp_aggregate",
                  "hdp_aggregate_backward", "hdp_wta", "hdp_predict_range"):
@@ -222,7 +224,7 @@ _ws_agg = Workspace()
 
 def build_tree(img: torch.Tensor, shapes, level: int, pix_lo=None, pix_hi=None,
                max_width: int = 0, beta=(19, 20), width: Optional[int] = None,
-               read_info: bool = True, forest: Optional[Forest] = None, ws=None) -> Forest:
+               read_info: bool = False, forest: Optional[Forest] = None, ws=None) -> Forest:
     """Minimum spanning tree (pix_lo None) or disparity forest of one layer."""
     n = n_pixels(shapes)
     assert img.shape == (n, 4) and img.dtype == torch.float32 and img.is_contiguous()
@@ -268,13 +270,6 @@ def cost_volume(left: torch.Tensor, right: torch.Tensor, shapes, forest: Optiona
     return out
 
 
-def _phase_args(forest: Forest):
-    if forest.phase_ptr is None:
-        forest.read_info()
-    pp = (C.c_int32 * len(forest.phase_ptr))(*forest.phase_ptr)
-    return pp, len(forest.phase_ptr) - 1
-
-
 def aggregate(forest: Forest, cost: torch.Tensor, sigma: float = 0.1, keep_up: bool = False,
               out: Optional[torch.Tensor] = None, up: Optional[torch.Tensor] = None, ws=None):
     """agg(v,x) = sum_u exp(-W(v,u)/sigma) cost(u,x) over the forest (eq. C).
@@ -285,11 +280,10 @@ def aggregate(forest: Forest, cost: torch.Tensor, sigma: float = 0.1, keep_up: b
         out = torch.empty_like(cost)
     if keep_up and up is None:
         up = torch.empty_like(cost)
-    pp, npz = _phase_args(forest)
     wsb = lib().hdp_aggregate_workspace_bytes(n, width)
     w = (ws or _ws_agg).get(wsb, cost.device)
     _check("hdp_aggregate", lib().hdp_aggregate(
-        C.byref(forest.st), width, pp, npz, _ptr(cost), float(sigma), _ptr(out), _ptr(up),
+        C.byref(forest.st), width, _ptr(cost), float(sigma), _ptr(out), _ptr(up),
         _ptr(w), wsb, _stream()))
     return (out, up) if keep_up else out
 
@@ -301,11 +295,10 @@ def aggregate_backward(forest: Forest, cost, agg, grad_agg, sigma=0.1, up=None,
     gc = torch.empty_like(cost)
     gw = torch.zeros(n, dtype=torch.float32, device=cost.device) if want_w else None
     gs = torch.zeros(1, dtype=torch.float32, device=cost.device) if want_sigma else None
-    pp, npz = _phase_args(forest)
     wsb = lib().hdp_aggregate_workspace_bytes(n, width)
     w = (ws or _ws_agg).get(wsb, cost.device)
     _check("hdp_aggregate_backward", lib().hdp_aggregate_backward(
-        C.byref(forest.st), width, pp, npz, _ptr(cost), _ptr(agg), _ptr(up),
+        C.byref(forest.st), width, _ptr(cost), _ptr(agg), _ptr(up),
         _ptr(grad_agg.contiguous()), float(sigma), _ptr(gc), _ptr(gw), _ptr(gs), _ptr(w), wsb,
         _stream()))
     return gc, gw, gs
@@ -337,6 +330,23 @@ def predict_range(disp_upper: torch.Tensor, upper_shapes, lower_shapes, S: int =
     return lo, hi
 
 
+# --- diagnostics -----------------------------------------------------------------------
+
+TIMER = dict(up_pass=0, down_pass=1, cost=2)
+
+
+def timer_arm(kernel_class: Optional[str]):
+    """Record HIP events around every launch of one kernel class (None: off)."""
+    _check("hdp_timer_arm", lib().hdp_timer_arm(-1 if kernel_class is None else TIMER[kernel_class]))
+
+
+def timer_read() -> Tuple[float, int]:
+    """(summed kernel milliseconds, launches) of the armed class; synchronises."""
+    ms = C.c_float(); n = C.c_int32()
+    _check("hdp_timer_read", lib().hdp_timer_read(C.byref(ms), C.byref(n)))
+    return float(ms.value), int(n.value)
+
+
 # --- the method ----------------------------------------------------------------------
 
 @dataclass
@@ -352,18 +362,20 @@ class LevelResult:
 
 
 def stereo_level(left_img, right_img, shapes, level, pix_lo=None, pix_hi=None, max_width=0,
-                 beta=(19, 20), sigma=0.1, params=None, keep=False) -> LevelResult:
+                 beta=(19, 20), sigma=0.1, params=None, keep=False, ws=None) -> LevelResult:
     """One layer (Section 3): forest, restricted cost, aggregation, WTA."""
-    f = build_tree(left_img, shapes, level, pix_lo, pix_hi, max_width=max_width, beta=beta)
+    ws = ws or {}
+    f = build_tree(left_img, shapes, level, pix_lo, pix_hi, max_width=max_width, beta=beta,
+                   read_info=False, ws=ws.get("tree"))
     cost = cost_volume(left_img, right_img, shapes, f, params=params)
-    agg = aggregate(f, cost, sigma)
+    agg = aggregate(f, cost, sigma, ws=ws.get("agg"))
     disp = wta(agg, shapes, f)
     return LevelResult(level=level, shapes=list(shapes), forest=f, disp=disp, pix_lo=pix_lo,
                        pix_hi=pix_hi, cost=cost if keep else None, agg=agg if keep else None)
 
 
 def hdp_stereo(left_rgb: torch.Tensor, right_rgb: torch.Tensor, shapes, S=2, L=3, window=4,
-               beta=(19, 20), sigma=0.1, params=None, keep=False) -> List[LevelResult]:
+               beta=(19, 20), sigma=0.1, params=None, keep=False, ws=None) -> List[LevelResult]:
     """Top-down HDP (Section 3): layer L over [0, d_L] with the MST, then for
     l = L-1..0 interval prediction -> disparity forest -> cost -> aggregation
     -> WTA.  left_rgb/right_rgb: uint8 [n0, 3].  Returns results indexed by layer."""
@@ -371,18 +383,45 @@ def hdp_stereo(left_rgb: torch.Tensor, right_rgb: torch.Tensor, shapes, S=2, L=3
     lp = pyramid(left_rgb, shapes, S, L)
     rp = pyramid(right_rgb, shapes, S, L)
     res: List[Optional[LevelResult]] = [None] * (L + 1)
-    res[L] = stereo_level(lp[L], rp[L], lv[L], L, sigma=sigma, params=params, keep=keep)
+    res[L] = stereo_level(lp[L], rp[L], lv[L], L, sigma=sigma, params=params, keep=keep, ws=ws)
     for l in range(L - 1, -1, -1):
         lo, hi = predict_range(res[l + 1].disp, lv[l + 1], lv[l], S, window)
         mw = min(S + 2 * window, max(d for _, _, d in lv[l]) + 1)
         res[l] = stereo_level(lp[l], rp[l], lv[l], l, lo, hi, max_width=mw, beta=beta,
-                              sigma=sigma, params=params, keep=keep)
+                              sigma=sigma, params=params, keep=keep, ws=ws)
     return res
 
 
-def full_range(left_rgb, right_rgb, shapes, sigma=0.1, params=None, keep=False) -> LevelResult:
+def full_range(left_rgb, right_rgb, shapes, sigma=0.1, params=None, keep=False,
+               ws=None) -> LevelResult:
     """Full-range MST aggregation + WTA at the input resolution (the baseline
     the method speeds up)."""
     lp = pyramid(left_rgb, shapes, 2, 0)
     rp = pyramid(right_rgb, shapes, 2, 0)
-    return stereo_level(lp[0], rp[0], shapes, 0, sigma=sigma, params=params, keep=keep)
+    return stereo_level(lp[0], rp[0], shapes, 0, sigma=sigma, params=params, keep=keep, ws=ws)
+
+
+class CapturedStep:
+    """A whole step captured once into a HIP graph and replayed.
+
+    ``fn(ws)`` must enqueue only library calls on the current stream (no host
+    synchronisation).  The step owns its workspaces, so no other call can
+    reallocate memory the graph refers to.  Inputs are read from the tensors
+    captured by ``fn``; overwrite them in place between replays."""
+
+    def __init__(self, fn, warmup: int = 1):
+        self.ws = {"tree": Workspace(), "agg": Workspace()}
+        self.stream = torch.cuda.Stream()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.stream):
+            for _ in range(warmup):
+                fn(self.ws)
+        torch.cuda.current_stream().wait_stream(self.stream)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=self.stream):
+            self.out = fn(self.ws)
+
+    def replay(self):
+        self.graph.replay()
+        return self.out

@@ -327,3 +327,22 @@ def test_adjoint_matches_oracle(H, orc):
     assert abs(float(gs.cpu()) - ds) <= REL * Bs, (float(gs.cpu()), ds, Bs)
     # recomputing U instead of reusing the forward's gives the same gradients
     np.testing.assert_array_equal(gc2.cpu().numpy(), gc.cpu().numpy())
+
+
+def test_graph_replay_matches_eager(H):
+    """The whole HDP step captured once and replayed several times (with eager
+    work in between) gives the eager result on every replay."""
+    shapes = [(96, 128, 63)]
+    pair = scenes.small_scene(91, 96, 128, 63)
+    L_rgb, R_rgb = rgb_dev(pair.left), rgb_dev(pair.right)
+    eager = [r.disp.cpu().numpy() for r in H.hdp_stereo(L_rgb, R_rgb, shapes, S=2, L=2, window=4)]
+    step = H.CapturedStep(lambda ws: H.hdp_stereo(L_rgb, R_rgb, shapes, S=2, L=2, window=4, ws=ws))
+    for rep in range(4):
+        out = step.replay()
+        torch.cuda.synchronize()
+        for l in range(3):
+            np.testing.assert_array_equal(out[l].disp.cpu().numpy(), eager[l],
+                                          err_msg=f"replay {rep} layer {l}")
+        # unrelated eager work between replays
+        H.full_range(R_rgb, L_rgb, [(96, 128, 63)])
+        torch.cuda.synchronize()
