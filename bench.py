@@ -36,7 +36,43 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="both", choices=["both", "hdp", "full"],
                     help="profiling aid: time only the HDP loop or only the full-range path")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched and adjoint workloads (profiling aid)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile schedule")
     return ap.parse_args()
+
+
+def _gen(args):
+    from paper_1509_08197_amd import scenes
+    return scenes.workload(*args)
+
+
+def gen_pairs(cfg, n):
+    """Seeded pairs of one workload, generated in parallel on the host."""
+    from multiprocessing import get_context
+    with get_context("fork").Pool(min(16, n)) as pool:
+        return pool.map(_gen, [(cfg, i) for i in range(n)])
+
+
+def upload(pairs):
+    import numpy as np
+    import torch
+    L = torch.from_numpy(np.concatenate([p.left.reshape(-1, 3) for p in pairs])).cuda()
+    R = torch.from_numpy(np.concatenate([p.right.reshape(-1, 3) for p in pairs])).cuda()
+    shapes = [(p.shape[0], p.shape[1], p.dmax) for p in pairs]
+    return L, R, shapes
+
+
+def autotune(hdp, tuner, results_by_level, sigma=0.1):
+    """Pick the tile schedule of every row width met in these results."""
+    cache = {}
+    done = {}
+    for r in sorted(results_by_level, key=lambda r: -r.forest.n):
+        w = r.forest.width
+        if w in done or r.cost is None:
+            continue
+        done[w] = tuner.tune(r.forest, r.cost, sigma, cache=cache)
+    return {w: f"{e['cpt']}x{e['rpg']}" for w, e in done.items()}
 
 
 def pass_bytes(forest, up: bool) -> float:
@@ -98,6 +134,15 @@ def main():
                                   "L=3 S=2, window 4, beta 19/20, sigma 0.1",
                       "global_batch": 1}}
 
+    from paper_1509_08197_amd import tuner
+    if not args.no_tune:
+        probe = hdp.hdp_stereo(L_rgb, R_rgb, shapes, S=P["S"], L=P["L"], window=P["window"],
+                               beta=P["beta"], keep=True)
+        probe.append(hdp.full_range(L_rgb, R_rgb, shapes, keep=True))
+        out["schedule"] = autotune(hdp, tuner, probe)
+        del probe
+        torch.cuda.empty_cache()
+
     if args.mode != "full":
         # the timed step is a whole-step HIP graph replay (captured once)
         step = hdp.CapturedStep(hdp_eager)
@@ -142,6 +187,10 @@ def main():
             out["full_range"]["speedup_hdp_over_full"] = t_full / (out["ms_per_step"] * 1e-3)
         del fstep
 
+    if not args.no_extra and args.mode == "both":
+        out["batched"] = bench_batched(hdp, scenes, timed, args)
+        out["adjoint"] = bench_adjoint(hdp, timed, args)
+
     if not args.no_cpu_baseline and args.mode == "both":
         from oracle import oracle
         t0 = time.perf_counter()
@@ -155,6 +204,97 @@ def main():
                                "seconds": t_cpu,
                                "host_cores_available": len(os.sched_getaffinity(0))}
     print(json.dumps(out))
+
+
+def bench_batched(hdp, scenes, timed, args):
+    """Uneven batches in one captured graph: 32 pairs (320-1392 x 240-1110,
+    64-256 labels) HDP forward; 64 road pairs 1242x375 HDP forward + adjoint."""
+    import torch
+    res = {}
+    pairs = gen_pairs(3, scenes.N_PAIRS[3])
+    L, R, shapes = upload(pairs)
+    P3 = scenes.HDP_PARAMS[3]
+    work = sum(h * w * (d + 1) for h, w, d in shapes)
+
+    def step3(ws=None):
+        return hdp.hdp_stereo(L, R, shapes, S=P3["S"], L=P3["L"], window=P3["window"],
+                              beta=P3["beta"], ws=ws)
+    g3 = hdp.CapturedStep(step3)
+    t3 = timed(g3.replay, max(3, args.steps // 2), 2)
+    res["uneven32_hdp_fwd"] = {"pairs": len(shapes), "Mpix": sum(h * w for h, w, _ in shapes) / 1e6,
+                               "ms_per_step": t3 * 1e3,
+                               "Mpix_disp_per_s_full_range_equiv": work / t3 / 1e6}
+    del g3, L, R
+    torch.cuda.empty_cache()
+
+    pairs = gen_pairs(5, scenes.N_PAIRS[5])
+    L, R, shapes = upload(pairs)
+    P5 = scenes.HDP_PARAMS[5]
+    work = sum(h * w * (d + 1) for h, w, d in shapes)
+    probe = hdp.hdp_stereo(L, R, shapes, S=P5["S"], L=P5["L"], window=P5["window"],
+                           beta=P5["beta"], keep=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    G = [torch.randn(r.agg.shape, device="cuda", generator=gen) for r in probe]
+    del probe
+
+    def fwd5(ws=None):
+        return hdp.hdp_stereo(L, R, shapes, S=P5["S"], L=P5["L"], window=P5["window"],
+                              beta=P5["beta"], keep=True, ws=ws)
+
+    def fwdbwd5(ws=None):
+        out = fwd5(ws)
+        agg_ws = ws["agg"] if ws else None
+        grads = [hdp.aggregate_backward(r.forest, r.cost, r.agg, G[i], 0.1, want_w=False,
+                                        ws=agg_ws) for i, r in enumerate(out)]
+        return out, grads
+    gf = hdp.CapturedStep(fwd5)
+    tf = timed(gf.replay, max(3, args.steps // 2), 2)
+    del gf
+    gb = hdp.CapturedStep(fwdbwd5)
+    tb = timed(gb.replay, max(3, args.steps // 2), 2)
+    del gb
+    res["road64_hdp_fwd_bwd"] = {"pairs": len(shapes),
+                                 "Mpix": sum(h * w for h, w, _ in shapes) / 1e6,
+                                 "fwd_ms": tf * 1e3, "fwd_bwd_ms": tb * 1e3,
+                                 "fwd_bwd_over_fwd": tb / tf,
+                                 "Mpix_disp_per_s_full_range_equiv_fwd": work / tf / 1e6}
+    del L, R
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_adjoint(hdp, timed, args):
+    """8 pairs 640x480, labels 0..127, full-range forest: aggregation forward
+    vs forward + adjoint (dL/dC, dL/dsigma; U kept as the checkpoint)."""
+    import torch
+    from paper_1509_08197_amd import scenes
+    pairs = gen_pairs(4, scenes.N_PAIRS[4])
+    L, R, shapes = upload(pairs)
+    lp = hdp.pyramid(L, shapes, 2, 0)
+    rp = hdp.pyramid(R, shapes, 2, 0)
+    f = hdp.build_tree(lp[0], shapes, 0)
+    cost = hdp.cost_volume(lp[0], rp[0], shapes, f)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    g = torch.randn(cost.shape, device="cuda", generator=gen)
+
+    def fwd(ws=None):
+        return hdp.aggregate(f, cost, 0.1, keep_up=True, ws=ws["agg"] if ws else None)
+
+    def fwdbwd(ws=None):
+        agg, up = fwd(ws)
+        return hdp.aggregate_backward(f, cost, agg, g, 0.1, up=up, want_w=True,
+                                      ws=ws["agg"] if ws else None)
+    a = hdp.CapturedStep(fwd)
+    ta = timed(a.replay, max(3, args.steps // 2), 2)
+    del a
+    b = hdp.CapturedStep(fwdbwd)
+    tb = timed(b.replay, max(3, args.steps // 2), 2)
+    del b
+    entries = f.n * f.width
+    return {"workload": "8 pairs 640x480, labels 0..127, full range", "entries": int(entries),
+            "fwd_ms": ta * 1e3, "fwd_bwd_ms": tb * 1e3, "fwd_bwd_over_fwd": tb / ta}
 
 
 if __name__ == "__main__":

@@ -181,6 +181,14 @@ HDP_API hdp_status hdp_forest_read_info(const hdp_forest *f, int32_t *info_host,
                                 int32_t *phase_ptr_host, void *stream);
 
 /*
+ * Replace the forest's edge weights (eq. weight) by wgt[v] for the edge
+ * (v, parent(v)), pixel order, float[n] (roots ignored): writes both the
+ * per-pixel and the per-row copies.  Used to differentiate with respect to
+ * learnable edge weights; the tree topology is unchanged.
+ */
+HDP_API hdp_status hdp_forest_set_weights(const hdp_forest *f, const float *wgt, void *stream);
+
+/*
  * Restricted matching cost E (eq. E) of one layer.
  *   left/right  level images of the two views, [n][4] as written by
  *               hdp_pyramid.
@@ -256,6 +264,18 @@ HDP_API hdp_status hdp_predict_range(const int32_t *disp_upper, const hdp_shape 
                              int32_t window, int32_t *pix_lo, int32_t *pix_hi, void *stream);
 
 HDP_API const char *hdp_status_str(hdp_status s);
+
+/*
+ * Tile schedule of the aggregation passes for rows of `width` labels: each
+ * thread handles `labels_per_thread` (1, 2 or 4; must divide width)
+ * consecutive labels of `rows_per_group` (4, 8 or 16; 16 only with 2 labels
+ * per thread) rows.  labels_per_thread = 0 restores the built-in
+ * choice.  Process-wide host setting read when a pass is launched (a captured
+ * graph keeps the schedule it was captured with); the workspace size does not
+ * depend on it.  Set by the autotuner.
+ */
+HDP_API hdp_status hdp_set_schedule(int32_t width, int32_t labels_per_thread,
+                                    int32_t rows_per_group);
 
 /*
  * Diagnostics (not for use under graph capture): time every launch of one

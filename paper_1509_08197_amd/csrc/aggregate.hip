@@ -28,7 +28,7 @@
 
 namespace hdp {
 
-constexpr int kRPG = 8;  // rows per thread group of a tile
+constexpr int kRPGDefault = 8;  // rows per thread group of a tile
 
 // Layout of the device-side pass plan (int32 words).
 enum {
@@ -44,19 +44,54 @@ enum {
 
 struct TileGeom {
     int cpt;     // labels per thread (4, 2 or 1)
+    int rpg;     // rows per thread group (4, 8 or 16)
     int lpr;     // threads per row
     int groups;  // row groups per tile
     int rows;    // rows per tile
 };
 
-static TileGeom tile_geom(int width) {
+// Schedule chosen per row width (0 = built-in default), set by the tuner.
+static int g_sched_cpt[HDP_MAX_LABELS + 1];
+static int g_sched_rpg[HDP_MAX_LABELS + 1];
+
+static bool schedule_valid(int width, int cpt, int rpg) {
+    if (cpt != 1 && cpt != 2 && cpt != 4) return false;
+    if (rpg != 4 && rpg != 8 && rpg != 16) return false;
+    if (width % cpt != 0) return false;
+    if (rpg == 16 && cpt != 2) return false;  // register budget
+    return true;
+}
+
+static TileGeom make_geom(int width, int cpt, int rpg) {
     TileGeom t;
-    t.cpt = (width >= 64 && width % 4 == 0) ? 4 : (width % 2 == 0 && width >= 8) ? 2 : 1;
-    t.lpr = (width + t.cpt - 1) / t.cpt;
+    t.cpt = cpt;
+    t.rpg = rpg;
+    t.lpr = (width + cpt - 1) / cpt;
     t.groups = kBlock / t.lpr;
     if (t.groups < 1) t.groups = 1;
-    t.rows = t.groups * kRPG;
+    t.rows = t.groups * rpg;
     return t;
+}
+
+static TileGeom tile_geom(int width) {
+    int cpt = g_sched_cpt[width], rpg = g_sched_rpg[width];
+    if (!cpt || !schedule_valid(width, cpt, rpg)) {
+        cpt = (width >= 64 && width % 4 == 0) ? 4 : (width % 2 == 0 && width >= 8) ? 2 : 1;
+        rpg = kRPGDefault;
+    }
+    return make_geom(width, cpt, rpg);
+}
+
+bool set_schedule(int width, int cpt, int rpg) {
+    if (width < 1 || width > HDP_MAX_LABELS) return false;
+    if (cpt == 0) {
+        g_sched_cpt[width] = g_sched_rpg[width] = 0;
+        return true;
+    }
+    if (!schedule_valid(width, cpt, rpg)) return false;
+    g_sched_cpt[width] = cpt;
+    g_sched_rpg[width] = rpg;
+    return true;
 }
 
 __global__ void k_coef(int64_t n, const float *__restrict__ rw, const int32_t *__restrict__ prow,
@@ -189,7 +224,7 @@ __device__ __forceinline__ void store_cols_dev(float *p, const double *c) {
     }
 }
 
-template <bool UP, int CPT>
+template <bool UP, int CPT, int kRPG>
 __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
     __shared__ double sP[kBlock];
     __shared__ double sX[kBlock * CPT];
@@ -434,8 +469,9 @@ struct AggWs {
     int64_t tiles;
 };
 
+// Upper bound on the tiles of any valid schedule (fewest rows per tile).
 static int64_t max_tiles(int64_t n, int width) {
-    return n / tile_geom(width).rows + HDP_MAX_PHASES + 2;
+    return n / make_geom(width, 1, 4).rows + HDP_MAX_PHASES + 2;
 }
 
 static AggWs carve_agg_ws(void *ws, int64_t n, int width, size_t *bytes) {
@@ -472,19 +508,28 @@ size_t aggregate_workspace_bytes(int64_t n, int width) {
     return b;
 }
 
-template <bool UP, int CPT>
-static void launch_pass(const PassArgs &A, const AggWs &w, hipStream_t st) {
-    k_pass_init<<<grid_for(w.tiles), kBlock, 0, st>>>(w.flag, w.flagw, w.ticket, w.tiles);
+template <bool UP, int CPT, int RPG>
+static void launch_pass(const PassArgs &A, const AggWs &w, int64_t tiles, hipStream_t st) {
+    k_pass_init<<<grid_for(tiles), kBlock, 0, st>>>(w.flag, w.flagw, w.ticket, tiles);
     timer_before(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
-    k_pass<UP, CPT><<<(unsigned)w.tiles, kBlock, 0, st>>>(A);
+    k_pass<UP, CPT, RPG><<<(unsigned)tiles, kBlock, 0, st>>>(A);
     timer_after(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
 }
 
 template <bool UP>
-static void run_pass(const PassArgs &A, const AggWs &w, int cpt, hipStream_t st) {
-    if (cpt == 4) launch_pass<UP, 4>(A, w, st);
-    else if (cpt == 2) launch_pass<UP, 2>(A, w, st);
-    else launch_pass<UP, 1>(A, w, st);
+static void run_pass(const PassArgs &A, const AggWs &w, const TileGeom &tg, hipStream_t st) {
+    int64_t tiles = A.n / tg.rows + HDP_MAX_PHASES + 2;  // >= the plan's tile count
+    if (tg.cpt == 4) {
+        if (tg.rpg == 4) launch_pass<UP, 4, 4>(A, w, tiles, st);
+        else launch_pass<UP, 4, 8>(A, w, tiles, st);
+    } else if (tg.cpt == 2) {
+        if (tg.rpg == 4) launch_pass<UP, 2, 4>(A, w, tiles, st);
+        else if (tg.rpg == 8) launch_pass<UP, 2, 8>(A, w, tiles, st);
+        else launch_pass<UP, 2, 16>(A, w, tiles, st);
+    } else {
+        if (tg.rpg == 4) launch_pass<UP, 1, 4>(A, w, tiles, st);
+        else launch_pass<UP, 1, 8>(A, w, tiles, st);
+    }
 }
 
 static PassArgs pass_args(const hdp_forest &f, int width, const AggWs &w, const TileGeom &tg) {
@@ -523,10 +568,10 @@ static void two_pass(const hdp_forest &f, int width, const float *src, float *up
     PassArgs A = pass_args(f, width, w, tg);
     A.src = src;
     A.dst = up;
-    run_pass<true>(A, w, tg.cpt, st);
+    run_pass<true>(A, w, tg, st);
     A.src = up;
     A.dst = out;
-    run_pass<false>(A, w, tg.cpt, st);
+    run_pass<false>(A, w, tg, st);
 }
 
 void launch_aggregate(const hdp_forest &f, int width, const float *cost, float sigma, float *agg,
@@ -607,7 +652,7 @@ void launch_aggregate_backward(const hdp_forest &f, int width, const float *cost
         PassArgs A = pass_args(f, width, w, tg);
         A.src = cost;
         A.dst = w.up;
-        run_pass<true>(A, w, tg.cpt, st);
+        run_pass<true>(A, w, tg, st);
         uc = w.up;
     }
     two_pass(f, width, grad_agg, w.ug, grad_cost, w, st);

@@ -224,6 +224,13 @@ hdp_status hdp_forest_read_info(const hdp_forest *f, int32_t *info_host, int32_t
     return HDP_OK;
 }
 
+hdp_status hdp_forest_set_weights(const hdp_forest *f, const float *wgt, void *stream) {
+    if (!f || !wgt || f->n < 1 || !f->node || !f->parent || !f->wgt || !f->rw) return HDP_EINVAL;
+    (void)hipGetLastError();
+    hdp::launch_set_weights(*f, wgt, (hipStream_t)stream);
+    return last_hip();
+}
+
 hdp_status hdp_cost_volume(const float *left, const float *right, const hdp_shape *shapes,
                            int32_t n_pairs, const hdp_forest *f, int32_t width,
                            const hdp_cost_params *p, float *cost, void *stream) {
@@ -312,6 +319,10 @@ hdp_status hdp_predict_range(const int32_t *disp_upper, const hdp_shape *upper,
     (void)hipGetLastError();
     hdp::launch_predict_range(disp_upper, gu, gl, S, window, pix_lo, pix_hi, (hipStream_t)stream);
     return last_hip();
+}
+
+hdp_status hdp_set_schedule(int32_t width, int32_t labels_per_thread, int32_t rows_per_group) {
+    return hdp::set_schedule(width, labels_per_thread, rows_per_group) ? HDP_OK : HDP_EINVAL;
 }
 
 hdp_status hdp_timer_arm(int32_t kernel_class) {

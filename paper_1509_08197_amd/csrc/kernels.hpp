@@ -18,7 +18,9 @@ size_t tree_workspace_bytes(int64_t n);
 void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
                        const int32_t *phi, int max_width, int width, const hdp_forest &f,
                        void *ws, hipStream_t st);
+void launch_set_weights(const hdp_forest &f, const float *w, hipStream_t st);
 size_t aggregate_workspace_bytes(int64_t n, int width);
+bool set_schedule(int width, int cpt, int rpg);
 void launch_aggregate(const hdp_forest &f, int width, const float *cost, float sigma, float *agg,
                       float *up, void *ws, hipStream_t st);
 void launch_aggregate_backward(const hdp_forest &f, int width, const float *cost, const float *agg,

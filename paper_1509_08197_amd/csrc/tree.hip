@@ -526,6 +526,23 @@ __global__ void k_finish_info(const int32_t *__restrict__ flags, int32_t *__rest
     info[HDP_INFO_WIDTH] = width;
 }
 
+// --- learnable edge weights -----------------------------------------------------------------
+
+__global__ void k_set_weights(int64_t n, const int32_t *__restrict__ node,
+                              const int32_t *__restrict__ parent, const float *__restrict__ w,
+                              float *__restrict__ wgt, float *__restrict__ rw) {
+    int64_t r = gtid();
+    if (r >= n) return;
+    int v = node[r];
+    float x = parent[v] >= 0 ? w[v] : 0.f;
+    wgt[v] = x;
+    rw[r] = x;
+}
+
+void launch_set_weights(const hdp_forest &f, const float *w, hipStream_t st) {
+    k_set_weights<<<grid_for(f.n), kBlock, 0, st>>>(f.n, f.node, f.parent, w, f.wgt, f.rw);
+}
+
 // --- workspace -----------------------------------------------------------------------------
 
 struct Bump {

@@ -84,9 +84,12 @@ def _declare(L):
     L.hdp_aggregate_backward.argtypes = [C.POINTER(ForestStruct), I32, P, P, P, P, F,
                                          P, P, P, P, SZ, P]
     L.hdp_wta.argtypes = [C.POINTER(ForestStruct), P, I32, I32, P, P, P]
+    L.hdp_forest_set_weights.argtypes = [C.POINTER(ForestStruct), P, P]
+    L.hdp_forest_set_weights.restype = I32
     L.hdp_predict_range.argtypes = [P, P, P, I32, I32, I32, P, P, P]
     L.hdp_status_str.argtypes = [I32]; L.hdp_status_str.restype = C.c_char_p
     L.hdp_timer_arm.argtypes = [I32]; L.hdp_timer_arm.restype = I32
+    L.hdp_set_schedule.argtypes = [I32, I32, I32]; L.hdp_set_schedule.restype = I32
     L.hdp_timer_read.argtypes = [P, P]; L.hdp_timer_read.restype = I32
     for name in ("hdp_forest_bind", "hdp_level_shapes", "hdp_pyramid", "hdp_build_tree",
                  "hdp_forest_read_info", "hdp_cost_volume", "hdp_aggregate",
@@ -248,6 +251,13 @@ def build_tree(img: torch.Tensor, shapes, level: int, pix_lo=None, pix_hi=None,
     return forest
 
 
+def set_weights(forest: Forest, wgt: torch.Tensor):
+    """Load per-pixel edge weights (edge to the parent) into the forest."""
+    assert wgt.shape == (forest.n,) and wgt.dtype == torch.float32 and wgt.is_contiguous()
+    _check("hdp_forest_set_weights",
+           lib().hdp_forest_set_weights(C.byref(forest.st), _ptr(wgt), _stream()))
+
+
 # --- cost, aggregation, WTA ---------------------------------------------------------
 
 def cost_params(a_c=0.89, tau_c=7.0, a_g=0.11, tau_g=2.0) -> CostParams:
@@ -333,6 +343,13 @@ def predict_range(disp_upper: torch.Tensor, upper_shapes, lower_shapes, S: int =
 # --- diagnostics -----------------------------------------------------------------------
 
 TIMER = dict(up_pass=0, down_pass=1, cost=2)
+
+
+def set_schedule(width: int, labels_per_thread: int, rows_per_group: int = 8):
+    """Tile schedule of the aggregation passes for rows of `width` labels
+    (labels_per_thread = 0 restores the built-in choice)."""
+    _check("hdp_set_schedule", lib().hdp_set_schedule(int(width), int(labels_per_thread),
+                                                      int(rows_per_group)))
 
 
 def timer_arm(kernel_class: Optional[str]):

@@ -346,3 +346,48 @@ def test_graph_replay_matches_eager(H):
         # unrelated eager work between replays
         H.full_range(R_rgb, L_rgb, [(96, 128, 63)])
         torch.cuda.synchronize()
+
+
+def test_autograd_tree_aggregate(H, orc):
+    """torch.autograd through TreeAggregate gives the oracle's gradients for the
+    cost volume, sigma and the per-edge weights; saving or recomputing the
+    up-pass checkpoint gives identical gradients."""
+    from paper_1509_08197_amd.autograd import tree_aggregate
+    Hh, Ww, dmax, sigma = 32, 48, 7, 0.1
+    pair = scenes.small_scene(78, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lp = H.pyramid(rgb_dev(pair.left), shapes, 2, 0)
+    rp = H.pyramid(rgb_dev(pair.right), shapes, 2, 0)
+    f = H.build_tree(lp[0], shapes, 0)
+    cost0 = H.cost_volume(lp[0], rp[0], shapes, f)
+    wl = torch.from_numpy(np.random.default_rng(4).normal(size=cost0.shape).astype(np.float32)).cuda()
+    grads = []
+    for save_up in (True, False):
+        cost = cost0.clone().requires_grad_(True)
+        sg = torch.tensor(sigma, device="cuda", requires_grad=True)
+        wgt = f.array("wgt").clone().requires_grad_(True)
+        agg = tree_aggregate(cost, sg, f, wgt, save_up=save_up)
+        (agg * wl).sum().backward()
+        grads.append((cost.grad.cpu().numpy(), float(sg.grad.cpu()), wgt.grad.cpu().numpy()))
+    np.testing.assert_array_equal(grads[0][0], grads[1][0])
+    np.testing.assert_array_equal(grads[0][2], grads[1][2])
+    assert grads[0][1] == grads[1][1]
+    F = forest_np(f)
+    node = F["node"]
+    key = orc.edge_keys(pair.left.astype(np.float64), 0)
+    in_tree, _, _, _ = orc.kruskal(Hh, Ww, key)
+    ref = orc.root_forest(Hh, Ww, in_tree, key, 0)
+    par, wg, od = ref["parent"], ref["wgt"], ref["order"]
+    C = orc.cost_volume(pair.left.astype(np.float64), pair.right.astype(np.float64), dmax)
+    Gp = np.zeros_like(C); Gp[node] = wl.cpu().numpy().astype(np.float64)
+    dC, dw, ds = orc.aggregate_backward_twopass(par, wg, od, sigma, C, Gp)
+    Aabs, Uabs = orc.aggregate_twopass(par, wg, od, sigma, np.abs(Gp), want_up=True)
+    AC, UC = orc.aggregate_twopass(par, wg, od, sigma, C, want_up=True)
+    got = np.zeros_like(C); got[node] = grads[0][0]
+    assert np.all(np.abs(got - dC) <= REL * Aabs)
+    s = np.where(par >= 0, np.exp(-wg / sigma), 0.0)
+    pp = np.maximum(par, 0)
+    B = np.sum(Uabs * (AC[pp] + s[:, None] * UC) + UC * (Aabs[pp] + s[:, None] * Uabs), axis=1)
+    B = np.where(par >= 0, B * s / sigma, 0.0)
+    assert np.all(np.abs(grads[0][2] - dw) <= REL * B + 1e-30)
+    assert abs(grads[0][1] - ds) <= REL * float(np.sum(B * wg / sigma))
