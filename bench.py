@@ -42,16 +42,10 @@ def parse():
     return ap.parse_args()
 
 
-def _gen(args):
-    from paper_1509_08197_amd import scenes
-    return scenes.workload(*args)
-
-
 def gen_pairs(cfg, n):
     """Seeded pairs of one workload, generated in parallel on the host."""
-    from multiprocessing import get_context
-    with get_context("fork").Pool(min(16, n)) as pool:
-        return pool.map(_gen, [(cfg, i) for i in range(n)])
+    from paper_1509_08197_amd import scenes
+    return scenes.workload_batch(cfg, n)
 
 
 def upload(pairs):

@@ -221,3 +221,17 @@ def random_cost(seed: int, n_rows: int, width: int) -> np.ndarray:
     """Non-negative float32 cost rows (exactly representable values)."""
     rng = np.random.default_rng(seed)
     return (rng.integers(0, 1 << 16, size=(n_rows, width)).astype(np.float32) / np.float32(4096.0))
+
+
+def _workload_args(args):
+    return workload(*args)
+
+
+def workload_batch(cfg: int, n: int = None, processes: int = 16):
+    """All pairs of a batched workload, generated in parallel host processes."""
+    n = N_PAIRS[cfg] if n is None else n
+    if n == 1 or processes <= 1:
+        return [workload(cfg, i) for i in range(n)]
+    from multiprocessing import get_context
+    with get_context("fork").Pool(min(processes, n)) as pool:
+        return pool.map(_workload_args, [(cfg, i) for i in range(n)])

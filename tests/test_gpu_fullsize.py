@@ -1,0 +1,188 @@
+"""GPU parity at the benchmark sizes, in the launch configuration bench.py
+times: trees and level order bit-exact on whole arrays, aggregated costs on
+sampled label slices the oracle computes one by one, WTA labels identical
+except at near-ties.  Batched runs are checked on spot pairs against
+single-pair oracle runs."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1509_08197_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def H():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1509_08197_amd import hdp
+    hdp.lib()
+    return hdp
+
+
+def rgb_dev(*imgs):
+    return torch.from_numpy(np.ascontiguousarray(
+        np.concatenate([im.reshape(-1, 3) for im in imgs]))).cuda()
+
+
+def rows_to_pixels(vol, node, lo, hi, labels, n):
+    """Values of a [n][width] volume at the given labels, pixel order (NaN outside)."""
+    out = np.full((len(labels), n), np.nan)
+    for k, x in enumerate(labels):
+        j = x - lo[node]
+        ok = (j >= 0) & (x <= hi[node]) & (j < vol.shape[1])
+        out[k, node[ok]] = vol[ok, j[ok]]
+    return out
+
+
+def assert_rel(got, ref, what):
+    m = ~np.isnan(ref)
+    assert np.array_equal(np.isnan(got), np.isnan(ref)), f"{what}: support differs"
+    err = np.abs(got[m] - ref[m]) / np.abs(ref[m])
+    assert err.max() <= REL, f"{what}: max rel err {err.max():.3g}"
+
+
+def check_layer(H, orc, lres, ores, labels, what):
+    f = lres.forest
+    n = f.n
+    torch.cuda.synchronize()
+    A = {k: f.array(k).cpu().numpy() for k in ("parent", "depth", "order", "node", "lo", "hi",
+                                                 "level_ptr")}
+    info = f.read_info()
+    assert info[7] == 0, f"{what}: guard {info[7]}"
+    np.testing.assert_array_equal(A["parent"], ores["parent"], err_msg=f"{what} parent")
+    np.testing.assert_array_equal(A["depth"], ores["depth"], err_msg=f"{what} depth")
+    np.testing.assert_array_equal(A["order"], ores["order"], err_msg=f"{what} order")
+    nl = ores["n_levels"]
+    np.testing.assert_array_equal(A["level_ptr"][:nl + 1], ores["level_ptr"])
+    got = rows_to_pixels(lres.agg.cpu().numpy(), A["node"], A["lo"], A["hi"], labels, n)
+    assert_rel(got, ores["sample_agg"], f"{what} aggregate")
+    d = lres.disp.cpu().numpy()
+    o = ores["disp"].ravel()
+    mism = d != o
+    near = (ores["c2"] - ores["c1"]) <= REL * np.abs(ores["c1"])
+    assert np.all(near[mism]), f"{what}: {int((mism & ~near).sum())} WTA mismatches off near-ties"
+    return int(mism.sum())
+
+
+def test_full_range_1344x1104(H, orc):
+    pair = scenes.workload(2)
+    Hh, Ww = pair.shape
+    shapes = [(Hh, Ww, 255)]
+    res = H.full_range(rgb_dev(pair.left), rgb_dev(pair.right), shapes, keep=True)
+    labels = [0, 37, 128, 255]
+    o = orc.stereo_level(pair.left.astype(np.float64), pair.right.astype(np.float64), 255, 0,
+                         sample_d=labels)
+    nm = check_layer(H, orc, res, o, labels, "full range 1344x1104")
+    print(f"full range: {nm} WTA near-tie mismatches")
+
+
+def test_hdp_layers_1344x1104_teacher_forced(H, orc):
+    """Every layer of the HDP step at full size, fed the oracle's labels of the
+    layer above (no inputs from the GPU path reach the oracle)."""
+    pair = scenes.workload(2)
+    Hh, Ww = pair.shape
+    P = scenes.HDP_PARAMS[2]
+    S, L, w = P["S"], P["L"], P["window"]
+    lv = H.level_shapes([(Hh, Ww, 255)], S, L)
+    lp = H.pyramid(rgb_dev(pair.left), [(Hh, Ww, 255)], S, L)
+    rp = H.pyramid(rgb_dev(pair.right), [(Hh, Ww, 255)], S, L)
+    ol = orc.pyramid(pair.left, S, L)
+    orr = orc.pyramid(pair.right, S, L)
+    # top layer: MST over the full range
+    dL = lv[L][0][2]
+    labels = [0, dL // 2, dL]
+    o = orc.stereo_level(ol[L], orr[L], dL, L, sample_d=labels)
+    r = H.stereo_level(lp[L], rp[L], lv[L], L, keep=True)
+    check_layer(H, orc, r, o, labels, f"layer {L}")
+    up = o["disp"]
+    for l in range(L - 1, -1, -1):
+        dl = lv[l][0][2]
+        lo, hi = orc.predict_range(up, lv[l][0][0], lv[l][0][1], S, w, dl)
+        labels = [int(np.median(lo)), int(np.median(hi)), dl]
+        o = orc.stereo_level(ol[l], orr[l], dl, l, lo, hi, beta=P["beta"], sample_d=labels)
+        glo, ghi = H.predict_range(torch.from_numpy(up.ravel().astype(np.int32)).cuda(),
+                                   lv[l + 1], lv[l], S, w)
+        np.testing.assert_array_equal(glo.cpu().numpy(), lo.ravel())
+        np.testing.assert_array_equal(ghi.cpu().numpy(), hi.ravel())
+        r = H.stereo_level(lp[l], rp[l], lv[l], l, glo, ghi, max_width=min(S + 2 * w, dl + 1),
+                           beta=P["beta"], keep=True)
+        nm = check_layer(H, orc, r, o, labels, f"layer {l}")
+        np.testing.assert_array_equal(r.forest.array("lo").cpu().numpy(), o["tree_lo"])
+        print(f"layer {l}: {nm} WTA near-tie mismatches")
+        up = o["disp"]
+
+
+def tree_signature(parent):
+    """Per pixel: (root, size, sum of member ids, sum of parent ids) of its tree."""
+    n = len(parent)
+    root = np.where(parent >= 0, parent, np.arange(n))
+    for _ in range(40):
+        nxt = root[root]
+        if np.array_equal(nxt, root):
+            break
+        root = nxt
+    size = np.bincount(root, minlength=n)
+    ids = np.bincount(root, weights=np.arange(n, dtype=np.float64), minlength=n)
+    pars = np.bincount(root, weights=parent.astype(np.float64), minlength=n)
+    return np.stack([root, size[root], ids[root], pars[root]], axis=1)
+
+
+def _end_to_end_pair(H, orc, gpu_res, off, pair, P, lv_index):
+    """Compare one pair of a batched GPU run with a single-pair oracle run.
+    A label may differ only at an oracle near-tie, or where an upstream near-tie
+    changed the pixel's disparity tree (its interval or its members)."""
+    ores = orc.hdp_stereo(pair.left, pair.right, pair.dmax, S=P["S"], L=P["L"],
+                          window=P["window"], beta=P["beta"], want_forest=True)
+    L = P["L"]
+    for l in range(L, -1, -1):
+        n_l = ores[l]["disp"].size
+        o0 = off[l][lv_index]
+        g = gpu_res[l].disp.cpu().numpy()[o0:o0 + n_l]
+        o = ores[l]["disp"].ravel()
+        gap = (ores[l]["c2"] - ores[l]["c1"]) / ores[l]["c1"]
+        mism = g != o
+        par = gpu_res[l].forest.array("parent").cpu().numpy()[o0:o0 + n_l]
+        par = np.where(par >= 0, par - o0, -1)
+        if l == L:  # top layer: same inputs, so the tree is identical
+            np.testing.assert_array_equal(par, ores[l]["parent"], err_msg="top layer tree")
+            same = np.ones_like(mism)
+        else:
+            glo = gpu_res[l].pix_lo.cpu().numpy()[o0:o0 + n_l]
+            same = (glo == ores[l]["pix_lo"].ravel()) & np.all(
+                tree_signature(par) == tree_signature(ores[l]["parent"]), axis=1)
+        assert np.all(gap[mism & same] <= REL), f"layer {l}: unexplained label mismatches"
+        print(f"pair {lv_index} layer {l}: {int(mism.sum())} differing labels, "
+              f"{int((~same).sum())} pixels with a different tree upstream")
+
+
+@pytest.mark.parametrize("cfg", [3, 5])
+def test_batched_spot_pairs(H, orc, cfg):
+    """Full batch of uneven pairs in one call (as benchmarked); spot pairs
+    against single-pair oracle runs, layer by layer."""
+    P = scenes.HDP_PARAMS[cfg]
+    pairs = scenes.workload_batch(cfg)
+    shapes = [(p.shape[0], p.shape[1], p.dmax) for p in pairs]
+    res = H.hdp_stereo(rgb_dev(*[p.left for p in pairs]), rgb_dev(*[p.right for p in pairs]),
+                       shapes, S=P["S"], L=P["L"], window=P["window"], beta=P["beta"])
+    lv = H.level_shapes(shapes, P["S"], P["L"])
+    off = [np.concatenate([[0], np.cumsum([h * w for h, w, _ in lv[l]])]) for l in range(P["L"] + 1)]
+    for i in (0, len(pairs) // 2, len(pairs) - 1):
+        _end_to_end_pair(H, orc, res, off, pairs[i], P, i)
+
+
+def test_largest_pair_mst(H, orc):
+    """One pair at the largest supported size (2^22 - 1 pixels limit): the MST
+    and its level order bit-exact, one aggregated slice within tolerance."""
+    Hh, Ww, d = 2047, 2048, 3
+    pair = scenes.small_scene(99, Hh, Ww, d)
+    shapes = [(Hh, Ww, d)]
+    res = H.full_range(rgb_dev(pair.left), rgb_dev(pair.right), shapes, keep=True)
+    o = orc.stereo_level(pair.left.astype(np.float64), pair.right.astype(np.float64), d, 0,
+                         sample_d=[1])
+    check_layer(H, orc, res, o, [1], "2047x2048")
