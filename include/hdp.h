@@ -263,6 +263,39 @@ HDP_API hdp_status hdp_predict_range(const int32_t *disp_upper, const hdp_shape 
                              const hdp_shape *lower, int32_t n_pairs, int32_t S,
                              int32_t window, int32_t *pix_lo, int32_t *pix_hi, void *stream);
 
+/*
+ * Batch plan: the whole top-down loop of the method (Section 3) for a fixed
+ * batch of pairs.  Layer L (the top of the graph pyramid) is searched over
+ * [0, d_L] with the minimum spanning tree; every layer l < L predicts its pixel
+ * intervals from layer l+1 (hdp_predict_range), builds the disparity forest,
+ * the restricted cost, the aggregation and the WTA.
+ * hdp_plan_create allocates every buffer once (this is the only place the
+ * library allocates) and captures one step into a HIP graph; hdp_plan_run
+ * copies the inputs (device pointers, uint8 [n0][3], NULL = already in the
+ * plan's input buffers, see hdp_plan_inputs), launches the graph on `stream`
+ * and copies the layer-0 labels to disp (device int32 [n0], NULL = skip).
+ * Runs on one plan must not overlap.  Layer results stay readable through
+ * hdp_plan_layer until the next run.
+ */
+typedef struct {
+    int32_t S, L;                 /* pyramid factor (2) and layers above the input */
+    int32_t window;               /* half-width w of the predicted interval */
+    int32_t beta_num, beta_den;   /* DT-Rule 2 threshold beta = num/den */
+    float sigma;                  /* smoothing constant */
+    hdp_cost_params cost;
+} hdp_params;
+
+typedef struct hdp_plan_s *hdp_plan;
+
+HDP_API hdp_status hdp_plan_create(const hdp_shape *shapes, int32_t n_pairs, const hdp_params *p,
+                                   hdp_plan *out);
+HDP_API hdp_status hdp_plan_run(hdp_plan plan, const uint8_t *left_rgb, const uint8_t *right_rgb,
+                                int32_t *disp, void *stream);
+HDP_API hdp_status hdp_plan_layer(hdp_plan plan, int32_t level, const hdp_forest **forest,
+                                  const int32_t **disp, const float **agg, int32_t *width);
+HDP_API hdp_status hdp_plan_inputs(hdp_plan plan, uint8_t **left_rgb, uint8_t **right_rgb);
+HDP_API hdp_status hdp_plan_destroy(hdp_plan plan);
+
 HDP_API const char *hdp_status_str(hdp_status s);
 
 /*

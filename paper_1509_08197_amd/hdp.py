@@ -45,6 +45,12 @@ class CostParams(C.Structure):
                 ("tau_g", C.c_float)]
 
 
+class Params(C.Structure):
+    _fields_ = [("S", C.c_int32), ("L", C.c_int32), ("window", C.c_int32),
+                ("beta_num", C.c_int32), ("beta_den", C.c_int32), ("sigma", C.c_float),
+                ("cost", CostParams)]
+
+
 class ForestStruct(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in (
         "parent", "depth", "tree", "lo", "hi", "row", "wgt", "order", "level_ptr", "node",
@@ -90,6 +96,15 @@ def _declare(L):
     L.hdp_status_str.argtypes = [I32]; L.hdp_status_str.restype = C.c_char_p
     L.hdp_timer_arm.argtypes = [I32]; L.hdp_timer_arm.restype = I32
     L.hdp_set_schedule.argtypes = [I32, I32, I32]; L.hdp_set_schedule.restype = I32
+    L.hdp_plan_create.argtypes = [P, I32, C.POINTER(Params), C.POINTER(C.c_void_p)]
+    L.hdp_plan_run.argtypes = [P, P, P, P, P]
+    L.hdp_plan_layer.argtypes = [P, I32, C.POINTER(C.POINTER(ForestStruct)),
+                                 C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(I32)]
+    L.hdp_plan_inputs.argtypes = [P, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]
+    L.hdp_plan_destroy.argtypes = [P]
+    for name in ("hdp_plan_create", "hdp_plan_run", "hdp_plan_layer", "hdp_plan_inputs",
+                 "hdp_plan_destroy"):
+        getattr(L, name).restype = I32
     L.hdp_timer_read.argtypes = [P, P]; L.hdp_timer_read.restype = I32
     for name in ("hdp_forest_bind", "hdp_level_shapes", "hdp_pyramid", "hdp_build_tree",
                  "hdp_forest_read_info", "hdp_cost_volume", "hdp_aggregate",
@@ -442,3 +457,59 @@ class CapturedStep:
     def replay(self):
         self.graph.replay()
         return self.out
+
+
+_hip = None
+
+
+def _hip_d2d(dst: int, src: int, nbytes: int):
+    """Device-to-device copy on the current stream (HIP runtime)."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+        _hip.hipMemcpyAsync.restype = C.c_int
+    if _hip.hipMemcpyAsync(C.c_void_p(dst), C.c_void_p(src), nbytes, 3, _stream()) != 0:
+        raise HdpError("hipMemcpyAsync", -5)
+
+
+class Plan:
+    """Native batch plan (C ABI hdp_plan_*): the whole top-down loop for a fixed
+    batch, buffers allocated once, one HIP graph launch per run."""
+
+    def __init__(self, shapes, S=2, L=3, window=4, beta=(19, 20), sigma=0.1, params=None):
+        self.shapes = list(shapes)
+        self.n0 = n_pixels(shapes)
+        p = Params(S, L, window, beta[0], beta[1], sigma, params or cost_params())
+        h = C.c_void_p()
+        _check("hdp_plan_create", lib().hdp_plan_create(_shapes(shapes), len(shapes), C.byref(p),
+                                                        C.byref(h)))
+        self.h = h
+        self.L = L
+
+    def run(self, left_rgb=None, right_rgb=None, disp: Optional[torch.Tensor] = None):
+        _check("hdp_plan_run", lib().hdp_plan_run(self.h, _ptr(left_rgb), _ptr(right_rgb),
+                                                  _ptr(disp), _stream()))
+        return disp
+
+    def layer_disp(self, level: int) -> torch.Tensor:
+        """Copy of the labels of one layer (after a run)."""
+        f = C.POINTER(ForestStruct)()
+        d = C.c_void_p()
+        _check("hdp_plan_layer", lib().hdp_plan_layer(self.h, level, C.byref(f), C.byref(d), None,
+                                                      None))
+        n = f.contents.n
+        out = torch.empty(n, dtype=torch.int32, device="cuda")
+        _hip_d2d(out.data_ptr(), d.value, 4 * n)
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hdp_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

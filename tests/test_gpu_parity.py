@@ -391,3 +391,22 @@ def test_autograd_tree_aggregate(H, orc):
     B = np.where(par >= 0, B * s / sigma, 0.0)
     assert np.all(np.abs(grads[0][2] - dw) <= REL * B + 1e-30)
     assert abs(grads[0][1] - ds) <= REL * float(np.sum(B * wg / sigma))
+
+
+def test_native_plan_matches_binding(H):
+    """The C-level batch plan (one HIP graph launch per run) gives the labels of
+    the Python-orchestrated loop on every layer, for two different inputs."""
+    shapes = [(70, 90, 63), (41, 57, 31)]
+    plan = H.Plan(shapes, S=2, L=2, window=4)
+    for seed in (0, 1):
+        pairs = [scenes.small_scene(300 + 10 * seed + i, h, w, d) for i, (h, w, d) in enumerate(shapes)]
+        L_rgb = rgb_dev(*[p.left for p in pairs]); R_rgb = rgb_dev(*[p.right for p in pairs])
+        ref = H.hdp_stereo(L_rgb, R_rgb, shapes, S=2, L=2, window=4)
+        disp = torch.empty(sum(h * w for h, w, _ in shapes), dtype=torch.int32, device="cuda")
+        plan.run(L_rgb, R_rgb, disp)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(disp.cpu().numpy(), ref[0].disp.cpu().numpy())
+        for l in (1, 2):
+            np.testing.assert_array_equal(plan.layer_disp(l).cpu().numpy(),
+                                          ref[l].disp.cpu().numpy())
+    plan.close()
