@@ -82,6 +82,22 @@ def pass_bytes(forest, up: bool) -> float:
     return 8.0 * n * w + 4.0 * heads * w + 21.0 * n + (8.0 * heads if up else 0.0)
 
 
+def measured_traffic():
+    """HBM bytes per aggregation-pass launch from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known size), or None
+    once the kernel source has changed since the counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        rec = json.load(open(os.path.join(root, "profiles", "k_pass_traffic.json")))
+        src = open(os.path.join(root, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -167,7 +183,8 @@ def main():
         achieved = byts / secs / 1e9
         out["roofline"] = {"kernel": "k_pass (two-pass aggregation, up and down)",
                            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": measured_traffic(),
                            "launches": launches, "avg_launch_us": secs / launches * 1e6,
                            "algorithmic_bytes_per_launch": byts / launches}
         del step
