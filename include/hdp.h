@@ -26,6 +26,8 @@
  *    while enqueueing is returned as HDP_EHIP.  No C++ exception crosses the
  *    ABI.
  *  - Labels are 0..dmax inclusive.
+ *  - Size limits: each pair at most 2^22 - 1 pixels, a batch at most 2^30 - 1
+ *    pixels per layer (HDP_ESHAPE otherwise).
  */
 #ifndef HDP_H_
 #define HDP_H_
@@ -65,7 +67,7 @@ typedef struct {
 
 /* Indices into hdp_forest.info (device int32 words written by hdp_build_tree). */
 enum {
-    HDP_INFO_N_LEVELS = 0,   /* 1 + largest depth */
+    HDP_INFO_N_LEVELS = 0,   /* 1 + largest depth (written by hdp_level_order) */
     HDP_INFO_N_PHASES = 1,   /* number of chain phases (1 + largest light depth) */
     HDP_INFO_N_TREES = 2,    /* number of trees in the forest */
     HDP_INFO_WIDTH = 3,      /* row width of the volume layout (labels per row) */
@@ -91,7 +93,8 @@ enum {
  *           roots.
  *   lo, hi  tree interval TreeIntv of the pixel's tree (labels).
  *   row     row of the pixel in the volume layout below.
- * Level order (canonical; not used by the aggregation schedule):
+ * Level order (canonical; written by hdp_level_order, not by hdp_build_tree,
+ * and not used by the aggregation schedule):
  *   order   pixel ids sorted by (depth, id); level_ptr[k] = first position of
  *           depth k, level_ptr[n_levels] = n.  level_ptr has n + 1 entries.
  * Volume layout: a cost or aggregated volume is float[n][width]; row r holds
@@ -173,6 +176,15 @@ HDP_API hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int
                           int32_t max_width, int32_t beta_num, int32_t beta_den,
                           int32_t width, const hdp_forest *f, void *ws, size_t ws_bytes,
                           void *stream);
+
+/*
+ * Canonical level order of a forest built by hdp_build_tree: order (pixel ids
+ * sorted by depth, ties by id), level_ptr and info[HDP_INFO_N_LEVELS].  This
+ * is the breadth-first processing order of the tree passes of Section 1; the
+ * aggregation here runs on the chain-phase rows instead and does not need it.
+ *   ws   scratch of at least hdp_build_tree_workspace_bytes(f->n) bytes.
+ */
+HDP_API hdp_status hdp_level_order(const hdp_forest *f, void *ws, size_t ws_bytes, void *stream);
 
 /* Host copy of the forest's scalars and phase table (synchronises `stream`;
  * diagnostics only, nothing on the hot path needs it).  Either pointer may be

@@ -32,7 +32,7 @@ void timer_after(int kernel_class, hipStream_t st) {
 
 namespace {
 
-constexpr int64_t kMaxPixels = (int64_t(1) << 30);  // tour slots 4n fit in int32
+constexpr int64_t kMaxPixels = (int64_t(1) << 30) - 1;  // tour slot ids 4v+d below 2^32 - 1
 constexpr int64_t kMaxPairPixels = (int64_t(1) << 22) - 1;  // packed depth field
 
 hdp_status last_hip() {
@@ -46,12 +46,14 @@ hdp_status make_geom(const hdp_shape *shapes, int32_t n_pairs, int32_t level, Le
     std::memset(g, 0, sizeof(*g));
     g->n_pairs = n_pairs;
     g->level = level;
-    int64_t off = 0;
+    int64_t off = 0, toff = 0;
     for (int i = 0; i < n_pairs; ++i) {
         const hdp_shape &s = shapes[i];
         if (s.H < 1 || s.W < 1 || s.dmax < 0 || s.dmax >= HDP_MAX_LABELS) return HDP_ESHAPE;
         int64_t px = (int64_t)s.H * s.W;
         if (px > kMaxPairPixels) return HDP_ESHAPE;
+        g->toff[i] = (int32_t)toff;
+        toff += (int64_t)((s.H + hdp::kTile - 1) / hdp::kTile) * ((s.W + hdp::kTile - 1) / hdp::kTile);
         g->off[i] = (int32_t)off;
         g->H[i] = s.H;
         g->W[i] = s.W;
@@ -60,6 +62,7 @@ hdp_status make_geom(const hdp_shape *shapes, int32_t n_pairs, int32_t level, Le
         if (off > kMaxPixels) return HDP_ESHAPE;
     }
     g->off[n_pairs] = (int32_t)off;
+    g->toff[n_pairs] = (int32_t)toff;
     return HDP_OK;
 }
 
@@ -206,6 +209,15 @@ hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int32_t n_p
     if (ws_bytes < hdp::tree_workspace_bytes(n)) return HDP_EWORKSPACE;
     (void)hipGetLastError();
     hdp::launch_build_tree(img, g, pix_lo, pix_hi, max_width, width, *f, ws, (hipStream_t)stream);
+    return last_hip();
+}
+
+hdp_status hdp_level_order(const hdp_forest *f, void *ws, size_t ws_bytes, void *stream) {
+    if (!f || !ws) return HDP_EINVAL;
+    if (f->n < 1 || !forest_ok(f, f->n)) return HDP_EINVAL;
+    if (ws_bytes < hdp::tree_workspace_bytes(f->n)) return HDP_EWORKSPACE;
+    (void)hipGetLastError();
+    hdp::launch_level_order(*f, ws, (hipStream_t)stream);
     return last_hip();
 }
 

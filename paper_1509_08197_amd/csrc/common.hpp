@@ -18,7 +18,10 @@ struct LevelGeom {
     int32_t H[HDP_MAX_PAIRS];
     int32_t W[HDP_MAX_PAIRS];
     int32_t dmax[HDP_MAX_PAIRS];
+    int32_t toff[HDP_MAX_PAIRS + 1];  // first kTile x kTile tile of each pair (row-major tiles)
 };
+
+constexpr int kTile = 32;  // side of the square pixel tiles of the tree builder's local phases
 
 // Pair that holds global pixel v (binary search over the offsets).
 __device__ __forceinline__ int pair_of(const LevelGeom &g, int v) {

@@ -18,6 +18,7 @@ size_t tree_workspace_bytes(int64_t n);
 void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
                        const int32_t *phi, int max_width, int width, const hdp_forest &f,
                        void *ws, hipStream_t st);
+void launch_level_order(const hdp_forest &f, void *ws, hipStream_t st);
 void launch_set_weights(const hdp_forest &f, const float *w, hipStream_t st);
 size_t aggregate_workspace_bytes(int64_t n, int width);
 bool set_schedule(int width, int cpt, int rpg);

@@ -35,233 +35,883 @@ enum {
     FLAG_WORDS = 128
 };
 
-// --- 1. edge keys ------------------------------------------------------------
+enum {
+    CTR_E = 0,      // live edges after the tile-local phase
+    CTR_RALL = 1,   // active components after the tile-local phase
+    CTR_ET = 2,     // edges left for the one-workgroup tail
+    CTR_RUNS = 3,   // run ends of the tile-local tour ranking
+    CTR_AT = 4,     // run ends left for the one-workgroup tail
+    kCounters = 8
+};
 
-__global__ void k_edge_keys(const float4 *__restrict__ img, LevelGeom g,
-                            const int32_t *__restrict__ plo, const int32_t *__restrict__ phi,
-                            int max_width, uint32_t *__restrict__ key, int32_t *__restrict__ info) {
-    int64_t v = gtid();
-    if (v >= g.off[g.n_pairs]) return;
-    PixelPos p = pixel_pos(g, (int)v);
-    float scale = ldexpf(1.0f, 2 * g.level);
-    float4 a = img[v];
-    if (plo) {
-        int lo = plo[v], hi = phi[v];
-        if (lo < 0 || hi < lo || hi > g.dmax[p.pair] || hi - lo + 1 > max_width)
-            atomicAdd(&info[HDP_INFO_BAD_INTERVAL], 1);
+// Rounds run by full-grid launches before one workgroup finishes the rest.
+constexpr int kBvGridRounds = 4;
+constexpr int kRankGridRounds = 8;
+
+// --- shared helpers ------------------------------------------------------------------
+
+constexpr int kLocalThreads = 1024;  // one workgroup per tile, one thread per pixel
+constexpr int kTilePx = kTile * kTile;
+constexpr int kGridCap = 1024;       // workgroups of the grid-stride list kernels
+
+__device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier for a workgroup that exchanges data through device-coherent global
+// memory: every wave's memory operations complete before the barrier.
+__device__ __forceinline__ void wg_sync() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Slot in a list for each lane with pred set: one atomic per wavefront.
+__device__ __forceinline__ int wave_append(bool pred, int32_t *count) {
+    uint64_t m = __ballot(pred);
+    if (m == 0) return -1;
+    int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(count, __popcll(m));
+    base = __shfl(base, leader, 64);
+    return base + __popcll(m & lanemask_lt());
+}
+
+struct TileInfo {
+    int pair, x0, y0, tw, th, W, H, base;
+};
+
+__device__ __forceinline__ TileInfo tile_info(const LevelGeom &g, int t) {
+    int lo = 0, hi = g.n_pairs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (g.toff[mid] <= t) lo = mid; else hi = mid - 1;
     }
-    for (int dir = 0; dir < 2; ++dir) {
-        bool inside = dir == 0 ? p.x + 1 < p.W : p.y + 1 < p.H;
-        uint32_t k = kNoKey;
-        if (inside) {
-            int64_t q = dir == 0 ? v + 1 : v + p.W;
-            if (!plo || (plo[v] == plo[q] && phi[v] == phi[q])) {
-                float4 b = img[q];
-                float m = fmaxf(fmaxf(fabsf(a.x - b.x), fabsf(a.y - b.y)), fabsf(a.z - b.z));
-                k = __float2uint_rn(m * scale);
+    TileInfo ti;
+    ti.pair = lo;
+    ti.W = g.W[lo];
+    ti.H = g.H[lo];
+    ti.base = g.off[lo];
+    int k = t - g.toff[lo];
+    int ntx = (ti.W + kTile - 1) / kTile;
+    int ty = k / ntx;
+    ti.x0 = (k - ty * ntx) * kTile;
+    ti.y0 = ty * kTile;
+    ti.tw = min(kTile, ti.W - ti.x0);
+    ti.th = min(kTile, ti.H - ti.y0);
+    return ti;
+}
+
+__device__ __forceinline__ int64_t tile_pixel(const TileInfo &t, int i) {
+    return t.base + (int64_t)(t.y0 + (i >> 5)) * t.W + t.x0 + (i & (kTile - 1));
+}
+
+// Integer edge key 4^level * max_c |dI_c| (exact: level images hold dyadic means).
+__device__ __forceinline__ uint32_t edge_key(float4 a, float4 b, float scale) {
+    float m = fmaxf(fmaxf(fabsf(a.x - b.x), fabsf(a.y - b.y)), fabsf(a.z - b.z));
+    return __float2uint_rn(m * scale);
+}
+
+__device__ __forceinline__ bool same_interval(const int32_t *plo, const int32_t *phi, int64_t v,
+                                              int64_t q) {
+    return !plo || (plo[v] == plo[q] && phi[v] == phi[q]);
+}
+
+__device__ __forceinline__ uint64_t key64(uint32_t k, int64_t eid) {
+    return ((uint64_t)k << 32) | (uint64_t)(uint32_t)eid;
+}
+
+__global__ void k_tree_init(int32_t *__restrict__ flags, int32_t *__restrict__ ctr,
+                            int32_t *__restrict__ info) {
+    int t = threadIdx.x;
+    if (t < FLAG_WORDS) flags[t] = 0;
+    if (t < kCounters) ctr[t] = 0;
+    if (t < HDP_INFO_WORDS) info[t] = 0;
+}
+
+// --- 1-2. spanning forest: tile-local phase ---------------------------------------
+// Every kTile x kTile tile runs Boruvka in LDS on its own pixels.  A local
+// component hooks only along its least (key, id) incident edge over ALL its
+// edges, including those that leave the tile; when that edge leaves the tile
+// the component waits for the global phase.  By the cut property every edge
+// taken is an edge of the minimum spanning forest, and when the loop stops
+// every component that still has an incident edge owns a pixel on the tile
+// border, which bounds the work left to the global rounds.
+//
+// Components are named by the pixel id of their local root.  cw[x] packs the
+// parent link of component x: low 32 bits the parent (x itself for a root),
+// high 32 bits 0 for a permanent link or r + 1 for a hook made in round r.
+
+__global__ __launch_bounds__(kLocalThreads) void k_local_msf(
+    const float4 *__restrict__ img, LevelGeom g, const int32_t *__restrict__ plo,
+    const int32_t *__restrict__ phi, int max_width, int32_t *__restrict__ comp0,
+    uint64_t *__restrict__ cw, uint64_t *__restrict__ best0, uint64_t *__restrict__ best1,
+    int32_t *__restrict__ lmin, int32_t *__restrict__ croot, int32_t *__restrict__ mnroot,
+    uint8_t *__restrict__ intree, uint64_t *__restrict__ E, int32_t *__restrict__ R,
+    int32_t *__restrict__ ctr, int32_t *__restrict__ info) {
+    __shared__ uint32_t kL[kTile], kU[kTile];
+    __shared__ int32_t lab[kTilePx], hk[kTilePx];
+    __shared__ unsigned long long best[kTilePx];
+    __shared__ int s_flag, s_nE, s_nR, s_bE, s_bR;
+    const TileInfo t = tile_info(g, blockIdx.x);
+    const float scale = ldexpf(1.0f, 2 * g.level);
+    const int i = threadIdx.x;
+    const int lx = i & (kTile - 1), ly = i >> 5;
+    const bool valid = lx < t.tw && ly < t.th;
+    const int64_t v = valid ? tile_pixel(t, i) : 0;
+    if (i < kTile) {
+        kL[i] = kNoKey;
+        kU[i] = kNoKey;
+    }
+    if (i == 0) {
+        s_nE = 0;
+        s_nR = 0;
+    }
+    lab[i] = i;
+    hk[i] = i;
+    __syncthreads();
+    // keys of the owned right / down edges (and of the edges entering from the
+    // left / top neighbour tiles); an edge between different intervals is absent
+    uint32_t kr = kNoKey, kd = kNoKey;
+    if (valid) {
+        int x = t.x0 + lx, y = t.y0 + ly;
+        float4 a = img[v];
+        if (plo) {
+            int lo = plo[v], hi = phi[v];
+            if (lo < 0 || hi < lo || hi > g.dmax[t.pair] || hi - lo + 1 > max_width)
+                atomicAdd(&info[HDP_INFO_BAD_INTERVAL], 1);
+        }
+        if (x + 1 < t.W && same_interval(plo, phi, v, v + 1)) kr = edge_key(a, img[v + 1], scale);
+        if (y + 1 < t.H && same_interval(plo, phi, v, v + t.W)) kd = edge_key(a, img[v + t.W], scale);
+        if (lx == 0 && x > 0 && same_interval(plo, phi, v - 1, v))
+            kL[ly] = edge_key(img[v - 1], a, scale);
+        if (ly == 0 && y > 0 && same_interval(plo, phi, v - t.W, v))
+            kU[lx] = edge_key(img[v - t.W], a, scale);
+        intree[2 * v] = 0;
+        intree[2 * v + 1] = 0;
+    }
+    const bool r_in = lx + 1 < t.tw, d_in = ly + 1 < t.th;
+    __syncthreads();
+    const uint32_t kl = lx == 0 ? kL[ly] : kNoKey, ku = ly == 0 ? kU[lx] : kNoKey;
+    auto offer = [&](int c, uint64_t k) {
+        if (best[c] > k) atomicMin(&best[c], (unsigned long long)k);
+    };
+    // Boruvka rounds in LDS until no component hooks (each round with a hook
+    // removes at least one component, so the loop ends)
+    for (int iter = 0; iter < kTilePx; ++iter) {
+        best[i] = kNoEdge;
+        if (i == 0) s_flag = 0;
+        __syncthreads();
+        if (valid) {
+            int c = lab[i];
+            if (kr != kNoKey) {
+                uint64_t k = key64(kr, 2 * v);
+                int cj = r_in ? lab[i + 1] : -1;
+                if (cj != c) {
+                    offer(c, k);
+                    if (cj >= 0) offer(cj, k);
+                }
+            }
+            if (kd != kNoKey) {
+                uint64_t k = key64(kd, 2 * v + 1);
+                int cj = d_in ? lab[i + kTile] : -1;
+                if (cj != c) {
+                    offer(c, k);
+                    if (cj >= 0) offer(cj, k);
+                }
+            }
+            if (kl != kNoKey) offer(c, key64(kl, 2 * (v - 1)));
+            if (ku != kNoKey) offer(c, key64(ku, 2 * (v - t.W) + 1));
+        }
+        __syncthreads();
+        uint64_t b = best[i];
+        if (valid && lab[i] == i && b != kNoEdge) {
+            uint32_t e = (uint32_t)b;
+            int pl = (int)(e >> 1) - t.base;  // pixel offsets inside the pair fit in 32 bits
+            int ql = (e & 1) ? pl + t.W : pl + 1;
+            int py = pl / t.W, px = pl - py * t.W;
+            int qy = ql / t.W, qx = ql - qy * t.W;
+            bool inside = px >= t.x0 && px < t.x0 + t.tw && py >= t.y0 && py < t.y0 + t.th &&
+                          qx >= t.x0 && qx < t.x0 + t.tw && qy >= t.y0 && qy < t.y0 + t.th;
+            if (inside) {  // a least edge that leaves the tile waits for the global rounds
+                int cp = lab[(py - t.y0) * kTile + (px - t.x0)];
+                int cq = lab[(qy - t.y0) * kTile + (qx - t.x0)];
+                int other = cp == i ? cq : cp;
+                if (!(best[other] == b && i < other)) {  // mutual choice: smaller index stays
+                    hk[i] = other;
+                    intree[e] = 1;
+                    s_flag = 1;
+                }
             }
         }
-        key[2 * v + dir] = k;
+        __syncthreads();
+        if (!s_flag) break;
+        int h = hk[i];
+        if (h != i) {
+            lab[i] = h;
+            hk[i] = i;
+        }
+        __syncthreads();
+        // pointer jumping until every pixel names its root (each change moves a
+        // label to a strict ancestor, so the loop ends)
+        for (int it = 0; it < kTilePx; ++it) {
+            int l = lab[i], ll = lab[l];
+            if (l != ll) lab[i] = ll;
+            if (!__syncthreads_or(l != ll)) break;
+        }
+    }
+    // smallest pixel id of every local component (hk reused)
+    hk[i] = 0x7fffffff;
+    __syncthreads();
+    if (valid) atomicMin(&hk[lab[i]], (int32_t)v);
+    __syncthreads();
+    // live edges (owned right / down edges not inside one component) and
+    // active components (with an incident edge left): reserve, then write
+    const int c = lab[i];
+    const bool live_r = valid && kr != kNoKey && (!r_in || lab[i + 1] != c);
+    const bool live_d = valid && kd != kNoKey && (!d_in || lab[i + kTile] != c);
+    const bool act = valid && c == i && best[i] != kNoEdge;
+    const uint64_t mr = __ballot(live_r), md = __ballot(live_d), ma = __ballot(act);
+    const int lane = i & 63;
+    int wE = 0, wR = 0;
+    if (lane == 0) {
+        wE = atomicAdd(&s_nE, __popcll(mr) + __popcll(md));
+        wR = atomicAdd(&s_nR, __popcll(ma));
+    }
+    __syncthreads();
+    if (i == 0) {
+        s_bE = s_nE ? atomicAdd(&ctr[CTR_E], s_nE) : 0;
+        s_bR = s_nR ? atomicAdd(&ctr[CTR_RALL], s_nR) : 0;
+    }
+    __syncthreads();
+    wE = __shfl(wE, 0, 64) + s_bE;
+    wR = __shfl(wR, 0, 64) + s_bR;
+    const uint64_t lt = lanemask_lt();
+    if (live_r) E[wE + __popcll(mr & lt)] = key64(kr, 2 * v);
+    if (live_d) E[wE + __popcll(mr) + __popcll(md & lt)] = key64(kd, 2 * v + 1);
+    if (act) R[wR + __popcll(ma & lt)] = (int32_t)v;
+    if (valid) {
+        comp0[v] = (int32_t)tile_pixel(t, c);
+        if (c == i) {
+            cw[v] = (uint64_t)(uint32_t)v;
+            best0[v] = kNoEdge;
+            best1[v] = kNoEdge;
+            lmin[v] = hk[i];
+            croot[v] = -1;
+            mnroot[v] = 0x7fffffff;
+        }
     }
 }
 
-// --- 2. Boruvka ----------------------------------------------------------------
+// --- 2. spanning forest: global rounds ---------------------------------------------
+// A few full-grid rounds (minimum edge over the live-edge list, then hooking
+// over the active components; dead edges are marked in place), then the edges
+// still in play are compacted and one workgroup finishes in LDS.  Finds of
+// round r's hooking step ignore round-r hooks, so every thread of that step
+// sees the components as they were when it began.  Within a full-grid launch
+// a thread may read a stale link; every link value ever stored is an ancestor,
+// so a stale read only makes a find longer.
 
-__global__ void k_bv_init(int32_t *__restrict__ comp, int32_t *__restrict__ nxt,
-                          uint64_t *__restrict__ best, int32_t *__restrict__ mn,
-                          uint8_t *__restrict__ intree, int64_t n, int32_t *__restrict__ flags,
-                          int32_t *__restrict__ info) {
-    int64_t v = gtid();
-    if (v < FLAG_WORDS) flags[v] = 0;
-    if (v < HDP_INFO_WORDS && v != HDP_INFO_BAD_INTERVAL) info[v] = 0;
-    if (v >= n) return;
-    comp[v] = (int32_t)v;
-    nxt[v] = (int32_t)v;
-    best[v] = kNoEdge;
-    mn[v] = 0x7fffffff;
-    intree[2 * v] = 0;
-    intree[2 * v + 1] = 0;
+// Root of component x counting the hooks of rounds < cut.  kCoherent: read the
+// links with device-coherent loads (needed when another wave of the same
+// launch stored them and the reader must see it).
+template <bool kCoherent>
+__device__ __forceinline__ int find_comp(const uint64_t *cw, int x, int cut, int32_t *info) {
+    // links form a forest; the bound only guards against a broken invariant
+    for (int it = 0; it < (1 << 24); ++it) {
+        uint64_t w = kCoherent ? ld_relaxed(&cw[x]) : cw[x];
+        int y = (int)(uint32_t)w;
+        int tag = (int)(w >> 32);
+        if (y == x || (tag != 0 && tag - 1 >= cut)) return x;
+        x = y;
+    }
+    info[HDP_INFO_ERROR] = 1;
+    return x;
 }
 
-__global__ void k_info_clear(int32_t *__restrict__ info) {
-    if (threadIdx.x == 0) info[HDP_INFO_BAD_INTERVAL] = 0;
+__device__ __forceinline__ int other_end(const LevelGeom &g, uint32_t e) {
+    int p = (int)(e >> 1);
+    return (e & 1) ? p + g.W[pair_of(g, p)] : p + 1;
 }
 
-__global__ void k_bv_minedge(int round, const int32_t *__restrict__ flags, LevelGeom g,
-                             uint32_t *__restrict__ key, const int32_t *__restrict__ comp,
-                             uint64_t *__restrict__ best) {
+template <bool kCoherent>
+__device__ __forceinline__ uint64_t ld_maybe(const uint64_t *p) {
+    return kCoherent ? ld_relaxed(p) : *p;
+}
+
+// Current components of both ends of edge k (with path shortcuts).
+template <bool kCoherent>
+__device__ __forceinline__ void edge_comps(const LevelGeom &g, uint64_t k,
+                                           const int32_t *__restrict__ comp0, uint64_t *cw, int *a,
+                                           int *b, int32_t *info) {
+    uint32_t e = (uint32_t)k;
+    int p = (int)(e >> 1), q = other_end(g, e);
+    int a0 = comp0[p], b0 = comp0[q];
+    *a = find_comp<kCoherent>(cw, a0, 1 << 30, info);
+    *b = find_comp<kCoherent>(cw, b0, 1 << 30, info);
+    if (*a != a0) st_relaxed(&cw[a0], (uint64_t)(uint32_t)*a);  // shortcut (permanent link)
+    if (*b != b0) st_relaxed(&cw[b0], (uint64_t)(uint32_t)*b);
+}
+
+__device__ __forceinline__ void offer_min(uint64_t *best, int x, uint64_t k, uint64_t seen) {
+    if (seen > k) atomicMin((unsigned long long *)&best[x], (unsigned long long)k);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gbv_minedge(
+    int round, const int32_t *__restrict__ flags, const int32_t *__restrict__ ctr, LevelGeom g,
+    uint64_t *__restrict__ E, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
+    uint64_t *__restrict__ best, int32_t *__restrict__ info) {
     if (round > 0 && flags[FLAG_BV + round - 1] == 0) return;
-    int64_t v = gtid();
-    if (v >= g.off[g.n_pairs]) return;
-    uint2 kk = reinterpret_cast<const uint2 *>(key)[v];
-    if (kk.x == kNoKey && kk.y == kNoKey) return;
-    int cu = comp[v];
-    for (int dir = 0; dir < 2; ++dir) {
-        uint32_t k = dir == 0 ? kk.x : kk.y;
-        if (k == kNoKey) continue;
-        int64_t q = dir == 0 ? v + 1 : v + g.W[pair_of(g, (int)v)];
-        int cq = comp[q];
-        if (cq == cu) {  // both ends already in one component: never needed again
-            key[2 * v + dir] = kNoKey;
+    const int nE = ctr[CTR_E];
+    for (int i = (int)gtid(); i < nE; i += gridDim.x * kBlock) {
+        uint64_t k = E[i];
+        if (k == kNoEdge) continue;
+        int a, b;
+        edge_comps<false>(g, k, comp0, cw, &a, &b, info);
+        if (a == b) {  // both ends in one component: never needed again
+            E[i] = kNoEdge;
             continue;
         }
-        uint64_t k64 = ((uint64_t)k << 32) | (uint64_t)(2 * v + dir);
-        if (best[cu] > k64) atomicMin((unsigned long long *)&best[cu], (unsigned long long)k64);
-        if (best[cq] > k64) atomicMin((unsigned long long *)&best[cq], (unsigned long long)k64);
+        offer_min(best, a, k, best[a]);
+        offer_min(best, b, k, best[b]);
     }
 }
 
-__global__ void k_bv_hook(int round, int32_t *__restrict__ flags, LevelGeom g,
-                          const uint64_t *__restrict__ best, const int32_t *__restrict__ comp,
-                          int32_t *__restrict__ nxt, uint8_t *__restrict__ intree) {
+__global__ __launch_bounds__(kBlock) void k_gbv_hook(
+    int round, int32_t *__restrict__ flags, const int32_t *__restrict__ ctr, LevelGeom g,
+    const int32_t *__restrict__ R, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
+    const uint64_t *__restrict__ best, uint64_t *__restrict__ best_next,
+    uint8_t *__restrict__ intree, int32_t *__restrict__ info) {
     if (round > 0 && flags[FLAG_BV + round - 1] == 0) return;
-    int64_t v = gtid();
-    if (v >= g.off[g.n_pairs]) return;
-    if (comp[v] != v) return;
-    uint64_t b = best[v];
-    if (b == kNoEdge) return;
-    uint32_t e = (uint32_t)b;
-    int p = (int)(e >> 1);
-    int q = (e & 1) ? p + g.W[pair_of(g, p)] : p + 1;
-    int cp = comp[p], cq = comp[q];
-    int other = cp == v ? cq : cp;
-    intree[e] = 1;
-    if (best[other] == b && v < other) return;  // mutual choice: the smaller id stays root
-    nxt[v] = other;
-    flags[FLAG_BV + round] = 1;
-}
-
-__global__ void k_bv_compress(int round, const int32_t *__restrict__ flags,
-                              int32_t *__restrict__ comp, int32_t *__restrict__ nxt,
-                              uint64_t *__restrict__ best, int64_t n, int32_t *__restrict__ info) {
-    if (flags[FLAG_BV + round] == 0) return;
-    int64_t v = gtid();
-    if (v >= n) return;
-    int c = comp[v];
-    int r = c;
-    int s = nxt[r];
-    // the hook pointers form a forest, so the walk ends at a root; the bound
-    // only guards against a broken invariant
-    for (int64_t it = 0; s != r && it < n; ++it) {
-        r = s;
-        s = nxt[r];
+    const int nR = ctr[CTR_RALL];
+    bool hooked = false;
+    for (int j = (int)gtid(); j < nR; j += gridDim.x * kBlock) {
+        int x = R[j];
+        if ((int)(uint32_t)cw[x] != x) continue;  // hooked in an earlier round
+        best_next[x] = kNoEdge;
+        uint64_t b = best[x];
+        if (b == kNoEdge) continue;  // no edge left: its tree is complete
+        uint32_t e = (uint32_t)b;
+        int cp = find_comp<false>(cw, comp0[e >> 1], round, info);
+        int cq = find_comp<false>(cw, comp0[other_end(g, e)], round, info);
+        int other = cp == x ? cq : cp;
+        if (best[other] == b && x < other) continue;  // mutual choice: the smaller id stays root
+        st_relaxed(&cw[x], ((uint64_t)(round + 1) << 32) | (uint32_t)other);
+        intree[e] = 1;
+        hooked = true;
     }
-    if (s != r) info[HDP_INFO_ERROR] = 1;
-    if (c != r) nxt[c] = r;  // path shortcut (any value written is an ancestor)
-    comp[v] = r;
-    best[v] = kNoEdge;
+    if (__ballot(hooked) && (threadIdx.x & 63) == 0) flags[FLAG_BV + round] = 1;
 }
 
-// --- 3. roots -------------------------------------------------------------------
+// edges still joining two components after the full-grid rounds
+__global__ __launch_bounds__(kBlock) void k_gbv_compact(
+    int K, const int32_t *__restrict__ flags, int32_t *__restrict__ ctr, LevelGeom g,
+    const uint64_t *__restrict__ E, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
+    uint64_t *__restrict__ Et, int32_t *__restrict__ info) {
+    if (flags[FLAG_BV + K - 1] == 0) return;
+    const int nE = ctr[CTR_E];
+    for (int i = (int)gtid(); i < nE; i += gridDim.x * kBlock) {
+        uint64_t k = E[i];
+        bool live = false;
+        if (k != kNoEdge) {
+            int a, b;
+            edge_comps<false>(g, k, comp0, cw, &a, &b, info);
+            live = a != b;
+        }
+        int pos = wave_append(live, &ctr[CTR_ET]);
+        if (live) Et[pos] = k;
+    }
+}
 
-// Smallest pixel id of every component.  Lanes of a wavefront that share a
-// component (the common case: components are large and pixels contiguous)
-// combine first, so one atomic per wavefront and component reaches memory.
-__global__ void k_rootmin(const int32_t *__restrict__ comp, int32_t *__restrict__ mn, int64_t n) {
-    __shared__ int s_c0, s_diff;
-    int64_t v = gtid();
-    bool valid = v < n;
-    int c = valid ? comp[v] : -1;
-    if (threadIdx.x == 0) { s_c0 = c; s_diff = 0; }
-    __syncthreads();
-    if (valid && c != s_c0) s_diff = 1;
-    __syncthreads();
-    if (!s_diff) {
-        // the whole workgroup lies in one component; thread 0 holds the smallest id
-        if (threadIdx.x == 0 && valid && mn[c] > (int32_t)v) atomicMin(&mn[c], (int32_t)v);
+// The remaining rounds in one workgroup.  With at most kTE edges and kTN
+// components the contracted graph is loaded into LDS (components renumbered
+// through a hash table) and finished there; otherwise the rounds run on the
+// global arrays with device-coherent loads.
+constexpr int kTE = 4096, kTN = 2048, kTH = 4096;
+
+__device__ __forceinline__ int hash_slot(int key) {
+    return (int)(((uint32_t)key * 2654435761u) >> 20) & (kTH - 1);
+}
+
+__global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
+    int K, int32_t *__restrict__ flags, const int32_t *__restrict__ ctr, LevelGeom g,
+    uint64_t *__restrict__ Et, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
+    uint64_t *__restrict__ best0, uint64_t *__restrict__ best1, uint8_t *__restrict__ intree,
+    int32_t *__restrict__ info) {
+    __shared__ unsigned long long ek[kTE];
+    __shared__ int32_t ea[kTE], eb[kTE];
+    __shared__ int32_t hkey[kTH], hval[kTH];
+    __shared__ int32_t rid[kTN], lab[kTN], hk[kTN], bidx[kTN];
+    __shared__ unsigned long long best[kTN];
+    __shared__ int s_nodes, s_flag;
+    if (flags[FLAG_BV + K - 1] == 0) return;
+    const int nE = ctr[CTR_ET];
+    const int tid = threadIdx.x;
+    bool lds_mode = nE <= kTE;
+    if (lds_mode) {
+        for (int h = tid; h < kTH; h += kLocalThreads) hkey[h] = -1;
+        if (tid == 0) s_nodes = 0;
+        __syncthreads();
+        // components of every edge (no link changes in this launch yet)
+        for (int i = tid; i < nE; i += kLocalThreads) {
+            uint64_t k = Et[i];
+            uint32_t e = (uint32_t)k;
+            int a = find_comp<false>(cw, comp0[e >> 1], 1 << 30, info);
+            int b = find_comp<false>(cw, comp0[other_end(g, e)], 1 << 30, info);
+            ek[i] = k;
+            ea[i] = a;
+            eb[i] = b;
+            for (int c : {a, b}) {
+                int h = hash_slot(c);
+                for (int it = 0; it < kTH; ++it) {
+                    int old = atomicCAS(&hkey[h], -1, c);
+                    if (old == -1 || old == c) break;
+                    h = (h + 1) & (kTH - 1);
+                }
+            }
+        }
+        __syncthreads();
+        for (int h = tid; h < kTH; h += kLocalThreads) {
+            int key = hkey[h];
+            if (key < 0) continue;
+            int idx = atomicAdd(&s_nodes, 1);
+            hval[h] = idx;
+            if (idx < kTN) rid[idx] = key;
+        }
+        __syncthreads();
+        lds_mode = s_nodes <= kTN;
+    }
+    if (lds_mode) {
+        const int nN = s_nodes;
+        auto lookup = [&](int key) {
+            int h = hash_slot(key);
+            for (int it = 0; it < kTH && hkey[h] != key; ++it) h = (h + 1) & (kTH - 1);
+            return hval[h];
+        };
+        for (int i = tid; i < nE; i += kLocalThreads) {
+            ea[i] = lookup(ea[i]);
+            eb[i] = lookup(eb[i]);
+        }
+        for (int j = tid; j < nN; j += kLocalThreads) {
+            lab[j] = j;
+            hk[j] = j;
+        }
+        __syncthreads();
+        for (int iter = 0; iter < kTN; ++iter) {
+            for (int j = tid; j < nN; j += kLocalThreads) best[j] = kNoEdge;
+            if (tid == 0) s_flag = 0;
+            __syncthreads();
+            for (int i = tid; i < nE; i += kLocalThreads) {
+                int ca = lab[ea[i]], cb = lab[eb[i]];
+                if (ca == cb) continue;
+                uint64_t k = ek[i];
+                if (best[ca] > k) atomicMin(&best[ca], (unsigned long long)k);
+                if (best[cb] > k) atomicMin(&best[cb], (unsigned long long)k);
+            }
+            __syncthreads();
+            for (int i = tid; i < nE; i += kLocalThreads) {
+                int ca = lab[ea[i]], cb = lab[eb[i]];
+                if (ca == cb) continue;
+                if (best[ca] == ek[i]) bidx[ca] = i;
+                if (best[cb] == ek[i]) bidx[cb] = i;
+            }
+            __syncthreads();
+            for (int j = tid; j < nN; j += kLocalThreads) {
+                if (lab[j] != j || best[j] == kNoEdge) continue;
+                int i = bidx[j];
+                int ca = lab[ea[i]], cb = lab[eb[i]];
+                int other = ca == j ? cb : ca;
+                if (best[other] == best[j] && j < other) continue;  // mutual: smaller index stays
+                hk[j] = other;
+                intree[(uint32_t)ek[i]] = 1;
+                s_flag = 1;
+            }
+            __syncthreads();
+            if (!s_flag) break;
+            if (tid == 0 && K + iter < 64) flags[FLAG_BV + K + iter] = 1;
+            for (int j = tid; j < nN; j += kLocalThreads) {
+                int h = hk[j];
+                if (h != j) {
+                    lab[j] = h;
+                    hk[j] = j;
+                }
+            }
+            __syncthreads();
+            for (int j = tid; j < nN; j += kLocalThreads) {
+                int r = lab[j];
+                for (int it = 0; it < kTN && lab[r] != r; ++it) r = lab[r];
+                lab[j] = r;
+            }
+            __syncthreads();
+        }
+        // permanent links from every merged component to its new root
+        for (int j = tid; j < nN; j += kLocalThreads) {
+            int r = lab[j];
+            if (r != j) cw[rid[j]] = (uint64_t)(uint32_t)rid[r];
+        }
         return;
     }
-    int c0 = __shfl(c, 0, 64);
-    uint64_t same = __ballot(c == c0);
-    uint64_t act = __ballot(valid);
-    if (same == act) {
-        if ((threadIdx.x & 63) == 0 && valid && mn[c0] > (int32_t)v) atomicMin(&mn[c0], (int32_t)v);
-        return;
+    // large case: rounds on the global arrays, hooking driven by the edges
+    // (each component hooks along the one edge equal to its minimum)
+    for (int r = K; r < 64; ++r) {
+        uint64_t *cur = (r & 1) ? best1 : best0, *nxt = (r & 1) ? best0 : best1;
+        for (int i = tid; i < nE; i += kLocalThreads) {
+            uint64_t k = ld_relaxed(&Et[i]);
+            if (k == kNoEdge) continue;
+            int a, b;
+            edge_comps<true>(g, k, comp0, cw, &a, &b, info);
+            if (a == b) {
+                st_relaxed(&Et[i], kNoEdge);
+                continue;
+            }
+            offer_min(cur, a, k, ld_relaxed(&cur[a]));
+            offer_min(cur, b, k, ld_relaxed(&cur[b]));
+        }
+        if (tid == 0) s_flag = 0;
+        wg_sync();
+        bool hooked = false;
+        for (int i = tid; i < nE; i += kLocalThreads) {
+            uint64_t k = ld_relaxed(&Et[i]);
+            if (k == kNoEdge) continue;
+            uint32_t e = (uint32_t)k;
+            int a = find_comp<true>(cw, comp0[e >> 1], r, info);
+            int b = find_comp<true>(cw, comp0[other_end(g, e)], r, info);
+            st_relaxed(&nxt[a], kNoEdge);
+            st_relaxed(&nxt[b], kNoEdge);
+            for (int side = 0; side < 2; ++side) {
+                int x = side ? b : a, other = side ? a : b;
+                if (ld_relaxed(&cur[x]) != k) continue;
+                if (ld_relaxed(&cur[other]) == k && x < other) continue;
+                st_relaxed(&cw[x], ((uint64_t)(r + 1) << 32) | (uint32_t)other);
+                intree[e] = 1;
+                hooked = true;
+            }
+        }
+        if (hooked) s_flag = 1;
+        wg_sync();
+        int any = s_flag;
+        if (!any) break;
+        if (tid == 0) flags[FLAG_BV + r] = 1;
+        __syncthreads();  // every thread has read s_flag before it is cleared
     }
-    if (valid && mn[c] > (int32_t)v) atomicMin(&mn[c], (int32_t)v);
 }
 
-__global__ void k_set_tree(const int32_t *__restrict__ comp, const int32_t *__restrict__ mn,
+// --- 3. roots: smallest pixel id of every tree -------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_gbv_final(
+    const int32_t *__restrict__ ctr, const int32_t *__restrict__ R,
+    const uint64_t *__restrict__ cw, const int32_t *__restrict__ lmin,
+    int32_t *__restrict__ croot, int32_t *__restrict__ mnroot, int32_t *__restrict__ info) {
+    const int nR = ctr[CTR_RALL];
+    for (int j = (int)gtid(); j < nR; j += gridDim.x * kBlock) {
+        int x = R[j];
+        int r = find_comp<false>(cw, x, 1 << 30, info);
+        croot[x] = r;
+        int m = lmin[x];
+        if (mnroot[r] > m) atomicMin(&mnroot[r], m);
+    }
+}
+
+// tree id (root pixel) of every pixel and its tree-edge bits: 1 right, 2 down,
+// 4 left, 8 up; bit 16 marks the root
+constexpr uint8_t kRootBit = 16;
+
+__global__ void k_set_tree(const int32_t *__restrict__ comp0, const int32_t *__restrict__ croot,
+                           const int32_t *__restrict__ lmin, const int32_t *__restrict__ mnroot,
                            const uint8_t *__restrict__ intree, LevelGeom g,
                            int32_t *__restrict__ tree, uint8_t *__restrict__ adj,
                            int32_t *__restrict__ info) {
     int64_t v = gtid();
     if (v >= g.off[g.n_pairs]) return;
-    int t = mn[comp[v]];
+    int x = comp0[v];
+    int c = croot[x];
+    int t = c >= 0 ? mnroot[c] : lmin[x];
     tree[v] = t;
-    if (t == v) atomicAdd(&info[HDP_INFO_N_TREES], 1);
     PixelPos p = pixel_pos(g, (int)v);
     uint8_t a = 0;
     if (intree[2 * v]) a |= 1;
     if (intree[2 * v + 1]) a |= 2;
     if (p.x > 0 && intree[2 * (v - 1)]) a |= 4;
     if (p.y > 0 && intree[2 * (v - p.W) + 1]) a |= 8;
+    if (t == v) {
+        a |= kRootBit;
+        atomicAdd(&info[HDP_INFO_N_TREES], 1);
+    }
     adj[v] = a;
 }
 
-// --- 4. Euler tour ranking ------------------------------------------------------
+// --- 4. Euler tour ranking ---------------------------------------------------------
+// Slot 4v+d = directed tree edge from v in direction d (0 right, 1 down, 2 left,
+// 3 up); its successor turns to the next tree edge of the far pixel, and the
+// tour of a tree ends at the slot that would return to the root's first edge.
+// Rank = hops to the end of the tour.  Each tile first ranks, in LDS, the runs
+// of its slots whose successors stay in the tile; a run ends at an exit (the
+// successor lies in another tile) or at the tour's end.  The run ends form a
+// short contracted list that pointer jumping ranks globally:
+//   lw[s]  = (index of the end of s's run) << 32 | hops from s to that end
+//   pr[i]  = (next run end) << 32 | hops, jumped until next = -1.
 
 __device__ __forceinline__ int64_t nbr(int64_t v, int d, int W) {
     return d == 0 ? v + 1 : d == 1 ? v + W : d == 2 ? v - 1 : v - W;
 }
 
-__device__ __forceinline__ int first_dir(uint8_t a) { return __ffs((int)a) - 1; }
+__device__ __forceinline__ int first_dir(uint8_t a) { return __ffs((int)(a & 15)) - 1; }
 
-// slot 4v+d = directed tree edge from v in direction d.  Packed word:
-// high 32 bits = next slot (-1 end of tour, -2 not an edge), low 32 = distance.
-__global__ void k_euler_init(LevelGeom g, const uint8_t *__restrict__ adj,
-                             const int32_t *__restrict__ tree, uint64_t *__restrict__ pr) {
-    int64_t s = gtid();
-    int64_t n = g.off[g.n_pairs];
-    if (s >= 4 * n) return;
-    int64_t v = s >> 2;
-    int d = (int)(s & 3);
-    uint8_t av = adj[v];
-    if (!((av >> d) & 1)) {
-        pr[s] = ((uint64_t)0xFFFFFFFEu << 32);
-        return;
-    }
-    int W = g.W[pair_of(g, (int)v)];
-    int64_t w = nbr(v, d, W);
-    uint8_t aw = adj[w];
+// direction of the tour step after arriving through direction d at a pixel with edge bits aw
+__device__ __forceinline__ int turn(uint8_t aw, int d) {
     int rd = d ^ 2, d2 = rd;
     for (int k = 1; k <= 4; ++k) {
         d2 = (rd + k) & 3;
         if ((aw >> d2) & 1) break;
     }
-    int64_t succ = 4 * w + d2;
-    bool end = tree[w] == w && d2 == first_dir(aw);
-    if (end)
-        pr[s] = ((uint64_t)0xFFFFFFFFu << 32);
-    else
-        pr[s] = ((uint64_t)(uint32_t)succ << 32) | 1u;
+    return d2;
 }
 
-__global__ void k_rank_round(int round, int32_t *__restrict__ flags, uint64_t *__restrict__ pr,
-                             int64_t n4) {
+constexpr int kHalo = kTile + 2;
+constexpr uint32_t kTourEnd = 0xFFFFFFFFu;
+constexpr int kSlotsPerThread = 4 * kTilePx / kLocalThreads;
+
+__global__ __launch_bounds__(kLocalThreads) void k_tour_local(
+    LevelGeom g, const uint8_t *__restrict__ adj, uint64_t *__restrict__ lw,
+    uint32_t *__restrict__ C, int32_t *__restrict__ ctr, int32_t *__restrict__ info) {
+    __shared__ uint8_t sadj[kHalo * kHalo];
+    __shared__ unsigned long long P[4 * kTilePx];
+    __shared__ int32_t tix[4 * kTilePx];
+    __shared__ int s_n, s_base;
+    const TileInfo t = tile_info(g, blockIdx.x);
+    const int tid = threadIdx.x;
+    for (int h = tid; h < kHalo * kHalo; h += kLocalThreads) {
+        int x = t.x0 + (h % kHalo) - 1, y = t.y0 + (h / kHalo) - 1;
+        bool in = x >= 0 && x < t.W && y >= 0 && y < t.H;
+        sadj[h] = in ? adj[t.base + (int64_t)y * t.W + x] : 0;
+    }
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    // slot ls = 4 * (ly * kTile + lx) + d; P = next << 32 | hops (run end: next = self)
+    constexpr unsigned long long kInvalid = ~0ull;
+    for (int k = 0; k < kSlotsPerThread; ++k) {
+        int ls = tid + k * kLocalThreads;
+        int i = ls >> 2, d = ls & 3;
+        int lx = i & (kTile - 1), ly = i >> 5;
+        unsigned long long w = kInvalid;
+        tix[ls] = 0;
+        if (lx < t.tw && ly < t.th && ((sadj[(ly + 1) * kHalo + lx + 1] >> d) & 1)) {
+            int wx = lx + (d == 0) - (d == 2), wy = ly + (d == 1) - (d == 3);
+            uint8_t aw = sadj[(wy + 1) * kHalo + wx + 1];
+            int d2 = turn(aw, d);
+            bool end = (aw & kRootBit) && d2 == first_dir(aw);
+            bool inside = wx >= 0 && wx < t.tw && wy >= 0 && wy < t.th;
+            if (end || !inside)
+                w = ((unsigned long long)ls << 32);
+            else
+                w = ((unsigned long long)(4 * (wy * kTile + wx) + d2) << 32) | 1ull;
+        }
+        P[ls] = w;
+    }
+    __syncthreads();
+    // pointer jumping inside the tile (runs hold at most 4 * kTilePx slots, so
+    // 13 rounds reach every run end; one more confirms)
+    bool converged = false;
+    for (int round = 0; round < 16; ++round) {
+        bool changed = false;
+        for (int k = 0; k < kSlotsPerThread; ++k) {
+            int ls = tid + k * kLocalThreads;
+            unsigned long long a = P[ls];
+            if (a == kInvalid) continue;
+            int nx = (int)(a >> 32);
+            if (nx == ls) continue;
+            unsigned long long b = P[nx];
+            int nn = (int)(b >> 32);
+            if (nn == nx) continue;  // next is its run's end: done
+            P[ls] = ((unsigned long long)nn << 32) | (uint32_t)((uint32_t)a + (uint32_t)b);
+            changed = true;
+        }
+        if (!__syncthreads_or(changed)) {
+            converged = true;
+            break;
+        }
+    }
+    if (!converged && tid == 0) info[HDP_INFO_ERROR] = 5;
+    // number the run ends (one LDS atomic per wavefront and slot group)
+    int wofs[kSlotsPerThread];
+    uint64_t wm[kSlotsPerThread];
+    const int lane = tid & 63;
+    for (int k = 0; k < kSlotsPerThread; ++k) {
+        int ls = tid + k * kLocalThreads;
+        unsigned long long a = P[ls];
+        bool term = a != kInvalid && (int)(a >> 32) == ls;
+        wm[k] = __ballot(term);
+        wofs[k] = 0;
+        if (lane == 0 && wm[k]) wofs[k] = atomicAdd(&s_n, __popcll(wm[k]));
+    }
+    __syncthreads();
+    if (tid == 0) s_base = s_n ? atomicAdd(&ctr[CTR_RUNS], s_n) : 0;
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    for (int k = 0; k < kSlotsPerThread; ++k) {
+        int ls = tid + k * kLocalThreads;
+        int base = __shfl(wofs[k], 0, 64) + s_base;
+        if (!((wm[k] >> lane) & 1)) continue;
+        int idx = base + __popcll(wm[k] & lt);
+        tix[ls] = idx;
+        int i = ls >> 2, d = ls & 3;
+        int lx = i & (kTile - 1), ly = i >> 5;
+        int wx = lx + (d == 0) - (d == 2), wy = ly + (d == 1) - (d == 3);
+        uint8_t aw = sadj[(wy + 1) * kHalo + wx + 1];
+        int d2 = turn(aw, d);
+        bool end = (aw & kRootBit) && d2 == first_dir(aw);
+        int64_t wg = t.base + (int64_t)(t.y0 + wy) * t.W + t.x0 + wx;
+        C[idx] = end ? kTourEnd : (uint32_t)(4 * wg + d2);
+    }
+    __syncthreads();
+    for (int k = 0; k < kSlotsPerThread; ++k) {
+        int ls = tid + k * kLocalThreads;
+        unsigned long long a = P[ls];
+        if (a == kInvalid) continue;
+        int64_t v = tile_pixel(t, ls >> 2);
+        lw[4 * v + (ls & 3)] = ((uint64_t)(uint32_t)tix[(int)(a >> 32)] << 32) | (uint32_t)a;
+    }
+}
+
+// contracted list: run end i -> the end of the run its successor starts
+__global__ __launch_bounds__(kBlock) void k_tour_link(const int32_t *__restrict__ ctr,
+                                                      const uint32_t *__restrict__ C,
+                                                      const uint64_t *__restrict__ lw,
+                                                      uint64_t *__restrict__ pr) {
+    const int nC = ctr[CTR_RUNS];
+    for (int i = (int)gtid(); i < nC; i += gridDim.x * kBlock) {
+        uint32_t s2 = C[i];
+        if (s2 == kTourEnd) {
+            pr[i] = (uint64_t)0xFFFFFFFFu << 32;
+        } else {
+            uint64_t w = lw[s2];
+            pr[i] = (w & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)w + 1u);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank_round(int round, int32_t *__restrict__ flags,
+                                                       const int32_t *__restrict__ ctr,
+                                                       uint64_t *__restrict__ pr) {
     if (round > 0 && flags[FLAG_RANK + round - 1] == 0) return;
-    int64_t s = gtid();
-    if (s >= n4) return;
-    uint64_t P = __hip_atomic_load(&pr[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int32_t nx = (int32_t)(P >> 32);
-    if (nx < 0) return;
-    uint64_t Q = __hip_atomic_load(&pr[nx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int32_t nn = (int32_t)(Q >> 32);
-    uint32_t dist = (uint32_t)P + (uint32_t)Q;
-    __hip_atomic_store(&pr[s], ((uint64_t)(uint32_t)nn << 32) | dist, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    if (nn >= 0) flags[FLAG_RANK + round] = 1;
+    const int nC = ctr[CTR_RUNS];
+    bool more = false;
+    for (int s = (int)gtid(); s < nC; s += gridDim.x * kBlock) {
+        uint64_t P = ld_relaxed(&pr[s]);
+        int32_t nx = (int32_t)(P >> 32);
+        if (nx < 0) continue;
+        uint64_t Q = ld_relaxed(&pr[nx]);
+        int32_t nn = (int32_t)(Q >> 32);
+        st_relaxed(&pr[s], ((uint64_t)(uint32_t)nn << 32) | (uint32_t)((uint32_t)P + (uint32_t)Q));
+        more |= nn >= 0;
+    }
+    if (__ballot(more) && (threadIdx.x & 63) == 0) flags[FLAG_RANK + round] = 1;
 }
 
-__device__ __forceinline__ uint32_t rank_of(const uint64_t *pr, int64_t s) {
-    return (uint32_t)pr[s];
+__global__ __launch_bounds__(kBlock) void k_rank_compact(int K, const int32_t *__restrict__ flags,
+                                                         int32_t *__restrict__ ctr,
+                                                         const uint64_t *__restrict__ pr,
+                                                         int32_t *__restrict__ At) {
+    if (flags[FLAG_RANK + K - 1] == 0) return;
+    const int nC = ctr[CTR_RUNS];
+    for (int s = (int)gtid(); s < nC; s += gridDim.x * kBlock) {
+        bool open = (int32_t)(pr[s] >> 32) >= 0;
+        int pos = wave_append(open, &ctr[CTR_AT]);
+        if (open) At[pos] = s;
+    }
 }
+
+// The unfinished entries in one workgroup: renumbered into LDS (entries that
+// point at a finished entry absorb its rank) and jumped there; a larger set
+// is jumped on the global array with device-coherent loads.
+constexpr int kTA = 8192;
+
+__global__ __launch_bounds__(kLocalThreads) void k_rank_tail(
+    int K, int32_t *__restrict__ flags, const int32_t *__restrict__ ctr,
+    const int32_t *__restrict__ At, int32_t *__restrict__ slot, uint64_t *__restrict__ pr,
+    int32_t *__restrict__ info) {
+    __shared__ unsigned long long L[kTA];
+    __shared__ int s_more;
+    if (flags[FLAG_RANK + K - 1] == 0) return;
+    const int nA = ctr[CTR_AT];
+    const int tid = threadIdx.x;
+    if (nA <= kTA) {
+        for (int j = tid; j < nA; j += kLocalThreads) slot[At[j]] = j;
+        wg_sync();
+        for (int j = tid; j < nA; j += kLocalThreads) {
+            uint64_t P = pr[At[j]];
+            int nx = (int32_t)(P >> 32);
+            uint64_t Q = pr[nx];
+            if ((int32_t)(Q >> 32) < 0)
+                L[j] = (0xFFFFFFFFull << 32) | (uint32_t)((uint32_t)P + (uint32_t)Q);
+            else
+                L[j] = ((uint64_t)(uint32_t)ld_relaxed(&slot[nx]) << 32) | (uint32_t)P;
+        }
+        for (int r = K; r < 64; ++r) {
+            if (tid == 0) s_more = 0;
+            __syncthreads();
+            bool more = false;
+            for (int j = tid; j < nA; j += kLocalThreads) {
+                unsigned long long a = L[j];
+                int nx = (int32_t)(a >> 32);
+                if (nx < 0) continue;
+                unsigned long long b = L[nx];
+                L[j] = (b & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)a + (uint32_t)b);
+                more |= (int32_t)(b >> 32) >= 0;
+            }
+            if (more) s_more = 1;
+            __syncthreads();
+            int any = s_more;
+            __syncthreads();  // every thread has read s_more before it is cleared
+            if (!any) break;
+            if (tid == 0) flags[FLAG_RANK + r] = 1;
+        }
+        for (int j = tid; j < nA; j += kLocalThreads)
+            pr[At[j]] = (0xFFFFFFFFull << 32) | (uint32_t)L[j];
+        return;
+    }
+    for (int r = K; r < 64; ++r) {
+        if (tid == 0) s_more = 0;
+        wg_sync();
+        bool more = false;
+        for (int j = tid; j < nA; j += kLocalThreads) {
+            int s = At[j];
+            uint64_t P = ld_relaxed(&pr[s]);
+            int32_t nx = (int32_t)(P >> 32);
+            if (nx < 0) continue;
+            uint64_t Q = ld_relaxed(&pr[nx]);
+            int32_t nn = (int32_t)(Q >> 32);
+            st_relaxed(&pr[s],
+                       ((uint64_t)(uint32_t)nn << 32) | (uint32_t)((uint32_t)P + (uint32_t)Q));
+            more |= nn >= 0;
+        }
+        if (more) s_more = 1;
+        wg_sync();
+        int any = s_more;
+        if (!any) return;
+        if (tid == 0) flags[FLAG_RANK + r] = 1;
+        __syncthreads();  // every thread has read s_more before it is cleared
+    }
+    if (tid == 0) info[HDP_INFO_ERROR] = 6;
+}
+
+struct Ranks {
+    const uint64_t *lw, *pr;
+    __device__ __forceinline__ uint32_t operator()(int64_t s) const {
+        uint64_t w = lw[s];
+        return (uint32_t)w + (uint32_t)pr[w >> 32];
+    }
+};
 
 // parent, subtree size and edge weight of the child side of every tree edge.
-// (edge weights are recomputed from the image: the key array no longer holds
-// the keys of edges that became internal during the spanning-forest rounds)
+// (edge weights are recomputed from the image with the key formula)
 __global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
-                         const float4 *__restrict__ img, const uint64_t *__restrict__ pr,
+                         const float4 *__restrict__ img, Ranks rank_of,
                          int32_t *__restrict__ parent, int32_t *__restrict__ size,
                          float *__restrict__ wgt) {
     int64_t v = gtid();
@@ -272,15 +922,13 @@ __global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
         int64_t e = 2 * v + dir;
         if (!intree[e]) continue;
         int64_t w = dir == 0 ? v + 1 : v + W;
-        uint32_t rv = rank_of(pr, 4 * v + dir);
-        uint32_t rw = rank_of(pr, 4 * w + (dir + 2));
+        uint32_t rv = rank_of(4 * v + dir);
+        uint32_t rw = rank_of(4 * w + (dir + 2));
         int64_t child, par;
         uint32_t sz;
         if (rv > rw) { child = w; par = v; sz = (rv - rw + 1) >> 1; }
         else { child = v; par = w; sz = (rw - rv + 1) >> 1; }
-        float4 a = img[v], b = img[w];
-        float m = fmaxf(fmaxf(fabsf(a.x - b.x), fabsf(a.y - b.y)), fabsf(a.z - b.z));
-        float k = (float)__float2uint_rn(m * ldexpf(1.0f, 2 * g.level));
+        float k = (float)edge_key(img[v], img[w], ldexpf(1.0f, 2 * g.level));
         parent[child] = (int32_t)par;
         size[child] = (int32_t)sz;
         wgt[child] = k * inv;
@@ -288,7 +936,7 @@ __global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
 }
 
 __global__ void k_root_info(int64_t n, const int32_t *__restrict__ tree,
-                            const uint8_t *__restrict__ adj, const uint64_t *__restrict__ pr,
+                            const uint8_t *__restrict__ adj, Ranks rank_of,
                             int32_t *__restrict__ parent, int32_t *__restrict__ size,
                             float *__restrict__ wgt, uint64_t *__restrict__ rootval) {
     int64_t v = gtid();
@@ -297,8 +945,8 @@ __global__ void k_root_info(int64_t n, const int32_t *__restrict__ tree,
     if (tree[v] == v) {
         parent[v] = -1;
         wgt[v] = 0.f;
-        uint8_t a = adj[v];
-        int32_t sz = a ? (int32_t)((rank_of(pr, 4 * v + first_dir(a)) + 1) >> 1) + 1 : 1;
+        uint8_t a = adj[v] & 15;
+        int32_t sz = a ? (int32_t)((rank_of(4 * v + first_dir(a)) + 1) >> 1) + 1 : 1;
         size[v] = sz;
         // packed for one scan: low = tour length 2(sz-1), high = node count sz
         rv = ((uint64_t)(uint32_t)sz << 32) | (uint32_t)(2 * (sz - 1));
@@ -337,7 +985,7 @@ __global__ void k_tour_scatter(LevelGeom g, const uint8_t *__restrict__ adj,
                                const int32_t *__restrict__ tree, const int32_t *__restrict__ parent,
                                const int32_t *__restrict__ size,
                                const int32_t *__restrict__ heavy_child,
-                               const uint64_t *__restrict__ pr, const uint64_t *__restrict__ rootoff,
+                               Ranks rank_of, const uint64_t *__restrict__ rootoff,
                                uint64_t *__restrict__ tourval, int32_t *__restrict__ info) {
     int64_t s = gtid();
     int64_t n = g.off[g.n_pairs];
@@ -350,7 +998,7 @@ __global__ void k_tour_scatter(LevelGeom g, const uint8_t *__restrict__ adj,
     int64_t root = tree[v];
     uint32_t toff = (uint32_t)rootoff[root];
     int64_t tlen = 2 * (int64_t)(size[root] - 1);
-    int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rank_of(pr, s));
+    int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rank_of(s));
     if (pos < toff || pos >= (int64_t)toff + tlen) {
         info[HDP_INFO_ERROR] = 2;
         return;
@@ -377,7 +1025,7 @@ __device__ __forceinline__ void wave_max_to(int32_t *dst, int32_t x) {
 
 __global__ void k_node_order(LevelGeom g, const uint8_t *__restrict__ adj,
                              const int32_t *__restrict__ tree, const int32_t *__restrict__ parent,
-                             const uint64_t *__restrict__ pr, const uint64_t *__restrict__ rootoff,
+                             Ranks rank_of, const uint64_t *__restrict__ rootoff,
                              const int32_t *__restrict__ size, const uint64_t *__restrict__ tourscan,
                              int32_t *__restrict__ depth, int32_t *__restrict__ ld,
                              int32_t *__restrict__ gpre, int32_t *__restrict__ info) {
@@ -394,7 +1042,7 @@ __global__ void k_node_order(LevelGeom g, const uint8_t *__restrict__ adj,
             // direction of the edge p -> w (a one-pixel-wide image has vertical edges only)
             int d = W == 1 ? (w > p ? 1 : 3) : w == p + 1 ? 0 : w == p + W ? 1 : w == p - 1 ? 2 : 3;
             int64_t tlen = 2 * (int64_t)(size[root] - 1);
-            int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rank_of(pr, 4 * p + d));
+            int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rank_of(4 * p + d));
             if (pos < toff || pos >= (int64_t)toff + tlen) {
                 info[HDP_INFO_ERROR] = 3;
                 pre = 0;
@@ -558,39 +1206,49 @@ struct Bump {
 };
 
 struct TreeWs {
-    uint32_t *key;
-    int32_t *comp, *nxt, *mn, *flags, *size, *heavy_child, *ld, *gpre, *seq;
-    uint64_t *best, *pr, *rootval, *tourval, *partial64;
+    int32_t *comp0, *lmin, *croot, *mnroot, *Rall, *At, *slot, *ctr, *flags;
+    int32_t *size, *heavy_child, *ld, *gpre, *seq;
+    uint64_t *cw, *best0, *best1, *E, *Et, *lw, *pr, *rootval, *tourval, *partial64;
+    uint32_t *C;
     uint8_t *intree, *adj;
-    int32_t *partial32, *hist, *sortA, *sortB, *cnt;
+    int32_t *partial32, *hist, *sortA, *sortB;
 };
 
 static TreeWs carve_tree_ws(void *ws, int64_t n, size_t *bytes) {
     Bump b{reinterpret_cast<char *>(ws)};
     TreeWs t;
     int64_t ntiles = scan_tiles(n + 1) + 1;
-    t.key = b.take<uint32_t>(2 * n);
-    t.comp = b.take<int32_t>(n);
-    t.nxt = b.take<int32_t>(n);
-    t.mn = b.take<int32_t>(n);
+    t.comp0 = b.take<int32_t>(n);
+    t.lmin = b.take<int32_t>(n);
+    t.croot = b.take<int32_t>(n);
+    t.mnroot = b.take<int32_t>(n);
+    t.Rall = b.take<int32_t>(n);
+    t.At = b.take<int32_t>(2 * n);
+    t.slot = b.take<int32_t>(2 * n);
+    t.ctr = b.take<int32_t>(kCounters);
     t.flags = b.take<int32_t>(FLAG_WORDS);
     t.size = b.take<int32_t>(n);
     t.heavy_child = b.take<int32_t>(n);
     t.ld = b.take<int32_t>(n);
     t.gpre = b.take<int32_t>(n);
     t.seq = b.take<int32_t>(n);
-    t.best = b.take<uint64_t>(n);
-    t.pr = b.take<uint64_t>(4 * n);
+    t.cw = b.take<uint64_t>(n);
+    t.best0 = b.take<uint64_t>(n);
+    t.best1 = b.take<uint64_t>(n);
+    t.E = b.take<uint64_t>(2 * n);
+    t.Et = b.take<uint64_t>(2 * n);
+    t.lw = b.take<uint64_t>(4 * n);
+    t.pr = b.take<uint64_t>(2 * n);
+    t.C = b.take<uint32_t>(2 * n);
     t.rootval = b.take<uint64_t>(n);
     t.tourval = b.take<uint64_t>(2 * n);
-    t.partial64 = b.take<uint64_t>(scan_tiles(4 * n) + 1);
+    t.partial64 = b.take<uint64_t>(scan_tiles(2 * n) + 1);
     t.intree = b.take<uint8_t>(2 * n);
     t.adj = b.take<uint8_t>(n);
     t.partial32 = b.take<int32_t>(scan_tiles(256 * ntiles) + 1);
     t.hist = b.take<int32_t>(256 * ntiles);
     t.sortA = b.take<int32_t>(n);
     t.sortB = b.take<int32_t>(n);
-    t.cnt = b.take<int32_t>(n + 1);
     *bytes = b.off + 256;
     return t;
 }
@@ -627,37 +1285,74 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     const float4 *im = reinterpret_cast<const float4 *>(img);
     unsigned gn = grid_for(n), gn4 = grid_for(4 * n);
 
-    // 1-2: keys and Boruvka
-    k_info_clear<<<1, 64, 0, st>>>(f.info);
-    k_bv_init<<<grid_for(n > FLAG_WORDS ? n : FLAG_WORDS), kBlock, 0, st>>>(
-        t.comp, t.nxt, t.best, t.mn, t.intree, n, t.flags, f.info);
-    k_edge_keys<<<gn, kBlock, 0, st>>>(im, g, plo, phi, max_width, t.key, f.info);
-    int bv_rounds = ceil_log2(n) + 2;
-    if (bv_rounds > 63) bv_rounds = 63;
-    for (int r = 0; r < bv_rounds; ++r) {
-        k_bv_minedge<<<gn, kBlock, 0, st>>>(r, t.flags, g, t.key, t.comp, t.best);
-        k_bv_hook<<<gn, kBlock, 0, st>>>(r, t.flags, g, t.best, t.comp, t.nxt, t.intree);
-        k_bv_compress<<<gn, kBlock, 0, st>>>(r, t.flags, t.comp, t.nxt, t.best, n, f.info);
+    // Round bounds.  After the tile-local phase every component that still has
+    // an edge owns a tile-border pixel, and the number of such components at
+    // least halves per global round.  A tour's contracted list has at most one
+    // entry per directed tree edge that crosses a tile border, plus its end.
+    int64_t border_px = 0, max_list = 2;
+    unsigned n_tiles = (unsigned)g.toff[g.n_pairs];
+    for (int p = 0; p < g.n_pairs; ++p) {
+        int H = g.H[p], W = g.W[p];
+        int tx = (W + kTile - 1) / kTile, ty = (H + kTile - 1) / kTile;
+        for (int j = 0; j < ty; ++j)
+            for (int i = 0; i < tx; ++i) {
+                int64_t tw = W - i * kTile < kTile ? W - i * kTile : kTile;
+                int64_t th = H - j * kTile < kTile ? H - j * kTile : kTile;
+                int64_t inner = (tw > 2 ? tw - 2 : 0) * (th > 2 ? th - 2 : 0);
+                border_px += tw * th - inner;
+            }
+        int64_t crossing = (int64_t)H * (tx - 1) + (int64_t)W * (ty - 1);
+        if (2 * crossing + 2 > max_list) max_list = 2 * crossing + 2;
     }
+    unsigned g_edges = grid_for(2 * n) < (unsigned)kGridCap ? grid_for(2 * n) : kGridCap;
+    unsigned g_roots = grid_for(border_px) < (unsigned)kGridCap ? grid_for(border_px) : kGridCap;
+
+    // 1-2: spanning forest (tile-local phase, full-grid rounds, one-workgroup tail)
+    k_tree_init<<<1, FLAG_WORDS, 0, st>>>(t.flags, t.ctr, f.info);
+    k_local_msf<<<n_tiles, kLocalThreads, 0, st>>>(im, g, plo, phi, max_width, t.comp0, t.cw,
+                                                   t.best0, t.best1, t.lmin, t.croot, t.mnroot,
+                                                   t.intree, t.E, t.Rall, t.ctr, f.info);
+    int bv_rounds = ceil_log2(border_px) + 1;
+    if (bv_rounds > kBvGridRounds) bv_rounds = kBvGridRounds;
+    if (bv_rounds < 1) bv_rounds = 1;
+    for (int r = 0; r < bv_rounds; ++r) {
+        uint64_t *bc = (r & 1) ? t.best1 : t.best0, *bn = (r & 1) ? t.best0 : t.best1;
+        k_gbv_minedge<<<g_edges, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.E, t.comp0, t.cw, bc,
+                                                  f.info);
+        k_gbv_hook<<<g_roots, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Rall, t.comp0, t.cw, bc, bn,
+                                               t.intree, f.info);
+    }
+    k_gbv_compact<<<g_edges, kBlock, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
+                                              t.Et, f.info);
+    k_gbv_tail<<<1, kLocalThreads, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.Et, t.comp0, t.cw,
+                                            t.best0, t.best1, t.intree, f.info);
     // 3: roots
-    k_rootmin<<<gn, kBlock, 0, st>>>(t.comp, t.mn, n);
-    k_set_tree<<<gn, kBlock, 0, st>>>(t.comp, t.mn, t.intree, g, f.tree, t.adj, f.info);
+    k_gbv_final<<<g_roots, kBlock, 0, st>>>(t.ctr, t.Rall, t.cw, t.lmin, t.croot, t.mnroot, f.info);
+    k_set_tree<<<gn, kBlock, 0, st>>>(t.comp0, t.croot, t.lmin, t.mnroot, t.intree, g, f.tree,
+                                      t.adj, f.info);
     // 4: Euler tour ranks
-    k_euler_init<<<gn4, kBlock, 0, st>>>(g, t.adj, f.tree, t.pr);
-    int rk_rounds = ceil_log2(2 * n) + 2;
-    if (rk_rounds > 63) rk_rounds = 63;
-    for (int r = 0; r < rk_rounds; ++r) k_rank_round<<<gn4, kBlock, 0, st>>>(r, t.flags, t.pr, 4 * n);
-    k_parent<<<gn, kBlock, 0, st>>>(g, t.intree, im, t.pr, f.parent, t.size, f.wgt);
-    k_root_info<<<gn, kBlock, 0, st>>>(n, f.tree, t.adj, t.pr, f.parent, t.size, f.wgt, t.rootval);
+    k_tour_local<<<n_tiles, kLocalThreads, 0, st>>>(g, t.adj, t.lw, t.C, t.ctr, f.info);
+    k_tour_link<<<g_edges, kBlock, 0, st>>>(t.ctr, t.C, t.lw, t.pr);
+    int rk_rounds = ceil_log2(max_list) + 1;
+    if (rk_rounds > kRankGridRounds) rk_rounds = kRankGridRounds;
+    if (rk_rounds < 1) rk_rounds = 1;
+    for (int r = 0; r < rk_rounds; ++r)
+        k_rank_round<<<g_edges, kBlock, 0, st>>>(r, t.flags, t.ctr, t.pr);
+    k_rank_compact<<<g_edges, kBlock, 0, st>>>(rk_rounds, t.flags, t.ctr, t.pr, t.At);
+    k_rank_tail<<<1, kLocalThreads, 0, st>>>(rk_rounds, t.flags, t.ctr, t.At, t.slot, t.pr,
+                                             f.info);
+    Ranks rk{t.lw, t.pr};
+    k_parent<<<gn, kBlock, 0, st>>>(g, t.intree, im, rk, f.parent, t.size, f.wgt);
+    k_root_info<<<gn, kBlock, 0, st>>>(n, f.tree, t.adj, rk, f.parent, t.size, f.wgt, t.rootval);
     // 5: heavy child
     k_heavy<<<gn, kBlock, 0, st>>>(g, t.adj, f.parent, t.size, t.heavy_child);
     // 6: tour offsets, tour values, prefix sum, per-node depth / light depth / preorder
     device_scan<uint64_t>(t.rootval, t.rootval, n, t.partial64, nullptr, false, st);
-    k_tour_scatter<<<gn4, kBlock, 0, st>>>(g, t.adj, f.tree, f.parent, t.size, t.heavy_child, t.pr,
+    k_tour_scatter<<<gn4, kBlock, 0, st>>>(g, t.adj, f.tree, f.parent, t.size, t.heavy_child, rk,
                                            t.rootval, t.tourval, f.info);
     int64_t tour_len = 2 * n;  // upper bound; entries past the real length are never read
     device_scan<uint64_t>(t.tourval, t.tourval, tour_len, t.partial64, nullptr, true, st);
-    k_node_order<<<gn, kBlock, 0, st>>>(g, t.adj, f.tree, f.parent, t.pr, t.rootval, t.size,
+    k_node_order<<<gn, kBlock, 0, st>>>(g, t.adj, f.tree, f.parent, rk, t.rootval, t.size,
                                         t.tourval, f.depth, t.ld, t.gpre, f.info);
     // 7: rows (stable partition of the preorder by light depth)
     k_scatter_seq<<<gn, kBlock, 0, st>>>(t.gpre, t.seq, n, f.info);
@@ -674,8 +1369,15 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     k_rows<<<gn, kBlock, 0, st>>>(g, f.node, f.row, f.parent, f.wgt, t.heavy_child, t.adj, f.prow,
                                   f.heavy, f.lc, f.rw);
     k_intervals<<<gn, kBlock, 0, st>>>(g, plo, phi, f.lo, f.hi);
-    // 8: level order (stable LSD radix sort of ids by depth) and level_ptr
-    k_iota<<<gn, kBlock, 0, st>>>(t.sortA, n);
+    k_finish_info<<<1, 64, 0, st>>>(t.flags, f.info, width);
+}
+
+// 8: level order (stable LSD radix sort of ids by depth) and level_ptr
+void launch_level_order(const hdp_forest &f, void *ws, hipStream_t st) {
+    int64_t n = f.n;
+    size_t bytes;
+    TreeWs t = carve_tree_ws(ws, n, &bytes);
+    k_iota<<<grid_for(n), kBlock, 0, st>>>(t.sortA, n);
     int32_t *src = t.sortA, *dst = t.sortB;
     int passes = ceil_log2(n) <= 8 ? 1 : ceil_log2(n) <= 16 ? 2 : 3;
     for (int pass = 0; pass < passes; ++pass) {
@@ -686,7 +1388,6 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         dst = (out == t.sortB) ? t.sortA : t.sortB;
     }
     k_level_ptr<<<grid_for(n + 1), kBlock, 0, st>>>(f.order, f.depth, n, f.level_ptr, f.info);
-    k_finish_info<<<1, 64, 0, st>>>(t.flags, f.info, width);
 }
 
 }  // namespace hdp

@@ -82,6 +82,7 @@ def _declare(L):
     L.hdp_build_tree.argtypes = [P, P, I32, I32, P, P, I32, I32, I32, I32,
                                  C.POINTER(ForestStruct), P, SZ, P]
     L.hdp_forest_read_info.argtypes = [C.POINTER(ForestStruct), P, P, P]
+    L.hdp_level_order.argtypes = [C.POINTER(ForestStruct), P, SZ, P]
     L.hdp_cost_volume.argtypes = [P, P, P, I32, C.POINTER(ForestStruct), I32,
                                   C.POINTER(CostParams), P, P]
     L.hdp_aggregate_workspace_bytes.argtypes = [I64, I32]
@@ -242,8 +243,10 @@ _ws_agg = Workspace()
 
 def build_tree(img: torch.Tensor, shapes, level: int, pix_lo=None, pix_hi=None,
                max_width: int = 0, beta=(19, 20), width: Optional[int] = None,
-               read_info: bool = False, forest: Optional[Forest] = None, ws=None) -> Forest:
-    """Minimum spanning tree (pix_lo None) or disparity forest of one layer."""
+               read_info: bool = False, forest: Optional[Forest] = None, ws=None,
+               level_order: bool = True) -> Forest:
+    """Minimum spanning tree (pix_lo None) or disparity forest of one layer.
+    level_order: also fill the canonical (depth, id) order and level_ptr."""
     n = n_pixels(shapes)
     assert img.shape == (n, 4) and img.dtype == torch.float32 and img.is_contiguous()
     if width is None:
@@ -261,6 +264,9 @@ def build_tree(img: torch.Tensor, shapes, level: int, pix_lo=None, pix_hi=None,
     _check("hdp_build_tree", lib().hdp_build_tree(
         _ptr(img), _shapes(shapes), len(shapes), level, _ptr(pix_lo), _ptr(pix_hi), int(max_width),
         int(beta[0]), int(beta[1]), int(width), C.byref(forest.st), _ptr(w), wsb, _stream()))
+    if level_order:
+        _check("hdp_level_order",
+               lib().hdp_level_order(C.byref(forest.st), _ptr(w), wsb, _stream()))
     if read_info:
         forest.read_info()
     return forest
@@ -395,10 +401,11 @@ class LevelResult:
 
 def stereo_level(left_img, right_img, shapes, level, pix_lo=None, pix_hi=None, max_width=0,
                  beta=(19, 20), sigma=0.1, params=None, keep=False, ws=None) -> LevelResult:
-    """One layer (Section 3): forest, restricted cost, aggregation, WTA."""
+    """One layer (Section 3): forest, restricted cost, aggregation, WTA.
+    keep: also return cost and aggregated volumes and fill the forest's level order."""
     ws = ws or {}
     f = build_tree(left_img, shapes, level, pix_lo, pix_hi, max_width=max_width, beta=beta,
-                   read_info=False, ws=ws.get("tree"))
+                   read_info=False, ws=ws.get("tree"), level_order=keep)
     cost = cost_volume(left_img, right_img, shapes, f, params=params)
     agg = aggregate(f, cost, sigma, ws=ws.get("agg"))
     disp = wta(agg, shapes, f)
