@@ -94,24 +94,34 @@ bool set_schedule(int width, int cpt, int rpg) {
     return true;
 }
 
-__global__ void k_coef(int64_t n, const float *__restrict__ rw, const int32_t *__restrict__ prow,
-                       double inv_sigma, double *__restrict__ s, double *__restrict__ om) {
-    int64_t r = gtid();
-    if (r >= n) return;
-    if (prow[r] < 0) {
-        s[r] = 0.0;
-        om[r] = 1.0;
-    } else {
-        double w = (double)rw[r];
-        s[r] = exp(-w * inv_sigma);
-        om[r] = -expm1(-2.0 * w * inv_sigma);
-    }
-}
+constexpr int kPassSets = 3;  // flag sets: up, down (and a second up pass in the adjoint)
 
-// Ticket layout of both passes from the forest's phase table.
-__global__ void k_make_plan(const int32_t *__restrict__ phase_ptr, const int32_t *__restrict__ info,
-                            int rows, int32_t *__restrict__ plan) {
-    if (threadIdx.x != 0) return;
+// Prologue of an aggregation call, one launch: per-row coefficients
+// s = exp(-w / sigma) and 1 - s^2, cleared tile flags and tickets of every
+// pass, and (block 0) the ticket layout of both passes from the phase table.
+__global__ void k_prologue(int64_t n, const float *__restrict__ rw,
+                           const int32_t *__restrict__ prow, double inv_sigma,
+                           double *__restrict__ s, double *__restrict__ om,
+                           int32_t *__restrict__ flags, int64_t tiles, int32_t *__restrict__ ticket,
+                           const int32_t *__restrict__ phase_ptr, const int32_t *__restrict__ info,
+                           int rows, int32_t *__restrict__ plan) {
+    int64_t r = gtid();
+    if (r < n) {
+        if (prow[r] < 0) {
+            s[r] = 0.0;
+            om[r] = 1.0;
+        } else {
+            double w = (double)rw[r];
+            s[r] = exp(-w * inv_sigma);
+            om[r] = -expm1(-2.0 * w * inv_sigma);
+        }
+    }
+    if (r < tiles) {
+#pragma unroll
+        for (int k = 0; k < 2 * kPassSets; ++k) flags[k * tiles + r] = 0;
+    }
+    if (r < kPassSets) ticket[r] = 0;
+    if (r != 0) return;
     int K = info[HDP_INFO_N_PHASES];
     if (K < 1) K = 1;
     if (K > HDP_MAX_PHASES) K = HDP_MAX_PHASES;
@@ -448,20 +458,10 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
     }
 }
 
-__global__ void k_pass_init(int32_t *__restrict__ flag, int32_t *__restrict__ flagw,
-                            int32_t *__restrict__ ticket, int64_t tiles) {
-    int64_t i = gtid();
-    if (i < tiles) {
-        flag[i] = 0;
-        flagw[i] = 0;
-    }
-    if (i == 0) ticket[0] = 0;
-}
-
 // --- workspace --------------------------------------------------------------------
 
 struct AggWs {
-    int32_t *plan, *ticket, *flag, *flagw;
+    int32_t *plan, *ticket, *flags;  // flags: kPassSets x (flag[tiles], flagw[tiles])
     double *s, *om, *tP, *tX, *tI;
     float *up;      // U when the caller does not keep it
     float *ug;      // U of the gradient (backward)
@@ -487,9 +487,8 @@ static AggWs carve_agg_ws(void *ws, int64_t n, int width, size_t *bytes) {
     AggWs a;
     a.tiles = nt;
     a.plan = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * P_WORDS));
-    a.ticket = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * 4));
-    a.flag = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * nt));
-    a.flagw = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * nt));
+    a.ticket = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * kPassSets));
+    a.flags = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * 2 * kPassSets * nt));
     a.s = reinterpret_cast<double *>(take(sizeof(double) * n));
     a.om = reinterpret_cast<double *>(take(sizeof(double) * n));
     a.tP = reinterpret_cast<double *>(take(sizeof(double) * nt));
@@ -509,26 +508,29 @@ size_t aggregate_workspace_bytes(int64_t n, int width) {
 }
 
 template <bool UP, int CPT, int RPG>
-static void launch_pass(const PassArgs &A, const AggWs &w, int64_t tiles, hipStream_t st) {
-    k_pass_init<<<grid_for(tiles), kBlock, 0, st>>>(w.flag, w.flagw, w.ticket, tiles);
+static void launch_pass(const PassArgs &A, int64_t tiles, hipStream_t st) {
     timer_before(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
     k_pass<UP, CPT, RPG><<<(unsigned)tiles, kBlock, 0, st>>>(A);
     timer_after(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
 }
 
+// One pass with flag set `set` (cleared by the prologue of this call).
 template <bool UP>
-static void run_pass(const PassArgs &A, const AggWs &w, const TileGeom &tg, hipStream_t st) {
+static void run_pass(PassArgs A, const AggWs &w, const TileGeom &tg, int set, hipStream_t st) {
     int64_t tiles = A.n / tg.rows + HDP_MAX_PHASES + 2;  // >= the plan's tile count
+    A.ticket = w.ticket + set;
+    A.flag = w.flags + (int64_t)(2 * set) * w.tiles;
+    A.flagw = w.flags + (int64_t)(2 * set + 1) * w.tiles;
     if (tg.cpt == 4) {
-        if (tg.rpg == 4) launch_pass<UP, 4, 4>(A, w, tiles, st);
-        else launch_pass<UP, 4, 8>(A, w, tiles, st);
+        if (tg.rpg == 4) launch_pass<UP, 4, 4>(A, tiles, st);
+        else launch_pass<UP, 4, 8>(A, tiles, st);
     } else if (tg.cpt == 2) {
-        if (tg.rpg == 4) launch_pass<UP, 2, 4>(A, w, tiles, st);
-        else if (tg.rpg == 8) launch_pass<UP, 2, 8>(A, w, tiles, st);
-        else launch_pass<UP, 2, 16>(A, w, tiles, st);
+        if (tg.rpg == 4) launch_pass<UP, 2, 4>(A, tiles, st);
+        else if (tg.rpg == 8) launch_pass<UP, 2, 8>(A, tiles, st);
+        else launch_pass<UP, 2, 16>(A, tiles, st);
     } else {
-        if (tg.rpg == 4) launch_pass<UP, 1, 4>(A, w, tiles, st);
-        else launch_pass<UP, 1, 8>(A, w, tiles, st);
+        if (tg.rpg == 4) launch_pass<UP, 1, 4>(A, tiles, st);
+        else launch_pass<UP, 1, 8>(A, tiles, st);
     }
 }
 
@@ -545,9 +547,6 @@ static PassArgs pass_args(const hdp_forest &f, int width, const AggWs &w, const 
     A.prow = f.prow;
     A.lc = f.lc;
     A.plan = w.plan;
-    A.ticket = w.ticket;
-    A.flag = w.flag;
-    A.flagw = w.flagw;
     A.tP = w.tP;
     A.tX = w.tX;
     A.tI = w.tI;
@@ -557,21 +556,23 @@ static PassArgs pass_args(const hdp_forest &f, int width, const AggWs &w, const 
 
 // Coefficients and the plan of both passes (device side, no host sync).
 static void prologue(const hdp_forest &f, int width, float sigma, const AggWs &w, hipStream_t st) {
-    k_coef<<<grid_for(f.n), kBlock, 0, st>>>(f.n, f.rw, f.prow, 1.0 / (double)sigma, w.s, w.om);
-    k_make_plan<<<1, 64, 0, st>>>(f.phase_ptr, f.info, tile_geom(width).rows, w.plan);
+    int64_t m = f.n > w.tiles ? f.n : w.tiles;
+    k_prologue<<<grid_for(m), kBlock, 0, st>>>(f.n, f.rw, f.prow, 1.0 / (double)sigma, w.s, w.om,
+                                               w.flags, w.tiles, w.ticket, f.phase_ptr, f.info,
+                                               tile_geom(width).rows, w.plan);
 }
 
-// Two passes of `src` over the forest: U -> up, A -> out.
+// Two passes of `src` over the forest: U -> up, A -> out (flag sets up_set, up_set + 1).
 static void two_pass(const hdp_forest &f, int width, const float *src, float *up, float *out,
-                     const AggWs &w, hipStream_t st) {
+                     const AggWs &w, int up_set, hipStream_t st) {
     TileGeom tg = tile_geom(width);
     PassArgs A = pass_args(f, width, w, tg);
     A.src = src;
     A.dst = up;
-    run_pass<true>(A, w, tg, st);
+    run_pass<true>(A, w, tg, up_set, st);
     A.src = up;
     A.dst = out;
-    run_pass<false>(A, w, tg, st);
+    run_pass<false>(A, w, tg, up_set + 1, st);
 }
 
 void launch_aggregate(const hdp_forest &f, int width, const float *cost, float sigma, float *agg,
@@ -579,7 +580,7 @@ void launch_aggregate(const hdp_forest &f, int width, const float *cost, float s
     size_t bytes;
     AggWs w = carve_agg_ws(ws, f.n, width, &bytes);
     prologue(f, width, sigma, w, st);
-    two_pass(f, width, cost, up ? up : w.up, agg, w, st);
+    two_pass(f, width, cost, up ? up : w.up, agg, w, 0, st);
 }
 
 // --- adjoint ----------------------------------------------------------------------------
@@ -652,10 +653,10 @@ void launch_aggregate_backward(const hdp_forest &f, int width, const float *cost
         PassArgs A = pass_args(f, width, w, tg);
         A.src = cost;
         A.dst = w.up;
-        run_pass<true>(A, w, tg, st);
+        run_pass<true>(A, w, tg, 2, st);
         uc = w.up;
     }
-    two_pass(f, width, grad_agg, w.ug, grad_cost, w, st);
+    two_pass(f, width, grad_agg, w.ug, grad_cost, w, 0, st);
     if (grad_w || grad_sigma) {
         int64_t nb = (f.n * 64 + kBlock - 1) / kBlock;
         k_edge_grad<<<(unsigned)nb, kBlock, 0, st>>>(f.n, width, f.prow, f.node, f.rw, w.s, uc, agg,

@@ -19,24 +19,39 @@ __device__ __forceinline__ float match_cost(float4 L, const float4 *__restrict__
     return c.a_c * fminf(col, c.tau_c) + c.a_g * fminf(gd, c.tau_g);
 }
 
-// One thread per (row, column) entry of the volume.  node == NULL: rows are
+// One thread per CPT consecutive columns of a row (vector stores); a
+// workgroup covers kBlock / (width / CPT) whole rows.  node == NULL: rows are
 // pixels and the interval is [0, dmax of the pair].
-__global__ void k_cost_volume(const float4 *__restrict__ left, const float4 *__restrict__ right,
-                              LevelGeom g, const int32_t *__restrict__ node,
-                              const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
-                              int width, CostParams cp, float *__restrict__ cost, int64_t total) {
-    int64_t e = gtid();
-    if (e >= total) return;
-    int64_t r = e / width;
-    int j = (int)(e - r * width);
-    int v = node ? node[r] : (int)r;
-    PixelPos p = pixel_pos(g, v);
-    int a = node ? lo[v] : 0;
-    int b = node ? hi[v] : g.dmax[p.pair];
-    int label = a + j;
-    float out = 0.f;
-    if (label <= b) out = match_cost(left[v], right, v, p.x, label, cp);
-    cost[e] = out;
+template <int CPT>
+__global__ void __launch_bounds__(kBlock) k_cost_volume(
+    const float4 *__restrict__ left, const float4 *__restrict__ right, LevelGeom g,
+    const int32_t *__restrict__ node, const int32_t *__restrict__ lo,
+    const int32_t *__restrict__ hi, int width, CostParams cp, float *__restrict__ cost) {
+    const int lpr = width / CPT;
+    const int rows_per_block = kBlock / lpr;
+    const int gi = threadIdx.x / lpr;
+    if (gi >= rows_per_block) return;
+    const int j0 = (threadIdx.x - gi * lpr) * CPT;
+    const int64_t r = (int64_t)blockIdx.x * rows_per_block + gi;
+    if (r >= g.off[g.n_pairs]) return;
+    const int v = node ? node[r] : (int)r;
+    const PixelPos p = pixel_pos(g, v);
+    const int a = node ? lo[v] : 0;
+    const int b = node ? hi[v] : g.dmax[p.pair];
+    const float4 L = left[v];
+    float out[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        int label = a + j0 + c;
+        out[c] = label <= b ? match_cost(L, right, v, p.x, label, cp) : 0.f;
+    }
+    float *dst = cost + r * width + j0;
+    if (CPT == 4)
+        *reinterpret_cast<float4 *>(dst) = make_float4(out[0], out[1], out[2], out[3]);
+    else if (CPT == 2)
+        *reinterpret_cast<float2 *>(dst) = make_float2(out[0], out[1]);
+    else
+        dst[0] = out[0];
 }
 
 // Winner-takes-all, one thread per row (narrow rows).
@@ -53,9 +68,18 @@ __global__ void k_wta_thread(LevelGeom g, const int32_t *__restrict__ node,
     int nl = b - a + 1 < width ? b - a + 1 : width;
     float best = row[0];
     int bj = 0;
-    for (int j = 1; j < nl; ++j) {
-        float x = row[j];
-        if (x < best) { best = x; bj = j; }
+    if ((width & 1) == 0) {  // rows start 8-byte aligned: pairs of labels
+        const float2 *row2 = reinterpret_cast<const float2 *>(row);
+        for (int h = 0; 2 * h < nl; ++h) {
+            float2 x = row2[h];
+            if (x.x < best) { best = x.x; bj = 2 * h; }
+            if (2 * h + 1 < nl && x.y < best) { best = x.y; bj = 2 * h + 1; }
+        }
+    } else {
+        for (int j = 1; j < nl; ++j) {
+            float x = row[j];
+            if (x < best) { best = x; bj = j; }
+        }
     }
     disp[v] = a + bj;
 }
@@ -91,12 +115,20 @@ void launch_cost_volume(const float *left, const float *right, const LevelGeom &
                         const int32_t *node, const int32_t *lo, const int32_t *hi, int width,
                         const hdp_cost_params &p, float *cost, hipStream_t st) {
     int64_t n = g.off[g.n_pairs];
-    int64_t total = n * width;
     CostParams cp{p.a_c, p.tau_c, p.a_g, p.tau_g};
+    const float4 *L = reinterpret_cast<const float4 *>(left);
+    const float4 *R = reinterpret_cast<const float4 *>(right);
+    int cpt = (width % 4 == 0 && width / 4 <= kBlock) ? 4 : (width % 2 == 0 ? 2 : 1);
+    int lpr = width / cpt;
+    int rpb = kBlock / lpr;
+    unsigned blocks = (unsigned)((n + rpb - 1) / rpb);
     timer_before(HDP_TIMER_COST, st);
-    k_cost_volume<<<grid_for(total), kBlock, 0, st>>>(
-        reinterpret_cast<const float4 *>(left), reinterpret_cast<const float4 *>(right), g, node,
-        lo, hi, width, cp, cost, total);
+    if (cpt == 4)
+        k_cost_volume<4><<<blocks, kBlock, 0, st>>>(L, R, g, node, lo, hi, width, cp, cost);
+    else if (cpt == 2)
+        k_cost_volume<2><<<blocks, kBlock, 0, st>>>(L, R, g, node, lo, hi, width, cp, cost);
+    else
+        k_cost_volume<1><<<blocks, kBlock, 0, st>>>(L, R, g, node, lo, hi, width, cp, cost);
     timer_after(HDP_TIMER_COST, st);
 }
 

@@ -59,25 +59,18 @@ __global__ void k_scan_reduce(const T *__restrict__ in, int64_t n, T *__restrict
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// Exclusive scan of the per-tile partial sums, by one workgroup.
-template <typename T>
-__global__ void k_scan_partials(T *__restrict__ partial, int64_t nb, T *__restrict__ grand) {
-    T carry = 0;
-    for (int64_t c = 0; c < nb; c += kBlock) {
-        int64_t i = c + threadIdx.x;
-        T x = i < nb ? partial[i] : (T)0;
-        T tot;
-        T ex = block_excl_scan(x, &tot);
-        if (i < nb) partial[i] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0 && grand) *grand = carry;
-}
-
+// Scan of one tile; the tile's offset is the sum of the partial sums of all
+// preceding tiles, reduced by the whole workgroup (no serial pass over the
+// partials).
 template <typename T>
 __global__ void k_scan_apply(const T *__restrict__ in, T *__restrict__ out, int64_t n,
-                             const T *__restrict__ partial, int inclusive) {
-    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
+                             const T *__restrict__ partial, T *__restrict__ grand, int inclusive) {
+    const int64_t tile = blockIdx.x;
+    T pre = 0;
+    for (int64_t j = threadIdx.x; j < tile; j += kBlock) pre += partial[j];
+    T pre_all;
+    block_excl_scan(pre, &pre_all);
+    const int64_t base = tile * kScanTile + threadIdx.x * kScanPerThread;
     T v[kScanPerThread];
     T s = 0;
 #pragma unroll
@@ -86,27 +79,28 @@ __global__ void k_scan_apply(const T *__restrict__ in, T *__restrict__ out, int6
         s += v[i];
     }
     T tot;
-    T ex = block_excl_scan(s, &tot) + partial[blockIdx.x];
+    T ex = block_excl_scan(s, &tot) + pre_all;
 #pragma unroll
     for (int i = 0; i < kScanPerThread; ++i) {
         T nx = ex + v[i];
         if (base + i < n) out[base + i] = inclusive ? nx : ex;
         ex = nx;
     }
+    if (grand && tile == gridDim.x - 1 && threadIdx.x == 0) *grand = pre_all + tot;
 }
 
 inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
 // out[i] = sum of in[0..i-1] (exclusive) or in[0..i] (inclusive); in == out allowed.
 // partial: scratch of scan_tiles(n) elements; grand (device, may be NULL) = total.
+// Two launches: per-tile sums, then every tile adds the sums before it.
 template <typename T>
 inline void device_scan(const T *in, T *out, int64_t n, T *partial, T *grand, bool inclusive,
                         hipStream_t st) {
     int64_t nb = scan_tiles(n);
     if (nb < 1) nb = 1;
     k_scan_reduce<T><<<(unsigned)nb, kBlock, 0, st>>>(in, n, partial);
-    k_scan_partials<T><<<1, kBlock, 0, st>>>(partial, nb, grand);
-    k_scan_apply<T><<<(unsigned)nb, kBlock, 0, st>>>(in, out, n, partial, inclusive ? 1 : 0);
+    k_scan_apply<T><<<(unsigned)nb, kBlock, 0, st>>>(in, out, n, partial, grand, inclusive ? 1 : 0);
 }
 
 // ---------------------------------------------------------------------------

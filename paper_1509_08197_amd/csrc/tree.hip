@@ -638,10 +638,7 @@ __global__ void k_set_tree(const int32_t *__restrict__ comp0, const int32_t *__r
     if (intree[2 * v + 1]) a |= 2;
     if (p.x > 0 && intree[2 * (v - 1)]) a |= 4;
     if (p.y > 0 && intree[2 * (v - p.W) + 1]) a |= 8;
-    if (t == v) {
-        a |= kRootBit;
-        atomicAdd(&info[HDP_INFO_N_TREES], 1);
-    }
+    if (t == v) a |= kRootBit;
     adj[v] = a;
 }
 
@@ -908,16 +905,23 @@ struct Ranks {
     }
 };
 
-// parent, subtree size and edge weight of the child side of every tree edge.
-// (edge weights are recomputed from the image with the key formula)
+// Per pixel: parent, subtree size and edge weight of the child side of every
+// owned tree edge (sizes from the tour ranks; weights recomputed from the
+// image with the key formula), root data (tour length and node count, packed
+// for one scan), and the tree interval.
 __global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
                          const float4 *__restrict__ img, Ranks rank_of,
+                         const int32_t *__restrict__ tree, const uint8_t *__restrict__ adj,
+                         const int32_t *__restrict__ plo, const int32_t *__restrict__ phi,
                          int32_t *__restrict__ parent, int32_t *__restrict__ size,
-                         float *__restrict__ wgt) {
+                         float *__restrict__ wgt, uint64_t *__restrict__ rootval,
+                         int32_t *__restrict__ lo, int32_t *__restrict__ hi) {
     int64_t v = gtid();
     if (v >= g.off[g.n_pairs]) return;
-    int W = g.W[pair_of(g, (int)v)];
-    float inv = 1.0f / (255.0f * ldexpf(1.0f, 2 * g.level));
+    const int pair = pair_of(g, (int)v);
+    const int W = g.W[pair];
+    const float scale = ldexpf(1.0f, 2 * g.level);
+    const float inv = 1.0f / (255.0f * scale);
     for (int dir = 0; dir < 2; ++dir) {
         int64_t e = 2 * v + dir;
         if (!intree[e]) continue;
@@ -928,30 +932,28 @@ __global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
         uint32_t sz;
         if (rv > rw) { child = w; par = v; sz = (rv - rw + 1) >> 1; }
         else { child = v; par = w; sz = (rw - rv + 1) >> 1; }
-        float k = (float)edge_key(img[v], img[w], ldexpf(1.0f, 2 * g.level));
         parent[child] = (int32_t)par;
         size[child] = (int32_t)sz;
-        wgt[child] = k * inv;
+        wgt[child] = (float)edge_key(img[v], img[w], scale) * inv;
     }
-}
-
-__global__ void k_root_info(int64_t n, const int32_t *__restrict__ tree,
-                            const uint8_t *__restrict__ adj, Ranks rank_of,
-                            int32_t *__restrict__ parent, int32_t *__restrict__ size,
-                            float *__restrict__ wgt, uint64_t *__restrict__ rootval) {
-    int64_t v = gtid();
-    if (v >= n) return;
-    uint64_t rv = 0;
+    uint64_t rvl = 0;
     if (tree[v] == v) {
         parent[v] = -1;
         wgt[v] = 0.f;
         uint8_t a = adj[v] & 15;
         int32_t sz = a ? (int32_t)((rank_of(4 * v + first_dir(a)) + 1) >> 1) + 1 : 1;
         size[v] = sz;
-        // packed for one scan: low = tour length 2(sz-1), high = node count sz
-        rv = ((uint64_t)(uint32_t)sz << 32) | (uint32_t)(2 * (sz - 1));
+        // low = tour length 2(sz-1), high = node count sz
+        rvl = ((uint64_t)(uint32_t)sz << 32) | (uint32_t)(2 * (sz - 1));
     }
-    rootval[v] = rv;
+    rootval[v] = rvl;
+    if (plo) {
+        lo[v] = plo[v];
+        hi[v] = phi[v];
+    } else {
+        lo[v] = 0;
+        hi[v] = g.dmax[pair];
+    }
 }
 
 // --- 5. heavy child ----------------------------------------------------------------
@@ -987,31 +989,34 @@ __global__ void k_tour_scatter(LevelGeom g, const uint8_t *__restrict__ adj,
                                const int32_t *__restrict__ heavy_child,
                                Ranks rank_of, const uint64_t *__restrict__ rootoff,
                                uint64_t *__restrict__ tourval, int32_t *__restrict__ info) {
-    int64_t s = gtid();
-    int64_t n = g.off[g.n_pairs];
-    if (s >= 4 * n) return;
-    int64_t v = s >> 2;
-    int d = (int)(s & 3);
-    if (!((adj[v] >> d) & 1)) return;
-    int W = g.W[pair_of(g, (int)v)];
-    int64_t w = nbr(v, d, W);
-    int64_t root = tree[v];
-    uint32_t toff = (uint32_t)rootoff[root];
-    int64_t tlen = 2 * (int64_t)(size[root] - 1);
-    int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rank_of(s));
-    if (pos < toff || pos >= (int64_t)toff + tlen) {
-        info[HDP_INFO_ERROR] = 2;
-        return;
+    int64_t v = gtid();
+    if (v >= g.off[g.n_pairs]) return;
+    const uint8_t a = adj[v] & 15;
+    if (!a) return;
+    const int W = g.W[pair_of(g, (int)v)];
+    const int64_t root = tree[v];
+    const uint32_t toff = (uint32_t)rootoff[root];
+    const int64_t tlen = 2 * (int64_t)(size[root] - 1);
+    const int hv = heavy_child[v];
+    const int pv = parent[v];
+    for (int d = 0; d < 4; ++d) {
+        if (!((a >> d) & 1)) continue;
+        int64_t w = nbr(v, d, W);
+        int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rank_of(4 * v + d));
+        if (pos < toff || pos >= (int64_t)toff + tlen) {
+            info[HDP_INFO_ERROR] = 2;
+            continue;
+        }
+        uint64_t val;
+        if (w != pv) {  // down edge v -> child w
+            uint64_t light = hv != w ? 1 : 0;
+            val = (1ull << kDownShift) + (light << kLdShift) + 1ull;
+        } else {  // up edge v -> parent w
+            uint64_t light = heavy_child[w] != v ? 1 : 0;
+            val = 0ull - (light << kLdShift) - 1ull;
+        }
+        tourval[pos] = val;
     }
-    uint64_t val;
-    if (parent[w] == v) {  // down edge v -> w
-        uint64_t light = heavy_child[v] != w ? 1 : 0;
-        val = (1ull << kDownShift) + (light << kLdShift) + 1ull;
-    } else {  // up edge v -> parent w
-        uint64_t light = heavy_child[w] != v ? 1 : 0;
-        val = 0ull - (light << kLdShift) - 1ull;
-    }
-    tourval[pos] = val;
 }
 
 // Maximum over the active lanes of a wavefront, then one atomicMax.
@@ -1028,7 +1033,7 @@ __global__ void k_node_order(LevelGeom g, const uint8_t *__restrict__ adj,
                              Ranks rank_of, const uint64_t *__restrict__ rootoff,
                              const int32_t *__restrict__ size, const uint64_t *__restrict__ tourscan,
                              int32_t *__restrict__ depth, int32_t *__restrict__ ld,
-                             int32_t *__restrict__ gpre, int32_t *__restrict__ info) {
+                             int32_t *__restrict__ seq, int32_t *__restrict__ info) {
     int64_t w = gtid();
     int32_t dep = 0, l = 0;
     if (w < g.off[g.n_pairs]) {
@@ -1057,20 +1062,11 @@ __global__ void k_node_order(LevelGeom g, const uint8_t *__restrict__ adj,
         }
         depth[w] = dep;
         ld[w] = l;
-        gpre[w] = pre;
+        if (pre < 0 || pre >= g.off[g.n_pairs])
+            info[HDP_INFO_ERROR] = 4;
+        else
+            seq[pre] = (int32_t)w;
     }
-}
-
-__global__ void k_scatter_seq(const int32_t *__restrict__ gpre, int32_t *__restrict__ seq,
-                              int64_t n, int32_t *__restrict__ info) {
-    int64_t v = gtid();
-    if (v >= n) return;
-    int32_t q = gpre[v];
-    if (q < 0 || q >= n) {
-        info[HDP_INFO_ERROR] = 4;
-        return;
-    }
-    seq[q] = (int32_t)v;
 }
 
 struct LdKey {
@@ -1097,48 +1093,36 @@ __global__ void k_phase_ptr(const int32_t *__restrict__ offs, int64_t ntiles, in
 
 // --- 7. rows of the volume layout ---------------------------------------------------
 
-__global__ void k_rows(LevelGeom g, const int32_t *__restrict__ node,
-                       const int32_t *__restrict__ row_of, const int32_t *__restrict__ parent,
-                       const float *__restrict__ wgt, const int32_t *__restrict__ heavy_child,
-                       const uint8_t *__restrict__ adj, int32_t *__restrict__ prow,
-                       uint8_t *__restrict__ heavy, int32_t *__restrict__ lc,
-                       float *__restrict__ rw) {
-    int64_t r = gtid();
+// Per pixel v (coherent reads), scattered to its row r: parent row, heavy
+// flag, edge weight and the rows of up to three light children in ascending
+// pixel id.
+__global__ void k_rows(LevelGeom g, const int32_t *__restrict__ row_of,
+                       const int32_t *__restrict__ parent, const float *__restrict__ wgt,
+                       const int32_t *__restrict__ heavy_child, const uint8_t *__restrict__ adj,
+                       int32_t *__restrict__ prow, uint8_t *__restrict__ heavy,
+                       int32_t *__restrict__ lc, float *__restrict__ rw) {
+    int64_t v = gtid();
     int64_t n = g.off[g.n_pairs];
-    if (r >= n) return;
-    int64_t v = node[r];
-    int64_t p = parent[v];
+    if (v >= n) return;
+    const int64_t r = row_of[v];
+    const int64_t p = parent[v];
     prow[r] = p >= 0 ? row_of[p] : -1;
     heavy[r] = (p >= 0 && heavy_child[p] == v) ? 1 : 0;
     rw[r] = wgt[v];
-    int W = g.W[pair_of(g, (int)v)];
-    uint8_t a = adj[v];
-    const int order[4] = {3, 2, 0, 1};
+    const int W = g.W[pair_of(g, (int)v)];
+    const uint8_t a = adj[v];
+    const int order[4] = {3, 2, 0, 1};  // up, left, right, down: ascending pixel id
+    const int hc = heavy_child[v];
     int k = 0;
-    int hc = heavy_child[v];
     for (int i = 0; i < 4; ++i) {
         int d = order[i];
         if (!((a >> d) & 1)) continue;
         int64_t w = nbr(v, d, W);
-        if (parent[w] != v || w == hc) continue;
+        if (w == p || w == hc) continue;  // parent or heavy child
         if (k < 3) lc[(int64_t)k * n + r] = row_of[w];
         ++k;
     }
     for (; k < 3; ++k) lc[(int64_t)k * n + r] = -1;
-}
-
-__global__ void k_intervals(LevelGeom g, const int32_t *__restrict__ plo,
-                            const int32_t *__restrict__ phi, int32_t *__restrict__ lo,
-                            int32_t *__restrict__ hi) {
-    int64_t v = gtid();
-    if (v >= g.off[g.n_pairs]) return;
-    if (plo) {
-        lo[v] = plo[v];
-        hi[v] = phi[v];
-    } else {
-        lo[v] = 0;
-        hi[v] = g.dmax[pair_of(g, (int)v)];
-    }
 }
 
 // --- 8. canonical level order ------------------------------------------------------------
@@ -1162,8 +1146,10 @@ __global__ void k_level_ptr(const int32_t *__restrict__ order, const int32_t *__
 }
 
 __global__ void k_finish_info(const int32_t *__restrict__ flags, int32_t *__restrict__ info,
-                              int width) {
+                              int width, int64_t n, const uint64_t *__restrict__ root_total) {
     if (threadIdx.x != 0) return;
+    // every tree of sz nodes has a tour of 2(sz - 1) slots
+    info[HDP_INFO_N_TREES] = (int32_t)(n - (int64_t)((uint32_t)*root_total >> 1));
     int bv = 0, rk = 0;
     for (int r = 0; r < 64; ++r) {
         bv += flags[FLAG_BV + r] ? 1 : 0;
@@ -1207,8 +1193,8 @@ struct Bump {
 
 struct TreeWs {
     int32_t *comp0, *lmin, *croot, *mnroot, *Rall, *At, *slot, *ctr, *flags;
-    int32_t *size, *heavy_child, *ld, *gpre, *seq;
-    uint64_t *cw, *best0, *best1, *E, *Et, *lw, *pr, *rootval, *tourval, *partial64;
+    int32_t *size, *heavy_child, *ld, *seq;
+    uint64_t *cw, *best0, *best1, *E, *Et, *lw, *pr, *rootval, *tourval, *partial64, *root_total;
     uint32_t *C;
     uint8_t *intree, *adj;
     int32_t *partial32, *hist, *sortA, *sortB;
@@ -1230,7 +1216,6 @@ static TreeWs carve_tree_ws(void *ws, int64_t n, size_t *bytes) {
     t.size = b.take<int32_t>(n);
     t.heavy_child = b.take<int32_t>(n);
     t.ld = b.take<int32_t>(n);
-    t.gpre = b.take<int32_t>(n);
     t.seq = b.take<int32_t>(n);
     t.cw = b.take<uint64_t>(n);
     t.best0 = b.take<uint64_t>(n);
@@ -1243,6 +1228,7 @@ static TreeWs carve_tree_ws(void *ws, int64_t n, size_t *bytes) {
     t.rootval = b.take<uint64_t>(n);
     t.tourval = b.take<uint64_t>(2 * n);
     t.partial64 = b.take<uint64_t>(scan_tiles(2 * n) + 1);
+    t.root_total = b.take<uint64_t>(1);
     t.intree = b.take<uint8_t>(2 * n);
     t.adj = b.take<uint8_t>(n);
     t.partial32 = b.take<int32_t>(scan_tiles(256 * ntiles) + 1);
@@ -1283,7 +1269,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     size_t bytes;
     TreeWs t = carve_tree_ws(ws, n, &bytes);
     const float4 *im = reinterpret_cast<const float4 *>(img);
-    unsigned gn = grid_for(n), gn4 = grid_for(4 * n);
+    unsigned gn = grid_for(n);
 
     // Round bounds.  After the tile-local phase every component that still has
     // an edge owns a tile-border pixel, and the number of such components at
@@ -1342,20 +1328,19 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     k_rank_tail<<<1, kLocalThreads, 0, st>>>(rk_rounds, t.flags, t.ctr, t.At, t.slot, t.pr,
                                              f.info);
     Ranks rk{t.lw, t.pr};
-    k_parent<<<gn, kBlock, 0, st>>>(g, t.intree, im, rk, f.parent, t.size, f.wgt);
-    k_root_info<<<gn, kBlock, 0, st>>>(n, f.tree, t.adj, rk, f.parent, t.size, f.wgt, t.rootval);
+    k_parent<<<gn, kBlock, 0, st>>>(g, t.intree, im, rk, f.tree, t.adj, plo, phi, f.parent, t.size,
+                                    f.wgt, t.rootval, f.lo, f.hi);
     // 5: heavy child
     k_heavy<<<gn, kBlock, 0, st>>>(g, t.adj, f.parent, t.size, t.heavy_child);
     // 6: tour offsets, tour values, prefix sum, per-node depth / light depth / preorder
-    device_scan<uint64_t>(t.rootval, t.rootval, n, t.partial64, nullptr, false, st);
-    k_tour_scatter<<<gn4, kBlock, 0, st>>>(g, t.adj, f.tree, f.parent, t.size, t.heavy_child, rk,
-                                           t.rootval, t.tourval, f.info);
+    device_scan<uint64_t>(t.rootval, t.rootval, n, t.partial64, t.root_total, false, st);
+    k_tour_scatter<<<gn, kBlock, 0, st>>>(g, t.adj, f.tree, f.parent, t.size, t.heavy_child, rk,
+                                          t.rootval, t.tourval, f.info);
     int64_t tour_len = 2 * n;  // upper bound; entries past the real length are never read
     device_scan<uint64_t>(t.tourval, t.tourval, tour_len, t.partial64, nullptr, true, st);
     k_node_order<<<gn, kBlock, 0, st>>>(g, t.adj, f.tree, f.parent, rk, t.rootval, t.size,
-                                        t.tourval, f.depth, t.ld, t.gpre, f.info);
+                                        t.tourval, f.depth, t.ld, t.seq, f.info);
     // 7: rows (stable partition of the preorder by light depth)
-    k_scatter_seq<<<gn, kBlock, 0, st>>>(t.gpre, t.seq, n, f.info);
     {
         int64_t ntiles = scan_tiles(n);
         if (ntiles < 1) ntiles = 1;
@@ -1366,10 +1351,9 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         k_count_scatter<64, 6><<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles,
                                                                     f.node, f.row);
     }
-    k_rows<<<gn, kBlock, 0, st>>>(g, f.node, f.row, f.parent, f.wgt, t.heavy_child, t.adj, f.prow,
-                                  f.heavy, f.lc, f.rw);
-    k_intervals<<<gn, kBlock, 0, st>>>(g, plo, phi, f.lo, f.hi);
-    k_finish_info<<<1, 64, 0, st>>>(t.flags, f.info, width);
+    k_rows<<<gn, kBlock, 0, st>>>(g, f.row, f.parent, f.wgt, t.heavy_child, t.adj, f.prow, f.heavy,
+                                  f.lc, f.rw);
+    k_finish_info<<<1, 64, 0, st>>>(t.flags, f.info, width, n, t.root_total);
 }
 
 // 8: level order (stable LSD radix sort of ids by depth) and level_ptr
