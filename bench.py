@@ -57,18 +57,6 @@ def upload(pairs):
     return L, R, shapes
 
 
-def autotune(hdp, tuner, results_by_level, sigma=0.1):
-    """Pick the tile schedule of every row width met in these results."""
-    cache = {}
-    done = {}
-    for r in sorted(results_by_level, key=lambda r: -r.forest.n):
-        w = r.forest.width
-        if w in done or r.cost is None:
-            continue
-        done[w] = tuner.tune(r.forest, r.cost, sigma, cache=cache)
-    return {w: f"{e['cpt']}x{e['rpg']}" for w, e in done.items()}
-
-
 def pass_bytes(forest, up: bool) -> float:
     """Algorithmic HBM bytes of one aggregation pass over a forest: read the
     source volume and write the result (8 B per entry), read the previous-phase
@@ -145,16 +133,29 @@ def main():
                       "global_batch": 1}}
 
     from paper_1509_08197_amd import tuner
+    hdp_sched = full_sched = None
     if not args.no_tune:
+        # schedules picked by timing whole captured steps (one width at a time)
         probe = hdp.hdp_stereo(L_rgb, R_rgb, shapes, S=P["S"], L=P["L"], window=P["window"],
                                beta=P["beta"], keep=True)
-        probe.append(hdp.full_range(L_rgb, R_rgb, shapes, keep=True))
-        out["schedule"] = autotune(hdp, tuner, probe)
+        widths = sorted({r.forest.width for r in probe}, key=lambda w: -sum(
+            r.forest.n for r in probe if r.forest.width == w))
         del probe
+        if args.mode != "full":
+            hdp_sched = tuner.tune_step(hdp_eager, widths)
+        if args.mode != "hdp":
+            full_sched = tuner.tune_step(full_eager, [dmax + 1])
+        out["schedule"] = {"hdp": {str(k): v for k, v in (hdp_sched or {}).items()},
+                           "full_range": {str(k): v for k, v in (full_sched or {}).items()}}
         torch.cuda.empty_cache()
+
+    def use(sched):
+        for wdt, s in (sched or {}).items():
+            hdp.set_schedule(wdt, *(int(x) for x in s.split("x")))
 
     if args.mode != "full":
         # the timed step is a whole-step HIP graph replay (captured once)
+        use(hdp_sched)
         step = hdp.CapturedStep(hdp_eager)
         t_hdp = timed(step.replay, args.steps, args.warmup)
         res = hdp_eager()
@@ -190,6 +191,7 @@ def main():
         del step
 
     if args.mode != "hdp":
+        use(full_sched)
         fstep = hdp.CapturedStep(full_eager)
         t_full = timed(fstep.replay, max(2, args.steps // 4), 1)
         out["full_range"] = {"ms_per_step": t_full * 1e3,
@@ -199,6 +201,7 @@ def main():
         del fstep
 
     if not args.no_extra and args.mode == "both":
+        use(hdp_sched)
         out["batched"] = bench_batched(hdp, scenes, timed, args)
         out["adjoint"] = bench_adjoint(hdp, timed, args)
 

@@ -95,6 +95,12 @@ bool set_schedule(int width, int cpt, int rpg) {
 }
 
 constexpr int kPassSets = 3;  // flag sets: up, down (and a second up pass in the adjoint)
+// Narrow rows (at most kSentMaxWidth labels) use rows as signals: unwritten
+// values hold signalling-NaN patterns that no arithmetic produces.
+constexpr int kSentMaxWidth = 32;
+constexpr uint32_t kSentF = 0x7fa00001u;
+constexpr uint64_t kSent64 = 0x7fa000017fa00001ull;
+constexpr uint64_t kSentD = 0x7ff4000000000001ull;
 
 // Prologue of an aggregation call, one launch: per-row coefficients
 // s = exp(-w / sigma) and 1 - s^2, cleared tile flags and tickets of every
@@ -104,8 +110,16 @@ __global__ void k_prologue(int64_t n, const float *__restrict__ rw,
                            double *__restrict__ s, double *__restrict__ om,
                            int32_t *__restrict__ flags, int64_t tiles, int32_t *__restrict__ ticket,
                            const int32_t *__restrict__ phase_ptr, const int32_t *__restrict__ info,
-                           int rows, int32_t *__restrict__ plan) {
+                           int rows, int32_t *__restrict__ plan, uint32_t *__restrict__ fill0,
+                           uint32_t *__restrict__ fill1, int64_t fill_words,
+                           uint64_t *__restrict__ maps, int64_t map_words) {
     int64_t r = gtid();
+    // narrow rows: mark the up passes' outputs and the tile maps unwritten
+    for (int64_t i = r; i < fill_words; i += (int64_t)gridDim.x * blockDim.x) {
+        if (fill0) fill0[i] = kSentF;
+        if (fill1) fill1[i] = kSentF;
+    }
+    for (int64_t i = r; i < map_words; i += (int64_t)gridDim.x * blockDim.x) maps[i] = kSentD;
     if (r < n) {
         if (prow[r] < 0) {
             s[r] = 0.0;
@@ -158,6 +172,9 @@ struct PassArgs {
     double *tX;          // [tiles][width] tile map applied to 0
     double *tI;          // [tiles][width] value after the tile's last row
     int32_t *err;        // nonzero: a bounded wait timed out / inconsistent input
+    // narrow-row mode (rows as signals)
+    float *fill;         // up pass: rows of the following down pass's output to mark unwritten
+    double *tPs, *tXs;   // this pass's tile maps (tiles without a chain break), marked unwritten
 };
 
 // Data that crosses workgroups inside one launch (published tile maps, rows of
@@ -175,7 +192,7 @@ __device__ __forceinline__ void st_dev(T *p, T v) {
 }
 __device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0); }
 
-constexpr int64_t kSpinLimit = int64_t(1) << 24;
+constexpr int64_t kSpinLimit = int64_t(1) << 20;
 
 __device__ __forceinline__ int wait_nonzero(const int32_t *p, int32_t *err, int code) {
     int f = ld_dev(p);
@@ -458,11 +475,253 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
     }
 }
 
+// --- narrow rows: rows as signals ------------------------------------------------
+// For narrow rows (the HDP windows) the pass does without tile flags: the
+// output rows start out holding a signalling-NaN pattern that no arithmetic
+// produces, and a tile that gathers a row of the previous phase polls the row
+// itself.  Rows that do not depend on the tile's carry-in (those at or after
+// its first chain break) are stored as soon as they are known; the carry-in is
+// the value of the last row of the preceding tile (read the same way), or,
+// across a tile with no chain break, that tile's published map.  Maps are
+// FP64, also marked unwritten until published.
+
+// CPT labels of a row, once written (device-coherent loads, bounded poll).
+template <int CPT>
+__device__ __forceinline__ bool poll_cols(const float *p, float *v, int32_t *err, bool wait) {
+    for (int64_t it = 0;; ++it) {
+        bool ok = true;
+        if (CPT == 1) {
+            uint32_t u = ld_dev(reinterpret_cast<const uint32_t *>(p));
+            ok = u != kSentF;
+            v[0] = __uint_as_float(u);
+        } else {
+#pragma unroll
+            for (int h = 0; h < CPT / 2; ++h) {
+                uint64_t u = ld_dev(reinterpret_cast<const uint64_t *>(p) + h);
+                ok = ok && u != kSent64;
+                v[2 * h] = __uint_as_float((uint32_t)u);
+                v[2 * h + 1] = __uint_as_float((uint32_t)(u >> 32));
+            }
+        }
+        if (ok || !wait) return ok;
+        if (it > kSpinLimit) {
+            atomicMax(err, 20);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+template <bool UP, int CPT, int kRPG>
+__global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
+    __shared__ double sP[kBlock];
+    __shared__ double sX[kBlock * CPT];
+    __shared__ int s_ticket;
+    __shared__ double s_first;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_ticket = atomicAdd(A.ticket, 1);
+    __syncthreads();
+    const int T = s_ticket;
+    const int K = A.plan[P_NPH];
+    const int total = A.plan[UP ? P_TOT_UP : P_TOT_DN];
+    if (T >= total) return;
+    const int32_t *t0 = A.plan + (UP ? P_T0UP : P_T0DN);
+    const int32_t *row0 = A.plan + P_ROW0;
+    int q = 0;
+    while (q + 1 < K && t0[q + 1] <= T) ++q;
+    const int k = UP ? K - 1 - q : q;
+    const int tl = T - t0[q];
+    const int r0 = row0[k], r1 = row0[k + 1];
+    const int w = A.width, rows = A.rows;
+    const int g = tid / A.lpr, jl = tid - g * A.lpr;
+    const int j0 = jl * CPT;
+    const bool active = g < A.groups;
+
+    // stage 1: loads that do not depend on other tiles of this launch; the up
+    // pass also marks its rows of the down pass's output as unwritten
+    double av[kRPG];
+    double bv[kRPG][CPT];
+    int rr[kRPG], x0[kRPG], x1[kRPG], x2[kRPG];
+#pragma unroll
+    for (int i = 0; i < kRPG; ++i) {
+        int li = g * kRPG + i;
+        int r = UP ? r1 - 1 - (tl * rows + li) : r0 + tl * rows + li;
+        bool in = active && (UP ? r >= r0 : r < r1);
+        rr[i] = in ? r : -1;
+        av[i] = 1.0;
+        x0[i] = x1[i] = x2[i] = -1;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) bv[i][c] = 0.0;
+        if (!in) continue;
+        float v[CPT];
+        load_cols<CPT>(A.src + (int64_t)r * w + j0, v);
+        if (UP) {
+            if (A.fill) {
+#pragma unroll
+                for (int c = 0; c < CPT; ++c)
+                    reinterpret_cast<uint32_t *>(A.fill)[(int64_t)r * w + j0 + c] = kSentF;
+            }
+            av[i] = (r + 1 < r1 && A.heavy[r + 1]) ? A.s[r + 1] : 0.0;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) bv[i][c] = (double)v[c];
+            x0[i] = A.lc[r];
+            x1[i] = A.lc[A.n + r];
+            x2[i] = A.lc[2 * A.n + r];
+        } else {
+            bool hv = A.heavy[r];
+            av[i] = hv ? A.s[r] : 0.0;
+            double o = A.om[r];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) bv[i][c] = o * (double)v[c];
+            x0[i] = hv ? -1 : A.prow[r];
+        }
+    }
+
+    // stage 2: gather the rows of the previous phase, each once it is written
+#pragma unroll
+    for (int i = 0; i < kRPG; ++i) {
+        float v[CPT];
+        if (UP) {
+            int xs[3] = {x0[i], x1[i], x2[i]};
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                if (xs[m] < 0) continue;
+                double sc = A.s[xs[m]];
+                poll_cols<CPT>(A.dst + (int64_t)xs[m] * w + j0, v, A.err, true);
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
+            }
+        } else if (x0[i] >= 0) {
+            double sc = A.s[rr[i]];
+            poll_cols<CPT>(A.dst + (int64_t)x0[i] * w + j0, v, A.err, true);
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
+        }
+    }
+
+    // maps of this thread's rows, of the groups before it and of the tile
+    double P = 1.0, X[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) X[c] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kRPG; ++i) {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) X[c] = av[i] * X[c] + bv[i][c];
+        P *= av[i];
+    }
+    if (tid == 0) s_first = av[0];
+    sP[tid] = P;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) sX[tid * CPT + c] = X[c];
+    __syncthreads();
+    double Pt = 1.0, Xt[CPT], Pg = 1.0, Xg[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) Xt[c] = Xg[c] = 0.0;
+    if (active) {
+        for (int q2 = 0; q2 < A.groups; ++q2) {
+            if (q2 == g) {
+                Pg = Pt;
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) Xg[c] = Xt[c];
+            }
+            int o = q2 * A.lpr + jl;
+            double pq = sP[o];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) Xt[c] = pq * Xt[c] + sX[o * CPT + c];
+            Pt *= pq;
+        }
+    }
+    // a tile without a chain break publishes its map for the tiles after it
+    if (active && g == 0 && Pt != 0.0 && tl > 0) {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+            st_dev(reinterpret_cast<uint64_t *>(&A.tXs[(int64_t)T * w + j0 + c]),
+                   (uint64_t)__double_as_longlong(Xt[c]));
+        if (jl == 0)
+            st_dev(reinterpret_cast<uint64_t *>(&A.tPs[T]), (uint64_t)__double_as_longlong(Pt));
+    }
+    // rows at or after the tile's first chain break do not depend on the carry-in
+    if (active) {
+        double cv[CPT], pp = Pg;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) cv[c] = Xg[c];
+#pragma unroll
+        for (int i = 0; i < kRPG; ++i) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) cv[c] = av[i] * cv[c] + bv[i][c];
+            pp *= av[i];
+            if (pp == 0.0 && rr[i] >= 0) store_cols_dev<CPT>(A.dst + (int64_t)rr[i] * w + j0, cv);
+        }
+    }
+    if (tl == 0 || s_first == 0.0 || !active) return;  // every row was carry-independent
+
+    // carry-in: the last row of the preceding tile, or across a tile without a
+    // chain break its map and then the tile before it
+    double carry[CPT];
+    {
+        double mP = 1.0, mX[CPT];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) mX[c] = 0.0;
+        const int lim = t0[q];
+        int pred = T - 1;
+        for (int64_t it = 0;; ++it) {
+            // row processed just before tile pred + 1 of this phase
+            const int nxt = pred + 1 - lim;
+            const int lr = UP ? r1 - nxt * rows : r0 + nxt * rows - 1;
+            float v[CPT];
+            if (poll_cols<CPT>(A.dst + (int64_t)lr * w + j0, v, A.err, false)) {
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) carry[c] = mP * (double)v[c] + mX[c];
+                break;
+            }
+            if (pred > lim) {
+                uint64_t pw = ld_dev(reinterpret_cast<const uint64_t *>(&A.tPs[pred]));
+                bool ok = pw != kSentD;
+                double xv[CPT];
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    uint64_t u =
+                        ld_dev(reinterpret_cast<const uint64_t *>(&A.tXs[(int64_t)pred * w + j0 + c]));
+                    ok = ok && u != kSentD;
+                    xv[c] = __longlong_as_double((long long)u);
+                }
+                if (ok) {
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) mX[c] = mP * xv[c] + mX[c];
+                    mP *= __longlong_as_double((long long)pw);
+                    --pred;
+                    continue;
+                }
+            }
+            if (it > kSpinLimit) {
+                atomicMax(A.err, 21);
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) carry[c] = 0.0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+
+    // rows before the first chain break, with the carry-in
+    double cv[CPT], pp = Pg;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) cv[c] = Pg * carry[c] + Xg[c];
+#pragma unroll
+    for (int i = 0; i < kRPG; ++i) {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) cv[c] = av[i] * cv[c] + bv[i][c];
+        pp *= av[i];
+        if (pp != 0.0 && rr[i] >= 0) store_cols_dev<CPT>(A.dst + (int64_t)rr[i] * w + j0, cv);
+    }
+}
+
 // --- workspace --------------------------------------------------------------------
 
 struct AggWs {
     int32_t *plan, *ticket, *flags;  // flags: kPassSets x (flag[tiles], flagw[tiles])
     double *s, *om, *tP, *tX, *tI;
+    double *tPs, *tXs;  // narrow rows: kPassSets x tile maps (tiles, tiles x width)
     float *up;      // U when the caller does not keep it
     float *ug;      // U of the gradient (backward)
     double *red;    // per-block partial sums (backward)
@@ -494,6 +753,10 @@ static AggWs carve_agg_ws(void *ws, int64_t n, int width, size_t *bytes) {
     a.tP = reinterpret_cast<double *>(take(sizeof(double) * nt));
     a.tX = reinterpret_cast<double *>(take(sizeof(double) * nt * width));
     a.tI = reinterpret_cast<double *>(take(sizeof(double) * nt * width));
+    const bool narrow = width <= kSentMaxWidth;  // one block: the prologue marks it in one sweep
+    a.tPs = reinterpret_cast<double *>(
+        take(narrow ? sizeof(double) * kPassSets * nt * (width + 1) : 8));
+    a.tXs = a.tPs + (narrow ? kPassSets * nt : 0);
     a.up = reinterpret_cast<float *>(take(sizeof(float) * n * width));
     a.ug = reinterpret_cast<float *>(take(sizeof(float) * n * width));
     a.red = reinterpret_cast<double *>(take(sizeof(double) * (n / 4 + 64)));
@@ -510,17 +773,24 @@ size_t aggregate_workspace_bytes(int64_t n, int width) {
 template <bool UP, int CPT, int RPG>
 static void launch_pass(const PassArgs &A, int64_t tiles, hipStream_t st) {
     timer_before(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
-    k_pass<UP, CPT, RPG><<<(unsigned)tiles, kBlock, 0, st>>>(A);
+    if (A.width <= kSentMaxWidth)
+        k_pass_s<UP, CPT, RPG><<<(unsigned)tiles, kBlock, 0, st>>>(A);
+    else
+        k_pass<UP, CPT, RPG><<<(unsigned)tiles, kBlock, 0, st>>>(A);
     timer_after(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
 }
 
 // One pass with flag set `set` (cleared by the prologue of this call).
 template <bool UP>
-static void run_pass(PassArgs A, const AggWs &w, const TileGeom &tg, int set, hipStream_t st) {
+static void run_pass(PassArgs A, const AggWs &w, const TileGeom &tg, int set, hipStream_t st,
+                     float *fill = nullptr) {
     int64_t tiles = A.n / tg.rows + HDP_MAX_PHASES + 2;  // >= the plan's tile count
     A.ticket = w.ticket + set;
     A.flag = w.flags + (int64_t)(2 * set) * w.tiles;
     A.flagw = w.flags + (int64_t)(2 * set + 1) * w.tiles;
+    A.tPs = w.tPs + (int64_t)set * w.tiles;
+    A.tXs = w.tXs + (int64_t)set * w.tiles * A.width;
+    A.fill = fill;
     if (tg.cpt == 4) {
         if (tg.rpg == 4) launch_pass<UP, 4, 4>(A, tiles, st);
         else launch_pass<UP, 4, 8>(A, tiles, st);
@@ -555,11 +825,19 @@ static PassArgs pass_args(const hdp_forest &f, int width, const AggWs &w, const 
 }
 
 // Coefficients and the plan of both passes (device side, no host sync).
-static void prologue(const hdp_forest &f, int width, float sigma, const AggWs &w, hipStream_t st) {
+// fill0 / fill1: outputs of the up passes of this call (narrow rows only).
+static void prologue(const hdp_forest &f, int width, float sigma, const AggWs &w, hipStream_t st,
+                     float *fill0 = nullptr, float *fill1 = nullptr) {
     int64_t m = f.n > w.tiles ? f.n : w.tiles;
-    k_prologue<<<grid_for(m), kBlock, 0, st>>>(f.n, f.rw, f.prow, 1.0 / (double)sigma, w.s, w.om,
-                                               w.flags, w.tiles, w.ticket, f.phase_ptr, f.info,
-                                               tile_geom(width).rows, w.plan);
+    const bool narrow = width <= kSentMaxWidth;
+    int64_t fill_words = narrow ? f.n * width : 0;
+    int64_t map_words = narrow ? (int64_t)kPassSets * w.tiles * (width + 1) : 0;
+    k_prologue<<<grid_for(m), kBlock, 0, st>>>(
+        f.n, f.rw, f.prow, 1.0 / (double)sigma, w.s, w.om, w.flags, w.tiles, w.ticket,
+        f.phase_ptr, f.info, tile_geom(width).rows, w.plan,
+        narrow ? reinterpret_cast<uint32_t *>(fill0) : nullptr,
+        narrow ? reinterpret_cast<uint32_t *>(fill1) : nullptr, fill_words,
+        reinterpret_cast<uint64_t *>(w.tPs), map_words);
 }
 
 // Two passes of `src` over the forest: U -> up, A -> out (flag sets up_set, up_set + 1).
@@ -569,7 +847,7 @@ static void two_pass(const hdp_forest &f, int width, const float *src, float *up
     PassArgs A = pass_args(f, width, w, tg);
     A.src = src;
     A.dst = up;
-    run_pass<true>(A, w, tg, up_set, st);
+    run_pass<true>(A, w, tg, up_set, st, out);
     A.src = up;
     A.dst = out;
     run_pass<false>(A, w, tg, up_set + 1, st);
@@ -579,8 +857,9 @@ void launch_aggregate(const hdp_forest &f, int width, const float *cost, float s
                       float *up, void *ws, hipStream_t st) {
     size_t bytes;
     AggWs w = carve_agg_ws(ws, f.n, width, &bytes);
-    prologue(f, width, sigma, w, st);
-    two_pass(f, width, cost, up ? up : w.up, agg, w, 0, st);
+    float *U = up ? up : w.up;
+    prologue(f, width, sigma, w, st, U);
+    two_pass(f, width, cost, U, agg, w, 0, st);
 }
 
 // --- adjoint ----------------------------------------------------------------------------
@@ -646,7 +925,7 @@ void launch_aggregate_backward(const hdp_forest &f, int width, const float *cost
                                hipStream_t st) {
     size_t bytes;
     AggWs w = carve_agg_ws(ws, f.n, width, &bytes);
-    prologue(f, width, sigma, w, st);
+    prologue(f, width, sigma, w, st, w.ug, up ? nullptr : w.up);
     const float *uc = up;
     if (!uc) {  // recompute the up pass of the cost
         TileGeom tg = tile_geom(width);

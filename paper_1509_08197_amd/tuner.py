@@ -7,6 +7,9 @@ the device.  ``tune`` times every valid schedule on a real forest and cost
 volume of that width (HIP events around the whole aggregation) and keeps the
 fastest; results are cached in a JSON file keyed by device name, width and
 size class (log2 of the row count), and ``apply_cache`` installs them.
+``tune_step`` instead times a whole captured step (HIP graph replays) for
+each candidate, one width at a time, which also accounts for the schedule's
+effect on the kernels around the aggregation.
 """
 
 from __future__ import annotations
@@ -84,6 +87,38 @@ def tune(forest: "hdp.Forest", cost: torch.Tensor, sigma: float = 0.1, reps: int
     if cache is not None:
         cache.setdefault(_device_key(), {})[f"{width}:{size_class(forest.n)}"] = entry
     return entry
+
+
+def tune_step(step, widths, replays: int = 10, rounds: int = 3) -> Dict[int, str]:
+    """Coordinate search over the schedules of the given widths (in order),
+    timing graph replays of ``step`` (a function of a workspace dict, as for
+    ``hdp.CapturedStep``).  Leaves the best schedules installed; returns
+    {width: "CPTxRPG"}."""
+    chosen: Dict[int, str] = {}
+    for width in widths:
+        times = {}
+        for cpt, rpg in CANDIDATES:
+            if not valid(width, cpt, rpg):
+                continue
+            hdp.set_schedule(width, cpt, rpg)
+            g = hdp.CapturedStep(step)
+            best = float("inf")
+            for _ in range(rounds):
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev0.record()
+                for _ in range(replays):
+                    g.replay()
+                ev1.record()
+                torch.cuda.synchronize()
+                best = min(best, ev0.elapsed_time(ev1) / replays)
+            times[f"{cpt}x{rpg}"] = best
+            del g
+        pick = min(times, key=times.get)
+        cpt, rpg = (int(x) for x in pick.split("x"))
+        hdp.set_schedule(width, cpt, rpg)
+        chosen[width] = pick
+    return chosen
 
 
 def apply_cache(cache: Optional[Dict] = None) -> int:
