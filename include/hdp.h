@@ -147,6 +147,14 @@ HDP_API hdp_status hdp_level_shapes(const hdp_shape *shapes, int32_t n_pairs, in
 HDP_API hdp_status hdp_pyramid(const uint8_t *rgb, const hdp_shape *shapes, int32_t n_pairs,
                        int32_t S, int32_t L, float *levels, void *stream);
 
+/* The pyramids of both views of the batch (Section 2.1), in the same launches:
+ * identical to hdp_pyramid on left_rgb -> left_levels and on right_rgb ->
+ * right_levels. */
+HDP_API hdp_status hdp_pyramid_views(const uint8_t *left_rgb, const uint8_t *right_rgb,
+                                     const hdp_shape *shapes, int32_t n_pairs, int32_t S,
+                                     int32_t L, float *left_levels, float *right_levels,
+                                     void *stream);
+
 /* Bytes of scratch space hdp_build_tree needs for n pixels. */
 HDP_API size_t hdp_build_tree_workspace_bytes(int64_t n);
 

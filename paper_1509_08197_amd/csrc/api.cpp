@@ -163,9 +163,11 @@ hdp_status hdp_level_shapes(const hdp_shape *shapes, int32_t n_pairs, int32_t S,
     return HDP_OK;
 }
 
-hdp_status hdp_pyramid(const uint8_t *rgb, const hdp_shape *shapes, int32_t n_pairs, int32_t S,
-                       int32_t L, float *levels, void *stream) {
-    if (!rgb || !levels) return HDP_EINVAL;
+static hdp_status pyramid_views(const uint8_t *const *rgb, int views, const hdp_shape *shapes,
+                                int32_t n_pairs, int32_t S, int32_t L, float *const *levels,
+                                void *stream) {
+    for (int i = 0; i < views; ++i)
+        if (!rgb[i] || !levels[i]) return HDP_EINVAL;
     if (S != 2 || L < 0 || L > 8) return HDP_EINVAL;
     hdp_shape ls[(8 + 1) * HDP_MAX_PAIRS];
     hdp_status st = hdp_level_shapes(shapes, n_pairs, S, L, ls);
@@ -176,8 +178,21 @@ hdp_status hdp_pyramid(const uint8_t *rgb, const hdp_shape *shapes, int32_t n_pa
         if (st != HDP_OK) return st;
     }
     (void)hipGetLastError();
-    hdp::launch_pyramid(rgb, geoms, L, S, levels, (hipStream_t)stream);
+    hdp::launch_pyramid(rgb, views, geoms, L, S, levels, (hipStream_t)stream);
     return last_hip();
+}
+
+hdp_status hdp_pyramid(const uint8_t *rgb, const hdp_shape *shapes, int32_t n_pairs, int32_t S,
+                       int32_t L, float *levels, void *stream) {
+    return pyramid_views(&rgb, 1, shapes, n_pairs, S, L, &levels, stream);
+}
+
+hdp_status hdp_pyramid_views(const uint8_t *left_rgb, const uint8_t *right_rgb,
+                             const hdp_shape *shapes, int32_t n_pairs, int32_t S, int32_t L,
+                             float *left_levels, float *right_levels, void *stream) {
+    const uint8_t *rgb[2] = {left_rgb, right_rgb};
+    float *levels[2] = {left_levels, right_levels};
+    return pyramid_views(rgb, 2, shapes, n_pairs, S, L, levels, stream);
 }
 
 size_t hdp_build_tree_workspace_bytes(int64_t n) {

@@ -5,8 +5,8 @@
 
 namespace hdp {
 
-void launch_pyramid(const uint8_t *rgb, const LevelGeom *geoms, int L, int S, float *levels,
-                    hipStream_t st);
+void launch_pyramid(const uint8_t *const *rgb, int views, const LevelGeom *geoms, int L, int S,
+                    float *const *levels, hipStream_t st);
 void launch_predict_range(const int32_t *disp_up, const LevelGeom &gu, const LevelGeom &gl, int S,
                           int window, int32_t *lo, int32_t *hi, hipStream_t st);
 void launch_cost_volume(const float *left, const float *right, const LevelGeom &g,

@@ -73,9 +73,8 @@ bool dev_alloc(void **p, size_t bytes) {
 // Enqueue one top-down step on stream st (no host synchronisation).
 hdp_status enqueue_step(hdp_plan_s *P, hipStream_t st) {
     const hdp_params &p = P->p;
-    hdp_status s = hdp_pyramid(P->left, P->shapes.data(), P->n_pairs, p.S, p.L, P->lev_l, st);
-    if (s != HDP_OK) return s;
-    s = hdp_pyramid(P->right, P->shapes.data(), P->n_pairs, p.S, p.L, P->lev_r, st);
+    hdp_status s = hdp_pyramid_views(P->left, P->right, P->shapes.data(), P->n_pairs, p.S, p.L,
+                                     P->lev_l, P->lev_r, st);
     if (s != HDP_OK) return s;
     for (int l = p.L; l >= 0; --l) {
         Level &L = P->lv[l];

@@ -4,11 +4,20 @@
 
 namespace hdp {
 
+// One launch serves the two views of a pair batch: blockIdx.y selects the
+// view (rgb / level buffers of view y).
+struct Views {
+    const uint8_t *rgb[2];
+    float4 *lev[2];  // layer buffers of the current output layer
+    const float4 *src[2];  // layer buffers of the input layer (downsampling)
+};
+
 // Layer 0: uint8 RGB -> (R, G, B, gx) with gx = sum(x+1) - sum(x-1) (replicated
 // border); every value is an exact small integer in FP32.
-__global__ void k_level0(const uint8_t *__restrict__ rgb, LevelGeom g, float4 *__restrict__ out) {
+__global__ void k_level0(Views V, LevelGeom g) {
     int64_t v = gtid();
     if (v >= g.off[g.n_pairs]) return;
+    const uint8_t *rgb = V.rgb[blockIdx.y];
     PixelPos p = pixel_pos(g, (int)v);
     const uint8_t *c = rgb + 3 * v;
     int xr = p.x + 1 < p.W ? 1 : 0;
@@ -17,24 +26,20 @@ __global__ void k_level0(const uint8_t *__restrict__ rgb, LevelGeom g, float4 *_
     const uint8_t *cl = rgb + 3 * (v + xl);
     float sr = (float)((int)cr[0] + cr[1] + cr[2]);
     float sl = (float)((int)cl[0] + cl[1] + cl[2]);
-    out[v] = make_float4((float)c[0], (float)c[1], (float)c[2], sr - sl);
+    V.lev[blockIdx.y][v] = make_float4((float)c[0], (float)c[1], (float)c[2], sr - sl);
 }
 
-// Layer l+1 from layer l: mean over the children of the S x S square that lie
-// inside the image (S = 2: 1, 2 or 4 children, so the mean is exact).
-__global__ void k_downsample(const float4 *__restrict__ in, LevelGeom gi, float4 *__restrict__ out,
-                             LevelGeom go, int S) {
-    int64_t V = gtid();
-    if (V >= go.off[go.n_pairs]) return;
-    PixelPos P = pixel_pos(go, (int)V);
-    int Wi = gi.W[P.pair], Hi = gi.H[P.pair], bi = gi.off[P.pair];
+// Mean over the children of the S x S square of node (X, Y) that lie inside
+// layer l (S = 2: 1, 2 or 4 children, so the mean is exact).
+__device__ __forceinline__ float3 square_mean(const float4 *__restrict__ in, int bi, int Wi, int Hi,
+                                              int X, int Y, int S) {
     float r = 0.f, gg = 0.f, b = 0.f;
     int cnt = 0;
     for (int dy = 0; dy < S; ++dy) {
-        int y = S * P.y + dy;
+        int y = S * Y + dy;
         if (y >= Hi) break;
         for (int dx = 0; dx < S; ++dx) {
-            int x = S * P.x + dx;
+            int x = S * X + dx;
             if (x >= Wi) break;
             float4 c = in[bi + y * Wi + x];
             r += c.x; gg += c.y; b += c.z;
@@ -42,21 +47,25 @@ __global__ void k_downsample(const float4 *__restrict__ in, LevelGeom gi, float4
         }
     }
     float inv = 1.0f / (float)cnt;  // 1, 1/2, 1/4: exact
-    out[V] = make_float4(r * inv, gg * inv, b * inv, 0.f);
+    return make_float3(r * inv, gg * inv, b * inv);
 }
 
-// Fill the gx channel of a layer from the channel sums of its row neighbours.
-__global__ void k_gradient(float4 *__restrict__ img, LevelGeom g) {
-    int64_t v = gtid();
-    if (v >= g.off[g.n_pairs]) return;
-    PixelPos p = pixel_pos(g, (int)v);
-    int xr = p.x + 1 < p.W ? 1 : 0;
-    int xl = p.x > 0 ? -1 : 0;
-    float4 a = img[v + xr];
-    float4 b = img[v + xl];
+// Layer l+1 from layer l (Section 2.1), with its gx channel from the channel
+// sums of the row neighbours' means (replicated border).
+__global__ void k_downsample(Views V, LevelGeom gi, LevelGeom go, int S) {
+    int64_t Vx = gtid();
+    if (Vx >= go.off[go.n_pairs]) return;
+    const float4 *in = V.src[blockIdx.y];
+    PixelPos P = pixel_pos(go, (int)Vx);
+    int Wi = gi.W[P.pair], Hi = gi.H[P.pair], bi = gi.off[P.pair];
+    float3 m = square_mean(in, bi, Wi, Hi, P.x, P.y, S);
+    int xr = P.x + 1 < P.W ? P.x + 1 : P.x;
+    int xl = P.x > 0 ? P.x - 1 : P.x;
+    float3 a = xr == P.x ? m : square_mean(in, bi, Wi, Hi, xr, P.y, S);
+    float3 b = xl == P.x ? m : square_mean(in, bi, Wi, Hi, xl, P.y, S);
     float sr = (a.x + a.y) + a.z;
     float sl = (b.x + b.y) + b.z;
-    reinterpret_cast<float *>(img)[4 * v + 3] = sr - sl;
+    V.lev[blockIdx.y][Vx] = make_float4(m.x, m.y, m.z, sr - sl);
 }
 
 // PixelIntv = [S*i - w, S*i + S - 1 + w] clipped to [0, dmax_l], i = label of
@@ -74,18 +83,23 @@ __global__ void k_predict_range(const int32_t *__restrict__ disp_up, LevelGeom g
     hi[v] = b > dl ? dl : b;
 }
 
-void launch_pyramid(const uint8_t *rgb, const LevelGeom *geoms, int L, int S, float *levels,
-                    hipStream_t st) {
-    float4 *cur = reinterpret_cast<float4 *>(levels);
+void launch_pyramid(const uint8_t *const *rgb, int views, const LevelGeom *geoms, int L, int S,
+                    float *const *levels, hipStream_t st) {
+    Views V{};
+    for (int i = 0; i < views; ++i) {
+        V.rgb[i] = rgb[i];
+        V.lev[i] = reinterpret_cast<float4 *>(levels[i]);
+    }
     int64_t n0 = geoms[0].off[geoms[0].n_pairs];
-    k_level0<<<grid_for(n0), kBlock, 0, st>>>(rgb, geoms[0], cur);
+    k_level0<<<dim3(grid_for(n0), views), kBlock, 0, st>>>(V, geoms[0]);
     for (int l = 0; l < L; ++l) {
         int64_t ni = geoms[l].off[geoms[l].n_pairs];
         int64_t no = geoms[l + 1].off[geoms[l + 1].n_pairs];
-        float4 *nxt = cur + ni;
-        k_downsample<<<grid_for(no), kBlock, 0, st>>>(cur, geoms[l], nxt, geoms[l + 1], S);
-        k_gradient<<<grid_for(no), kBlock, 0, st>>>(nxt, geoms[l + 1]);
-        cur = nxt;
+        for (int i = 0; i < views; ++i) {
+            V.src[i] = V.lev[i];
+            V.lev[i] = V.lev[i] + ni;
+        }
+        k_downsample<<<dim3(grid_for(no), views), kBlock, 0, st>>>(V, geoms[l], geoms[l + 1], S);
     }
 }
 

@@ -299,7 +299,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
         comp0[v] = (int32_t)tile_pixel(t, c);
         if (c == i) {
             cw[v] = (uint64_t)(uint32_t)v;
-            best0[v] = kNoEdge;
+            // least live edge of the component: the first global round's
+            // minimum-edge step, already known here
+            best0[v] = best[i];
             best1[v] = kNoEdge;
             lmin[v] = hk[i];
             croot[v] = -1;
@@ -1303,8 +1305,9 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     if (bv_rounds < 1) bv_rounds = 1;
     for (int r = 0; r < bv_rounds; ++r) {
         uint64_t *bc = (r & 1) ? t.best1 : t.best0, *bn = (r & 1) ? t.best0 : t.best1;
-        k_gbv_minedge<<<g_edges, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.E, t.comp0, t.cw, bc,
-                                                  f.info);
+        if (r > 0)  // round 0's minimum edges come from the tile-local phase
+            k_gbv_minedge<<<g_edges, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
+                                                      bc, f.info);
         k_gbv_hook<<<g_roots, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Rall, t.comp0, t.cw, bc, bn,
                                                t.intree, f.info);
     }

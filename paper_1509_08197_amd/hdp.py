@@ -78,6 +78,7 @@ def _declare(L):
     L.hdp_forest_bind.argtypes = [P, SZ, I64, C.POINTER(ForestStruct)]
     L.hdp_level_shapes.argtypes = [P, I32, I32, I32, P]
     L.hdp_pyramid.argtypes = [P, P, I32, I32, I32, P, P]
+    L.hdp_pyramid_views.argtypes = [P, P, P, I32, I32, I32, P, P, P]
     L.hdp_build_tree_workspace_bytes.argtypes = [I64]; L.hdp_build_tree_workspace_bytes.restype = SZ
     L.hdp_build_tree.argtypes = [P, P, I32, I32, P, P, I32, I32, I32, I32,
                                  C.POINTER(ForestStruct), P, SZ, P]
@@ -166,6 +167,27 @@ def pyramid(rgb: torch.Tensor, shapes, S: int = 2, L: int = 3) -> List[torch.Ten
     for n in ns:
         views.append(out[off:off + n]); off += n
     return views
+
+
+def pyramid_views(left_rgb: torch.Tensor, right_rgb: torch.Tensor, shapes, S: int = 2,
+                  L: int = 3):
+    """Pyramids of both views in the same launches; returns (left levels, right levels)."""
+    for t in (left_rgb, right_rgb):
+        assert t.is_cuda and t.dtype == torch.uint8 and t.is_contiguous()
+    lv = level_shapes(shapes, S, L)
+    ns = [n_pixels(s) for s in lv]
+    outs = [torch.empty((sum(ns), 4), dtype=torch.float32, device=left_rgb.device)
+            for _ in range(2)]
+    _check("hdp_pyramid_views", lib().hdp_pyramid_views(
+        _ptr(left_rgb), _ptr(right_rgb), _shapes(shapes), len(shapes), S, L, _ptr(outs[0]),
+        _ptr(outs[1]), _stream()))
+    res = []
+    for out in outs:
+        views, off = [], 0
+        for n in ns:
+            views.append(out[off:off + n]); off += n
+        res.append(views)
+    return res[0], res[1]
 
 
 # --- forest ----------------------------------------------------------------------
@@ -419,8 +441,7 @@ def hdp_stereo(left_rgb: torch.Tensor, right_rgb: torch.Tensor, shapes, S=2, L=3
     l = L-1..0 interval prediction -> disparity forest -> cost -> aggregation
     -> WTA.  left_rgb/right_rgb: uint8 [n0, 3].  Returns results indexed by layer."""
     lv = level_shapes(shapes, S, L)
-    lp = pyramid(left_rgb, shapes, S, L)
-    rp = pyramid(right_rgb, shapes, S, L)
+    lp, rp = pyramid_views(left_rgb, right_rgb, shapes, S, L)
     res: List[Optional[LevelResult]] = [None] * (L + 1)
     res[L] = stereo_level(lp[L], rp[L], lv[L], L, sigma=sigma, params=params, keep=keep, ws=ws)
     for l in range(L - 1, -1, -1):
@@ -435,8 +456,7 @@ def full_range(left_rgb, right_rgb, shapes, sigma=0.1, params=None, keep=False,
                ws=None) -> LevelResult:
     """Full-range MST aggregation + WTA at the input resolution (the baseline
     the method speeds up)."""
-    lp = pyramid(left_rgb, shapes, 2, 0)
-    rp = pyramid(right_rgb, shapes, 2, 0)
+    lp, rp = pyramid_views(left_rgb, right_rgb, shapes, 2, 0)
     return stereo_level(lp[0], rp[0], shapes, 0, sigma=sigma, params=params, keep=keep, ws=ws)
 
 

@@ -124,6 +124,37 @@ def test_pyramid_exact(H, orc, Hh, Ww):
         np.testing.assert_array_equal(got, ref[l].astype(np.float32))
 
 
+def test_pyramid_views_and_gradient(H, orc):
+    """Both views in one call equal two single-view calls; the gx channel of
+    every layer is S(x+1) - S(x-1) of the channel sums S (replicated border),
+    exact because layer values are dyadic means."""
+    rng = np.random.default_rng(77)
+    shapes = [(45, 70, 31), (17, 5, 15)]
+    imgs = [rng.integers(0, 256, (h, w, 3)).astype(np.uint8) for h, w, _ in shapes]
+    imgs_r = [rng.integers(0, 256, (h, w, 3)).astype(np.uint8) for h, w, _ in shapes]
+    L = 3
+    lv_l, lv_r = H.pyramid_views(rgb_dev(*imgs), rgb_dev(*imgs_r), shapes, 2, L)
+    single_l = H.pyramid(rgb_dev(*imgs), shapes, 2, L)
+    single_r = H.pyramid(rgb_dev(*imgs_r), shapes, 2, L)
+    for l in range(L + 1):
+        np.testing.assert_array_equal(lv_l[l].cpu().numpy(), single_l[l].cpu().numpy())
+        np.testing.assert_array_equal(lv_r[l].cpu().numpy(), single_r[l].cpu().numpy())
+    off = 0
+    got = [lv_l[l].cpu().numpy() for l in range(L + 1)]
+    offs = [0] * (L + 1)
+    for img in imgs:
+        ref = orc.pyramid(img, 2, L)
+        for l in range(L + 1):
+            h, w = ref[l].shape[:2]
+            g = got[l][offs[l]:offs[l] + h * w].reshape(h, w, 4)
+            offs[l] += h * w
+            np.testing.assert_array_equal(g[..., :3], ref[l].astype(np.float32))
+            S = ref[l].sum(axis=2)
+            right = np.concatenate([S[:, 1:], S[:, -1:]], axis=1)
+            left = np.concatenate([S[:, :1], S[:, :-1]], axis=1)
+            np.testing.assert_array_equal(g[..., 3], (right - left).astype(np.float32))
+
+
 # --- trees -------------------------------------------------------------------------
 
 @pytest.mark.parametrize("Hh,Ww,seed", [(120, 160, 1), (31, 47, 2), (1, 64, 3), (64, 1, 4),
