@@ -610,12 +610,31 @@ __global__ __launch_bounds__(kBlock) void k_gbv_final(
     const uint64_t *__restrict__ cw, const int32_t *__restrict__ lmin,
     int32_t *__restrict__ croot, int32_t *__restrict__ mnroot, int32_t *__restrict__ info) {
     const int nR = ctr[CTR_RALL];
-    for (int j = (int)gtid(); j < nR; j += gridDim.x * kBlock) {
-        int x = R[j];
-        int r = find_comp<false>(cw, x, 1 << 30, info);
-        croot[x] = r;
-        int m = lmin[x];
-        if (mnroot[r] > m) atomicMin(&mnroot[r], m);
+    // uniform trip count, so every lane takes part in the wavefront reductions
+    for (int base = blockIdx.x * kBlock; base < nR; base += gridDim.x * kBlock) {
+        const int j = base + (int)threadIdx.x;
+        const bool valid = j < nR;
+        int r = -1, m = 0x7fffffff;
+        if (valid) {
+            int x = R[j];
+            r = find_comp<false>(cw, x, 1 << 30, info);
+            croot[x] = r;
+            m = lmin[x];
+        }
+        const uint64_t mv = __ballot(valid);
+        if (mv == 0) continue;
+        const int lead = __ffsll((unsigned long long)mv) - 1;
+        const int r0 = __shfl(r, lead, 64);
+        if (__ballot(valid && r != r0) == 0) {
+            // one tree in this wavefront (the common case): one atomic
+            for (int off = 32; off > 0; off >>= 1) {
+                int o = __shfl_xor(m, off, 64);
+                m = o < m ? o : m;
+            }
+            if ((int)(threadIdx.x & 63) == lead && mnroot[r0] > m) atomicMin(&mnroot[r0], m);
+        } else if (valid && mnroot[r] > m) {
+            atomicMin(&mnroot[r], m);
+        }
     }
 }
 
