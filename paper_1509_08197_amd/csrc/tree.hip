@@ -52,7 +52,7 @@ constexpr int kRankGridRounds = 8;
 
 constexpr int kLocalThreads = 1024;  // one workgroup per tile, one thread per pixel
 constexpr int kTilePx = kTile * kTile;
-constexpr int kGridCap = 1024;       // workgroups of the grid-stride list kernels
+constexpr int kGridCap = 2048;       // workgroups of the grid-stride list kernels
 
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
