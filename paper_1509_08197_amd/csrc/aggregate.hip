@@ -516,6 +516,8 @@ template <bool UP, int CPT, int kRPG>
 __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
     __shared__ double sP[kBlock];
     __shared__ double sX[kBlock * CPT];
+    __shared__ double sSegP[4 * kSentMaxWidth];  // 4 segments x (threads per row <= width)
+    __shared__ double sSegX[4 * kSentMaxWidth * CPT];
     __shared__ int s_ticket;
     __shared__ double s_first;
     const int tid = threadIdx.x;
@@ -614,20 +616,54 @@ __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
 #pragma unroll
     for (int c = 0; c < CPT; ++c) sX[tid * CPT + c] = X[c];
     __syncthreads();
-    double Pt = 1.0, Xt[CPT], Pg = 1.0, Xg[CPT];
+    // Exclusive map of the groups before this thread's group (Pg, Xg) and the
+    // tile map (Pt, Xt), in two levels: the groups are cut into kSeg segments
+    // scanned at the same time, then the segment maps are combined.
+    constexpr int kSeg = 4;
+    const int seg_len = (A.groups + kSeg - 1) / kSeg;
+    const int sg = g / seg_len;
+    double Pg = 1.0, Xg[CPT];
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) Xt[c] = Xg[c] = 0.0;
+    for (int c = 0; c < CPT; ++c) Xg[c] = 0.0;
     if (active) {
-        for (int q2 = 0; q2 < A.groups; ++q2) {
-            if (q2 == g) {
-                Pg = Pt;
+        const int q_end = min((sg + 1) * seg_len, A.groups);
+        double Ps = 1.0, Xs[CPT];
 #pragma unroll
-                for (int c = 0; c < CPT; ++c) Xg[c] = Xt[c];
+        for (int c = 0; c < CPT; ++c) Xs[c] = 0.0;
+        for (int q2 = sg * seg_len; q2 < q_end; ++q2) {
+            if (q2 == g) {
+                Pg = Ps;
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) Xg[c] = Xs[c];
             }
             int o = q2 * A.lpr + jl;
             double pq = sP[o];
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) Xt[c] = pq * Xt[c] + sX[o * CPT + c];
+            for (int c = 0; c < CPT; ++c) Xs[c] = pq * Xs[c] + sX[o * CPT + c];
+            Ps *= pq;
+        }
+        if (g == q_end - 1) {  // the segment's last group publishes the segment map
+            sSegP[sg * A.lpr + jl] = Ps;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) sSegX[(sg * A.lpr + jl) * CPT + c] = Xs[c];
+        }
+    }
+    __syncthreads();
+    double Pt = 1.0, Xt[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) Xt[c] = 0.0;
+    if (active) {
+        const int nseg = (A.groups + seg_len - 1) / seg_len;
+        for (int q2 = 0; q2 < nseg; ++q2) {
+            if (q2 == sg) {  // segments before this one, then this group's offset in it
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) Xg[c] = Pg * Xt[c] + Xg[c];
+                Pg *= Pt;
+            }
+            int o = q2 * A.lpr + jl;
+            double pq = sSegP[o];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) Xt[c] = pq * Xt[c] + sSegX[o * CPT + c];
             Pt *= pq;
         }
     }
