@@ -30,6 +30,14 @@ namespace hdp {
 
 constexpr int kRPGDefault = 8;  // rows per thread group of a tile
 
+// Narrow rows (at most kSentMaxWidth labels) use rows as signals: unwritten
+// values hold signalling-NaN patterns that no arithmetic produces.
+constexpr int kSentMaxWidth = 32;
+constexpr uint32_t kSentF = 0x7fa00001u;
+constexpr uint64_t kSent64 = 0x7fa000017fa00001ull;
+constexpr uint64_t kSentD = 0x7ff4000000000001ull;
+
+
 // Layout of the device-side pass plan (int32 words).
 enum {
     P_NPH = 0,      // number of phases K
@@ -77,7 +85,7 @@ static TileGeom tile_geom(int width) {
     int cpt = g_sched_cpt[width], rpg = g_sched_rpg[width];
     if (!cpt || !schedule_valid(width, cpt, rpg)) {
         cpt = (width >= 64 && width % 4 == 0) ? 4 : (width % 2 == 0 && width >= 8) ? 2 : 1;
-        rpg = kRPGDefault;
+        rpg = width <= kSentMaxWidth ? 4 : kRPGDefault;  // narrow rows: shorter tiles measured faster
     }
     return make_geom(width, cpt, rpg);
 }
@@ -95,12 +103,6 @@ bool set_schedule(int width, int cpt, int rpg) {
 }
 
 constexpr int kPassSets = 3;  // flag sets: up, down (and a second up pass in the adjoint)
-// Narrow rows (at most kSentMaxWidth labels) use rows as signals: unwritten
-// values hold signalling-NaN patterns that no arithmetic produces.
-constexpr int kSentMaxWidth = 32;
-constexpr uint32_t kSentF = 0x7fa00001u;
-constexpr uint64_t kSent64 = 0x7fa000017fa00001ull;
-constexpr uint64_t kSentD = 0x7ff4000000000001ull;
 
 // Prologue of an aggregation call, one launch: per-row coefficients
 // s = exp(-w / sigma) and 1 - s^2, cleared tile flags and tickets of every
