@@ -47,6 +47,9 @@ enum {
 // Rounds run by full-grid launches before one workgroup finishes the rest.
 constexpr int kBvGridRounds = 4;
 constexpr int kRankGridRounds = 8;
+// Contracted tour lists of at most this many runs skip the full-grid rounds
+// and go straight to the one-workgroup tail.
+constexpr int kTailOnly = 4096;
 
 // --- shared helpers ------------------------------------------------------------------
 
@@ -816,6 +819,7 @@ __global__ __launch_bounds__(kBlock) void k_tour_link(const int32_t *__restrict_
 __global__ __launch_bounds__(kBlock) void k_rank_round(int round, int32_t *__restrict__ flags,
                                                        const int32_t *__restrict__ ctr,
                                                        uint64_t *__restrict__ pr) {
+    if (ctr[CTR_RUNS] <= kTailOnly) return;  // short lists: the one-workgroup tail alone
     if (round > 0 && flags[FLAG_RANK + round - 1] == 0) return;
     const int nC = ctr[CTR_RUNS];
     bool more = false;
@@ -835,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_compact(int K, const int32_t *_
                                                          int32_t *__restrict__ ctr,
                                                          const uint64_t *__restrict__ pr,
                                                          int32_t *__restrict__ At) {
-    if (flags[FLAG_RANK + K - 1] == 0) return;
+    if (ctr[CTR_RUNS] > kTailOnly && flags[FLAG_RANK + K - 1] == 0) return;
     const int nC = ctr[CTR_RUNS];
     for (int s = (int)gtid(); s < nC; s += gridDim.x * kBlock) {
         bool open = (int32_t)(pr[s] >> 32) >= 0;
@@ -855,7 +859,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_rank_tail(
     int32_t *__restrict__ info) {
     __shared__ unsigned long long L[kTA];
     __shared__ int s_more;
-    if (flags[FLAG_RANK + K - 1] == 0) return;
+    if (ctr[CTR_RUNS] > kTailOnly && flags[FLAG_RANK + K - 1] == 0) return;
     const int nA = ctr[CTR_AT];
     const int tid = threadIdx.x;
     if (nA <= kTA) {
