@@ -74,7 +74,10 @@ enum {
     HDP_INFO_MST_ROUNDS = 4, /* hooking rounds the spanning-forest build used */
     HDP_INFO_RANK_ROUNDS = 5,/* pointer-jumping rounds of the tour ranking */
     HDP_INFO_BAD_INTERVAL = 6,/* pixels whose interval was empty or wider than allowed */
-    HDP_INFO_ERROR = 7       /* nonzero if an internal consistency guard tripped */
+    HDP_INFO_ERROR = 7,      /* nonzero if an internal consistency guard tripped */
+    HDP_INFO_LIVE_EDGES = 8, /* edges still joining two components after the tile-local phase */
+    HDP_INFO_ACTIVE_COMPONENTS = 9, /* components with an edge left after the tile-local phase */
+    HDP_INFO_TOUR_RUNS = 10  /* entries of the contracted Euler-tour list */
 };
 
 /*

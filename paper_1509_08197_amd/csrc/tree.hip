@@ -47,9 +47,12 @@ enum {
 // Rounds run by full-grid launches before one workgroup finishes the rest.
 constexpr int kBvGridRounds = 4;
 constexpr int kRankGridRounds = 8;
-// Contracted tour lists of at most this many runs skip the full-grid rounds
-// and go straight to the one-workgroup tail.
-constexpr int kTailOnly = 4096;
+// Sizes of the one-workgroup LDS tails: spanning forest (edges, components,
+// hash slots) and tour ranking (list entries).
+constexpr int kTE = 4096, kTN = 2048, kTH = 4096;
+constexpr int kTA = 8192;
+// A contracted graph of at most kTE live edges, or a contracted tour list of
+// at most kTA entries, skips the full-grid rounds and goes straight to its tail.
 
 // --- shared helpers ------------------------------------------------------------------
 
@@ -72,6 +75,20 @@ __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {
 __device__ __forceinline__ void wg_sync() {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+}
+
+// Workgroup barrier that also tells whether any thread passed true: one
+// barrier, where __syncthreads_or takes a reduction and two.  Three LDS words
+// are used in rotation (rr, the same in every thread, names this round's
+// word); the word two rounds ahead is cleared after the barrier, when no
+// thread still reads it and none writes it before the next barrier.
+__device__ __forceinline__ bool wg_any(bool p, int *w3, int &rr) {
+    if (p) w3[rr] = 1;
+    __syncthreads();
+    const bool any = w3[rr] != 0;
+    if (threadIdx.x == 0) w3[rr == 0 ? 2 : rr - 1] = 0;
+    rr = rr == 2 ? 0 : rr + 1;
+    return any;
 }
 
 // Slot in a list for each lane with pred set: one atomic per wavefront.
@@ -157,10 +174,11 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     int32_t *__restrict__ lmin, int32_t *__restrict__ croot, int32_t *__restrict__ mnroot,
     uint8_t *__restrict__ intree, uint64_t *__restrict__ E, int32_t *__restrict__ R,
     int32_t *__restrict__ ctr, int32_t *__restrict__ info) {
-    __shared__ uint32_t kL[kTile], kU[kTile];
+    __shared__ uint32_t kL[kTile], kU[kTile], kR[kTilePx], kD[kTilePx];
     __shared__ int32_t lab[kTilePx], hk[kTilePx];
     __shared__ unsigned long long best[kTilePx];
-    __shared__ int s_flag, s_nE, s_nR, s_bE, s_bR;
+    __shared__ uint8_t tR[kTilePx], tD[kTilePx];  // tree edges taken, by owning pixel
+    __shared__ int s_flag[2], s_any[3], s_nE, s_nR, s_bE, s_bR;
     const TileInfo t = tile_info(g, blockIdx.x);
     const float scale = ldexpf(1.0f, 2 * g.level);
     const int i = threadIdx.x;
@@ -174,9 +192,16 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     if (i == 0) {
         s_nE = 0;
         s_nR = 0;
+        s_flag[0] = 0;
+        s_flag[1] = 0;
+        s_any[0] = 0;
+        s_any[1] = 0;
+        s_any[2] = 0;
     }
     lab[i] = i;
-    hk[i] = i;
+    best[i] = kNoEdge;
+    tR[i] = 0;
+    tD[i] = 0;
     __syncthreads();
     // keys of the owned right / down edges (and of the edges entering from the
     // left / top neighbour tiles); an edge between different intervals is absent
@@ -195,45 +220,62 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
             kL[ly] = edge_key(img[v - 1], a, scale);
         if (ly == 0 && y > 0 && same_interval(plo, phi, v - t.W, v))
             kU[lx] = edge_key(img[v - t.W], a, scale);
-        intree[2 * v] = 0;
-        intree[2 * v + 1] = 0;
     }
+    kR[i] = kr;
+    kD[i] = kd;
     const bool r_in = lx + 1 < t.tw, d_in = ly + 1 < t.th;
     __syncthreads();
-    const uint32_t kl = lx == 0 ? kL[ly] : kNoKey, ku = ly == 0 ? kU[lx] : kNoKey;
-    auto offer = [&](int c, uint64_t k) {
-        if (best[c] > k) atomicMin(&best[c], (unsigned long long)k);
-    };
+    // (key, id) of the pixel's four edges; the left / up ones are the right /
+    // down edges of the neighbour (or of the neighbour tile's pixel)
+    const uint32_t kl = lx == 0 ? kL[ly] : kR[i - 1], ku = ly == 0 ? kU[lx] : kD[i - kTile];
+    const uint64_t er = kr != kNoKey ? key64(kr, 2 * v) : kNoEdge;
+    const uint64_t ed = kd != kNoKey ? key64(kd, 2 * v + 1) : kNoEdge;
+    const uint64_t el = valid && kl != kNoKey ? key64(kl, 2 * (v - 1)) : kNoEdge;
+    const uint64_t eu = valid && ku != kNoKey ? key64(ku, 2 * (v - t.W) + 1) : kNoEdge;
+    const int lane = i & 63;
     // Boruvka rounds in LDS until no component hooks (each round with a hook
-    // removes at least one component, so the loop ends)
+    // removes at least one component, so the loop ends).  A pixel's own label
+    // and hook are written only by its thread and live in registers; the tree
+    // edges are kept in LDS and stored once at the end, so that no barrier
+    // waits on global stores.
+    int myl = i, rr = 0;
     for (int iter = 0; iter < kTilePx; ++iter) {
-        best[i] = kNoEdge;
-        if (i == 0) s_flag = 0;
-        __syncthreads();
+        const int par = iter & 1;
+        // every pixel offers its least edge to another component to its own
+        // component; a wavefront whose offers all name one component makes
+        // one atomic (late rounds, when components are large)
+        int c = -1;
+        uint64_t m = kNoEdge;
         if (valid) {
-            int c = lab[i];
-            if (kr != kNoKey) {
-                uint64_t k = key64(kr, 2 * v);
-                int cj = r_in ? lab[i + 1] : -1;
-                if (cj != c) {
-                    offer(c, k);
-                    if (cj >= 0) offer(cj, k);
+            c = myl;
+            // the four neighbour labels, loaded together (an absent
+            // neighbour reads the pixel's own slot)
+            const int nr = lab[r_in ? i + 1 : i], nd = lab[d_in ? i + kTile : i];
+            const int nl = lab[lx > 0 ? i - 1 : i], nu = lab[ly > 0 ? i - kTile : i];
+            if (er != kNoEdge && (!r_in || nr != c)) m = er;
+            if (ed != kNoEdge && (!d_in || nd != c)) m = ed < m ? ed : m;
+            if (el != kNoEdge && (lx == 0 || nl != c)) m = el < m ? el : m;
+            if (eu != kNoEdge && (ly == 0 || nu != c)) m = eu < m ? eu : m;
+        }
+        const bool has = m != kNoEdge;
+        const uint64_t mh = __ballot(has);
+        if (mh) {
+            const int lead = __ffsll((unsigned long long)mh) - 1;
+            const int c0 = __shfl(c, lead, 64);
+            if (__ballot(has && c != c0) == 0) {
+                for (int off = 32; off > 0; off >>= 1) {
+                    uint64_t o = __shfl_xor((unsigned long long)m, off, 64);
+                    m = o < m ? o : m;
                 }
+                if (lane == lead && best[c0] > m) atomicMin(&best[c0], (unsigned long long)m);
+            } else if (has && best[c] > m) {
+                atomicMin(&best[c], (unsigned long long)m);
             }
-            if (kd != kNoKey) {
-                uint64_t k = key64(kd, 2 * v + 1);
-                int cj = d_in ? lab[i + kTile] : -1;
-                if (cj != c) {
-                    offer(c, k);
-                    if (cj >= 0) offer(cj, k);
-                }
-            }
-            if (kl != kNoKey) offer(c, key64(kl, 2 * (v - 1)));
-            if (ku != kNoKey) offer(c, key64(ku, 2 * (v - t.W) + 1));
         }
         __syncthreads();
-        uint64_t b = best[i];
-        if (valid && lab[i] == i && b != kNoEdge) {
+        const uint64_t b = best[i];
+        int hook = i;
+        if (valid && myl == i && b != kNoEdge) {
             uint32_t e = (uint32_t)b;
             int pl = (int)(e >> 1) - t.base;  // pixel offsets inside the pair fit in 32 bits
             int ql = (e & 1) ? pl + t.W : pl + 1;
@@ -242,30 +284,39 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
             bool inside = px >= t.x0 && px < t.x0 + t.tw && py >= t.y0 && py < t.y0 + t.th &&
                           qx >= t.x0 && qx < t.x0 + t.tw && qy >= t.y0 && qy < t.y0 + t.th;
             if (inside) {  // a least edge that leaves the tile waits for the global rounds
-                int cp = lab[(py - t.y0) * kTile + (px - t.x0)];
+                int lp = (py - t.y0) * kTile + (px - t.x0);
+                int cp = lab[lp];
                 int cq = lab[(qy - t.y0) * kTile + (qx - t.x0)];
                 int other = cp == i ? cq : cp;
                 if (!(best[other] == b && i < other)) {  // mutual choice: smaller index stays
-                    hk[i] = other;
-                    intree[e] = 1;
-                    s_flag = 1;
+                    hook = other;
+                    if (e & 1) tD[lp] = 1;
+                    else tR[lp] = 1;
+                    s_flag[par] = 1;
                 }
             }
         }
         __syncthreads();
-        if (!s_flag) break;
-        int h = hk[i];
-        if (h != i) {
-            lab[i] = h;
-            hk[i] = i;
+        if (!s_flag[par]) break;  // best[] keeps this round's least edges
+        best[i] = kNoEdge;
+        if (i == 0) s_flag[par ^ 1] = 0;
+        if (hook != i) {
+            myl = hook;
+            lab[i] = hook;
         }
         __syncthreads();
         // pointer jumping until every pixel names its root (each change moves a
-        // label to a strict ancestor, so the loop ends)
+        // label to a strict ancestor, so the loop ends; roots stay roots here,
+        // so a pixel whose new label is a root is done)
         for (int it = 0; it < kTilePx; ++it) {
-            int l = lab[i], ll = lab[l];
-            if (l != ll) lab[i] = ll;
-            if (!__syncthreads_or(l != ll)) break;
+            int ll = lab[myl];
+            bool more = false;
+            if (ll != myl) {
+                myl = ll;
+                lab[i] = ll;
+                more = lab[ll] != ll;
+            }
+            if (!wg_any(more, s_any, rr)) break;
         }
     }
     // smallest pixel id of every local component (hk reused)
@@ -280,7 +331,6 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     const bool live_d = valid && kd != kNoKey && (!d_in || lab[i + kTile] != c);
     const bool act = valid && c == i && best[i] != kNoEdge;
     const uint64_t mr = __ballot(live_r), md = __ballot(live_d), ma = __ballot(act);
-    const int lane = i & 63;
     int wE = 0, wR = 0;
     if (lane == 0) {
         wE = atomicAdd(&s_nE, __popcll(mr) + __popcll(md));
@@ -299,6 +349,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     if (live_d) E[wE + __popcll(mr) + __popcll(md & lt)] = key64(kd, 2 * v + 1);
     if (act) R[wR + __popcll(ma & lt)] = (int32_t)v;
     if (valid) {
+        *reinterpret_cast<uint16_t *>(&intree[2 * v]) = (uint16_t)(tR[i] | (tD[i] << 8));
         comp0[v] = (int32_t)tile_pixel(t, c);
         if (c == i) {
             cw[v] = (uint64_t)(uint32_t)v;
@@ -371,6 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_gbv_minedge(
     int round, const int32_t *__restrict__ flags, const int32_t *__restrict__ ctr, LevelGeom g,
     uint64_t *__restrict__ E, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
     uint64_t *__restrict__ best, int32_t *__restrict__ info) {
+    if (ctr[CTR_E] <= kTE) return;  // small contracted graph: the tail alone
     if (round > 0 && flags[FLAG_BV + round - 1] == 0) return;
     const int nE = ctr[CTR_E];
     for (int i = (int)gtid(); i < nE; i += gridDim.x * kBlock) {
@@ -392,6 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_gbv_hook(
     const int32_t *__restrict__ R, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
     const uint64_t *__restrict__ best, uint64_t *__restrict__ best_next,
     uint8_t *__restrict__ intree, int32_t *__restrict__ info) {
+    if (ctr[CTR_E] <= kTE) return;
     if (round > 0 && flags[FLAG_BV + round - 1] == 0) return;
     const int nR = ctr[CTR_RALL];
     bool hooked = false;
@@ -418,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_gbv_compact(
     int K, const int32_t *__restrict__ flags, int32_t *__restrict__ ctr, LevelGeom g,
     const uint64_t *__restrict__ E, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
     uint64_t *__restrict__ Et, int32_t *__restrict__ info) {
-    if (flags[FLAG_BV + K - 1] == 0) return;
+    if (ctr[CTR_E] > kTE && flags[FLAG_BV + K - 1] == 0) return;
     const int nE = ctr[CTR_E];
     for (int i = (int)gtid(); i < nE; i += gridDim.x * kBlock) {
         uint64_t k = E[i];
@@ -437,7 +490,6 @@ __global__ __launch_bounds__(kBlock) void k_gbv_compact(
 // components the contracted graph is loaded into LDS (components renumbered
 // through a hash table) and finished there; otherwise the rounds run on the
 // global arrays with device-coherent loads.
-constexpr int kTE = 4096, kTN = 2048, kTH = 4096;
 
 __device__ __forceinline__ int hash_slot(int key) {
     return (int)(((uint32_t)key * 2654435761u) >> 20) & (kTH - 1);
@@ -454,7 +506,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
     __shared__ int32_t rid[kTN], lab[kTN], hk[kTN], bidx[kTN];
     __shared__ unsigned long long best[kTN];
     __shared__ int s_nodes, s_flag;
-    if (flags[FLAG_BV + K - 1] == 0) return;
+    if (ctr[CTR_E] > kTE && flags[FLAG_BV + K - 1] == 0) return;
     const int nE = ctr[CTR_ET];
     const int tid = threadIdx.x;
     bool lds_mode = nE <= kTE;
@@ -703,7 +755,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
     __shared__ uint8_t sadj[kHalo * kHalo];
     __shared__ unsigned long long P[4 * kTilePx];
     __shared__ int32_t tix[4 * kTilePx];
-    __shared__ int s_n, s_base;
+    __shared__ int s_n, s_base, s_any[3];
     const TileInfo t = tile_info(g, blockIdx.x);
     const int tid = threadIdx.x;
     for (int h = tid; h < kHalo * kHalo; h += kLocalThreads) {
@@ -711,7 +763,12 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
         bool in = x >= 0 && x < t.W && y >= 0 && y < t.H;
         sadj[h] = in ? adj[t.base + (int64_t)y * t.W + x] : 0;
     }
-    if (tid == 0) s_n = 0;
+    if (tid == 0) {
+        s_n = 0;
+        s_any[0] = 0;
+        s_any[1] = 0;
+        s_any[2] = 0;
+    }
     __syncthreads();
     // slot ls = 4 * (ly * kTile + lx) + d; P = next << 32 | hops (run end: next = self)
     constexpr unsigned long long kInvalid = ~0ull;
@@ -735,24 +792,34 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
         P[ls] = w;
     }
     __syncthreads();
-    // pointer jumping inside the tile (runs hold at most 4 * kTilePx slots, so
-    // 13 rounds reach every run end; one more confirms)
+    // Pointer jumping inside the tile (runs hold at most 4 * kTilePx slots, so
+    // 13 rounds reach every run end; one more confirms).  Only the owning
+    // thread writes a slot, so each thread keeps its slots in registers and a
+    // round is one batch of independent loads of the successors' entries.
+    unsigned long long own[kSlotsPerThread];
+    uint32_t live = 0;
+    for (int k = 0; k < kSlotsPerThread; ++k) {
+        int ls = tid + k * kLocalThreads;
+        own[k] = P[ls];
+        if (own[k] != kInvalid && (int)(own[k] >> 32) != ls) live |= 1u << k;
+    }
     bool converged = false;
+    int rr = 0;
     for (int round = 0; round < 16; ++round) {
-        bool changed = false;
+        unsigned long long nxt[kSlotsPerThread];
+        for (int k = 0; k < kSlotsPerThread; ++k)
+            nxt[k] = ((live >> k) & 1) ? P[(int)(own[k] >> 32)] : 0ull;
         for (int k = 0; k < kSlotsPerThread; ++k) {
-            int ls = tid + k * kLocalThreads;
-            unsigned long long a = P[ls];
-            if (a == kInvalid) continue;
-            int nx = (int)(a >> 32);
-            if (nx == ls) continue;
-            unsigned long long b = P[nx];
-            int nn = (int)(b >> 32);
-            if (nn == nx) continue;  // next is its run's end: done
-            P[ls] = ((unsigned long long)nn << 32) | (uint32_t)((uint32_t)a + (uint32_t)b);
-            changed = true;
+            if (!((live >> k) & 1)) continue;
+            int nx = (int)(own[k] >> 32), nn = (int)(nxt[k] >> 32);
+            if (nn == nx) {  // next is its run's end: done
+                live &= ~(1u << k);
+                continue;
+            }
+            own[k] = ((unsigned long long)nn << 32) | (uint32_t)((uint32_t)own[k] + (uint32_t)nxt[k]);
+            P[tid + k * kLocalThreads] = own[k];
         }
-        if (!__syncthreads_or(changed)) {
+        if (!wg_any(live != 0, s_any, rr)) {
             converged = true;
             break;
         }
@@ -819,7 +886,7 @@ __global__ __launch_bounds__(kBlock) void k_tour_link(const int32_t *__restrict_
 __global__ __launch_bounds__(kBlock) void k_rank_round(int round, int32_t *__restrict__ flags,
                                                        const int32_t *__restrict__ ctr,
                                                        uint64_t *__restrict__ pr) {
-    if (ctr[CTR_RUNS] <= kTailOnly) return;  // short lists: the one-workgroup tail alone
+    if (ctr[CTR_RUNS] <= kTA) return;  // short lists: the one-workgroup tail alone
     if (round > 0 && flags[FLAG_RANK + round - 1] == 0) return;
     const int nC = ctr[CTR_RUNS];
     bool more = false;
@@ -839,7 +906,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_compact(int K, const int32_t *_
                                                          int32_t *__restrict__ ctr,
                                                          const uint64_t *__restrict__ pr,
                                                          int32_t *__restrict__ At) {
-    if (ctr[CTR_RUNS] > kTailOnly && flags[FLAG_RANK + K - 1] == 0) return;
+    if (ctr[CTR_RUNS] > kTA && flags[FLAG_RANK + K - 1] == 0) return;
     const int nC = ctr[CTR_RUNS];
     for (int s = (int)gtid(); s < nC; s += gridDim.x * kBlock) {
         bool open = (int32_t)(pr[s] >> 32) >= 0;
@@ -851,15 +918,13 @@ __global__ __launch_bounds__(kBlock) void k_rank_compact(int K, const int32_t *_
 // The unfinished entries in one workgroup: renumbered into LDS (entries that
 // point at a finished entry absorb its rank) and jumped there; a larger set
 // is jumped on the global array with device-coherent loads.
-constexpr int kTA = 8192;
-
 __global__ __launch_bounds__(kLocalThreads) void k_rank_tail(
     int K, int32_t *__restrict__ flags, const int32_t *__restrict__ ctr,
     const int32_t *__restrict__ At, int32_t *__restrict__ slot, uint64_t *__restrict__ pr,
     int32_t *__restrict__ info) {
     __shared__ unsigned long long L[kTA];
     __shared__ int s_more;
-    if (ctr[CTR_RUNS] > kTailOnly && flags[FLAG_RANK + K - 1] == 0) return;
+    if (ctr[CTR_RUNS] > kTA && flags[FLAG_RANK + K - 1] == 0) return;
     const int nA = ctr[CTR_AT];
     const int tid = threadIdx.x;
     if (nA <= kTA) {
@@ -1170,9 +1235,13 @@ __global__ void k_level_ptr(const int32_t *__restrict__ order, const int32_t *__
     if (i == n) info[HDP_INFO_N_LEVELS] = d;
 }
 
-__global__ void k_finish_info(const int32_t *__restrict__ flags, int32_t *__restrict__ info,
-                              int width, int64_t n, const uint64_t *__restrict__ root_total) {
+__global__ void k_finish_info(const int32_t *__restrict__ flags, const int32_t *__restrict__ ctr,
+                              int32_t *__restrict__ info, int width, int64_t n,
+                              const uint64_t *__restrict__ root_total) {
     if (threadIdx.x != 0) return;
+    info[HDP_INFO_LIVE_EDGES] = ctr[CTR_E];
+    info[HDP_INFO_ACTIVE_COMPONENTS] = ctr[CTR_RALL];
+    info[HDP_INFO_TOUR_RUNS] = ctr[CTR_RUNS];
     // every tree of sz nodes has a tour of 2(sz - 1) slots
     info[HDP_INFO_N_TREES] = (int32_t)(n - (int64_t)((uint32_t)*root_total >> 1));
     int bv = 0, rk = 0;
@@ -1379,7 +1448,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     }
     k_rows<<<gn, kBlock, 0, st>>>(g, f.row, f.parent, f.wgt, t.heavy_child, t.adj, f.prow, f.heavy,
                                   f.lc, f.rw);
-    k_finish_info<<<1, 64, 0, st>>>(t.flags, f.info, width, n, t.root_total);
+    k_finish_info<<<1, 64, 0, st>>>(t.flags, t.ctr, f.info, width, n, t.root_total);
 }
 
 // 8: level order (stable LSD radix sort of ids by depth) and level_ptr
