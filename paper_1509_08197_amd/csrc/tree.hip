@@ -58,6 +58,7 @@ constexpr int kTA = 8192;
 
 constexpr int kLocalThreads = 1024;  // one workgroup per tile, one thread per pixel
 constexpr int kTilePx = kTile * kTile;
+constexpr int kHalo = kTile + 2;      // a tile with a one-pixel border
 constexpr int kGridCap = 2048;       // workgroups of the grid-stride list kernels
 
 __device__ __forceinline__ uint64_t ld_relaxed(const uint64_t *p) {
@@ -89,6 +90,33 @@ __device__ __forceinline__ bool wg_any(bool p, int *w3, int &rr) {
     if (threadIdx.x == 0) w3[rr == 0 ? 2 : rr - 1] = 0;
     rr = rr == 2 ? 0 : rr + 1;
     return any;
+}
+
+// One step of a wavefront minimum: each lane takes the smaller of its value
+// and the value the DPP pattern kCtrl moves to it (rows outside kRowMask, and
+// disabled source lanes, contribute the identity ~0).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint64_t dpp_min_step(uint64_t v) {
+    const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+    const uint32_t slo = (uint32_t)__builtin_amdgcn_update_dpp(-1, lo, kCtrl, kRowMask, 0xF, false);
+    const uint32_t shi = (uint32_t)__builtin_amdgcn_update_dpp(-1, hi, kCtrl, kRowMask, 0xF, false);
+    const uint64_t o = ((uint64_t)shi << 32) | slo;
+    return o < v ? o : v;
+}
+
+// Minimum of v over the 64 lanes of the wavefront (all lanes active), by DPP
+// row steps without LDS: within quads, half rows and rows, then across rows
+// with the row broadcasts; lane 63 ends with the total.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+    v = dpp_min_step<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v = dpp_min_step<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = dpp_min_step<0x141, 0xF>(v);  // row_half_mirror
+    v = dpp_min_step<0x140, 0xF>(v);  // row_mirror
+    v = dpp_min_step<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_min_step<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Slot in a list for each lane with pred set: one atomic per wavefront.
@@ -226,12 +254,16 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     const bool r_in = lx + 1 < t.tw, d_in = ly + 1 < t.th;
     __syncthreads();
     // (key, id) of the pixel's four edges; the left / up ones are the right /
-    // down edges of the neighbour (or of the neighbour tile's pixel)
+    // down edges of the neighbour (or of the neighbour tile's pixel).  Ids are
+    // tile-local, 2 * (halo row * kHalo + halo column) + direction of the
+    // owning pixel: ordered as the global ids 2 * pixel + direction are, for
+    // every edge this tile sees (both orders are row, column, direction).
     const uint32_t kl = lx == 0 ? kL[ly] : kR[i - 1], ku = ly == 0 ? kU[lx] : kD[i - kTile];
-    const uint64_t er = kr != kNoKey ? key64(kr, 2 * v) : kNoEdge;
-    const uint64_t ed = kd != kNoKey ? key64(kd, 2 * v + 1) : kNoEdge;
-    const uint64_t el = valid && kl != kNoKey ? key64(kl, 2 * (v - 1)) : kNoEdge;
-    const uint64_t eu = valid && ku != kNoKey ? key64(ku, 2 * (v - t.W) + 1) : kNoEdge;
+    const int hid = (ly + 1) * kHalo + lx + 1;
+    const uint64_t er = kr != kNoKey ? key64(kr, 2 * hid) : kNoEdge;
+    const uint64_t ed = kd != kNoKey ? key64(kd, 2 * hid + 1) : kNoEdge;
+    const uint64_t el = valid && kl != kNoKey ? key64(kl, 2 * (hid - 1)) : kNoEdge;
+    const uint64_t eu = valid && ku != kNoKey ? key64(ku, 2 * (hid - kHalo) + 1) : kNoEdge;
     const int lane = i & 63;
     // Boruvka rounds in LDS until no component hooks (each round with a hook
     // removes at least one component, so the loop ends).  A pixel's own label
@@ -261,12 +293,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
         const uint64_t mh = __ballot(has);
         if (mh) {
             const int lead = __ffsll((unsigned long long)mh) - 1;
-            const int c0 = __shfl(c, lead, 64);
+            const int c0 = __builtin_amdgcn_readlane(c, lead);
             if (__ballot(has && c != c0) == 0) {
-                for (int off = 32; off > 0; off >>= 1) {
-                    uint64_t o = __shfl_xor((unsigned long long)m, off, 64);
-                    m = o < m ? o : m;
-                }
+                m = wave_min_u64(m);
                 if (lane == lead && best[c0] > m) atomicMin(&best[c0], (unsigned long long)m);
             } else if (has && best[c] > m) {
                 atomicMin(&best[c], (unsigned long long)m);
@@ -276,17 +305,15 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
         const uint64_t b = best[i];
         int hook = i;
         if (valid && myl == i && b != kNoEdge) {
-            uint32_t e = (uint32_t)b;
-            int pl = (int)(e >> 1) - t.base;  // pixel offsets inside the pair fit in 32 bits
-            int ql = (e & 1) ? pl + t.W : pl + 1;
-            int py = pl / t.W, px = pl - py * t.W;
-            int qy = ql / t.W, qx = ql - qy * t.W;
-            bool inside = px >= t.x0 && px < t.x0 + t.tw && py >= t.y0 && py < t.y0 + t.th &&
-                          qx >= t.x0 && qx < t.x0 + t.tw && qy >= t.y0 && qy < t.y0 + t.th;
+            const uint32_t e = (uint32_t)b;
+            const int o = (int)(e >> 1), oy = o / kHalo;
+            const int px = o - oy * kHalo - 1, py = oy - 1;  // owning pixel, tile coordinates
+            const int qx = px + (int)(~e & 1), qy = py + (int)(e & 1);
+            const bool inside = px >= 0 && py >= 0 && qx < t.tw && qy < t.th;
             if (inside) {  // a least edge that leaves the tile waits for the global rounds
-                int lp = (py - t.y0) * kTile + (px - t.x0);
+                int lp = py * kTile + px;
                 int cp = lab[lp];
-                int cq = lab[(qy - t.y0) * kTile + (qx - t.x0)];
+                int cq = lab[qy * kTile + qx];
                 int other = cp == i ? cq : cp;
                 if (!(best[other] == b && i < other)) {  // mutual choice: smaller index stays
                     hook = other;
@@ -355,7 +382,14 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
             cw[v] = (uint64_t)(uint32_t)v;
             // least live edge of the component: the first global round's
             // minimum-edge step, already known here
-            best0[v] = best[i];
+            const uint64_t bl = best[i];
+            if (bl != kNoEdge) {
+                const int o = (int)((uint32_t)bl >> 1), oy = o / kHalo;
+                const int64_t p = t.base + (int64_t)(t.y0 + oy - 1) * t.W + t.x0 + (o - oy * kHalo) - 1;
+                best0[v] = key64((uint32_t)(bl >> 32), 2 * p + (int64_t)(bl & 1));
+            } else {
+                best0[v] = kNoEdge;
+            }
             best1[v] = kNoEdge;
             lmin[v] = hk[i];
             croot[v] = -1;
@@ -745,7 +779,6 @@ __device__ __forceinline__ int turn(uint8_t aw, int d) {
     return d2;
 }
 
-constexpr int kHalo = kTile + 2;
 constexpr uint32_t kTourEnd = 0xFFFFFFFFu;
 constexpr int kSlotsPerThread = 4 * kTilePx / kLocalThreads;
 
@@ -753,7 +786,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
     LevelGeom g, const uint8_t *__restrict__ adj, uint64_t *__restrict__ lw,
     uint32_t *__restrict__ C, int32_t *__restrict__ ctr, int32_t *__restrict__ info) {
     __shared__ uint8_t sadj[kHalo * kHalo];
-    __shared__ unsigned long long P[4 * kTilePx];
+    __shared__ uint32_t P[4 * kTilePx];
     __shared__ int32_t tix[4 * kTilePx];
     __shared__ int s_n, s_base, s_any[3];
     const TileInfo t = tile_info(g, blockIdx.x);
@@ -770,53 +803,51 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
         s_any[2] = 0;
     }
     __syncthreads();
-    // slot ls = 4 * (ly * kTile + lx) + d; P = next << 32 | hops (run end: next = self)
-    constexpr unsigned long long kInvalid = ~0ull;
+    // slot ls = 4 * (ly * kTile + lx) + d; P = next << 16 | hops (run end:
+    // next = self; a run has fewer than 4 * kTilePx hops)
+    constexpr uint32_t kInvalid = ~0u;
+    // Only the owning thread writes a slot, so each thread keeps its slots in
+    // registers; a pointer-jumping round is one batch of independent loads.
+    uint32_t own[kSlotsPerThread];
+    uint32_t live = 0;
     for (int k = 0; k < kSlotsPerThread; ++k) {
         int ls = tid + k * kLocalThreads;
         int i = ls >> 2, d = ls & 3;
         int lx = i & (kTile - 1), ly = i >> 5;
-        unsigned long long w = kInvalid;
-        tix[ls] = 0;
+        uint32_t w = kInvalid;
         if (lx < t.tw && ly < t.th && ((sadj[(ly + 1) * kHalo + lx + 1] >> d) & 1)) {
             int wx = lx + (d == 0) - (d == 2), wy = ly + (d == 1) - (d == 3);
             uint8_t aw = sadj[(wy + 1) * kHalo + wx + 1];
             int d2 = turn(aw, d);
             bool end = (aw & kRootBit) && d2 == first_dir(aw);
             bool inside = wx >= 0 && wx < t.tw && wy >= 0 && wy < t.th;
-            if (end || !inside)
-                w = ((unsigned long long)ls << 32);
-            else
-                w = ((unsigned long long)(4 * (wy * kTile + wx) + d2) << 32) | 1ull;
+            if (end || !inside) {
+                w = (uint32_t)ls << 16;
+            } else {
+                w = ((uint32_t)(4 * (wy * kTile + wx) + d2) << 16) | 1u;
+                live |= 1u << k;
+            }
         }
+        own[k] = w;
         P[ls] = w;
     }
     __syncthreads();
-    // Pointer jumping inside the tile (runs hold at most 4 * kTilePx slots, so
-    // 13 rounds reach every run end; one more confirms).  Only the owning
-    // thread writes a slot, so each thread keeps its slots in registers and a
-    // round is one batch of independent loads of the successors' entries.
-    unsigned long long own[kSlotsPerThread];
-    uint32_t live = 0;
-    for (int k = 0; k < kSlotsPerThread; ++k) {
-        int ls = tid + k * kLocalThreads;
-        own[k] = P[ls];
-        if (own[k] != kInvalid && (int)(own[k] >> 32) != ls) live |= 1u << k;
-    }
+    // pointer jumping inside the tile (13 rounds reach every run end; one
+    // more confirms)
     bool converged = false;
     int rr = 0;
     for (int round = 0; round < 16; ++round) {
-        unsigned long long nxt[kSlotsPerThread];
+        uint32_t nxt[kSlotsPerThread];
         for (int k = 0; k < kSlotsPerThread; ++k)
-            nxt[k] = ((live >> k) & 1) ? P[(int)(own[k] >> 32)] : 0ull;
+            nxt[k] = ((live >> k) & 1) ? P[own[k] >> 16] : 0u;
         for (int k = 0; k < kSlotsPerThread; ++k) {
             if (!((live >> k) & 1)) continue;
-            int nx = (int)(own[k] >> 32), nn = (int)(nxt[k] >> 32);
+            uint32_t nx = own[k] >> 16, nn = nxt[k] >> 16;
             if (nn == nx) {  // next is its run's end: done
                 live &= ~(1u << k);
                 continue;
             }
-            own[k] = ((unsigned long long)nn << 32) | (uint32_t)((uint32_t)own[k] + (uint32_t)nxt[k]);
+            own[k] = (nn << 16) | ((own[k] & 0xFFFFu) + (nxt[k] & 0xFFFFu));
             P[tid + k * kLocalThreads] = own[k];
         }
         if (!wg_any(live != 0, s_any, rr)) {
@@ -831,8 +862,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
     const int lane = tid & 63;
     for (int k = 0; k < kSlotsPerThread; ++k) {
         int ls = tid + k * kLocalThreads;
-        unsigned long long a = P[ls];
-        bool term = a != kInvalid && (int)(a >> 32) == ls;
+        bool term = own[k] != kInvalid && (int)(own[k] >> 16) == ls;
         wm[k] = __ballot(term);
         wofs[k] = 0;
         if (lane == 0 && wm[k]) wofs[k] = atomicAdd(&s_n, __popcll(wm[k]));
@@ -859,10 +889,10 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
     __syncthreads();
     for (int k = 0; k < kSlotsPerThread; ++k) {
         int ls = tid + k * kLocalThreads;
-        unsigned long long a = P[ls];
+        uint32_t a = own[k];
         if (a == kInvalid) continue;
         int64_t v = tile_pixel(t, ls >> 2);
-        lw[4 * v + (ls & 3)] = ((uint64_t)(uint32_t)tix[(int)(a >> 32)] << 32) | (uint32_t)a;
+        lw[4 * v + (ls & 3)] = ((uint64_t)(uint32_t)tix[a >> 16] << 32) | (a & 0xFFFFu);
     }
 }
 
