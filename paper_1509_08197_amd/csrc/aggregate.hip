@@ -260,15 +260,18 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
     __shared__ int s_ticket;
     __shared__ int s_win[64];
     __shared__ double s_first;
+    __shared__ int32_t s_plan[P_WORDS];
     const int tid = threadIdx.x;
+    // the ticket, and meanwhile the whole plan into LDS (one word per thread)
     if (tid == 0) s_ticket = atomicAdd(A.ticket, 1);
+    if (tid < P_WORDS) s_plan[tid] = A.plan[tid];
     __syncthreads();
     const int T = s_ticket;
-    const int K = A.plan[P_NPH];
-    const int total = A.plan[UP ? P_TOT_UP : P_TOT_DN];
+    const int K = s_plan[P_NPH];
+    const int total = s_plan[UP ? P_TOT_UP : P_TOT_DN];
     if (T >= total) return;
-    const int32_t *t0 = A.plan + (UP ? P_T0UP : P_T0DN);
-    const int32_t *row0 = A.plan + P_ROW0;
+    const int32_t *t0 = s_plan + (UP ? P_T0UP : P_T0DN);
+    const int32_t *row0 = s_plan + P_ROW0;
     int q = 0;
     while (q + 1 < K && t0[q + 1] <= T) ++q;
     const int k = UP ? K - 1 - q : q;
@@ -301,19 +304,25 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
         float v[CPT];
         load_cols<CPT>(A.src + (int64_t)r * w + j0, v);
         if (UP) {
-            av[i] = (r + 1 < r1 && A.heavy[r + 1]) ? A.s[r + 1] : 0.0;
+            // heavy flag and coefficient of the next row, loaded together
+            const int rn = r + 1 < r1 ? r + 1 : r;
+            const bool hn = A.heavy[rn];
+            const double sn = A.s[rn];
+            av[i] = (r + 1 < r1 && hn) ? sn : 0.0;
 #pragma unroll
             for (int c = 0; c < CPT; ++c) bv[i][c] = (double)v[c];
             x0[i] = A.lc[r];
             x1[i] = A.lc[A.n + r];
             x2[i] = A.lc[2 * A.n + r];
         } else {
-            bool hv = A.heavy[r];
-            av[i] = hv ? A.s[r] : 0.0;
-            double o = A.om[r];
+            // heavy flag, coefficients and parent row, loaded together
+            const bool hv = A.heavy[r];
+            const double sr = A.s[r], o = A.om[r];
+            const int pr = A.prow[r];
+            av[i] = hv ? sr : 0.0;
 #pragma unroll
             for (int c = 0; c < CPT; ++c) bv[i][c] = o * (double)v[c];
-            x0[i] = hv ? -1 : A.prow[r];
+            x0[i] = hv ? -1 : pr;
         }
     }
 
@@ -522,15 +531,18 @@ __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
     __shared__ double sSegX[4 * kSentMaxWidth * CPT];
     __shared__ int s_ticket;
     __shared__ double s_first;
+    __shared__ int32_t s_plan[P_WORDS];
     const int tid = threadIdx.x;
+    // the ticket, and meanwhile the whole plan into LDS (one word per thread)
     if (tid == 0) s_ticket = atomicAdd(A.ticket, 1);
+    if (tid < P_WORDS) s_plan[tid] = A.plan[tid];
     __syncthreads();
     const int T = s_ticket;
-    const int K = A.plan[P_NPH];
-    const int total = A.plan[UP ? P_TOT_UP : P_TOT_DN];
+    const int K = s_plan[P_NPH];
+    const int total = s_plan[UP ? P_TOT_UP : P_TOT_DN];
     if (T >= total) return;
-    const int32_t *t0 = A.plan + (UP ? P_T0UP : P_T0DN);
-    const int32_t *row0 = A.plan + P_ROW0;
+    const int32_t *t0 = s_plan + (UP ? P_T0UP : P_T0DN);
+    const int32_t *row0 = s_plan + P_ROW0;
     int q = 0;
     while (q + 1 < K && t0[q + 1] <= T) ++q;
     const int k = UP ? K - 1 - q : q;
@@ -565,19 +577,25 @@ __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
                 for (int c = 0; c < CPT; ++c)
                     reinterpret_cast<uint32_t *>(A.fill)[(int64_t)r * w + j0 + c] = kSentF;
             }
-            av[i] = (r + 1 < r1 && A.heavy[r + 1]) ? A.s[r + 1] : 0.0;
+            // heavy flag and coefficient of the next row, loaded together
+            const int rn = r + 1 < r1 ? r + 1 : r;
+            const bool hn = A.heavy[rn];
+            const double sn = A.s[rn];
+            av[i] = (r + 1 < r1 && hn) ? sn : 0.0;
 #pragma unroll
             for (int c = 0; c < CPT; ++c) bv[i][c] = (double)v[c];
             x0[i] = A.lc[r];
             x1[i] = A.lc[A.n + r];
             x2[i] = A.lc[2 * A.n + r];
         } else {
-            bool hv = A.heavy[r];
-            av[i] = hv ? A.s[r] : 0.0;
-            double o = A.om[r];
+            // heavy flag, coefficients and parent row, loaded together
+            const bool hv = A.heavy[r];
+            const double sr = A.s[r], o = A.om[r];
+            const int pr = A.prow[r];
+            av[i] = hv ? sr : 0.0;
 #pragma unroll
             for (int c = 0; c < CPT; ++c) bv[i][c] = o * (double)v[c];
-            x0[i] = hv ? -1 : A.prow[r];
+            x0[i] = hv ? -1 : pr;
         }
     }
 
