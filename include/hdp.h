@@ -111,6 +111,8 @@ enum {
  *   heavy   1 if the row's pixel is its parent's heavy child (same chain).
  *   lc      [3][n] rows of the light children, -1 where absent.
  *   rw      weight of the row's edge to its parent (= wgt[node]).
+ *   rx      column (x) of the row's pixel in its image.
+ *   rlh     interval of the row's pixel, lo | hi << 16 (= lo[node], hi[node]).
  *   phase_ptr  HDP_MAX_PHASES + 1 entries.
  *   info    HDP_INFO_WORDS device scalars (see HDP_INFO_*).
  */
@@ -123,6 +125,7 @@ typedef struct {
     uint8_t *heavy;
     float *rw;
     int32_t *phase_ptr, *info;
+    int32_t *rx, *rlh;
 } hdp_forest;
 
 /* Bytes of the single device buffer that holds a forest of n pixels. */
@@ -273,6 +276,29 @@ HDP_API hdp_status hdp_aggregate_backward(const hdp_forest *f, int32_t width, co
  */
 HDP_API hdp_status hdp_wta(const hdp_forest *f, const hdp_shape *shapes, int32_t n_pairs,
                    int32_t width, const float *agg, int32_t *disp, void *stream);
+
+/*
+ * One layer's matching after the forest is built: restricted cost (Section
+ * 3.3, eq. E), tree aggregation (eq. W, eq. S, eq. C) and winner-takes-all,
+ * with the same results as hdp_cost_volume + hdp_aggregate + hdp_wta.  For
+ * rows of at most 32 labels the up pass computes each row's cost from the
+ * level images as it goes (no cost volume in memory) and the down pass writes
+ * each row's winning label as its row is finished (no separate WTA read of the
+ * aggregated volume); wider rows run the three steps one after another with
+ * the cost volume in the workspace.
+ *   left, right, shapes, n_pairs, f, width, p: as hdp_cost_volume (f required).
+ *   sigma       > 0, as hdp_aggregate.
+ *   agg         float[n][width], receives the aggregated volume (volume layout).
+ *   disp        int32[n] in pixel order, receives the labels.
+ *   ws          hdp_aggregate_workspace_bytes(n, width) bytes of device memory.
+ * Asynchronous on `stream`, never synchronises with the host, capturable.
+ * Returns HDP_EINVAL for NULL arguments or a forest that does not match the
+ * batch, HDP_EWORKSPACE for a short workspace.
+ */
+HDP_API hdp_status hdp_match_layer(const float *left, const float *right, const hdp_shape *shapes,
+                           int32_t n_pairs, const hdp_forest *f, int32_t width,
+                           const hdp_cost_params *p, float sigma, float *agg, int32_t *disp,
+                           void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Pixel interval prediction (Section 3.1) for layer l from the disparity map

@@ -25,6 +25,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "matchcost.hpp"
 
 namespace hdp {
 
@@ -177,6 +178,12 @@ struct PassArgs {
     // narrow-row mode (rows as signals)
     float *fill;         // up pass: rows of the following down pass's output to mark unwritten
     double *tPs, *tXs;   // this pass's tile maps (tiles without a chain break), marked unwritten
+    // fused matching (narrow rows): the up pass computes its cost rows from the
+    // level images, the down pass writes each row's winning label
+    const float4 *imL, *imR;
+    CostParams cp;
+    const int32_t *node, *rx, *rlh;
+    int32_t *disp;
 };
 
 // Data that crosses workgroups inside one launch (published tile maps, rows of
@@ -412,16 +419,17 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
     __syncthreads();
     if (tid == 0) st_dev(&A.flag[T], incl_now ? 2 : 1);
 
-    // carry-in by decoupled look-back, 64 predecessors per step
+    // Carry-in by decoupled look-back, 64 predecessors per step: the nearest
+    // tile that published its value, then the maps of the tiles after it
+    // applied forward one tile at a time.  A tile's published value is its map
+    // applied to its own carry in the same way, so the carry does not depend
+    // on which predecessors had finished (results are reproducible).
     double carry[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) carry[c] = 0.0;
     if (tl > 0 && s_first != 0.0) {
-        double mP = 1.0, mX[CPT];
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) mX[c] = 0.0;
         const int lim = t0[q];
-        int base = T - 1;
+        int base = T - 1, found = -1;
         for (;;) {
             int cnt = base - lim + 1;
             cnt = cnt < 64 ? cnt : 64;
@@ -430,28 +438,25 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
             int m = -1;
             for (int L = 0; L < cnt; ++L)
                 if (s_win[L] == 2) { m = L; break; }
-            int upto = m >= 0 ? m : cnt;
-            if (active) {
-                for (int L = 0; L < upto; ++L) {
-                    int tk = base - L;
-                    double pk = ld_dev(&A.tP[tk]);
-#pragma unroll
-                    for (int c = 0; c < CPT; ++c)
-                        mX[c] = mP * ld_dev(&A.tX[(int64_t)tk * w + j0 + c]) + mX[c];
-                    mP *= pk;
-                }
-                if (m >= 0) {
-#pragma unroll
-                    for (int c = 0; c < CPT; ++c)
-                        carry[c] = mP * ld_dev(&A.tI[(int64_t)(base - m) * w + j0 + c]) + mX[c];
-                }
+            if (m >= 0) {
+                found = base - m;
+                break;
             }
-            if (m >= 0) break;
             base -= cnt;
             __syncthreads();
             if (base < lim) {  // a phase's first tile always publishes its value
                 atomicMax(A.err, 19);
                 break;
+            }
+        }
+        if (active && found >= 0) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) carry[c] = ld_dev(&A.tI[(int64_t)found * w + j0 + c]);
+            for (int tk = found + 1; tk < T; ++tk) {
+                const double pk = ld_dev(&A.tP[tk]);
+#pragma unroll
+                for (int c = 0; c < CPT; ++c)
+                    carry[c] = fma(pk, carry[c], ld_dev(&A.tX[(int64_t)tk * w + j0 + c]));
             }
         }
     }
@@ -473,9 +478,9 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
             for (int c = 0; c < CPT; ++c) cv[c] = av[i] * cv[c] + bv[i][c];
             if (rr[i] >= 0) store_cols_dev<CPT>(A.dst + (int64_t)rr[i] * w + j0, cv);
         }
-        if (!incl_now && g == A.groups - 1) {
+        if (!incl_now && g == A.groups - 1) {  // value after the tile: its map applied to the carry
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) st_dev(&A.tI[(int64_t)T * w + j0 + c], cv[c]);
+            for (int c = 0; c < CPT; ++c) st_dev(&A.tI[(int64_t)T * w + j0 + c], fma(Pt, carry[c], Xt[c]));
         }
     }
     stores_complete();
@@ -523,8 +528,11 @@ __device__ __forceinline__ bool poll_cols(const float *p, float *v, int32_t *err
     }
 }
 
-template <bool UP, int CPT, int kRPG>
+// FUSE: the up pass computes the cost of its rows (eq. E) instead of reading a
+// cost volume, and the down pass reduces every row to its winning label.
+template <bool UP, int CPT, int kRPG, bool FUSE>
 __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
+    constexpr bool kWta = FUSE && !UP;
     __shared__ double sP[kBlock];
     __shared__ double sX[kBlock * CPT];
     __shared__ double sSegP[4 * kSentMaxWidth];  // 4 segments x (threads per row <= width)
@@ -532,6 +540,8 @@ __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
     __shared__ int s_ticket;
     __shared__ double s_first;
     __shared__ int32_t s_plan[P_WORDS];
+    __shared__ float sWb[kWta ? kBlock * kRPG : 1];  // fused winner-takes-all candidates
+    __shared__ int sWj[kWta ? kBlock * kRPG : 1];
     const int tid = threadIdx.x;
     // the ticket, and meanwhile the whole plan into LDS (one word per thread)
     if (tid == 0) s_ticket = atomicAdd(A.ticket, 1);
@@ -553,6 +563,20 @@ __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
     const int j0 = jl * CPT;
     const bool active = g < A.groups;
 
+    // fused matching: pixel, column and interval of every row, loaded first
+    int fv[kRPG], fx[kRPG], flh[kRPG];
+    if (FUSE) {
+#pragma unroll
+        for (int i = 0; i < kRPG; ++i) {
+            int li = g * kRPG + i;
+            int r = UP ? r1 - 1 - (tl * rows + li) : r0 + tl * rows + li;
+            bool in = active && (UP ? r >= r0 : r < r1);
+            fv[i] = in ? A.node[r] : 0;
+            fx[i] = in && UP ? A.rx[r] : 0;
+            flh[i] = in ? A.rlh[r] : 0;
+        }
+    }
+
     // stage 1: loads that do not depend on other tiles of this launch; the up
     // pass also marks its rows of the down pass's output as unwritten
     double av[kRPG];
@@ -570,7 +594,17 @@ __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
         for (int c = 0; c < CPT; ++c) bv[i][c] = 0.0;
         if (!in) continue;
         float v[CPT];
-        load_cols<CPT>(A.src + (int64_t)r * w + j0, v);
+        if (FUSE && UP) {  // cost of labels lo + j0 .. (columns past hi hold 0)
+            const float4 Lp = A.imL[fv[i]];
+            const int a = flh[i] & 0xFFFF, b = flh[i] >> 16;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int label = a + j0 + c;
+                v[c] = label <= b ? match_cost(Lp, A.imR, fv[i], fx[i], label, A.cp) : 0.f;
+            }
+        } else {
+            load_cols<CPT>(A.src + (int64_t)r * w + j0, v);
+        }
         if (UP) {
             if (A.fill) {
 #pragma unroll
@@ -696,6 +730,26 @@ __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
         if (jl == 0)
             st_dev(reinterpret_cast<uint64_t *>(&A.tPs[T]), (uint64_t)__double_as_longlong(Pt));
     }
+    // fused winner-takes-all: per row, this thread's least value and its column
+    // (first of equal values), taken as the row is stored
+    float wb[kRPG];
+    int wj[kRPG];
+#pragma unroll
+    for (int i = 0; i < kRPG; ++i) {
+        wb[i] = __builtin_inff();
+        wj[i] = 0x7fffffff;
+    }
+    auto take = [&](int i, const double *cv) {
+        const int nl = (flh[i] >> 16) - (flh[i] & 0xFFFF);  // last valid column
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const float x = (float)cv[c];
+            if (j0 + c <= nl && x < wb[i]) {
+                wb[i] = x;
+                wj[i] = j0 + c;
+            }
+        }
+    };
     // rows at or after the tile's first chain break do not depend on the carry-in
     if (active) {
         double cv[CPT], pp = Pg;
@@ -706,69 +760,111 @@ __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
 #pragma unroll
             for (int c = 0; c < CPT; ++c) cv[c] = av[i] * cv[c] + bv[i][c];
             pp *= av[i];
-            if (pp == 0.0 && rr[i] >= 0) store_cols_dev<CPT>(A.dst + (int64_t)rr[i] * w + j0, cv);
+            if (pp == 0.0 && rr[i] >= 0) {
+                store_cols_dev<CPT>(A.dst + (int64_t)rr[i] * w + j0, cv);
+                if (kWta) take(i, cv);
+            }
         }
     }
-    if (tl == 0 || s_first == 0.0 || !active) return;  // every row was carry-independent
+    const bool carried = !(tl == 0 || s_first == 0.0 || !active);
+    if (!kWta && !carried) return;  // every row was carry-independent
 
-    // carry-in: the last row of the preceding tile, or across a tile without a
-    // chain break its map and then the tile before it
-    double carry[CPT];
-    {
-        double mP = 1.0, mX[CPT];
+    if (carried) {
+        // Carry-in: the last row of the preceding tile, or across tiles without
+        // a chain break (whose maps are published) the last row of an earlier
+        // tile with those maps applied forward one tile at a time, rounded as
+        // a stored row.  Such a tile stores its last row the same way (its map
+        // applied to its carry), so the carry does not depend on which path
+        // was taken (results are reproducible).
+        double carry[CPT];
+        {
+            const int lim = t0[q];
+            int pred = T - 1;
+            for (int64_t it = 0;; ++it) {
+                // row processed just before tile pred + 1 of this phase
+                const int nxt = pred + 1 - lim;
+                const int lr = UP ? r1 - nxt * rows : r0 + nxt * rows - 1;
+                float v[CPT];
+                if (poll_cols<CPT>(A.dst + (int64_t)lr * w + j0, v, A.err, false)) {
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) mX[c] = 0.0;
-        const int lim = t0[q];
-        int pred = T - 1;
-        for (int64_t it = 0;; ++it) {
-            // row processed just before tile pred + 1 of this phase
-            const int nxt = pred + 1 - lim;
-            const int lr = UP ? r1 - nxt * rows : r0 + nxt * rows - 1;
-            float v[CPT];
-            if (poll_cols<CPT>(A.dst + (int64_t)lr * w + j0, v, A.err, false)) {
+                    for (int c = 0; c < CPT; ++c) carry[c] = (double)v[c];
+                    for (int tk = pred + 1; tk < T; ++tk) {
+                        const double pk = __longlong_as_double(
+                            (long long)ld_dev(reinterpret_cast<const uint64_t *>(&A.tPs[tk])));
 #pragma unroll
-                for (int c = 0; c < CPT; ++c) carry[c] = mP * (double)v[c] + mX[c];
-                break;
-            }
-            if (pred > lim) {
-                uint64_t pw = ld_dev(reinterpret_cast<const uint64_t *>(&A.tPs[pred]));
-                bool ok = pw != kSentD;
-                double xv[CPT];
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) {
-                    uint64_t u =
-                        ld_dev(reinterpret_cast<const uint64_t *>(&A.tXs[(int64_t)pred * w + j0 + c]));
-                    ok = ok && u != kSentD;
-                    xv[c] = __longlong_as_double((long long)u);
+                        for (int c = 0; c < CPT; ++c) {
+                            const double xk = __longlong_as_double((long long)ld_dev(
+                                reinterpret_cast<const uint64_t *>(&A.tXs[(int64_t)tk * w + j0 + c])));
+                            carry[c] = (double)(float)fma(pk, carry[c], xk);
+                        }
+                    }
+                    break;
                 }
-                if (ok) {
+                if (pred > lim) {  // map of tile pred published: look one tile further back
+                    bool ok = ld_dev(reinterpret_cast<const uint64_t *>(&A.tPs[pred])) != kSentD;
 #pragma unroll
-                    for (int c = 0; c < CPT; ++c) mX[c] = mP * xv[c] + mX[c];
-                    mP *= __longlong_as_double((long long)pw);
-                    --pred;
-                    continue;
+                    for (int c = 0; c < CPT; ++c)
+                        ok = ok && ld_dev(reinterpret_cast<const uint64_t *>(
+                                       &A.tXs[(int64_t)pred * w + j0 + c])) != kSentD;
+                    if (ok) {
+                        --pred;
+                        continue;
+                    }
                 }
-            }
-            if (it > kSpinLimit) {
-                atomicMax(A.err, 21);
+                if (it > kSpinLimit) {
+                    atomicMax(A.err, 21);
 #pragma unroll
-                for (int c = 0; c < CPT; ++c) carry[c] = 0.0;
-                break;
+                    for (int c = 0; c < CPT; ++c) carry[c] = 0.0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
             }
-            __builtin_amdgcn_s_sleep(1);
+        }
+
+        // rows before the first chain break, with the carry-in; in a tile
+        // without a break the last row is the tile map applied to the carry
+        double cv[CPT], pp = Pg;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) cv[c] = Pg * carry[c] + Xg[c];
+#pragma unroll
+        for (int i = 0; i < kRPG; ++i) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) cv[c] = av[i] * cv[c] + bv[i][c];
+            pp *= av[i];
+            if (pp != 0.0 && rr[i] >= 0) {
+                if (Pt != 0.0 && g == A.groups - 1 && i == kRPG - 1) {
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) cv[c] = fma(Pt, carry[c], Xt[c]);
+                }
+                store_cols_dev<CPT>(A.dst + (int64_t)rr[i] * w + j0, cv);
+                if (kWta) take(i, cv);
+            }
         }
     }
 
-    // rows before the first chain break, with the carry-in
-    double cv[CPT], pp = Pg;
+    if (kWta) {  // the row's threads are consecutive: combine their candidates in LDS
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) cv[c] = Pg * carry[c] + Xg[c];
+        for (int i = 0; i < kRPG; ++i) {
+            sWb[tid * kRPG + i] = wb[i];
+            sWj[tid * kRPG + i] = wj[i];
+        }
+        __syncthreads();
+        if (active && jl == 0) {
 #pragma unroll
-    for (int i = 0; i < kRPG; ++i) {
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) cv[c] = av[i] * cv[c] + bv[i][c];
-        pp *= av[i];
-        if (pp != 0.0 && rr[i] >= 0) store_cols_dev<CPT>(A.dst + (int64_t)rr[i] * w + j0, cv);
+            for (int i = 0; i < kRPG; ++i) {
+                if (rr[i] < 0) continue;
+                float best = sWb[tid * kRPG + i];
+                int bj = sWj[tid * kRPG + i];
+                for (int o = 1; o < A.lpr; ++o) {  // later threads hold later columns
+                    const float x = sWb[(tid + o) * kRPG + i];
+                    if (x < best) {
+                        best = x;
+                        bj = sWj[(tid + o) * kRPG + i];
+                    }
+                }
+                A.disp[fv[i]] = (flh[i] & 0xFFFF) + bj;
+            }
+        }
     }
 }
 
@@ -826,18 +922,19 @@ size_t aggregate_workspace_bytes(int64_t n, int width) {
     return b;
 }
 
-template <bool UP, int CPT, int RPG>
+// FUSE (narrow rows only): the fused matching variant of the narrow-row pass.
+template <bool UP, int CPT, int RPG, bool FUSE>
 static void launch_pass(const PassArgs &A, int64_t tiles, hipStream_t st) {
     timer_before(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
-    if (A.width <= kSentMaxWidth)
-        k_pass_s<UP, CPT, RPG><<<(unsigned)tiles, kBlock, 0, st>>>(A);
+    if (FUSE || A.width <= kSentMaxWidth)
+        k_pass_s<UP, CPT, RPG, FUSE><<<(unsigned)tiles, kBlock, 0, st>>>(A);
     else
         k_pass<UP, CPT, RPG><<<(unsigned)tiles, kBlock, 0, st>>>(A);
     timer_after(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
 }
 
 // One pass with flag set `set` (cleared by the prologue of this call).
-template <bool UP>
+template <bool UP, bool FUSE = false>
 static void run_pass(PassArgs A, const AggWs &w, const TileGeom &tg, int set, hipStream_t st,
                      float *fill = nullptr) {
     int64_t tiles = A.n / tg.rows + HDP_MAX_PHASES + 2;  // >= the plan's tile count
@@ -848,15 +945,15 @@ static void run_pass(PassArgs A, const AggWs &w, const TileGeom &tg, int set, hi
     A.tXs = w.tXs + (int64_t)set * w.tiles * A.width;
     A.fill = fill;
     if (tg.cpt == 4) {
-        if (tg.rpg == 4) launch_pass<UP, 4, 4>(A, tiles, st);
-        else launch_pass<UP, 4, 8>(A, tiles, st);
+        if (tg.rpg == 4) launch_pass<UP, 4, 4, FUSE>(A, tiles, st);
+        else launch_pass<UP, 4, 8, FUSE>(A, tiles, st);
     } else if (tg.cpt == 2) {
-        if (tg.rpg == 4) launch_pass<UP, 2, 4>(A, tiles, st);
-        else if (tg.rpg == 8) launch_pass<UP, 2, 8>(A, tiles, st);
-        else launch_pass<UP, 2, 16>(A, tiles, st);
+        if (tg.rpg == 4) launch_pass<UP, 2, 4, FUSE>(A, tiles, st);
+        else if (tg.rpg == 8) launch_pass<UP, 2, 8, FUSE>(A, tiles, st);
+        else launch_pass<UP, 2, 16, FUSE>(A, tiles, st);
     } else {
-        if (tg.rpg == 4) launch_pass<UP, 1, 4>(A, tiles, st);
-        else launch_pass<UP, 1, 8>(A, tiles, st);
+        if (tg.rpg == 4) launch_pass<UP, 1, 4, FUSE>(A, tiles, st);
+        else launch_pass<UP, 1, 8, FUSE>(A, tiles, st);
     }
 }
 
@@ -916,6 +1013,39 @@ void launch_aggregate(const hdp_forest &f, int width, const float *cost, float s
     float *U = up ? up : w.up;
     prologue(f, width, sigma, w, st, U);
     two_pass(f, width, cost, U, agg, w, 0, st);
+}
+
+// Cost, aggregation and winner-takes-all of one layer.  Narrow rows: the two
+// fused passes (no cost volume in memory, no separate WTA launch).  Wide rows:
+// the cost volume is built in the workspace and the three steps run apart.
+void launch_match(const float *left, const float *right, const LevelGeom &g, const hdp_forest &f,
+                  int width, const hdp_cost_params &p, float sigma, float *agg, int32_t *disp,
+                  void *ws, hipStream_t st) {
+    size_t bytes;
+    AggWs w = carve_agg_ws(ws, f.n, width, &bytes);
+    if (width > kSentMaxWidth) {
+        launch_cost_volume(left, right, g, f.node, f.lo, f.hi, width, p, w.ug, st);
+        prologue(f, width, sigma, w, st, w.up);
+        two_pass(f, width, w.ug, w.up, agg, w, 0, st);
+        launch_wta(g, f.node, f.lo, f.hi, width, agg, disp, st);
+        return;
+    }
+    prologue(f, width, sigma, w, st, w.up);
+    TileGeom tg = tile_geom(width);
+    PassArgs A = pass_args(f, width, w, tg);
+    A.imL = reinterpret_cast<const float4 *>(left);
+    A.imR = reinterpret_cast<const float4 *>(right);
+    A.cp = CostParams{p.a_c, p.tau_c, p.a_g, p.tau_g};
+    A.node = f.node;
+    A.rx = f.rx;
+    A.rlh = f.rlh;
+    A.disp = disp;
+    A.src = nullptr;
+    A.dst = w.up;
+    run_pass<true, true>(A, w, tg, 0, st, agg);
+    A.src = w.up;
+    A.dst = agg;
+    run_pass<false, true>(A, w, tg, 1, st);
 }
 
 // --- adjoint ----------------------------------------------------------------------------

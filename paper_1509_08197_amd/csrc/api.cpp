@@ -76,7 +76,7 @@ int max_dmax(const LevelGeom &g) {
 
 struct FLayout {
     size_t parent, depth, tree, lo, hi, row, wgt, order, level_ptr, node, prow, lc, heavy, rw,
-        phase_ptr, info, end;
+        phase_ptr, info, rx, rlh, end;
 };
 
 FLayout forest_layout(int64_t n) {
@@ -104,6 +104,8 @@ FLayout forest_layout(int64_t n) {
     L.rw = take(4 * n);
     L.phase_ptr = take(4 * (HDP_MAX_PHASES + 1));
     L.info = take(4 * HDP_INFO_WORDS);
+    L.rx = take(4 * n);
+    L.rlh = take(4 * n);
     L.end = (off + 255) & ~size_t(255);
     return L;
 }
@@ -111,7 +113,7 @@ FLayout forest_layout(int64_t n) {
 bool forest_ok(const hdp_forest *f, int64_t n) {
     return f && f->n == n && f->parent && f->depth && f->tree && f->lo && f->hi && f->row &&
            f->wgt && f->order && f->level_ptr && f->node && f->prow && f->lc && f->heavy &&
-           f->rw && f->phase_ptr && f->info;
+           f->rw && f->phase_ptr && f->info && f->rx && f->rlh;
 }
 
 }  // namespace
@@ -143,6 +145,8 @@ hdp_status hdp_forest_bind(void *buf, size_t bytes, int64_t n, hdp_forest *f) {
     f->rw = reinterpret_cast<float *>(b + L.rw);
     f->phase_ptr = reinterpret_cast<int32_t *>(b + L.phase_ptr);
     f->info = reinterpret_cast<int32_t *>(b + L.info);
+    f->rx = reinterpret_cast<int32_t *>(b + L.rx);
+    f->rlh = reinterpret_cast<int32_t *>(b + L.rlh);
     return HDP_OK;
 }
 
@@ -295,6 +299,23 @@ hdp_status hdp_aggregate(const hdp_forest *f, int32_t width, const float *cost, 
     if (ws_bytes < hdp::aggregate_workspace_bytes(f->n, width)) return HDP_EWORKSPACE;
     (void)hipGetLastError();
     hdp::launch_aggregate(*f, width, cost, sigma, agg, up, ws, (hipStream_t)stream);
+    return last_hip();
+}
+
+hdp_status hdp_match_layer(const float *left, const float *right, const hdp_shape *shapes,
+                           int32_t n_pairs, const hdp_forest *f, int32_t width,
+                           const hdp_cost_params *p, float sigma, float *agg, int32_t *disp,
+                           void *ws, size_t ws_bytes, void *stream) {
+    if (!left || !right || !p || !agg || !disp || !ws || !(sigma > 0.f)) return HDP_EINVAL;
+    LevelGeom g;
+    hdp_status st = make_geom(shapes, n_pairs, 0, &g);
+    if (st != HDP_OK) return st;
+    if (!forest_ok(f, total_pixels(g))) return HDP_EINVAL;
+    st = check_agg(f, width);
+    if (st != HDP_OK) return st;
+    if (ws_bytes < hdp::aggregate_workspace_bytes(f->n, width)) return HDP_EWORKSPACE;
+    (void)hipGetLastError();
+    hdp::launch_match(left, right, g, *f, width, *p, sigma, agg, disp, ws, (hipStream_t)stream);
     return last_hip();
 }
 

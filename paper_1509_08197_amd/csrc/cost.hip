@@ -1,23 +1,9 @@
 // Restricted matching cost E (Section 3.3, eq. E) and winner-takes-all.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "matchcost.hpp"
 
 namespace hdp {
-
-struct CostParams {
-    float a_c, tau_c, a_g, tau_g;
-};
-
-// M(v, label): colour term from the channel differences, gradient term from
-// the difference of the gx numerators (gray gradient = gx / 6).
-__device__ __forceinline__ float match_cost(float4 L, const float4 *__restrict__ right, int v,
-                                            int x, int label, const CostParams &c) {
-    if (x - label < 0) return c.a_c * c.tau_c + c.a_g * c.tau_g;
-    float4 R = right[v - label];
-    float col = (fabsf(L.x - R.x) + fabsf(L.y - R.y) + fabsf(L.z - R.z)) / 3.0f;
-    float gd = fabsf(L.w - R.w) / 6.0f;
-    return c.a_c * fminf(col, c.tau_c) + c.a_g * fminf(gd, c.tau_g);
-}
 
 // One thread per CPT consecutive columns of a row (vector stores); a
 // workgroup covers kBlock / (width / CPT) whole rows.  node == NULL: rows are

@@ -24,6 +24,9 @@ size_t aggregate_workspace_bytes(int64_t n, int width);
 bool set_schedule(int width, int cpt, int rpg);
 void launch_aggregate(const hdp_forest &f, int width, const float *cost, float sigma, float *agg,
                       float *up, void *ws, hipStream_t st);
+void launch_match(const float *left, const float *right, const LevelGeom &g, const hdp_forest &f,
+                  int width, const hdp_cost_params &p, float sigma, float *agg, int32_t *disp,
+                  void *ws, hipStream_t st);
 void launch_aggregate_backward(const hdp_forest &f, int width, const float *cost, const float *agg,
                                const float *up, const float *grad_agg, float sigma,
                                float *grad_cost, float *grad_w, float *grad_sigma, void *ws,

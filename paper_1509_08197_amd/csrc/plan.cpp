@@ -20,7 +20,7 @@ struct Level {
     void *forest_buf = nullptr;
     hdp_forest forest{};
     int32_t *pix_lo = nullptr, *pix_hi = nullptr;
-    float *cost = nullptr, *agg = nullptr;
+    float *agg = nullptr;
     int32_t *disp = nullptr;
     size_t level_off = 0;  // offset of this layer in the pyramid buffers (float4 units)
 };
@@ -53,7 +53,6 @@ void free_plan(hdp_plan_s *P) {
         (void)hipFree(L.forest_buf);
         (void)hipFree(L.pix_lo);
         (void)hipFree(L.pix_hi);
-        (void)hipFree(L.cost);
         (void)hipFree(L.agg);
         (void)hipFree(L.disp);
     }
@@ -90,13 +89,8 @@ hdp_status enqueue_step(hdp_plan_s *P, hipStream_t st) {
                            l < p.L ? L.pix_hi : nullptr, L.max_width, p.beta_num, p.beta_den,
                            L.width, &L.forest, P->ws_tree, P->ws_tree_bytes, st);
         if (s != HDP_OK) return s;
-        s = hdp_cost_volume(li, ri, L.shapes.data(), P->n_pairs, &L.forest, L.width, &p.cost,
-                            L.cost, st);
-        if (s != HDP_OK) return s;
-        s = hdp_aggregate(&L.forest, L.width, L.cost, p.sigma, L.agg, nullptr, P->ws_agg,
-                          P->ws_agg_bytes, st);
-        if (s != HDP_OK) return s;
-        s = hdp_wta(&L.forest, L.shapes.data(), P->n_pairs, L.width, L.agg, L.disp, st);
+        s = hdp_match_layer(li, ri, L.shapes.data(), P->n_pairs, &L.forest, L.width, &p.cost,
+                            p.sigma, L.agg, L.disp, P->ws_agg, P->ws_agg_bytes, st);
         if (s != HDP_OK) return s;
     }
     return HDP_OK;
@@ -148,7 +142,6 @@ hdp_status hdp_plan_create(const hdp_shape *shapes, int32_t n_pairs, const hdp_p
         ok = dev_alloc(&L.forest_buf, fb) &&
              hdp_forest_bind(L.forest_buf, fb, L.n, &L.forest) == HDP_OK &&
              dev_alloc((void **)&L.pix_lo, 4 * L.n) && dev_alloc((void **)&L.pix_hi, 4 * L.n) &&
-             dev_alloc((void **)&L.cost, 4 * L.n * L.width) &&
              dev_alloc((void **)&L.agg, 4 * L.n * L.width) && dev_alloc((void **)&L.disp, 4 * L.n);
         size_t wt = hdp_build_tree_workspace_bytes(L.n);
         size_t wa = hdp_aggregate_workspace_bytes(L.n, L.width);

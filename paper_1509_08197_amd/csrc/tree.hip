@@ -936,7 +936,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_compact(int K, const int32_t *_
                                                          int32_t *__restrict__ ctr,
                                                          const uint64_t *__restrict__ pr,
                                                          int32_t *__restrict__ At) {
-    if (ctr[CTR_RUNS] > kTA && flags[FLAG_RANK + K - 1] == 0) return;
+    if (K > 0 && ctr[CTR_RUNS] > kTA && flags[FLAG_RANK + K - 1] == 0) return;
     const int nC = ctr[CTR_RUNS];
     for (int s = (int)gtid(); s < nC; s += gridDim.x * kBlock) {
         bool open = (int32_t)(pr[s] >> 32) >= 0;
@@ -954,7 +954,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_rank_tail(
     int32_t *__restrict__ info) {
     __shared__ unsigned long long L[kTA];
     __shared__ int s_more;
-    if (ctr[CTR_RUNS] > kTA && flags[FLAG_RANK + K - 1] == 0) return;
+    if (K > 0 && ctr[CTR_RUNS] > kTA && flags[FLAG_RANK + K - 1] == 0) return;
     const int nA = ctr[CTR_AT];
     const int tid = threadIdx.x;
     if (nA <= kTA) {
@@ -1214,13 +1214,16 @@ __global__ void k_phase_ptr(const int32_t *__restrict__ offs, int64_t ntiles, in
 // --- 7. rows of the volume layout ---------------------------------------------------
 
 // Per pixel v (coherent reads), scattered to its row r: parent row, heavy
-// flag, edge weight and the rows of up to three light children in ascending
-// pixel id.
+// flag, edge weight, the rows of up to three light children in ascending
+// pixel id, and the pixel's column and interval (read by the fused matching
+// pass instead of the pixel arrays).
 __global__ void k_rows(LevelGeom g, const int32_t *__restrict__ row_of,
                        const int32_t *__restrict__ parent, const float *__restrict__ wgt,
                        const int32_t *__restrict__ heavy_child, const uint8_t *__restrict__ adj,
+                       const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
                        int32_t *__restrict__ prow, uint8_t *__restrict__ heavy,
-                       int32_t *__restrict__ lc, float *__restrict__ rw) {
+                       int32_t *__restrict__ lc, float *__restrict__ rw,
+                       int32_t *__restrict__ rx, int32_t *__restrict__ rlh) {
     int64_t v = gtid();
     int64_t n = g.off[g.n_pairs];
     if (v >= n) return;
@@ -1229,7 +1232,10 @@ __global__ void k_rows(LevelGeom g, const int32_t *__restrict__ row_of,
     prow[r] = p >= 0 ? row_of[p] : -1;
     heavy[r] = (p >= 0 && heavy_child[p] == v) ? 1 : 0;
     rw[r] = wgt[v];
-    const int W = g.W[pair_of(g, (int)v)];
+    const int pair = pair_of(g, (int)v);
+    const int W = g.W[pair];
+    rx[r] = ((int)v - g.off[pair]) % W;
+    rlh[r] = lo[v] | (hi[v] << 16);
     const uint8_t a = adj[v];
     const int order[4] = {3, 2, 0, 1};  // up, left, right, down: ascending pixel id
     const int hc = heavy_child[v];
@@ -1268,19 +1274,18 @@ __global__ void k_level_ptr(const int32_t *__restrict__ order, const int32_t *__
 __global__ void k_finish_info(const int32_t *__restrict__ flags, const int32_t *__restrict__ ctr,
                               int32_t *__restrict__ info, int width, int64_t n,
                               const uint64_t *__restrict__ root_total) {
-    if (threadIdx.x != 0) return;
+    // one wavefront: lane r reads round r's flags
+    const int r = threadIdx.x;
+    const uint64_t bv = __ballot(r < 64 && flags[FLAG_BV + r] != 0);
+    const uint64_t rk = __ballot(r < 64 && flags[FLAG_RANK + r] != 0);
+    if (r != 0) return;
     info[HDP_INFO_LIVE_EDGES] = ctr[CTR_E];
     info[HDP_INFO_ACTIVE_COMPONENTS] = ctr[CTR_RALL];
     info[HDP_INFO_TOUR_RUNS] = ctr[CTR_RUNS];
     // every tree of sz nodes has a tour of 2(sz - 1) slots
     info[HDP_INFO_N_TREES] = (int32_t)(n - (int64_t)((uint32_t)*root_total >> 1));
-    int bv = 0, rk = 0;
-    for (int r = 0; r < 64; ++r) {
-        bv += flags[FLAG_BV + r] ? 1 : 0;
-        rk += flags[FLAG_RANK + r] ? 1 : 0;
-    }
-    info[HDP_INFO_MST_ROUNDS] = bv;
-    info[HDP_INFO_RANK_ROUNDS] = rk;
+    info[HDP_INFO_MST_ROUNDS] = __popcll(bv);
+    info[HDP_INFO_RANK_ROUNDS] = __popcll(rk);
     info[HDP_INFO_WIDTH] = width;
 }
 
@@ -1399,7 +1404,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     // an edge owns a tile-border pixel, and the number of such components at
     // least halves per global round.  A tour's contracted list has at most one
     // entry per directed tree edge that crosses a tile border, plus its end.
-    int64_t border_px = 0, max_list = 2;
+    int64_t border_px = 0, max_list = 2, runs_bound = 0;
     unsigned n_tiles = (unsigned)g.toff[g.n_pairs];
     for (int p = 0; p < g.n_pairs; ++p) {
         int H = g.H[p], W = g.W[p];
@@ -1413,6 +1418,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
             }
         int64_t crossing = (int64_t)H * (tx - 1) + (int64_t)W * (ty - 1);
         if (2 * crossing + 2 > max_list) max_list = 2 * crossing + 2;
+        runs_bound += 2 * crossing + 1;
     }
     unsigned g_edges = grid_for(2 * n) < (unsigned)kGridCap ? grid_for(2 * n) : kGridCap;
     unsigned g_roots = grid_for(border_px) < (unsigned)kGridCap ? grid_for(border_px) : kGridCap;
@@ -1447,6 +1453,10 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     int rk_rounds = ceil_log2(max_list) + 1;
     if (rk_rounds > kRankGridRounds) rk_rounds = kRankGridRounds;
     if (rk_rounds < 1) rk_rounds = 1;
+    // Without intervals every pair's forest is one spanning tree (one tour), so
+    // the contracted list is bounded by runs_bound: a list that fits the LDS
+    // tail needs no full-grid rounds at all.
+    if (!plo && runs_bound <= kTA) rk_rounds = 0;
     for (int r = 0; r < rk_rounds; ++r)
         k_rank_round<<<g_edges, kBlock, 0, st>>>(r, t.flags, t.ctr, t.pr);
     k_rank_compact<<<g_edges, kBlock, 0, st>>>(rk_rounds, t.flags, t.ctr, t.pr, t.At);
@@ -1476,8 +1486,8 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         k_count_scatter<64, 6><<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles,
                                                                     f.node, f.row);
     }
-    k_rows<<<gn, kBlock, 0, st>>>(g, f.row, f.parent, f.wgt, t.heavy_child, t.adj, f.prow, f.heavy,
-                                  f.lc, f.rw);
+    k_rows<<<gn, kBlock, 0, st>>>(g, f.row, f.parent, f.wgt, t.heavy_child, t.adj, f.lo, f.hi,
+                                  f.prow, f.heavy, f.lc, f.rw, f.rx, f.rlh);
     k_finish_info<<<1, 64, 0, st>>>(t.flags, t.ctr, f.info, width, n, t.root_total);
 }
 

@@ -54,7 +54,7 @@ class Params(C.Structure):
 class ForestStruct(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in (
         "parent", "depth", "tree", "lo", "hi", "row", "wgt", "order", "level_ptr", "node",
-        "prow", "lc", "heavy", "rw", "phase_ptr", "info")]
+        "prow", "lc", "heavy", "rw", "phase_ptr", "info", "rx", "rlh")]
 
 
 _lib = None
@@ -92,6 +92,8 @@ def _declare(L):
     L.hdp_aggregate_backward.argtypes = [C.POINTER(ForestStruct), I32, P, P, P, P, F,
                                          P, P, P, P, SZ, P]
     L.hdp_wta.argtypes = [C.POINTER(ForestStruct), P, I32, I32, P, P, P]
+    L.hdp_match_layer.argtypes = [P, P, P, I32, C.POINTER(ForestStruct), I32,
+                                  C.POINTER(CostParams), F, P, P, P, SZ, P]
     L.hdp_forest_set_weights.argtypes = [C.POINTER(ForestStruct), P, P]
     L.hdp_forest_set_weights.restype = I32
     L.hdp_predict_range.argtypes = [P, P, P, I32, I32, I32, P, P, P]
@@ -369,6 +371,25 @@ def wta(agg: torch.Tensor, shapes, forest: Optional[Forest] = None,
     return out
 
 
+def match_layer(left: torch.Tensor, right: torch.Tensor, shapes, forest: Forest,
+                sigma: float = 0.1, params: Optional[CostParams] = None, agg=None, disp=None,
+                ws=None):
+    """Cost, aggregation and WTA of one layer in one call (fused passes for
+    rows of at most 32 labels).  Returns (agg, disp)."""
+    n, width = forest.n, forest.width
+    if agg is None:
+        agg = torch.empty((n, width), dtype=torch.float32, device=left.device)
+    if disp is None:
+        disp = torch.empty(n, dtype=torch.int32, device=left.device)
+    p = params or cost_params()
+    wsb = lib().hdp_aggregate_workspace_bytes(n, width)
+    w = (ws or _ws_agg).get(wsb, left.device)
+    _check("hdp_match_layer", lib().hdp_match_layer(
+        _ptr(left), _ptr(right), _shapes(shapes), len(shapes), C.byref(forest.st), int(width),
+        C.byref(p), float(sigma), _ptr(agg), _ptr(disp), _ptr(w), wsb, _stream()))
+    return agg, disp
+
+
 def predict_range(disp_upper: torch.Tensor, upper_shapes, lower_shapes, S: int = 2,
                   window: int = 4, out=None):
     n = n_pixels(lower_shapes)
@@ -424,15 +445,20 @@ class LevelResult:
 def stereo_level(left_img, right_img, shapes, level, pix_lo=None, pix_hi=None, max_width=0,
                  beta=(19, 20), sigma=0.1, params=None, keep=False, ws=None) -> LevelResult:
     """One layer (Section 3): forest, restricted cost, aggregation, WTA.
-    keep: also return cost and aggregated volumes and fill the forest's level order."""
+    keep: run the three steps apart and also return the cost and aggregated
+    volumes (and fill the forest's level order); otherwise one fused call."""
     ws = ws or {}
     f = build_tree(left_img, shapes, level, pix_lo, pix_hi, max_width=max_width, beta=beta,
                    read_info=False, ws=ws.get("tree"), level_order=keep)
+    if not keep:
+        agg, disp = match_layer(left_img, right_img, shapes, f, sigma, params, ws=ws.get("agg"))
+        return LevelResult(level=level, shapes=list(shapes), forest=f, disp=disp, pix_lo=pix_lo,
+                           pix_hi=pix_hi, cost=None, agg=None)
     cost = cost_volume(left_img, right_img, shapes, f, params=params)
     agg = aggregate(f, cost, sigma, ws=ws.get("agg"))
     disp = wta(agg, shapes, f)
     return LevelResult(level=level, shapes=list(shapes), forest=f, disp=disp, pix_lo=pix_lo,
-                       pix_hi=pix_hi, cost=cost if keep else None, agg=agg if keep else None)
+                       pix_hi=pix_hi, cost=cost, agg=agg)
 
 
 def hdp_stereo(left_rgb: torch.Tensor, right_rgb: torch.Tensor, shapes, S=2, L=3, window=4,

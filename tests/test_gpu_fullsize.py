@@ -118,6 +118,31 @@ def test_hdp_layers_1344x1104_teacher_forced(H, orc):
         up = o["disp"]
 
 
+def test_fused_hdp_step_1344x1104(H):
+    """The HDP step as benchmarked (fused matching on every layer) against the
+    three separate steps (validated against the oracle above) on the same
+    forests: aggregated volumes and labels bit for bit."""
+    pair = scenes.workload(2)
+    Hh, Ww = pair.shape
+    P = scenes.HDP_PARAMS[2]
+    S, L = P["S"], P["L"]
+    shapes = [(Hh, Ww, 255)]
+    Lr, Rr = rgb_dev(pair.left), rgb_dev(pair.right)
+    res = H.hdp_stereo(Lr, Rr, shapes, S=S, L=L, window=P["window"], beta=P["beta"])
+    lv = H.level_shapes(shapes, S, L)
+    lp, rp = H.pyramid_views(Lr, Rr, shapes, S, L)
+    for l in range(L, -1, -1):
+        f = res[l].forest
+        cost = H.cost_volume(lp[l], rp[l], lv[l], f)
+        agg3 = H.aggregate(f, cost, 0.1)
+        disp3 = H.wta(agg3, lv[l], f)
+        aggf, dispf = H.match_layer(lp[l], rp[l], lv[l], f)
+        torch.cuda.synchronize()
+        assert torch.equal(aggf, agg3), f"layer {l}: aggregated volumes differ"
+        assert torch.equal(dispf, disp3), f"layer {l}: labels differ"
+        assert torch.equal(res[l].disp, disp3), f"layer {l}: step labels differ"
+
+
 def tree_signature(parent):
     """Per pixel: (root, size, sum of member ids, sum of parent ids) of its tree."""
     n = len(parent)

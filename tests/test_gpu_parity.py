@@ -302,6 +302,66 @@ def test_hdp_end_to_end_small(H, orc):
         print(f"layer {l}: {int(mism.sum())} label mismatches, {int((gap <= REL).sum())} near-ties")
 
 
+def _three_steps(H, lp, rp, shapes, f, sigma=0.1):
+    cost = H.cost_volume(lp, rp, shapes, f)
+    agg = H.aggregate(f, cost, sigma)
+    return agg, H.wta(agg, shapes, f)
+
+
+@pytest.mark.parametrize("case", ["hdp_layer0", "hdp_layer1_batch", "top_width32", "wide_width64"])
+def test_fused_match_layer_equals_three_steps(H, case):
+    """hdp_match_layer (fused cost in the up pass, fused WTA in the down pass for
+    rows of <= 32 labels; the three steps apart for wider rows) gives bit for bit
+    the aggregated volume and the labels of hdp_cost_volume + hdp_aggregate +
+    hdp_wta on the same forest."""
+    S, L, w = 2, 3, 4
+    if case == "hdp_layer1_batch":
+        shapes = [(96, 128, 63), (37, 53, 31), (1, 40, 15)]
+    elif case == "wide_width64":
+        shapes = [(45, 70, 63)]
+    elif case == "top_width32":
+        shapes = [(70, 90, 31)]
+    else:
+        shapes = [(96, 128, 63)]
+    pairs = [scenes.small_scene(500 + i, h, wd, d) for i, (h, wd, d) in enumerate(shapes)]
+    Lr, Rr = rgb_dev(*[p.left for p in pairs]), rgb_dev(*[p.right for p in pairs])
+    if case in ("top_width32", "wide_width64"):
+        lp, rp = H.pyramid_views(Lr, Rr, shapes, S, 0)
+        lv, level, lo, hi, mw = shapes, 0, None, None, 0
+        lp, rp = lp[0], rp[0]
+    else:
+        level = 1 if case == "hdp_layer1_batch" else 0
+        lvs = H.level_shapes(shapes, S, L)
+        res = H.hdp_stereo(Lr, Rr, shapes, S=S, L=L, window=w)
+        lo, hi = H.predict_range(res[level + 1].disp, lvs[level + 1], lvs[level], S, w)
+        lps, rps = H.pyramid_views(Lr, Rr, shapes, S, L)
+        lp, rp, lv = lps[level], rps[level], lvs[level]
+        mw = min(S + 2 * w, max(d for _, _, d in lv) + 1)
+    f = H.build_tree(lp, lv, level, lo, hi, max_width=mw)
+    agg3, disp3 = _three_steps(H, lp, rp, lv, f)
+    aggf, dispf = H.match_layer(lp, rp, lv, f)
+    torch.cuda.synchronize()
+    assert f.read_info()[7] == 0
+    assert torch.equal(aggf, agg3), f"{case}: aggregated volumes differ"
+    assert torch.equal(dispf, disp3), f"{case}: labels differ"
+
+
+@pytest.mark.parametrize("Hh,Ww,dmax", [(70, 90, 31), (45, 70, 127)])
+def test_aggregate_reproducible(H, Hh, Ww, dmax):
+    """Two aggregations of the same cost give the same bits (narrow rows with
+    32 labels, wide rows with 128): a tile's carry does not depend on which of
+    its predecessors had finished."""
+    pair = scenes.small_scene(77, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lp, rp = H.pyramid_views(rgb_dev(pair.left), rgb_dev(pair.right), shapes, 2, 0)
+    f = H.build_tree(lp[0], shapes, 0)
+    cost = H.cost_volume(lp[0], rp[0], shapes, f)
+    runs = [H.aggregate(f, cost, 0.1).clone() for _ in range(4)]
+    torch.cuda.synchronize()
+    for r in runs[1:]:
+        assert torch.equal(r, runs[0])
+
+
 def test_batched_matches_single(H):
     """Two uneven pairs in one call give the per-pair results of single calls."""
     shapes = [(50, 70, 31), (33, 41, 15)]
