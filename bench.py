@@ -57,17 +57,30 @@ def upload(pairs):
     return L, R, shapes
 
 
+# Layers of at least this many rows take the winner-takes-all inside the down
+# pass (kFusedWtaMinRows in aggregate.hip); smaller ones run it as its own kernel.
+FUSED_WTA_MIN_ROWS = 1 << 18
+
+
 def pass_bytes(forest, up: bool) -> float:
-    """Algorithmic HBM bytes of one aggregation pass over a forest: read the
-    source volume and write the result (8 B per entry), read the previous-phase
-    row of every chain head (4 B per label), and the per-row coefficients and
-    links (21 B per row, plus 8 B per light child in the up pass)."""
+    """Algorithmic HBM bytes of one fused matching pass over a forest
+    (hdp_match_layer, rows of <= 32 labels).  Both passes: the previous-phase
+    row of every chain head (4 B per label) and the per-row coefficients and
+    links (21 B per row).  Up: write U (4 B per entry), the row's pixel, column
+    and interval (12 B per row), its left and right image pixels (32 B per row)
+    and 8 B per light child.  Down: read U and write the aggregated volume (8 B
+    per entry); with the fused winner-takes-all also the row's pixel and
+    interval (8 B) and its label (4 B)."""
     import torch
     n, w = forest.n, forest.width
     heavy = forest.array("heavy")
     prow = forest.array("prow")
     heads = int(torch.count_nonzero((heavy == 0) & (prow >= 0)).item())
-    return 8.0 * n * w + 4.0 * heads * w + 21.0 * n + (8.0 * heads if up else 0.0)
+    common = 4.0 * heads * w + 21.0 * n
+    if up:
+        return common + 4.0 * n * w + (12.0 + 32.0) * n + 8.0 * heads
+    wta = 12.0 * n if n >= FUSED_WTA_MIN_ROWS else 0.0
+    return common + 8.0 * n * w + wta
 
 
 def measured_traffic():
@@ -182,7 +195,8 @@ def main():
         secs = sum(v[1] for v in rl.values())
         launches = sum(v[2] for v in rl.values())
         achieved = byts / secs / 1e9
-        out["roofline"] = {"kernel": "k_pass (two-pass aggregation, up and down)",
+        out["roofline"] = {"kernel": "k_pass_s (fused matching passes: cost in the up pass, "
+                                     "winner-takes-all in the down pass)",
                            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                            "traffic": measured_traffic(),

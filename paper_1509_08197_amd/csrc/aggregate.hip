@@ -1015,6 +1015,11 @@ void launch_aggregate(const hdp_forest &f, int width, const float *cost, float s
     two_pass(f, width, cost, U, agg, w, 0, st);
 }
 
+// Layers of at least this many rows take the winner-takes-all inside the down
+// pass; smaller ones (whose passes are bound by the phase dependency chain)
+// run it as its own kernel.
+constexpr int64_t kFusedWtaMinRows = int64_t(1) << 18;
+
 // Cost, aggregation and winner-takes-all of one layer.  Narrow rows: the two
 // fused passes (no cost volume in memory, no separate WTA launch).  Wide rows:
 // the cost volume is built in the workspace and the three steps run apart.
@@ -1045,7 +1050,12 @@ void launch_match(const float *left, const float *right, const LevelGeom &g, con
     run_pass<true, true>(A, w, tg, 0, st, agg);
     A.src = w.up;
     A.dst = agg;
-    run_pass<false, true>(A, w, tg, 1, st);
+    if (f.n >= kFusedWtaMinRows) {
+        run_pass<false, true>(A, w, tg, 1, st);
+    } else {
+        run_pass<false, false>(A, w, tg, 1, st);
+        launch_wta(g, f.node, f.lo, f.hi, width, agg, disp, st);
+    }
 }
 
 // --- adjoint ----------------------------------------------------------------------------

@@ -125,9 +125,10 @@ __global__ void k_count_hist(const int32_t *__restrict__ src, int64_t n, KeyFn k
 }
 
 template <int NB, int NBITS, typename KeyFn>
-__global__ void k_count_scatter(const int32_t *__restrict__ src, int64_t n, KeyFn key_of,
-                                const int32_t *__restrict__ offs, int64_t ntiles,
-                                int32_t *__restrict__ dst, int32_t *__restrict__ pos_of) {
+__device__ __forceinline__ void count_scatter_tile(const int32_t *__restrict__ src, int64_t n,
+                                                   KeyFn key_of, const int32_t *__restrict__ offs,
+                                                   int64_t ntiles, int32_t *__restrict__ dst,
+                                                   int32_t *__restrict__ pos_of) {
     __shared__ int32_t run[NB];
     __shared__ int32_t wcnt[kBlock / 64][NB];
     int wv = threadIdx.x >> 6;
@@ -167,6 +168,13 @@ __global__ void k_count_scatter(const int32_t *__restrict__ src, int64_t n, KeyF
         }
         __syncthreads();
     }
+}
+
+template <int NB, int NBITS, typename KeyFn>
+__global__ void k_count_scatter(const int32_t *__restrict__ src, int64_t n, KeyFn key_of,
+                                const int32_t *__restrict__ offs, int64_t ntiles,
+                                int32_t *__restrict__ dst, int32_t *__restrict__ pos_of) {
+    count_scatter_tile<NB, NBITS>(src, n, key_of, offs, ntiles, dst, pos_of);
 }
 
 }  // namespace hdp

@@ -1200,15 +1200,41 @@ struct DigitKey {
     __device__ int operator()(int64_t, int32_t x) const { return (depth[x] >> shift) & 255; }
 };
 
-__global__ void k_phase_ptr(const int32_t *__restrict__ offs, int64_t ntiles, int64_t n,
-                            int32_t *__restrict__ phase_ptr, int32_t *__restrict__ info) {
-    int k = threadIdx.x;
-    if (k > HDP_MAX_PHASES) return;
-    int32_t v = offs[(int64_t)k * ntiles];  // rows with light depth < k
-    phase_ptr[k] = v;
-    // phases = 1 + largest light depth present: the first k with all rows below it
-    int32_t prev = k > 0 ? offs[(int64_t)(k - 1) * ntiles] : 0;
-    if (k > 0 && v == n && prev < n) info[HDP_INFO_N_PHASES] = k;
+// Rows: the stable partition of the preorder by light depth (counting
+// scatter over the scanned per-tile histograms), and in block 0 the chain-phase
+// table read from the same scanned histograms.
+__global__ void k_phase_rows(const int32_t *__restrict__ seq, int64_t n, LdKey key,
+                             const int32_t *__restrict__ offs, int64_t ntiles,
+                             int32_t *__restrict__ node, int32_t *__restrict__ row,
+                             int32_t *__restrict__ phase_ptr, int32_t *__restrict__ info) {
+    const int k = threadIdx.x;
+    if (blockIdx.x == 0 && k <= HDP_MAX_PHASES) {
+        int32_t v = offs[(int64_t)k * ntiles];  // rows with light depth < k
+        phase_ptr[k] = v;
+        // phases = 1 + largest light depth present: the first k with all rows below it
+        int32_t prev = k > 0 ? offs[(int64_t)(k - 1) * ntiles] : 0;
+        if (k > 0 && v == n && prev < n) info[HDP_INFO_N_PHASES] = k;
+    }
+    count_scatter_tile<64, 6>(seq, n, key, offs, ntiles, node, row);
+}
+
+// Build statistics into info (one wavefront: lane r reads round r's flags).
+__device__ __forceinline__ void finish_info(const int32_t *__restrict__ flags,
+                                            const int32_t *__restrict__ ctr,
+                                            int32_t *__restrict__ info, int width, int64_t n,
+                                            const uint64_t *__restrict__ root_total) {
+    const int r = threadIdx.x;
+    const uint64_t bv = __ballot(r < 64 && flags[FLAG_BV + r] != 0);
+    const uint64_t rk = __ballot(r < 64 && flags[FLAG_RANK + r] != 0);
+    if (r != 0) return;
+    info[HDP_INFO_LIVE_EDGES] = ctr[CTR_E];
+    info[HDP_INFO_ACTIVE_COMPONENTS] = ctr[CTR_RALL];
+    info[HDP_INFO_TOUR_RUNS] = ctr[CTR_RUNS];
+    // every tree of sz nodes has a tour of 2(sz - 1) slots
+    info[HDP_INFO_N_TREES] = (int32_t)(n - (int64_t)((uint32_t)*root_total >> 1));
+    info[HDP_INFO_MST_ROUNDS] = __popcll(bv);
+    info[HDP_INFO_RANK_ROUNDS] = __popcll(rk);
+    info[HDP_INFO_WIDTH] = width;
 }
 
 // --- 7. rows of the volume layout ---------------------------------------------------
@@ -1223,9 +1249,13 @@ __global__ void k_rows(LevelGeom g, const int32_t *__restrict__ row_of,
                        const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
                        int32_t *__restrict__ prow, uint8_t *__restrict__ heavy,
                        int32_t *__restrict__ lc, float *__restrict__ rw,
-                       int32_t *__restrict__ rx, int32_t *__restrict__ rlh) {
+                       int32_t *__restrict__ rx, int32_t *__restrict__ rlh,
+                       const int32_t *__restrict__ flags, const int32_t *__restrict__ ctr,
+                       int32_t *__restrict__ info, int width,
+                       const uint64_t *__restrict__ root_total) {
     int64_t v = gtid();
     int64_t n = g.off[g.n_pairs];
+    if (blockIdx.x == 0 && threadIdx.x < 64) finish_info(flags, ctr, info, width, n, root_total);
     if (v >= n) return;
     const int64_t r = row_of[v];
     const int64_t p = parent[v];
@@ -1271,23 +1301,6 @@ __global__ void k_level_ptr(const int32_t *__restrict__ order, const int32_t *__
     if (i == n) info[HDP_INFO_N_LEVELS] = d;
 }
 
-__global__ void k_finish_info(const int32_t *__restrict__ flags, const int32_t *__restrict__ ctr,
-                              int32_t *__restrict__ info, int width, int64_t n,
-                              const uint64_t *__restrict__ root_total) {
-    // one wavefront: lane r reads round r's flags
-    const int r = threadIdx.x;
-    const uint64_t bv = __ballot(r < 64 && flags[FLAG_BV + r] != 0);
-    const uint64_t rk = __ballot(r < 64 && flags[FLAG_RANK + r] != 0);
-    if (r != 0) return;
-    info[HDP_INFO_LIVE_EDGES] = ctr[CTR_E];
-    info[HDP_INFO_ACTIVE_COMPONENTS] = ctr[CTR_RALL];
-    info[HDP_INFO_TOUR_RUNS] = ctr[CTR_RUNS];
-    // every tree of sz nodes has a tour of 2(sz - 1) slots
-    info[HDP_INFO_N_TREES] = (int32_t)(n - (int64_t)((uint32_t)*root_total >> 1));
-    info[HDP_INFO_MST_ROUNDS] = __popcll(bv);
-    info[HDP_INFO_RANK_ROUNDS] = __popcll(rk);
-    info[HDP_INFO_WIDTH] = width;
-}
 
 // --- learnable edge weights -----------------------------------------------------------------
 
@@ -1482,13 +1495,12 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         LdKey key{t.ld};
         k_count_hist<64><<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles);
         device_scan<int32_t>(t.hist, t.hist, 64 * ntiles, t.partial32, nullptr, false, st);
-        k_phase_ptr<<<1, 64, 0, st>>>(t.hist, ntiles, n, f.phase_ptr, f.info);
-        k_count_scatter<64, 6><<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles,
-                                                                    f.node, f.row);
+        k_phase_rows<<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles, f.node,
+                                                          f.row, f.phase_ptr, f.info);
     }
     k_rows<<<gn, kBlock, 0, st>>>(g, f.row, f.parent, f.wgt, t.heavy_child, t.adj, f.lo, f.hi,
-                                  f.prow, f.heavy, f.lc, f.rw, f.rx, f.rlh);
-    k_finish_info<<<1, 64, 0, st>>>(t.flags, t.ctr, f.info, width, n, t.root_total);
+                                  f.prow, f.heavy, f.lc, f.rw, f.rx, f.rlh, t.flags, t.ctr,
+                                  f.info, width, t.root_total);
 }
 
 // 8: level order (stable LSD radix sort of ids by depth) and level_ptr
