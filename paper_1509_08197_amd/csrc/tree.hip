@@ -195,6 +195,28 @@ __global__ void k_tree_init(int32_t *__restrict__ flags, int32_t *__restrict__ c
 // parent link of component x: low 32 bits the parent (x itself for a root),
 // high 32 bits 0 for a permanent link or r + 1 for a hook made in round r.
 
+// Slots of the per-tile table of component pairs (at most 2 * kTilePx live
+// edges inside a tile, so the table never needs more).
+constexpr int kPairSlots = 2 * kTilePx;
+
+// Least edge key per unordered pair {a, b} of local components (a, b <
+// kTilePx): open addressing on the pair, then a 64-bit atomic minimum.
+// Returns the slot, or -1 if the table is full (the edge is then kept).
+__device__ __forceinline__ int pair_min(int32_t *pk, unsigned long long *pv, int a, int b,
+                                        uint64_t key) {
+    const int pair = (a < b ? a : b) * kTilePx + (a < b ? b : a);
+    int h = (int)(((uint32_t)pair * 2654435761u) >> 21) & (kPairSlots - 1);
+    for (int it = 0; it < kPairSlots; ++it) {
+        const int old = atomicCAS(&pk[h], -1, pair);
+        if (old == -1 || old == pair) {
+            if (pv[h] > key) atomicMin(&pv[h], (unsigned long long)key);
+            return h;
+        }
+        h = (h + 1) & (kPairSlots - 1);
+    }
+    return -1;
+}
+
 __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     const float4 *__restrict__ img, LevelGeom g, const int32_t *__restrict__ plo,
     const int32_t *__restrict__ phi, int max_width, int32_t *__restrict__ comp0,
@@ -206,6 +228,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     __shared__ int32_t lab[kTilePx], hk[kTilePx];
     __shared__ unsigned long long best[kTilePx];
     __shared__ uint8_t tR[kTilePx], tD[kTilePx];  // tree edges taken, by owning pixel
+    __shared__ int32_t pk[kPairSlots];               // component pair of a table slot
+    __shared__ unsigned long long pv[kPairSlots];    // least (key, id) edge of the pair
     __shared__ int s_flag[2], s_any[3], s_nE, s_nR, s_bE, s_bR;
     const TileInfo t = tile_info(g, blockIdx.x);
     const float scale = ldexpf(1.0f, 2 * g.level);
@@ -346,16 +370,29 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
             if (!wg_any(more, s_any, rr)) break;
         }
     }
-    // smallest pixel id of every local component (hk reused)
+    // smallest pixel id of every local component (hk reused); empty pair table
     hk[i] = 0x7fffffff;
+    for (int h = i; h < kPairSlots; h += kLocalThreads) {
+        pk[h] = -1;
+        pv[h] = kNoEdge;
+    }
     __syncthreads();
     if (valid) atomicMin(&hk[lab[i]], (int32_t)v);
-    __syncthreads();
-    // live edges (owned right / down edges not inside one component) and
-    // active components (with an incident edge left): reserve, then write
+    // Live edges: owned right / down edges not inside one component.  Of the
+    // edges inside the tile joining the same two components only the least
+    // (key, id) is kept: in the graph with the local components contracted the
+    // others are the heavier of two parallel edges, never in the forest.
     const int c = lab[i];
-    const bool live_r = valid && kr != kNoKey && (!r_in || lab[i + 1] != c);
-    const bool live_d = valid && kd != kNoKey && (!d_in || lab[i + kTile] != c);
+    const int cr = r_in ? lab[i + 1] : -1, cd = d_in ? lab[i + kTile] : -1;
+    bool live_r = valid && kr != kNoKey && cr != c;
+    bool live_d = valid && kd != kNoKey && cd != c;
+    const uint64_t gr = key64(kr, 2 * v), gd = key64(kd, 2 * v + 1);
+    const int sr = live_r && cr >= 0 ? pair_min(pk, pv, c, cr, gr) : -1;
+    const int sd = live_d && cd >= 0 ? pair_min(pk, pv, c, cd, gd) : -1;
+    __syncthreads();
+    if (sr >= 0 && pv[sr] != gr) live_r = false;
+    if (sd >= 0 && pv[sd] != gd) live_d = false;
+    // active components (with an incident edge left); reserve, then write
     const bool act = valid && c == i && best[i] != kNoEdge;
     const uint64_t mr = __ballot(live_r), md = __ballot(live_d), ma = __ballot(act);
     int wE = 0, wR = 0;
@@ -372,8 +409,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     wE = __shfl(wE, 0, 64) + s_bE;
     wR = __shfl(wR, 0, 64) + s_bR;
     const uint64_t lt = lanemask_lt();
-    if (live_r) E[wE + __popcll(mr & lt)] = key64(kr, 2 * v);
-    if (live_d) E[wE + __popcll(mr) + __popcll(md & lt)] = key64(kd, 2 * v + 1);
+    if (live_r) E[wE + __popcll(mr & lt)] = gr;
+    if (live_d) E[wE + __popcll(mr) + __popcll(md & lt)] = gd;
     if (act) R[wR + __popcll(ma & lt)] = (int32_t)v;
     if (valid) {
         *reinterpret_cast<uint16_t *>(&intree[2 * v]) = (uint16_t)(tR[i] | (tD[i] << 8));
