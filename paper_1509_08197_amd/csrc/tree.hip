@@ -1276,36 +1276,37 @@ __device__ __forceinline__ void finish_info(const int32_t *__restrict__ flags,
 
 // --- 7. rows of the volume layout ---------------------------------------------------
 
-// Per pixel v (coherent reads), scattered to its row r: parent row, heavy
+// Per row r (coalesced writes) from its pixel v = node[r] (gathered reads;
+// consecutive rows are neighbouring pixels of a chain): parent row, heavy
 // flag, edge weight, the rows of up to three light children in ascending
 // pixel id, and the pixel's column and interval (read by the fused matching
-// pass instead of the pixel arrays).
-__global__ void k_rows(LevelGeom g, const int32_t *__restrict__ row_of,
-                       const int32_t *__restrict__ parent, const float *__restrict__ wgt,
-                       const int32_t *__restrict__ heavy_child, const uint8_t *__restrict__ adj,
-                       const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
-                       int32_t *__restrict__ prow, uint8_t *__restrict__ heavy,
-                       int32_t *__restrict__ lc, float *__restrict__ rw,
-                       int32_t *__restrict__ rx, int32_t *__restrict__ rlh,
-                       const int32_t *__restrict__ flags, const int32_t *__restrict__ ctr,
-                       int32_t *__restrict__ info, int width,
+// pass instead of the pixel arrays).  Block 0 also writes the build statistics.
+__global__ void k_rows(LevelGeom g, const int32_t *__restrict__ node,
+                       const int32_t *__restrict__ row_of, const int32_t *__restrict__ parent,
+                       const float *__restrict__ wgt, const int32_t *__restrict__ heavy_child,
+                       const uint8_t *__restrict__ adj, const int32_t *__restrict__ lo,
+                       const int32_t *__restrict__ hi, int32_t *__restrict__ prow,
+                       uint8_t *__restrict__ heavy, int32_t *__restrict__ lc,
+                       float *__restrict__ rw, int32_t *__restrict__ rx,
+                       int32_t *__restrict__ rlh, const int32_t *__restrict__ flags,
+                       const int32_t *__restrict__ ctr, int32_t *__restrict__ info, int width,
                        const uint64_t *__restrict__ root_total) {
-    int64_t v = gtid();
-    int64_t n = g.off[g.n_pairs];
+    const int64_t r = gtid();
+    const int64_t n = g.off[g.n_pairs];
     if (blockIdx.x == 0 && threadIdx.x < 64) finish_info(flags, ctr, info, width, n, root_total);
-    if (v >= n) return;
-    const int64_t r = row_of[v];
-    const int64_t p = parent[v];
+    if (r >= n) return;
+    const int v = node[r];
+    const int p = parent[v];
+    const uint8_t a = adj[v];
+    const int hc = heavy_child[v];
+    const int pair = pair_of(g, v);
+    const int W = g.W[pair];
+    rw[r] = wgt[v];
+    rx[r] = (v - g.off[pair]) % W;
+    rlh[r] = lo[v] | (hi[v] << 16);
     prow[r] = p >= 0 ? row_of[p] : -1;
     heavy[r] = (p >= 0 && heavy_child[p] == v) ? 1 : 0;
-    rw[r] = wgt[v];
-    const int pair = pair_of(g, (int)v);
-    const int W = g.W[pair];
-    rx[r] = ((int)v - g.off[pair]) % W;
-    rlh[r] = lo[v] | (hi[v] << 16);
-    const uint8_t a = adj[v];
     const int order[4] = {3, 2, 0, 1};  // up, left, right, down: ascending pixel id
-    const int hc = heavy_child[v];
     int k = 0;
     for (int i = 0; i < 4; ++i) {
         int d = order[i];
@@ -1535,8 +1536,8 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         k_phase_rows<<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles, f.node,
                                                           f.row, f.phase_ptr, f.info);
     }
-    k_rows<<<gn, kBlock, 0, st>>>(g, f.row, f.parent, f.wgt, t.heavy_child, t.adj, f.lo, f.hi,
-                                  f.prow, f.heavy, f.lc, f.rw, f.rx, f.rlh, t.flags, t.ctr,
+    k_rows<<<gn, kBlock, 0, st>>>(g, f.node, f.row, f.parent, f.wgt, t.heavy_child, t.adj, f.lo,
+                                  f.hi, f.prow, f.heavy, f.lc, f.rw, f.rx, f.rlh, t.flags, t.ctr,
                                   f.info, width, t.root_total);
 }
 
