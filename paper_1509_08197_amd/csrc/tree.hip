@@ -48,8 +48,10 @@ enum {
 constexpr int kBvGridRounds = 4;
 constexpr int kRankGridRounds = 8;
 // Sizes of the one-workgroup LDS tails: spanning forest (edges, components,
-// hash slots) and tour ranking (list entries).
-constexpr int kTE = 4096, kTN = 2048, kTH = 4096;
+// hash slots; endpoints and component state are 16-bit indices) and tour
+// ranking (list entries).
+constexpr int kTE = 6144, kTN = 3072, kTH = 4096;
+constexpr int kTailEdgesPerThread = kTE / 1024;
 constexpr int kTA = 8192;
 // A contracted graph of at most kTE live edges, or a contracted tour list of
 // at most kTA entries, skips the full-grid rounds and goes straight to its tail.
@@ -571,30 +573,66 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
     uint64_t *__restrict__ Et, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
     uint64_t *__restrict__ best0, uint64_t *__restrict__ best1, uint8_t *__restrict__ intree,
     int32_t *__restrict__ info) {
+    static_assert(kTailEdgesPerThread * kLocalThreads == kTE, "edges per thread");
     __shared__ unsigned long long ek[kTE];
-    __shared__ int32_t ea[kTE], eb[kTE];
-    __shared__ int32_t hkey[kTH], hval[kTH];
-    __shared__ int32_t rid[kTN], lab[kTN], hk[kTN], bidx[kTN];
+    __shared__ uint16_t ea[kTE], eb[kTE];
+    __shared__ int32_t hkey[kTH];
+    __shared__ uint16_t hval[kTH];
+    __shared__ int32_t rid[kTN];
+    __shared__ uint16_t lab[kTN], hk[kTN], bidx[kTN];
     __shared__ unsigned long long best[kTN];
-    __shared__ int s_nodes, s_flag;
+    __shared__ int s_nodes, s_flag, s_any[3];
     if (ctr[CTR_E] > kTE && flags[FLAG_BV + K - 1] == 0) return;
     const int nE = ctr[CTR_ET];
     const int tid = threadIdx.x;
     bool lds_mode = nE <= kTE;
+    int ra[kTailEdgesPerThread], rb[kTailEdgesPerThread];  // endpoint components (pixel ids)
     if (lds_mode) {
         for (int h = tid; h < kTH; h += kLocalThreads) hkey[h] = -1;
-        if (tid == 0) s_nodes = 0;
+        if (tid == 0) {
+            s_nodes = 0;
+            s_any[0] = s_any[1] = s_any[2] = 0;
+        }
         __syncthreads();
-        // components of every edge (no link changes in this launch yet)
-        for (int i = tid; i < nE; i += kLocalThreads) {
-            uint64_t k = Et[i];
-            uint32_t e = (uint32_t)k;
-            int a = find_comp<false>(cw, comp0[e >> 1], 1 << 30, info);
-            int b = find_comp<false>(cw, comp0[other_end(g, e)], 1 << 30, info);
-            ek[i] = k;
-            ea[i] = a;
-            eb[i] = b;
-            for (int c : {a, b}) {
+        // components of every edge (no link changes in this launch yet), into
+        // the hash table of components.  A thread resolves its edges together:
+        // one batch of loads per step of the link chains.
+        uint64_t k0[kTailEdgesPerThread];
+#pragma unroll
+        for (int q = 0; q < kTailEdgesPerThread; ++q) {
+            const int i = tid + q * kLocalThreads;
+            k0[q] = i < nE ? Et[i] : kNoEdge;
+        }
+#pragma unroll
+        for (int q = 0; q < kTailEdgesPerThread; ++q) {
+            ra[q] = rb[q] = -1;
+            if (k0[q] == kNoEdge) continue;
+            const uint32_t e = (uint32_t)k0[q];
+            ra[q] = comp0[e >> 1];
+            rb[q] = comp0[other_end(g, e)];
+        }
+        for (int it = 0; it < (1 << 24); ++it) {  // links form a forest
+            uint64_t wa[kTailEdgesPerThread], wb[kTailEdgesPerThread];
+#pragma unroll
+            for (int q = 0; q < kTailEdgesPerThread; ++q) {
+                wa[q] = ra[q] >= 0 ? cw[ra[q]] : 0;
+                wb[q] = rb[q] >= 0 ? cw[rb[q]] : 0;
+            }
+            bool more = false;
+#pragma unroll
+            for (int q = 0; q < kTailEdgesPerThread; ++q) {
+                if (ra[q] < 0) continue;
+                const int ya = (int)(uint32_t)wa[q], yb = (int)(uint32_t)wb[q];
+                if (ya != ra[q]) { ra[q] = ya; more = true; }
+                if (yb != rb[q]) { rb[q] = yb; more = true; }
+            }
+            if (!more) break;
+        }
+#pragma unroll
+        for (int q = 0; q < kTailEdgesPerThread; ++q) {
+            if (k0[q] == kNoEdge) continue;
+            ek[tid + q * kLocalThreads] = k0[q];
+            for (int c : {ra[q], rb[q]}) {
                 int h = hash_slot(c);
                 for (int it = 0; it < kTH; ++it) {
                     int old = atomicCAS(&hkey[h], -1, c);
@@ -604,83 +642,139 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
             }
         }
         __syncthreads();
+        // dense component numbers (a full table means more than kTN components)
         for (int h = tid; h < kTH; h += kLocalThreads) {
             int key = hkey[h];
             if (key < 0) continue;
             int idx = atomicAdd(&s_nodes, 1);
-            hval[h] = idx;
+            hval[h] = (uint16_t)idx;
             if (idx < kTN) rid[idx] = key;
         }
         __syncthreads();
         lds_mode = s_nodes <= kTN;
     }
     if (lds_mode) {
+        // Rounds in LDS.  Each thread keeps its edges (key, dense endpoints) in
+        // registers and loads what a pass needs for all of them at once.
         const int nN = s_nodes;
         auto lookup = [&](int key) {
             int h = hash_slot(key);
             for (int it = 0; it < kTH && hkey[h] != key; ++it) h = (h + 1) & (kTH - 1);
             return hval[h];
         };
-        for (int i = tid; i < nE; i += kLocalThreads) {
-            ea[i] = lookup(ea[i]);
-            eb[i] = lookup(eb[i]);
+        uint64_t mk[kTailEdgesPerThread];
+        int ma[kTailEdgesPerThread], mb[kTailEdgesPerThread];
+#pragma unroll
+        for (int q = 0; q < kTailEdgesPerThread; ++q) {
+            const int i = tid + q * kLocalThreads;
+            mk[q] = kNoEdge;
+            ma[q] = mb[q] = 0;
+            if (i >= nE) continue;
+            mk[q] = ek[i];
+            ma[q] = lookup(ra[q]);
+            mb[q] = lookup(rb[q]);
+            ea[i] = (uint16_t)ma[q];
+            eb[i] = (uint16_t)mb[q];
         }
-        for (int j = tid; j < nN; j += kLocalThreads) {
-            lab[j] = j;
-            hk[j] = j;
+        // components j = tid + k * kLocalThreads belong to this thread, which
+        // alone writes their label (kept in registers too)
+        constexpr int kTailNodesPerThread = kTN / kLocalThreads;
+        static_assert(kTailNodesPerThread * kLocalThreads == kTN, "nodes per thread");
+        int ml[kTailNodesPerThread];
+#pragma unroll
+        for (int k = 0; k < kTailNodesPerThread; ++k) {
+            const int j = tid + k * kLocalThreads;
+            ml[k] = j;
+            if (j >= nN) continue;
+            lab[j] = (uint16_t)j;
+            hk[j] = (uint16_t)j;
+            best[j] = kNoEdge;
         }
+        if (tid == 0) s_flag = 0;
+        int rr = 0;
         __syncthreads();
         for (int iter = 0; iter < kTN; ++iter) {
-            for (int j = tid; j < nN; j += kLocalThreads) best[j] = kNoEdge;
-            if (tid == 0) s_flag = 0;
-            __syncthreads();
-            for (int i = tid; i < nE; i += kLocalThreads) {
-                int ca = lab[ea[i]], cb = lab[eb[i]];
-                if (ca == cb) continue;
-                uint64_t k = ek[i];
-                if (best[ca] > k) atomicMin(&best[ca], (unsigned long long)k);
-                if (best[cb] > k) atomicMin(&best[cb], (unsigned long long)k);
+            // least live edge of every component (dead edges drop out for good)
+            int ca[kTailEdgesPerThread], cb[kTailEdgesPerThread];
+#pragma unroll
+            for (int q = 0; q < kTailEdgesPerThread; ++q) {
+                ca[q] = lab[ma[q]];
+                cb[q] = lab[mb[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < kTailEdgesPerThread; ++q) {
+                if (ca[q] == cb[q]) mk[q] = kNoEdge;
+                if (mk[q] == kNoEdge) continue;
+                if (best[ca[q]] > mk[q]) atomicMin(&best[ca[q]], (unsigned long long)mk[q]);
+                if (best[cb[q]] > mk[q]) atomicMin(&best[cb[q]], (unsigned long long)mk[q]);
             }
             __syncthreads();
-            for (int i = tid; i < nE; i += kLocalThreads) {
-                int ca = lab[ea[i]], cb = lab[eb[i]];
-                if (ca == cb) continue;
-                if (best[ca] == ek[i]) bidx[ca] = i;
-                if (best[cb] == ek[i]) bidx[cb] = i;
+            // the edge that is each component's minimum
+#pragma unroll
+            for (int q = 0; q < kTailEdgesPerThread; ++q) {
+                if (mk[q] == kNoEdge) continue;
+                const uint16_t i = (uint16_t)(tid + q * kLocalThreads);
+                if (best[ca[q]] == mk[q]) bidx[ca[q]] = i;
+                if (best[cb[q]] == mk[q]) bidx[cb[q]] = i;
             }
             __syncthreads();
-            for (int j = tid; j < nN; j += kLocalThreads) {
-                if (lab[j] != j || best[j] == kNoEdge) continue;
-                int i = bidx[j];
-                int ca = lab[ea[i]], cb = lab[eb[i]];
-                int other = ca == j ? cb : ca;
-                if (best[other] == best[j] && j < other) continue;  // mutual: smaller index stays
-                hk[j] = other;
-                intree[(uint32_t)ek[i]] = 1;
-                s_flag = 1;
+            // hooks (mutual choice: the smaller index stays the root); a hooked
+            // component never becomes a root again, so its bidx keeps the edge
+            bool hooked = false;
+#pragma unroll
+            for (int k = 0; k < kTailNodesPerThread; ++k) {
+                const int j = tid + k * kLocalThreads;
+                if (j >= nN || ml[k] != j) continue;
+                const uint64_t bj = best[j];
+                if (bj == kNoEdge) continue;
+                const int i = bidx[j];
+                const int xa = lab[ea[i]], xb = lab[eb[i]];
+                const int other = xa == j ? xb : xa;
+                if (best[other] == bj && j < other) continue;
+                hk[j] = (uint16_t)other;
+                hooked = true;
             }
+            if (hooked) s_flag = iter + 1;
             __syncthreads();
-            if (!s_flag) break;
+            if (s_flag != iter + 1) break;
             if (tid == 0 && K + iter < 64) flags[FLAG_BV + K + iter] = 1;
-            for (int j = tid; j < nN; j += kLocalThreads) {
-                int h = hk[j];
+#pragma unroll
+            for (int k = 0; k < kTailNodesPerThread; ++k) {
+                const int j = tid + k * kLocalThreads;
+                if (j >= nN) continue;
+                best[j] = kNoEdge;
+                const int h = hk[j];
                 if (h != j) {
-                    lab[j] = h;
-                    hk[j] = j;
+                    ml[k] = h;
+                    lab[j] = (uint16_t)h;
+                    hk[j] = (uint16_t)j;
                 }
             }
             __syncthreads();
-            for (int j = tid; j < nN; j += kLocalThreads) {
-                int r = lab[j];
-                for (int it = 0; it < kTN && lab[r] != r; ++it) r = lab[r];
-                lab[j] = r;
+            // pointer jumping until every component names its root (labels only
+            // move to ancestors; roots stay roots, so a new root label ends it)
+            for (int it = 0; it < kTN; ++it) {
+                int ll[kTailNodesPerThread];
+#pragma unroll
+                for (int k = 0; k < kTailNodesPerThread; ++k)
+                    ll[k] = tid + k * kLocalThreads < nN ? lab[ml[k]] : ml[k];
+                bool more = false;
+#pragma unroll
+                for (int k = 0; k < kTailNodesPerThread; ++k) {
+                    if (ll[k] == ml[k]) continue;
+                    ml[k] = ll[k];
+                    lab[tid + k * kLocalThreads] = (uint16_t)ll[k];
+                    more |= lab[ll[k]] != ll[k];
+                }
+                if (!wg_any(more, s_any, rr)) break;
             }
-            __syncthreads();
         }
-        // permanent links from every merged component to its new root
+        // tree edges and permanent links of every merged component
         for (int j = tid; j < nN; j += kLocalThreads) {
             int r = lab[j];
-            if (r != j) cw[rid[j]] = (uint64_t)(uint32_t)rid[r];
+            if (r == j) continue;
+            intree[(uint32_t)ek[bidx[j]]] = 1;
+            cw[rid[j]] = (uint64_t)(uint32_t)rid[r];
         }
         return;
     }
