@@ -1159,18 +1159,48 @@ struct Ranks {
 // Per pixel: parent, subtree size and edge weight of the child side of every
 // owned tree edge (sizes from the tour ranks; weights recomputed from the
 // image with the key formula), root data (tour length and node count, packed
-// for one scan), and the tree interval.
+// for one scan), the tree interval, and the pixel's heavy child.
 __global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
                          const float4 *__restrict__ img, Ranks rank_of,
                          const int32_t *__restrict__ tree, const uint8_t *__restrict__ adj,
                          const int32_t *__restrict__ plo, const int32_t *__restrict__ phi,
                          int32_t *__restrict__ parent, int32_t *__restrict__ size,
                          float *__restrict__ wgt, uint64_t *__restrict__ rootval,
-                         int32_t *__restrict__ lo, int32_t *__restrict__ hi) {
+                         int32_t *__restrict__ lo, int32_t *__restrict__ hi,
+                         int32_t *__restrict__ heavy_child) {
     int64_t v = gtid();
     if (v >= g.off[g.n_pairs]) return;
     const int pair = pair_of(g, (int)v);
     const int W = g.W[pair];
+    // heavy child: the child with the largest subtree (first in ascending pixel
+    // id on ties); w is a child when the tour enters v -> w before w -> v, and
+    // its subtree has (rank(v -> w) - rank(w -> v) + 1) / 2 nodes
+    {
+        const uint8_t a = adj[v];
+        const int order[4] = {3, 2, 0, 1};  // up, left, right, down: ascending pixel id
+        uint32_t rv[4], rw[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int d = order[i];
+            rv[i] = rw[i] = 0;
+            if (!((a >> d) & 1)) continue;
+            rv[i] = rank_of(4 * v + d);
+            rw[i] = rank_of(4 * nbr(v, d, W) + ((d + 2) & 3));
+        }
+        int best = -1;
+        uint32_t bs = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int d = order[i];
+            if (!((a >> d) & 1) || rv[i] <= rw[i]) continue;
+            const uint32_t sz = (rv[i] - rw[i] + 1) >> 1;
+            if (sz > bs) {
+                bs = sz;
+                best = (int)nbr(v, d, W);
+            }
+        }
+        heavy_child[v] = best;
+    }
     const float scale = ldexpf(1.0f, 2 * g.level);
     const float inv = 1.0f / (255.0f * scale);
     for (int dir = 0; dir < 2; ++dir) {
@@ -1205,27 +1235,6 @@ __global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
         lo[v] = 0;
         hi[v] = g.dmax[pair];
     }
-}
-
-// --- 5. heavy child ----------------------------------------------------------------
-
-__global__ void k_heavy(LevelGeom g, const uint8_t *__restrict__ adj,
-                        const int32_t *__restrict__ parent, const int32_t *__restrict__ size,
-                        int32_t *__restrict__ heavy_child) {
-    int64_t v = gtid();
-    if (v >= g.off[g.n_pairs]) return;
-    int W = g.W[pair_of(g, (int)v)];
-    uint8_t a = adj[v];
-    const int order[4] = {3, 2, 0, 1};  // up, left, right, down: ascending pixel id
-    int best = -1, bs = -1;
-    for (int i = 0; i < 4; ++i) {
-        int d = order[i];
-        if (!((a >> d) & 1)) continue;
-        int64_t w = nbr(v, d, W);
-        if (parent[w] != v) continue;
-        if (size[w] > bs) { bs = size[w]; best = (int)w; }
-    }
-    heavy_child[v] = best;
 }
 
 // --- 6. tour prefix sum: depth, light depth, preorder ---------------------------------
@@ -1608,10 +1617,9 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     k_rank_tail<<<1, kLocalThreads, 0, st>>>(rk_rounds, t.flags, t.ctr, t.At, t.slot, t.pr,
                                              f.info);
     Ranks rk{t.lw, t.pr};
+    // 5: parents, subtree sizes, heavy children
     k_parent<<<gn, kBlock, 0, st>>>(g, t.intree, im, rk, f.tree, t.adj, plo, phi, f.parent, t.size,
-                                    f.wgt, t.rootval, f.lo, f.hi);
-    // 5: heavy child
-    k_heavy<<<gn, kBlock, 0, st>>>(g, t.adj, f.parent, t.size, t.heavy_child);
+                                    f.wgt, t.rootval, f.lo, f.hi, t.heavy_child);
     // 6: tour offsets, tour values, prefix sum, per-node depth / light depth / preorder
     device_scan<uint64_t>(t.rootval, t.rootval, n, t.partial64, t.root_total, false, st);
     k_tour_scatter<<<gn, kBlock, 0, st>>>(g, t.adj, f.tree, f.parent, t.size, t.heavy_child, rk,
