@@ -133,6 +133,35 @@ def test_aggregate_validation(lib):
                            None) == -1  # width > 256
 
 
+def test_match_layer_validation(lib):
+    """hdp_match_layer rejects bad arguments on the host, before any launch."""
+    L = lib.lib()
+    H, W = 8, 8
+    n = H * W
+    buf, st, addr = _fake_forest(lib, n)
+    dummy = C.c_void_p(addr)
+    shapes = (lib.Shape * 1)(lib.Shape(H, W, 15))
+    p = lib.cost_params()
+    ws = L.hdp_aggregate_workspace_bytes(n, 10)
+    ok = dict(left=dummy, right=dummy, shapes=shapes, n_pairs=1, f=C.byref(st), width=10,
+              p=C.byref(p), sigma=C.c_float(0.1), agg=dummy, disp=dummy, ws=dummy, wsb=ws)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.hdp_match_layer(a["left"], a["right"], a["shapes"], a["n_pairs"], a["f"],
+                                 a["width"], a["p"], a["sigma"], a["agg"], a["disp"], a["ws"],
+                                 a["wsb"], None)
+
+    assert call(left=None) == -1
+    assert call(disp=None) == -1
+    assert call(sigma=C.c_float(0.0)) == -1
+    assert call(width=300) == -1
+    assert call(wsb=ws - 1) == -3
+    other = (lib.Shape * 1)(lib.Shape(H, W + 1, 15))  # forest does not match the batch
+    assert call(shapes=other) == -1
+    assert call(n_pairs=0) == -2
+
+
 def test_workspace_sizes_grow(lib):
     L = lib.lib()
     a = [L.hdp_build_tree_workspace_bytes(n) for n in (10, 1000, 100000)]
