@@ -109,20 +109,40 @@ constexpr int kPassSets = 3;  // flag sets: up, down (and a second up pass in th
 // s = exp(-w / sigma) and 1 - s^2, cleared tile flags and tickets of every
 // pass, and (block 0) the ticket layout of both passes from the phase table.
 __global__ void k_prologue(int64_t n, const float *__restrict__ rw,
-                           const int32_t *__restrict__ prow, double inv_sigma,
-                           double *__restrict__ s, double *__restrict__ om,
+                           const int32_t *__restrict__ prow, const uint8_t *__restrict__ heavy,
+                           double inv_sigma, double *__restrict__ s, double *__restrict__ om,
                            int32_t *__restrict__ flags, int64_t tiles, int32_t *__restrict__ ticket,
                            const int32_t *__restrict__ phase_ptr, const int32_t *__restrict__ info,
                            int rows, int32_t *__restrict__ plan, uint32_t *__restrict__ fill0,
-                           uint32_t *__restrict__ fill1, int64_t fill_words,
+                           uint32_t *__restrict__ fill1, int width,
                            uint64_t *__restrict__ maps, int64_t map_words) {
+    __shared__ int32_t sph[HDP_MAX_PHASES + 1];
     int64_t r = gtid();
-    // narrow rows: mark the up passes' outputs and the tile maps unwritten
-    for (int64_t i = r; i < fill_words; i += (int64_t)gridDim.x * blockDim.x) {
-        if (fill0) fill0[i] = kSentF;
-        if (fill1) fill1[i] = kSentF;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int K = info[HDP_INFO_N_PHASES];
+    K = K < 1 ? 1 : (K > HDP_MAX_PHASES ? HDP_MAX_PHASES : K);
+    if ((int)threadIdx.x <= K) sph[threadIdx.x] = phase_ptr[threadIdx.x];
+    __syncthreads();
+    // Narrow rows: mark unwritten the rows of the up passes' outputs that a
+    // tile polls (chain heads below a light edge, read by their parent's tile,
+    // and the last row of every up-pass tile, read for the next tile's carry),
+    // and the tile maps.
+    if (fill0 || fill1) {
+        for (int64_t i = r; i < n; i += stride) {
+            int lo = 0, hi = K - 1;  // phase of row i
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sph[mid] <= i) lo = mid; else hi = mid - 1;
+            }
+            const bool last = (sph[lo + 1] - i) % rows == 0;
+            if (!last && (prow[i] < 0 || heavy[i])) continue;
+            for (int c = 0; c < width; ++c) {
+                if (fill0) fill0[i * width + c] = kSentF;
+                if (fill1) fill1[i * width + c] = kSentF;
+            }
+        }
     }
-    for (int64_t i = r; i < map_words; i += (int64_t)gridDim.x * blockDim.x) maps[i] = kSentD;
+    for (int64_t i = r; i < map_words; i += stride) maps[i] = kSentD;
     if (r < n) {
         if (prow[r] < 0) {
             s[r] = 0.0;
@@ -139,9 +159,6 @@ __global__ void k_prologue(int64_t n, const float *__restrict__ rw,
     }
     if (r < kPassSets) ticket[r] = 0;
     if (r != 0) return;
-    int K = info[HDP_INFO_N_PHASES];
-    if (K < 1) K = 1;
-    if (K > HDP_MAX_PHASES) K = HDP_MAX_PHASES;
     plan[P_NPH] = K;
     plan[P_ROWS] = rows;
     for (int k = 0; k <= K; ++k) plan[P_ROW0 + k] = phase_ptr[k];
@@ -606,11 +623,6 @@ __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
             load_cols<CPT>(A.src + (int64_t)r * w + j0, v);
         }
         if (UP) {
-            if (A.fill) {
-#pragma unroll
-                for (int c = 0; c < CPT; ++c)
-                    reinterpret_cast<uint32_t *>(A.fill)[(int64_t)r * w + j0 + c] = kSentF;
-            }
             // heavy flag and coefficient of the next row, loaded together
             const int rn = r + 1 < r1 ? r + 1 : r;
             const bool hn = A.heavy[rn];
@@ -621,6 +633,13 @@ __global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
             x0[i] = A.lc[r];
             x1[i] = A.lc[A.n + r];
             x2[i] = A.lc[2 * A.n + r];
+            // rows of the down pass's output that its tiles poll: parents of a
+            // chain head (a light child) and the last row of every down tile
+            if (A.fill && (x0[i] >= 0 || (r - r0 + 1) % rows == 0)) {
+#pragma unroll
+                for (int c = 0; c < CPT; ++c)
+                    reinterpret_cast<uint32_t *>(A.fill)[(int64_t)r * w + j0 + c] = kSentF;
+            }
         } else {
             // heavy flag, coefficients and parent row, loaded together
             const bool hv = A.heavy[r];
@@ -983,13 +1002,12 @@ static void prologue(const hdp_forest &f, int width, float sigma, const AggWs &w
                      float *fill0 = nullptr, float *fill1 = nullptr) {
     int64_t m = f.n > w.tiles ? f.n : w.tiles;
     const bool narrow = width <= kSentMaxWidth;
-    int64_t fill_words = narrow ? f.n * width : 0;
     int64_t map_words = narrow ? (int64_t)kPassSets * w.tiles * (width + 1) : 0;
     k_prologue<<<grid_for(m), kBlock, 0, st>>>(
-        f.n, f.rw, f.prow, 1.0 / (double)sigma, w.s, w.om, w.flags, w.tiles, w.ticket,
+        f.n, f.rw, f.prow, f.heavy, 1.0 / (double)sigma, w.s, w.om, w.flags, w.tiles, w.ticket,
         f.phase_ptr, f.info, tile_geom(width).rows, w.plan,
         narrow ? reinterpret_cast<uint32_t *>(fill0) : nullptr,
-        narrow ? reinterpret_cast<uint32_t *>(fill1) : nullptr, fill_words,
+        narrow ? reinterpret_cast<uint32_t *>(fill1) : nullptr, width,
         reinterpret_cast<uint64_t *>(w.tPs), map_words);
 }
 

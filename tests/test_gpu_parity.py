@@ -346,6 +346,34 @@ def test_fused_match_layer_equals_three_steps(H, case):
     assert torch.equal(dispf, disp3), f"{case}: labels differ"
 
 
+def test_workspace_reuse_no_stale_rows(H):
+    """Only the rows a tile polls are marked unwritten before a pass; a call on
+    a workspace that holds another input's rows must still give the results of
+    a fresh workspace, bit for bit (HDP layer 0 and the full-range top layer)."""
+    shapes = [(96, 128, 63)]
+    S, L, w = 2, 3, 4
+    lvs = H.level_shapes(shapes, S, L)
+    runs = []
+    for seed in (11, 12):
+        p = scenes.small_scene(seed, *shapes[0])
+        Lr, Rr = rgb_dev(p.left), rgb_dev(p.right)
+        res = H.hdp_stereo(Lr, Rr, shapes, S=S, L=L, window=w)
+        lps, rps = H.pyramid_views(Lr, Rr, shapes, S, L)
+        runs.append((res, lps, rps))
+    shared = H.Workspace()
+    for level in (0, L):
+        for k in (0, 1):  # input 0 then input 1 on the shared workspace
+            res, lps, rps = runs[k]
+            aggs, disps = H.match_layer(lps[level], rps[level], lvs[level], res[level].forest,
+                                        ws=shared)
+        res, lps, rps = runs[1]
+        aggf, dispf = H.match_layer(lps[level], rps[level], lvs[level], res[level].forest,
+                                    ws=H.Workspace())
+        torch.cuda.synchronize()
+        assert torch.equal(aggs, aggf), f"layer {level}: stale rows in the aggregated volume"
+        assert torch.equal(disps, dispf), f"layer {level}: stale rows in the labels"
+
+
 @pytest.mark.parametrize("Hh,Ww,dmax", [(70, 90, 31), (45, 70, 127)])
 def test_aggregate_reproducible(H, Hh, Ww, dmax):
     """Two aggregations of the same cost give the same bits (narrow rows with
