@@ -258,22 +258,33 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     tD[i] = 0;
     __syncthreads();
     // keys of the owned right / down edges (and of the edges entering from the
-    // left / top neighbour tiles); an edge between different intervals is absent
+    // left / top neighbour tiles); an edge between different intervals is
+    // absent.  Every load is issued first (clamped to the pixel itself where a
+    // neighbour does not exist), then the edges are decided.
     uint32_t kr = kNoKey, kd = kNoKey;
     if (valid) {
-        int x = t.x0 + lx, y = t.y0 + ly;
-        float4 a = img[v];
+        const int x = t.x0 + lx, y = t.y0 + ly;
+        const bool hr = x + 1 < t.W, hd = y + 1 < t.H;
+        const bool hl = lx == 0 && x > 0, hu = ly == 0 && y > 0;
+        const int64_t vr = hr ? v + 1 : v, vd = hd ? v + t.W : v;
+        const int64_t vl = hl ? v - 1 : v, vu = hu ? v - t.W : v;
+        const float4 a = img[v], ar = img[vr], ad = img[vd], al = img[vl], au = img[vu];
+        bool sr = true, sd = true, sl = true, su = true;
         if (plo) {
-            int lo = plo[v], hi = phi[v];
+            const int lo = plo[v], hi = phi[v];
+            const int lor = plo[vr], hir = phi[vr], lod = plo[vd], hid = phi[vd];
+            const int lol = plo[vl], hil = phi[vl], lou = plo[vu], hiu = phi[vu];
             if (lo < 0 || hi < lo || hi > g.dmax[t.pair] || hi - lo + 1 > max_width)
                 atomicAdd(&info[HDP_INFO_BAD_INTERVAL], 1);
+            sr = lo == lor && hi == hir;
+            sd = lo == lod && hi == hid;
+            sl = lo == lol && hi == hil;
+            su = lo == lou && hi == hiu;
         }
-        if (x + 1 < t.W && same_interval(plo, phi, v, v + 1)) kr = edge_key(a, img[v + 1], scale);
-        if (y + 1 < t.H && same_interval(plo, phi, v, v + t.W)) kd = edge_key(a, img[v + t.W], scale);
-        if (lx == 0 && x > 0 && same_interval(plo, phi, v - 1, v))
-            kL[ly] = edge_key(img[v - 1], a, scale);
-        if (ly == 0 && y > 0 && same_interval(plo, phi, v - t.W, v))
-            kU[lx] = edge_key(img[v - t.W], a, scale);
+        if (hr && sr) kr = edge_key(a, ar, scale);
+        if (hd && sd) kd = edge_key(a, ad, scale);
+        if (hl && sl) kL[ly] = edge_key(al, a, scale);
+        if (hu && su) kU[lx] = edge_key(au, a, scale);
     }
     kR[i] = kr;
     kD[i] = kd;
