@@ -880,16 +880,20 @@ __global__ void k_set_tree(const int32_t *__restrict__ comp0, const int32_t *__r
                            int32_t *__restrict__ info) {
     int64_t v = gtid();
     if (v >= g.off[g.n_pairs]) return;
+    const PixelPos p = pixel_pos(g, (int)v);
+    // the four edge bits load together with the component chain
+    const uint8_t er = intree[2 * v], ed = intree[2 * v + 1];
+    const uint8_t el = intree[p.x > 0 ? 2 * (v - 1) : 2 * v];
+    const uint8_t eu = intree[p.y > 0 ? 2 * (v - p.W) + 1 : 2 * v];
     int x = comp0[v];
     int c = croot[x];
     int t = c >= 0 ? mnroot[c] : lmin[x];
     tree[v] = t;
-    PixelPos p = pixel_pos(g, (int)v);
     uint8_t a = 0;
-    if (intree[2 * v]) a |= 1;
-    if (intree[2 * v + 1]) a |= 2;
-    if (p.x > 0 && intree[2 * (v - 1)]) a |= 4;
-    if (p.y > 0 && intree[2 * (v - p.W) + 1]) a |= 8;
+    if (er) a |= 1;
+    if (ed) a |= 2;
+    if (p.x > 0 && el) a |= 4;
+    if (p.y > 0 && eu) a |= 8;
     if (t == v) a |= kRootBit;
     adj[v] = a;
 }
@@ -1171,9 +1175,8 @@ struct Ranks {
 // owned tree edge (sizes from the tour ranks; weights recomputed from the
 // image with the key formula), root data (tour length and node count, packed
 // for one scan), the tree interval, and the pixel's heavy child.
-__global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
-                         const float4 *__restrict__ img, Ranks rank_of,
-                         const int32_t *__restrict__ tree, const uint8_t *__restrict__ adj,
+__global__ void k_parent(LevelGeom g, const float4 *__restrict__ img, Ranks rank_of,
+                         const uint8_t *__restrict__ adj,
                          const int32_t *__restrict__ plo, const int32_t *__restrict__ phi,
                          int32_t *__restrict__ parent, int32_t *__restrict__ size,
                          float *__restrict__ wgt, uint64_t *__restrict__ rootval,
@@ -1183,28 +1186,50 @@ __global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
     if (v >= g.off[g.n_pairs]) return;
     const int pair = pair_of(g, (int)v);
     const int W = g.W[pair];
+    const float scale = ldexpf(1.0f, 2 * g.level);
+    const float inv = 1.0f / (255.0f * scale);
+    // tree-edge bits (1 right, 2 down, 4 left, 8 up; 16 root) and the ranks of
+    // both directed slots of every tree edge, each step one batch of loads
+    const uint8_t a = adj[v];
+    uint64_t wv[4], ww[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const bool e = (a >> d) & 1;
+        wv[d] = e ? rank_of.lw[4 * v + d] : 0;
+        ww[d] = e ? rank_of.lw[4 * nbr(v, d, W) + ((d + 2) & 3)] : 0;
+    }
+    uint32_t rv[4], rw[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const bool e = (a >> d) & 1;
+        rv[d] = e ? (uint32_t)wv[d] + (uint32_t)rank_of.pr[wv[d] >> 32] : 0;
+        rw[d] = e ? (uint32_t)ww[d] + (uint32_t)rank_of.pr[ww[d] >> 32] : 0;
+    }
+    // owned edges (right, down): the child side gets parent, subtree size, weight
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+        if (!((a >> dir) & 1)) continue;
+        const int64_t w = dir == 0 ? v + 1 : v + W;
+        int64_t child, par;
+        uint32_t sz;
+        if (rv[dir] > rw[dir]) { child = w; par = v; sz = (rv[dir] - rw[dir] + 1) >> 1; }
+        else { child = v; par = w; sz = (rw[dir] - rv[dir] + 1) >> 1; }
+        parent[child] = (int32_t)par;
+        size[child] = (int32_t)sz;
+        wgt[child] = (float)edge_key(img[v], img[w], scale) * inv;
+    }
     // heavy child: the child with the largest subtree (first in ascending pixel
     // id on ties); w is a child when the tour enters v -> w before w -> v, and
     // its subtree has (rank(v -> w) - rank(w -> v) + 1) / 2 nodes
     {
-        const uint8_t a = adj[v];
         const int order[4] = {3, 2, 0, 1};  // up, left, right, down: ascending pixel id
-        uint32_t rv[4], rw[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int d = order[i];
-            rv[i] = rw[i] = 0;
-            if (!((a >> d) & 1)) continue;
-            rv[i] = rank_of(4 * v + d);
-            rw[i] = rank_of(4 * nbr(v, d, W) + ((d + 2) & 3));
-        }
         int best = -1;
         uint32_t bs = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int d = order[i];
-            if (!((a >> d) & 1) || rv[i] <= rw[i]) continue;
-            const uint32_t sz = (rv[i] - rw[i] + 1) >> 1;
+            if (!((a >> d) & 1) || rv[d] <= rw[d]) continue;
+            const uint32_t sz = (rv[d] - rw[d] + 1) >> 1;
             if (sz > bs) {
                 bs = sz;
                 best = (int)nbr(v, d, W);
@@ -1212,28 +1237,19 @@ __global__ void k_parent(LevelGeom g, const uint8_t *__restrict__ intree,
         }
         heavy_child[v] = best;
     }
-    const float scale = ldexpf(1.0f, 2 * g.level);
-    const float inv = 1.0f / (255.0f * scale);
-    for (int dir = 0; dir < 2; ++dir) {
-        int64_t e = 2 * v + dir;
-        if (!intree[e]) continue;
-        int64_t w = dir == 0 ? v + 1 : v + W;
-        uint32_t rv = rank_of(4 * v + dir);
-        uint32_t rw = rank_of(4 * w + (dir + 2));
-        int64_t child, par;
-        uint32_t sz;
-        if (rv > rw) { child = w; par = v; sz = (rv - rw + 1) >> 1; }
-        else { child = v; par = w; sz = (rw - rv + 1) >> 1; }
-        parent[child] = (int32_t)par;
-        size[child] = (int32_t)sz;
-        wgt[child] = (float)edge_key(img[v], img[w], scale) * inv;
-    }
     uint64_t rvl = 0;
-    if (tree[v] == v) {
+    if (a & kRootBit) {
         parent[v] = -1;
         wgt[v] = 0.f;
-        uint8_t a = adj[v] & 15;
-        int32_t sz = a ? (int32_t)((rank_of(4 * v + first_dir(a)) + 1) >> 1) + 1 : 1;
+        const uint8_t t4 = a & 15;
+        int32_t sz = 1;
+        if (t4) {
+            const int fd = first_dir(t4);
+            uint32_t r0 = rv[0];
+#pragma unroll
+            for (int d = 1; d < 4; ++d) r0 = d == fd ? rv[d] : r0;
+            sz = (int32_t)((r0 + 1) >> 1) + 1;
+        }
         size[v] = sz;
         // low = tour length 2(sz-1), high = node count sz
         rvl = ((uint64_t)(uint32_t)sz << 32) | (uint32_t)(2 * (sz - 1));
@@ -1265,15 +1281,26 @@ __global__ void k_tour_scatter(LevelGeom g, const uint8_t *__restrict__ adj,
     const uint8_t a = adj[v] & 15;
     if (!a) return;
     const int W = g.W[pair_of(g, (int)v)];
+    // loads in three batches: the pixel's own data and slot words, then the
+    // root data and run-end ranks, then the stores
     const int64_t root = tree[v];
-    const uint32_t toff = (uint32_t)rootoff[root];
-    const int64_t tlen = 2 * (int64_t)(size[root] - 1);
     const int hv = heavy_child[v];
     const int pv = parent[v];
+    uint64_t wv[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) wv[d] = ((a >> d) & 1) ? rank_of.lw[4 * v + d] : 0;
+    const uint32_t toff = (uint32_t)rootoff[root];
+    const int64_t tlen = 2 * (int64_t)(size[root] - 1);
+    const int hp = pv >= 0 ? heavy_child[pv] : -1;
+    uint32_t rk[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+        rk[d] = ((a >> d) & 1) ? (uint32_t)wv[d] + (uint32_t)rank_of.pr[wv[d] >> 32] : 0;
+#pragma unroll
     for (int d = 0; d < 4; ++d) {
         if (!((a >> d) & 1)) continue;
         int64_t w = nbr(v, d, W);
-        int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rank_of(4 * v + d));
+        int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rk[d]);
         if (pos < toff || pos >= (int64_t)toff + tlen) {
             info[HDP_INFO_ERROR] = 2;
             continue;
@@ -1283,7 +1310,7 @@ __global__ void k_tour_scatter(LevelGeom g, const uint8_t *__restrict__ adj,
             uint64_t light = hv != w ? 1 : 0;
             val = (1ull << kDownShift) + (light << kLdShift) + 1ull;
         } else {  // up edge v -> parent w
-            uint64_t light = heavy_child[w] != v ? 1 : 0;
+            uint64_t light = hp != v ? 1 : 0;
             val = 0ull - (light << kLdShift) - 1ull;
         }
         tourval[pos] = val;
@@ -1629,8 +1656,8 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
                                              f.info);
     Ranks rk{t.lw, t.pr};
     // 5: parents, subtree sizes, heavy children
-    k_parent<<<gn, kBlock, 0, st>>>(g, t.intree, im, rk, f.tree, t.adj, plo, phi, f.parent, t.size,
-                                    f.wgt, t.rootval, f.lo, f.hi, t.heavy_child);
+    k_parent<<<gn, kBlock, 0, st>>>(g, im, rk, t.adj, plo, phi, f.parent, t.size, f.wgt,
+                                    t.rootval, f.lo, f.hi, t.heavy_child);
     // 6: tour offsets, tour values, prefix sum, per-node depth / light depth / preorder
     device_scan<uint64_t>(t.rootval, t.rootval, n, t.partial64, t.root_total, false, st);
     k_tour_scatter<<<gn, kBlock, 0, st>>>(g, t.adj, f.tree, f.parent, t.size, t.heavy_child, rk,
