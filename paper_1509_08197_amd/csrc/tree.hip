@@ -474,6 +474,26 @@ __device__ __forceinline__ int find_comp(const uint64_t *cw, int x, int cut, int
     return x;
 }
 
+// Roots of components x and y counting the hooks of rounds < cut, the two
+// link chains followed in lockstep (one batch of loads per step).
+__device__ __forceinline__ void find_comp2(const uint64_t *cw, int &x, int &y, int cut,
+                                           int32_t *info) {
+    bool dx = false, dy = false;
+    for (int it = 0; it < (1 << 24); ++it) {
+        const uint64_t wx = dx ? 0 : cw[x], wy = dy ? 0 : cw[y];
+        if (!dx) {
+            const int nx = (int)(uint32_t)wx, tag = (int)(wx >> 32);
+            if (nx == x || (tag != 0 && tag - 1 >= cut)) dx = true; else x = nx;
+        }
+        if (!dy) {
+            const int ny = (int)(uint32_t)wy, tag = (int)(wy >> 32);
+            if (ny == y || (tag != 0 && tag - 1 >= cut)) dy = true; else y = ny;
+        }
+        if (dx && dy) return;
+    }
+    info[HDP_INFO_ERROR] = 1;
+}
+
 __device__ __forceinline__ int other_end(const LevelGeom &g, uint32_t e) {
     int p = (int)(e >> 1);
     return (e & 1) ? p + g.W[pair_of(g, p)] : p + 1;
@@ -506,20 +526,26 @@ __global__ __launch_bounds__(kBlock) void k_gbv_minedge(
     int round, const int32_t *__restrict__ flags, const int32_t *__restrict__ ctr, LevelGeom g,
     uint64_t *__restrict__ E, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
     uint64_t *__restrict__ best, int32_t *__restrict__ info) {
-    if (ctr[CTR_E] <= kTE) return;  // small contracted graph: the tail alone
-    if (round > 0 && flags[FLAG_BV + round - 1] == 0) return;
-    const int nE = ctr[CTR_E];
+    const int nE = ctr[CTR_E];  // loaded together with the round's flag
+    const int more = round > 0 ? flags[FLAG_BV + round - 1] : 1;
+    if (nE <= kTE) return;  // small contracted graph: the tail alone
+    if (more == 0) return;
     for (int i = (int)gtid(); i < nE; i += gridDim.x * kBlock) {
         uint64_t k = E[i];
         if (k == kNoEdge) continue;
-        int a, b;
-        edge_comps<false>(g, k, comp0, cw, &a, &b, info);
+        const uint32_t e = (uint32_t)k;
+        const int a0 = comp0[e >> 1], b0 = comp0[other_end(g, e)];
+        int a = a0, b = b0;
+        find_comp2(cw, a, b, 1 << 30, info);
+        if (a != a0) st_relaxed(&cw[a0], (uint64_t)(uint32_t)a);  // shortcut (permanent link)
+        if (b != b0) st_relaxed(&cw[b0], (uint64_t)(uint32_t)b);
         if (a == b) {  // both ends in one component: never needed again
             E[i] = kNoEdge;
             continue;
         }
-        offer_min(best, a, k, best[a]);
-        offer_min(best, b, k, best[b]);
+        const uint64_t ba = best[a], bb = best[b];
+        offer_min(best, a, k, ba);
+        offer_min(best, b, k, bb);
     }
 }
 
@@ -528,19 +554,21 @@ __global__ __launch_bounds__(kBlock) void k_gbv_hook(
     const int32_t *__restrict__ R, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
     const uint64_t *__restrict__ best, uint64_t *__restrict__ best_next,
     uint8_t *__restrict__ intree, int32_t *__restrict__ info) {
-    if (ctr[CTR_E] <= kTE) return;
-    if (round > 0 && flags[FLAG_BV + round - 1] == 0) return;
-    const int nR = ctr[CTR_RALL];
+    const int nE = ctr[CTR_E], nR = ctr[CTR_RALL];  // loaded together with the flag
+    const int more = round > 0 ? flags[FLAG_BV + round - 1] : 1;
+    if (nE <= kTE) return;
+    if (more == 0) return;
     bool hooked = false;
     for (int j = (int)gtid(); j < nR; j += gridDim.x * kBlock) {
         int x = R[j];
-        if ((int)(uint32_t)cw[x] != x) continue;  // hooked in an earlier round
+        const uint64_t wx = cw[x];
+        const uint64_t b = best[x];
+        if ((int)(uint32_t)wx != x) continue;  // hooked in an earlier round
         best_next[x] = kNoEdge;
-        uint64_t b = best[x];
         if (b == kNoEdge) continue;  // no edge left: its tree is complete
         uint32_t e = (uint32_t)b;
-        int cp = find_comp<false>(cw, comp0[e >> 1], round, info);
-        int cq = find_comp<false>(cw, comp0[other_end(g, e)], round, info);
+        int cp = comp0[e >> 1], cq = comp0[other_end(g, e)];
+        find_comp2(cw, cp, cq, round, info);
         int other = cp == x ? cq : cp;
         if (best[other] == b && x < other) continue;  // mutual choice: the smaller id stays root
         st_relaxed(&cw[x], ((uint64_t)(round + 1) << 32) | (uint32_t)other);
@@ -555,8 +583,9 @@ __global__ __launch_bounds__(kBlock) void k_gbv_compact(
     int K, const int32_t *__restrict__ flags, int32_t *__restrict__ ctr, LevelGeom g,
     const uint64_t *__restrict__ E, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
     uint64_t *__restrict__ Et, int32_t *__restrict__ info) {
-    if (ctr[CTR_E] > kTE && flags[FLAG_BV + K - 1] == 0) return;
     const int nE = ctr[CTR_E];
+    const int more = flags[FLAG_BV + K - 1];
+    if (nE > kTE && more == 0) return;
     for (int i = (int)gtid(); i < nE; i += gridDim.x * kBlock) {
         uint64_t k = E[i];
         bool live = false;
@@ -1062,9 +1091,10 @@ __global__ __launch_bounds__(kBlock) void k_tour_link(const int32_t *__restrict_
 __global__ __launch_bounds__(kBlock) void k_rank_round(int round, int32_t *__restrict__ flags,
                                                        const int32_t *__restrict__ ctr,
                                                        uint64_t *__restrict__ pr) {
-    if (ctr[CTR_RUNS] <= kTA) return;  // short lists: the one-workgroup tail alone
-    if (round > 0 && flags[FLAG_RANK + round - 1] == 0) return;
-    const int nC = ctr[CTR_RUNS];
+    const int nC = ctr[CTR_RUNS];  // loaded together with the round's flag
+    const int prev = round > 0 ? flags[FLAG_RANK + round - 1] : 1;
+    if (nC <= kTA) return;  // short lists: the one-workgroup tail alone
+    if (prev == 0) return;
     bool more = false;
     for (int s = (int)gtid(); s < nC; s += gridDim.x * kBlock) {
         uint64_t P = ld_relaxed(&pr[s]);
@@ -1335,17 +1365,23 @@ __global__ void k_node_order(LevelGeom g, const uint8_t *__restrict__ adj,
     int64_t w = gtid();
     int32_t dep = 0, l = 0;
     if (w < g.off[g.n_pairs]) {
-        int64_t root = tree[w];
-        uint64_t ro = rootoff[root];
+        // loads in dependency batches: tree and parent; root data and the slot
+        // word of the edge parent -> w; its run end; the tour prefix sum there
+        const int64_t root = tree[w];
+        const int64_t p = parent[w];
+        const bool nonroot = root != w && p >= 0;
+        const int W = g.W[pair_of(g, (int)w)];
+        // direction of the edge p -> w (a one-pixel-wide image has vertical edges only)
+        const int d = W == 1 ? (w > p ? 1 : 3) : w == p + 1 ? 0 : w == p + W ? 1 : w == p - 1 ? 2 : 3;
+        const uint64_t ro = rootoff[root];
+        const int32_t szr = size[root];
+        const uint64_t lwv = nonroot ? rank_of.lw[4 * p + d] : 0;
         uint32_t toff = (uint32_t)ro, noff = (uint32_t)(ro >> 32);
         int32_t pre = (int32_t)noff;
-        if (root != w) {
-            int64_t p = parent[w];
-            int W = g.W[pair_of(g, (int)w)];
-            // direction of the edge p -> w (a one-pixel-wide image has vertical edges only)
-            int d = W == 1 ? (w > p ? 1 : 3) : w == p + 1 ? 0 : w == p + W ? 1 : w == p - 1 ? 2 : 3;
-            int64_t tlen = 2 * (int64_t)(size[root] - 1);
-            int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rank_of(4 * p + d));
+        if (nonroot) {
+            const uint32_t rk = (uint32_t)lwv + (uint32_t)rank_of.pr[lwv >> 32];
+            int64_t tlen = 2 * (int64_t)(szr - 1);
+            int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rk);
             if (pos < toff || pos >= (int64_t)toff + tlen) {
                 info[HDP_INFO_ERROR] = 3;
                 pre = 0;
@@ -1445,16 +1481,23 @@ __global__ void k_rows(LevelGeom g, const int32_t *__restrict__ node,
     rw[r] = wgt[v];
     rx[r] = (v - g.off[pair]) % W;
     rlh[r] = lo[v] | (hi[v] << 16);
-    prow[r] = p >= 0 ? row_of[p] : -1;
-    heavy[r] = (p >= 0 && heavy_child[p] == v) ? 1 : 0;
+    // rows of the parent and of every tree neighbour, loaded together
     const int order[4] = {3, 2, 0, 1};  // up, left, right, down: ascending pixel id
+    int64_t nw[4];
+    int rn[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) nw[i] = ((a >> order[i]) & 1) ? nbr(v, order[i], W) : -1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rn[i] = nw[i] >= 0 ? row_of[nw[i]] : -1;
+    const int hp = p >= 0 ? heavy_child[p] : -1;
+    const int rp = p >= 0 ? row_of[p] : -1;
+    prow[r] = rp;
+    heavy[r] = (p >= 0 && hp == v) ? 1 : 0;
     int k = 0;
+#pragma unroll
     for (int i = 0; i < 4; ++i) {
-        int d = order[i];
-        if (!((a >> d) & 1)) continue;
-        int64_t w = nbr(v, d, W);
-        if (w == p || w == hc) continue;  // parent or heavy child
-        if (k < 3) lc[(int64_t)k * n + r] = row_of[w];
+        if (nw[i] < 0 || nw[i] == p || nw[i] == hc) continue;  // parent or heavy child
+        if (k < 3) lc[(int64_t)k * n + r] = rn[i];
         ++k;
     }
     for (; k < 3; ++k) lc[(int64_t)k * n + r] = -1;
