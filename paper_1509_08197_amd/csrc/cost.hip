@@ -54,17 +54,19 @@ __global__ void k_wta_thread(LevelGeom g, const int32_t *__restrict__ node,
     int nl = b - a + 1 < width ? b - a + 1 : width;
     float best = row[0];
     int bj = 0;
+    // the loop runs over the whole row (its loads do not wait for the
+    // interval); columns past the interval are skipped
     if ((width & 1) == 0) {  // rows start 8-byte aligned: pairs of labels
         const float2 *row2 = reinterpret_cast<const float2 *>(row);
-        for (int h = 0; 2 * h < nl; ++h) {
+        for (int h = 0; 2 * h < width; ++h) {
             float2 x = row2[h];
-            if (x.x < best) { best = x.x; bj = 2 * h; }
+            if (2 * h < nl && x.x < best) { best = x.x; bj = 2 * h; }
             if (2 * h + 1 < nl && x.y < best) { best = x.y; bj = 2 * h + 1; }
         }
     } else {
-        for (int j = 1; j < nl; ++j) {
+        for (int j = 1; j < width; ++j) {
             float x = row[j];
-            if (x < best) { best = x; bj = j; }
+            if (j < nl && x < best) { best = x; bj = j; }
         }
     }
     disp[v] = a + bj;

@@ -246,6 +246,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     if (i == 0) {
         s_nE = 0;
         s_nR = 0;
+        s_bE = 0;
+        s_bR = 0;
         s_flag[0] = 0;
         s_flag[1] = 0;
         s_any[0] = 0;
@@ -414,9 +416,13 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
         wR = atomicAdd(&s_nR, __popcll(ma));
     }
     __syncthreads();
-    if (i == 0) {
-        s_bE = s_nE ? atomicAdd(&ctr[CTR_E], s_nE) : 0;
-        s_bR = s_nR ? atomicAdd(&ctr[CTR_RALL], s_nR) : 0;
+    if (i == 0 && (s_nE | s_nR)) {  // both reservations in one 64-bit atomic
+        static_assert(CTR_RALL == CTR_E + 1 && CTR_E % 2 == 0, "adjacent counters");
+        const unsigned long long old =
+            atomicAdd(reinterpret_cast<unsigned long long *>(&ctr[CTR_E]),
+                      (unsigned long long)(uint32_t)s_nE | ((unsigned long long)s_nR << 32));
+        s_bE = (int)(uint32_t)old;
+        s_bR = (int)(old >> 32);
     }
     __syncthreads();
     wE = __shfl(wE, 0, 64) + s_bE;
