@@ -58,11 +58,51 @@ __global__ void k_downsample(Views V, LevelGeom gi, LevelGeom go, int S) {
     const float4 *in = V.src[blockIdx.y];
     PixelPos P = pixel_pos(go, (int)Vx);
     int Wi = gi.W[P.pair], Hi = gi.H[P.pair], bi = gi.off[P.pair];
-    float3 m = square_mean(in, bi, Wi, Hi, P.x, P.y, S);
     int xr = P.x + 1 < P.W ? P.x + 1 : P.x;
     int xl = P.x > 0 ? P.x - 1 : P.x;
-    float3 a = xr == P.x ? m : square_mean(in, bi, Wi, Hi, xr, P.y, S);
-    float3 b = xl == P.x ? m : square_mean(in, bi, Wi, Hi, xl, P.y, S);
+    float3 m, a, b;
+    if (S == 2) {
+        // the 2 x 2 squares of the node and its row neighbours: all 12 child
+        // loads issued at once (clamped), then the means in the order of
+        // square_mean (row by row, left to right)
+        const int y0 = 2 * P.y, y1 = 2 * P.y + 1 < Hi ? 2 * P.y + 1 : 2 * P.y;
+        const bool hy = 2 * P.y + 1 < Hi;
+        int cx[6];
+        bool hx[3];
+        const int nx[3] = {xl, P.x, xr};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            cx[2 * k] = 2 * nx[k];
+            hx[k] = 2 * nx[k] + 1 < Wi;
+            cx[2 * k + 1] = hx[k] ? 2 * nx[k] + 1 : 2 * nx[k];
+        }
+        float4 c0[6], c1[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            c0[q] = in[bi + y0 * Wi + cx[q]];
+            c1[q] = in[bi + y1 * Wi + cx[q]];
+        }
+        float3 mm[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float r = c0[2 * k].x, gg = c0[2 * k].y, bb = c0[2 * k].z;
+            int cnt = 1;
+            if (hx[k]) { r += c0[2 * k + 1].x; gg += c0[2 * k + 1].y; bb += c0[2 * k + 1].z; ++cnt; }
+            if (hy) {
+                r += c1[2 * k].x; gg += c1[2 * k].y; bb += c1[2 * k].z; ++cnt;
+                if (hx[k]) { r += c1[2 * k + 1].x; gg += c1[2 * k + 1].y; bb += c1[2 * k + 1].z; ++cnt; }
+            }
+            const float inv = 1.0f / (float)cnt;  // 1, 1/2, 1/4: exact
+            mm[k] = make_float3(r * inv, gg * inv, bb * inv);
+        }
+        b = mm[0];
+        m = mm[1];
+        a = mm[2];
+    } else {
+        m = square_mean(in, bi, Wi, Hi, P.x, P.y, S);
+        a = xr == P.x ? m : square_mean(in, bi, Wi, Hi, xr, P.y, S);
+        b = xl == P.x ? m : square_mean(in, bi, Wi, Hi, xl, P.y, S);
+    }
     float sr = (a.x + a.y) + a.z;
     float sl = (b.x + b.y) + b.z;
     V.lev[blockIdx.y][Vx] = make_float4(m.x, m.y, m.z, sr - sl);

@@ -116,10 +116,22 @@ __global__ void k_count_hist(const int32_t *__restrict__ src, int64_t n, KeyFn k
     for (int k = threadIdx.x; k < NB; k += kBlock) h[k] = 0;
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * kScanTile;
-    for (int i = threadIdx.x; i < kScanTile; i += kBlock) {
-        int64_t e = base + i;
-        if (e < n) atomicAdd(&h[key_of(e, src[e])], 1);
+    // elements, then keys, each one batch of loads
+    int32_t xs[kScanPerThread];
+#pragma unroll
+    for (int q = 0; q < kScanPerThread; ++q) {
+        const int64_t e = base + q * kBlock + threadIdx.x;
+        xs[q] = e < n ? src[e] : 0;
     }
+    int ks[kScanPerThread];
+#pragma unroll
+    for (int q = 0; q < kScanPerThread; ++q) {
+        const int64_t e = base + q * kBlock + threadIdx.x;
+        ks[q] = e < n ? key_of(e, xs[q]) : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kScanPerThread; ++q)
+        if (ks[q] >= 0) atomicAdd(&h[ks[q]], 1);
     __syncthreads();
     for (int k = threadIdx.x; k < NB; k += kBlock) hist[(int64_t)k * ntiles + blockIdx.x] = h[k];
 }
@@ -138,11 +150,25 @@ __device__ __forceinline__ void count_scatter_tile(const int32_t *__restrict__ s
     }
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * kScanTile;
+    // every step's element and key loaded up front (two batches of loads)
+    int32_t xs[kScanPerThread];
+    int ks[kScanPerThread];
+#pragma unroll
+    for (int step = 0; step < kScanPerThread; ++step) {
+        const int64_t e = base + step * kBlock + threadIdx.x;
+        xs[step] = e < n ? src[e] : 0;
+    }
+#pragma unroll
+    for (int step = 0; step < kScanPerThread; ++step) {
+        const int64_t e = base + step * kBlock + threadIdx.x;
+        ks[step] = e < n ? key_of(e, xs[step]) : 0;
+    }
+#pragma unroll
     for (int step = 0; step < kScanPerThread; ++step) {
         int64_t e = base + step * kBlock + threadIdx.x;
         bool valid = e < n;
-        int32_t x = valid ? src[e] : 0;
-        int key = valid ? key_of(e, x) : 0;
+        int32_t x = xs[step];
+        int key = ks[step];
         uint64_t m = __ballot(valid);
         if (!valid) m = ~m;
 #pragma unroll

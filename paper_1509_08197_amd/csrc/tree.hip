@@ -628,8 +628,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
     __shared__ uint16_t lab[kTN], hk[kTN], bidx[kTN];
     __shared__ unsigned long long best[kTN];
     __shared__ int s_nodes, s_flag, s_any[3];
-    if (ctr[CTR_E] > kTE && flags[FLAG_BV + K - 1] == 0) return;
-    const int nE = ctr[CTR_ET];
+    const int nLive = ctr[CTR_E], nE = ctr[CTR_ET];  // loaded together with the flag
+    const int prev = flags[FLAG_BV + K - 1];
+    if (nLive > kTE && prev == 0) return;
     const int tid = threadIdx.x;
     bool lds_mode = nE <= kTE;
     int ra[kTailEdgesPerThread], rb[kTailEdgesPerThread];  // endpoint components (pixel ids)
@@ -1118,8 +1119,9 @@ __global__ __launch_bounds__(kBlock) void k_rank_compact(int K, const int32_t *_
                                                          int32_t *__restrict__ ctr,
                                                          const uint64_t *__restrict__ pr,
                                                          int32_t *__restrict__ At) {
-    if (K > 0 && ctr[CTR_RUNS] > kTA && flags[FLAG_RANK + K - 1] == 0) return;
-    const int nC = ctr[CTR_RUNS];
+    const int nC = ctr[CTR_RUNS];  // loaded together with the last round's flag
+    const int prev = K > 0 ? flags[FLAG_RANK + K - 1] : 1;
+    if (nC > kTA && prev == 0) return;
     for (int s = (int)gtid(); s < nC; s += gridDim.x * kBlock) {
         bool open = (int32_t)(pr[s] >> 32) >= 0;
         int pos = wave_append(open, &ctr[CTR_AT]);
@@ -1136,8 +1138,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_rank_tail(
     int32_t *__restrict__ info) {
     __shared__ unsigned long long L[kTA];
     __shared__ int s_more;
-    if (K > 0 && ctr[CTR_RUNS] > kTA && flags[FLAG_RANK + K - 1] == 0) return;
-    const int nA = ctr[CTR_AT];
+    const int nRuns = ctr[CTR_RUNS], nA = ctr[CTR_AT];  // loaded together with the flag
+    const int prev = K > 0 ? flags[FLAG_RANK + K - 1] : 1;
+    if (nRuns > kTA && prev == 0) return;
     const int tid = threadIdx.x;
     if (nA <= kTA) {
         for (int j = tid; j < nA; j += kLocalThreads) slot[At[j]] = j;
