@@ -1210,76 +1210,87 @@ struct Ranks {
     }
 };
 
-// Per pixel: parent, subtree size and edge weight of the child side of every
-// owned tree edge (sizes from the tour ranks; weights recomputed from the
-// image with the key formula), root data (tour length and node count, packed
-// for one scan), the tree interval, and the pixel's heavy child.
+// Node code of a pixel, packed so that the row-order kernels gather one 8-byte
+// record (code, edge weight) per row: bits 0-4 tree-edge bits and root bit,
+// 5-6 direction of the parent, 7 has a heavy child, 8-9 its direction,
+// 16-23 interval low label, 24-31 interval high label (labels are below 256).
+constexpr uint32_t kHasHeavy = 1u << 7;
+__device__ __forceinline__ int code_pdir(uint32_t c) { return (c & kRootBit) ? -1 : (int)(c >> 5) & 3; }
+__device__ __forceinline__ int code_hdir(uint32_t c) { return (c & kHasHeavy) ? (int)(c >> 8) & 3 : -1; }
+
+// Per pixel (all writes coalesced): its parent (the tree neighbour whose edge
+// toward it comes first on the tour), the weight of the edge to the parent
+// (recomputed from the image with the key formula), its heavy child, the tree
+// interval, the node record, and for a root its node count and the root data
+// (tour length and node count, packed for one scan).
 __global__ void k_parent(LevelGeom g, const float4 *__restrict__ img, Ranks rank_of,
                          const uint8_t *__restrict__ adj,
                          const int32_t *__restrict__ plo, const int32_t *__restrict__ phi,
                          int32_t *__restrict__ parent, int32_t *__restrict__ size,
                          float *__restrict__ wgt, uint64_t *__restrict__ rootval,
                          int32_t *__restrict__ lo, int32_t *__restrict__ hi,
-                         int32_t *__restrict__ heavy_child) {
+                         uint2 *__restrict__ nrec) {
     int64_t v = gtid();
     if (v >= g.off[g.n_pairs]) return;
     const int pair = pair_of(g, (int)v);
     const int W = g.W[pair];
     const float scale = ldexpf(1.0f, 2 * g.level);
     const float inv = 1.0f / (255.0f * scale);
-    // tree-edge bits (1 right, 2 down, 4 left, 8 up; 16 root) and the ranks of
-    // both directed slots of every tree edge, each step one batch of loads
+    // tree-edge bits (1 right, 2 down, 4 left, 8 up; 16 root), then in one
+    // batch the slot words of both directions of every tree edge, the colours
+    // of the pixel and its tree neighbours and the interval; then the run
+    // prefixes
     const uint8_t a = adj[v];
     uint64_t wv[4], ww[4];
+    float4 cw[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         const bool e = (a >> d) & 1;
+        const int64_t w = nbr(v, d, W);
         wv[d] = e ? rank_of.lw[4 * v + d] : 0;
-        ww[d] = e ? rank_of.lw[4 * nbr(v, d, W) + ((d + 2) & 3)] : 0;
+        ww[d] = e ? rank_of.lw[4 * w + ((d + 2) & 3)] : 0;
+        cw[d] = e ? img[w] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    uint32_t rv[4], rw[4];
+    const float4 cv = img[v];
+    const int l = plo ? plo[v] : 0;
+    const int h = plo ? phi[v] : g.dmax[pair];
+    uint32_t rv[4], rw[4], kw[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         const bool e = (a >> d) & 1;
         rv[d] = e ? (uint32_t)wv[d] + (uint32_t)rank_of.pr[wv[d] >> 32] : 0;
         rw[d] = e ? (uint32_t)ww[d] + (uint32_t)rank_of.pr[ww[d] >> 32] : 0;
+        // key of the edge to every tree neighbour, taken from its lower pixel
+        // id first as in the forest build (only the parent's is kept)
+        kw[d] = d >= 2 ? edge_key(cw[d], cv, scale) : edge_key(cv, cw[d], scale);
     }
-    // owned edges (right, down): the child side gets parent, subtree size, weight
+    // w is a child when the tour takes v -> w before w -> v (higher rank = earlier),
+    // with (rank(v -> w) - rank(w -> v) + 1) / 2 nodes in its subtree; the
+    // heavy child has the largest subtree (first in ascending pixel id on ties)
+    const int order[4] = {3, 2, 0, 1};  // up, left, right, down: ascending pixel id
+    int pd = -1, hd = -1;
+    uint32_t bs = 0;
 #pragma unroll
-    for (int dir = 0; dir < 2; ++dir) {
-        if (!((a >> dir) & 1)) continue;
-        const int64_t w = dir == 0 ? v + 1 : v + W;
-        int64_t child, par;
-        uint32_t sz;
-        if (rv[dir] > rw[dir]) { child = w; par = v; sz = (rv[dir] - rw[dir] + 1) >> 1; }
-        else { child = v; par = w; sz = (rw[dir] - rv[dir] + 1) >> 1; }
-        parent[child] = (int32_t)par;
-        size[child] = (int32_t)sz;
-        wgt[child] = (float)edge_key(img[v], img[w], scale) * inv;
-    }
-    // heavy child: the child with the largest subtree (first in ascending pixel
-    // id on ties); w is a child when the tour enters v -> w before w -> v, and
-    // its subtree has (rank(v -> w) - rank(w -> v) + 1) / 2 nodes
-    {
-        const int order[4] = {3, 2, 0, 1};  // up, left, right, down: ascending pixel id
-        int best = -1;
-        uint32_t bs = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int d = order[i];
-            if (!((a >> d) & 1) || rv[d] <= rw[d]) continue;
-            const uint32_t sz = (rv[d] - rw[d] + 1) >> 1;
-            if (sz > bs) {
-                bs = sz;
-                best = (int)nbr(v, d, W);
-            }
+    for (int i = 0; i < 4; ++i) {
+        const int d = order[i];
+        const bool e = (a >> d) & 1;
+        if (e && rv[d] < rw[d]) pd = d;
+        const uint32_t sz = e && rv[d] > rw[d] ? (rv[d] - rw[d] + 1) >> 1 : 0;
+        if (sz > bs) {
+            bs = sz;
+            hd = d;
         }
-        heavy_child[v] = best;
     }
+    int32_t par = -1;
+    float wt = 0.f;
     uint64_t rvl = 0;
-    if (a & kRootBit) {
-        parent[v] = -1;
-        wgt[v] = 0.f;
+    if (!(a & kRootBit)) {
+        uint32_t k = kw[0];
+#pragma unroll
+        for (int d = 1; d < 4; ++d) k = d == pd ? kw[d] : k;
+        par = (int32_t)nbr(v, pd, W);
+        wt = (float)k * inv;
+    } else {
         const uint8_t t4 = a & 15;
         int32_t sz = 1;
         if (t4) {
@@ -1293,14 +1304,15 @@ __global__ void k_parent(LevelGeom g, const float4 *__restrict__ img, Ranks rank
         // low = tour length 2(sz-1), high = node count sz
         rvl = ((uint64_t)(uint32_t)sz << 32) | (uint32_t)(2 * (sz - 1));
     }
+    parent[v] = par;
+    wgt[v] = wt;
     rootval[v] = rvl;
-    if (plo) {
-        lo[v] = plo[v];
-        hi[v] = phi[v];
-    } else {
-        lo[v] = 0;
-        hi[v] = g.dmax[pair];
-    }
+    lo[v] = l;
+    hi[v] = h;
+    uint32_t code = (uint32_t)a | ((uint32_t)(l & 255) << 16) | ((uint32_t)(h & 255) << 24);
+    if (pd >= 0) code |= (uint32_t)pd << 5;
+    if (hd >= 0) code |= kHasHeavy | ((uint32_t)hd << 8);
+    nrec[v] = make_uint2(code, __float_as_uint(wt));
 }
 
 // --- 6. tour prefix sum: depth, light depth, preorder ---------------------------------
@@ -1309,28 +1321,28 @@ constexpr int kDepthBits = 22;
 constexpr int kLdShift = 22;
 constexpr int kDownShift = 28;
 
-__global__ void k_tour_scatter(LevelGeom g, const uint8_t *__restrict__ adj,
-                               const int32_t *__restrict__ tree, const int32_t *__restrict__ parent,
-                               const int32_t *__restrict__ size,
-                               const int32_t *__restrict__ heavy_child,
+__global__ void k_tour_scatter(LevelGeom g, const uint2 *__restrict__ nrec,
+                               const int32_t *__restrict__ tree, const int32_t *__restrict__ size,
                                Ranks rank_of, const uint64_t *__restrict__ rootoff,
                                uint64_t *__restrict__ tourval, int32_t *__restrict__ info) {
     int64_t v = gtid();
     if (v >= g.off[g.n_pairs]) return;
-    const uint8_t a = adj[v] & 15;
+    const uint32_t c = nrec[v].x;
+    const uint8_t a = c & 15;
     if (!a) return;
     const int W = g.W[pair_of(g, (int)v)];
+    const int pd = code_pdir(c), hd = code_hdir(c);
     // loads in three batches: the pixel's own data and slot words, then the
-    // root data and run-end ranks, then the stores
+    // root data, the parent's code and the run-end ranks, then the stores
     const int64_t root = tree[v];
-    const int hv = heavy_child[v];
-    const int pv = parent[v];
     uint64_t wv[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) wv[d] = ((a >> d) & 1) ? rank_of.lw[4 * v + d] : 0;
     const uint32_t toff = (uint32_t)rootoff[root];
     const int64_t tlen = 2 * (int64_t)(size[root] - 1);
-    const int hp = pv >= 0 ? heavy_child[pv] : -1;
+    const uint32_t cp = pd >= 0 ? nrec[nbr(v, pd, W)].x : 0;
+    // v is its parent's heavy child when the parent's heavy direction points back at v
+    const bool vheavy = pd >= 0 && code_hdir(cp) == ((pd + 2) & 3);
     uint32_t rk[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d)
@@ -1338,18 +1350,17 @@ __global__ void k_tour_scatter(LevelGeom g, const uint8_t *__restrict__ adj,
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         if (!((a >> d) & 1)) continue;
-        int64_t w = nbr(v, d, W);
         int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rk[d]);
         if (pos < toff || pos >= (int64_t)toff + tlen) {
             info[HDP_INFO_ERROR] = 2;
             continue;
         }
         uint64_t val;
-        if (w != pv) {  // down edge v -> child w
-            uint64_t light = hv != w ? 1 : 0;
+        if (d != pd) {  // down edge v -> child
+            uint64_t light = d != hd ? 1 : 0;
             val = (1ull << kDownShift) + (light << kLdShift) + 1ull;
-        } else {  // up edge v -> parent w
-            uint64_t light = hp != v ? 1 : 0;
+        } else {  // up edge v -> parent
+            uint64_t light = vheavy ? 0 : 1;
             val = 0ull - (light << kLdShift) - 1ull;
         }
         tourval[pos] = val;
@@ -1365,8 +1376,8 @@ __device__ __forceinline__ void wave_max_to(int32_t *dst, int32_t x) {
     if ((threadIdx.x & 63) == 0) atomicMax(dst, x);
 }
 
-__global__ void k_node_order(LevelGeom g, const uint8_t *__restrict__ adj,
-                             const int32_t *__restrict__ tree, const int32_t *__restrict__ parent,
+__global__ void k_node_order(LevelGeom g, const uint2 *__restrict__ nrec,
+                             const int32_t *__restrict__ tree,
                              Ranks rank_of, const uint64_t *__restrict__ rootoff,
                              const int32_t *__restrict__ size, const uint64_t *__restrict__ tourscan,
                              int32_t *__restrict__ depth, int32_t *__restrict__ ld,
@@ -1374,14 +1385,14 @@ __global__ void k_node_order(LevelGeom g, const uint8_t *__restrict__ adj,
     int64_t w = gtid();
     int32_t dep = 0, l = 0;
     if (w < g.off[g.n_pairs]) {
-        // loads in dependency batches: tree and parent; root data and the slot
-        // word of the edge parent -> w; its run end; the tour prefix sum there
+        // loads in dependency batches: tree and node code; root data and the
+        // slot word of the edge parent -> w; its run end; the tour prefix sum there
         const int64_t root = tree[w];
-        const int64_t p = parent[w];
-        const bool nonroot = root != w && p >= 0;
+        const int pd = code_pdir(nrec[w].x);
+        const bool nonroot = pd >= 0;
         const int W = g.W[pair_of(g, (int)w)];
-        // direction of the edge p -> w (a one-pixel-wide image has vertical edges only)
-        const int d = W == 1 ? (w > p ? 1 : 3) : w == p + 1 ? 0 : w == p + W ? 1 : w == p - 1 ? 2 : 3;
+        const int64_t p = nonroot ? nbr(w, pd, W) : -1;
+        const int d = (pd + 2) & 3;  // direction of the edge p -> w
         const uint64_t ro = rootoff[root];
         const int32_t szr = size[root];
         const uint64_t lwv = nonroot ? rank_of.lw[4 * p + d] : 0;
@@ -1462,18 +1473,21 @@ __device__ __forceinline__ void finish_info(const int32_t *__restrict__ flags,
 
 // --- 7. rows of the volume layout ---------------------------------------------------
 
-// Per row r (coalesced writes) from its pixel v = node[r] (gathered reads;
-// consecutive rows are neighbouring pixels of a chain): parent row, heavy
-// flag, edge weight, the rows of up to three light children in ascending
-// pixel id, and the pixel's column and interval (read by the fused matching
-// pass instead of the pixel arrays).  Block 0 also writes the build statistics.
+// Per row r (coalesced writes) from its pixel v = node[r] (gathered reads:
+// the node record, then the rows of the tree neighbours; consecutive rows
+// are neighbouring pixels of a chain): parent row, heavy flag, edge weight,
+// the rows of up to three light children in ascending pixel id, and the
+// pixel's column and interval (read by the fused matching pass instead of the
+// pixel arrays).  A heavy child is the row right after its parent's: the rows
+// are the preorder split stably by light depth, and everything the preorder
+// visits between a node and its heavy child lies below a light edge, while a
+// light child cannot directly follow its parent (the parent's heavy child
+// comes right after the parent in the parent's class).  Block 0 also writes
+// the build statistics.
 __global__ void k_rows(LevelGeom g, const int32_t *__restrict__ node,
-                       const int32_t *__restrict__ row_of, const int32_t *__restrict__ parent,
-                       const float *__restrict__ wgt, const int32_t *__restrict__ heavy_child,
-                       const uint8_t *__restrict__ adj, const int32_t *__restrict__ lo,
-                       const int32_t *__restrict__ hi, int32_t *__restrict__ prow,
-                       uint8_t *__restrict__ heavy, int32_t *__restrict__ lc,
-                       float *__restrict__ rw, int32_t *__restrict__ rx,
+                       const int32_t *__restrict__ row_of, const uint2 *__restrict__ nrec,
+                       int32_t *__restrict__ prow, uint8_t *__restrict__ heavy,
+                       int32_t *__restrict__ lc, float *__restrict__ rw, int32_t *__restrict__ rx,
                        int32_t *__restrict__ rlh, const int32_t *__restrict__ flags,
                        const int32_t *__restrict__ ctr, int32_t *__restrict__ info, int width,
                        const uint64_t *__restrict__ root_total) {
@@ -1482,30 +1496,30 @@ __global__ void k_rows(LevelGeom g, const int32_t *__restrict__ node,
     if (blockIdx.x == 0 && threadIdx.x < 64) finish_info(flags, ctr, info, width, n, root_total);
     if (r >= n) return;
     const int v = node[r];
-    const int p = parent[v];
-    const uint8_t a = adj[v];
-    const int hc = heavy_child[v];
+    const uint2 rec = nrec[v];
+    const uint32_t c = rec.x;
     const int pair = pair_of(g, v);
     const int W = g.W[pair];
-    rw[r] = wgt[v];
-    rx[r] = (v - g.off[pair]) % W;
-    rlh[r] = lo[v] | (hi[v] << 16);
-    // rows of the parent and of every tree neighbour, loaded together
+    const int pd = code_pdir(c), hd = code_hdir(c);
+    // rows of every tree neighbour (the parent among them), loaded together
     const int order[4] = {3, 2, 0, 1};  // up, left, right, down: ascending pixel id
-    int64_t nw[4];
     int rn[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) nw[i] = ((a >> order[i]) & 1) ? nbr(v, order[i], W) : -1;
+    for (int i = 0; i < 4; ++i)
+        rn[i] = ((c >> order[i]) & 1) ? row_of[nbr(v, order[i], W)] : -1;
+    rw[r] = __uint_as_float(rec.y);
+    rx[r] = (v - g.off[pair]) % W;
+    rlh[r] = (int32_t)(((c >> 16) & 255) | (((c >> 24) & 255) << 16));
+    int rp = -1;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) rn[i] = nw[i] >= 0 ? row_of[nw[i]] : -1;
-    const int hp = p >= 0 ? heavy_child[p] : -1;
-    const int rp = p >= 0 ? row_of[p] : -1;
+    for (int i = 0; i < 4; ++i) rp = order[i] == pd ? rn[i] : rp;
     prow[r] = rp;
-    heavy[r] = (p >= 0 && hp == v) ? 1 : 0;
+    heavy[r] = (rp >= 0 && rp == r - 1) ? 1 : 0;
     int k = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        if (nw[i] < 0 || nw[i] == p || nw[i] == hc) continue;  // parent or heavy child
+        const int d = order[i];
+        if (!((c >> d) & 1) || d == pd || d == hd) continue;  // parent or heavy child
         if (k < 3) lc[(int64_t)k * n + r] = rn[i];
         ++k;
     }
@@ -1566,9 +1580,10 @@ struct Bump {
 
 struct TreeWs {
     int32_t *comp0, *lmin, *croot, *mnroot, *Rall, *At, *slot, *ctr, *flags;
-    int32_t *size, *heavy_child, *ld, *seq;
+    int32_t *size, *ld, *seq;
     uint64_t *cw, *best0, *best1, *E, *Et, *lw, *pr, *rootval, *tourval, *partial64, *root_total;
     uint32_t *C;
+    uint2 *nrec;
     uint8_t *intree, *adj;
     int32_t *partial32, *hist, *sortA, *sortB;
 };
@@ -1587,7 +1602,6 @@ static TreeWs carve_tree_ws(void *ws, int64_t n, size_t *bytes) {
     t.ctr = b.take<int32_t>(kCounters);
     t.flags = b.take<int32_t>(FLAG_WORDS);
     t.size = b.take<int32_t>(n);
-    t.heavy_child = b.take<int32_t>(n);
     t.ld = b.take<int32_t>(n);
     t.seq = b.take<int32_t>(n);
     t.cw = b.take<uint64_t>(n);
@@ -1598,6 +1612,7 @@ static TreeWs carve_tree_ws(void *ws, int64_t n, size_t *bytes) {
     t.lw = b.take<uint64_t>(4 * n);
     t.pr = b.take<uint64_t>(2 * n);
     t.C = b.take<uint32_t>(2 * n);
+    t.nrec = b.take<uint2>(n);
     t.rootval = b.take<uint64_t>(n);
     t.tourval = b.take<uint64_t>(2 * n);
     t.partial64 = b.take<uint64_t>(scan_tiles(2 * n) + 1);
@@ -1709,14 +1724,14 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     Ranks rk{t.lw, t.pr};
     // 5: parents, subtree sizes, heavy children
     k_parent<<<gn, kBlock, 0, st>>>(g, im, rk, t.adj, plo, phi, f.parent, t.size, f.wgt,
-                                    t.rootval, f.lo, f.hi, t.heavy_child);
+                                    t.rootval, f.lo, f.hi, t.nrec);
     // 6: tour offsets, tour values, prefix sum, per-node depth / light depth / preorder
     device_scan<uint64_t>(t.rootval, t.rootval, n, t.partial64, t.root_total, false, st);
-    k_tour_scatter<<<gn, kBlock, 0, st>>>(g, t.adj, f.tree, f.parent, t.size, t.heavy_child, rk,
+    k_tour_scatter<<<gn, kBlock, 0, st>>>(g, t.nrec, f.tree, t.size, rk,
                                           t.rootval, t.tourval, f.info);
     int64_t tour_len = 2 * n;  // upper bound; entries past the real length are never read
     device_scan<uint64_t>(t.tourval, t.tourval, tour_len, t.partial64, nullptr, true, st);
-    k_node_order<<<gn, kBlock, 0, st>>>(g, t.adj, f.tree, f.parent, rk, t.rootval, t.size,
+    k_node_order<<<gn, kBlock, 0, st>>>(g, t.nrec, f.tree, rk, t.rootval, t.size,
                                         t.tourval, f.depth, t.ld, t.seq, f.info);
     // 7: rows (stable partition of the preorder by light depth)
     {
@@ -1728,9 +1743,8 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         k_phase_rows<<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles, f.node,
                                                           f.row, f.phase_ptr, f.info);
     }
-    k_rows<<<gn, kBlock, 0, st>>>(g, f.node, f.row, f.parent, f.wgt, t.heavy_child, t.adj, f.lo,
-                                  f.hi, f.prow, f.heavy, f.lc, f.rw, f.rx, f.rlh, t.flags, t.ctr,
-                                  f.info, width, t.root_total);
+    k_rows<<<gn, kBlock, 0, st>>>(g, f.node, f.row, t.nrec, f.prow, f.heavy, f.lc, f.rw, f.rx,
+                                  f.rlh, t.flags, t.ctr, f.info, width, t.root_total);
 }
 
 // 8: level order (stable LSD radix sort of ids by depth) and level_ptr
