@@ -1223,15 +1223,12 @@ __device__ __forceinline__ int code_hdir(uint32_t c) { return (c & kHasHeavy) ? 
 // (recomputed from the image with the key formula), its heavy child, the tree
 // interval, the node record, and for a root its node count and the root data
 // (tour length and node count, packed for one scan).
-__global__ void k_parent(LevelGeom g, const float4 *__restrict__ img, Ranks rank_of,
-                         const uint8_t *__restrict__ adj,
-                         const int32_t *__restrict__ plo, const int32_t *__restrict__ phi,
-                         int32_t *__restrict__ parent, int32_t *__restrict__ size,
-                         float *__restrict__ wgt, uint64_t *__restrict__ rootval,
-                         int32_t *__restrict__ lo, int32_t *__restrict__ hi,
-                         uint2 *__restrict__ nrec) {
-    int64_t v = gtid();
-    if (v >= g.off[g.n_pairs]) return;
+__device__ __forceinline__ uint64_t parent_of_pixel(
+    int64_t v, const LevelGeom &g, const float4 *__restrict__ img, Ranks rank_of,
+    const uint8_t *__restrict__ adj, const int32_t *__restrict__ plo,
+    const int32_t *__restrict__ phi, int32_t *__restrict__ parent, int32_t *__restrict__ size,
+    float *__restrict__ wgt, uint64_t *__restrict__ rootval, int32_t *__restrict__ lo,
+    int32_t *__restrict__ hi, uint2 *__restrict__ nrec) {
     const int pair = pair_of(g, (int)v);
     const int W = g.W[pair];
     const float scale = ldexpf(1.0f, 2 * g.level);
@@ -1313,6 +1310,34 @@ __global__ void k_parent(LevelGeom g, const float4 *__restrict__ img, Ranks rank
     if (pd >= 0) code |= (uint32_t)pd << 5;
     if (hd >= 0) code |= kHasHeavy | ((uint32_t)hd << 8);
     nrec[v] = make_uint2(code, __float_as_uint(wt));
+    return rvl;
+}
+
+// One workgroup per scan tile of pixels, so the tile sums of the root data
+// (the first half of the root-data scan) come out of the same launch.
+constexpr int kParentThreads = kScanTile;
+__global__ __launch_bounds__(kParentThreads) void k_parent(
+    LevelGeom g, const float4 *__restrict__ img, Ranks rank_of, const uint8_t *__restrict__ adj,
+    const int32_t *__restrict__ plo, const int32_t *__restrict__ phi,
+    int32_t *__restrict__ parent, int32_t *__restrict__ size, float *__restrict__ wgt,
+    uint64_t *__restrict__ rootval, int32_t *__restrict__ lo, int32_t *__restrict__ hi,
+    uint2 *__restrict__ nrec, uint64_t *__restrict__ tile_sum) {
+    __shared__ uint64_t s_w[kParentThreads / 64];
+    const int64_t v = (int64_t)blockIdx.x * kParentThreads + threadIdx.x;
+    uint64_t x = 0;
+    if (v < g.off[g.n_pairs])
+        x = parent_of_pixel(v, g, img, rank_of, adj, plo, phi, parent, size, wgt, rootval, lo,
+                            hi, nrec);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int i = 0; i < kParentThreads / 64; ++i) t += s_w[i];
+        tile_sum[blockIdx.x] = t;
+    }
 }
 
 // --- 6. tour prefix sum: depth, light depth, preorder ---------------------------------
@@ -1324,7 +1349,8 @@ constexpr int kDownShift = 28;
 __global__ void k_tour_scatter(LevelGeom g, const uint2 *__restrict__ nrec,
                                const int32_t *__restrict__ tree, const int32_t *__restrict__ size,
                                Ranks rank_of, const uint64_t *__restrict__ rootoff,
-                               uint64_t *__restrict__ tourval, int32_t *__restrict__ info) {
+                               uint64_t *__restrict__ tourval, int32_t *__restrict__ posw,
+                               int32_t *__restrict__ info) {
     int64_t v = gtid();
     if (v >= g.off[g.n_pairs]) return;
     const uint32_t c = nrec[v].x;
@@ -1351,7 +1377,10 @@ __global__ void k_tour_scatter(LevelGeom g, const uint2 *__restrict__ nrec,
     for (int d = 0; d < 4; ++d) {
         if (!((a >> d) & 1)) continue;
         int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rk[d]);
-        if (pos < toff || pos >= (int64_t)toff + tlen) {
+        const bool bad = pos < toff || pos >= (int64_t)toff + tlen;
+        // the child of a down edge learns where its edge sits on the tour
+        if (d != pd) posw[nbr(v, d, W)] = bad ? -1 : (int32_t)pos;
+        if (bad) {
             info[HDP_INFO_ERROR] = 2;
             continue;
         }
@@ -1377,42 +1406,34 @@ __device__ __forceinline__ void wave_max_to(int32_t *dst, int32_t x) {
 }
 
 __global__ void k_node_order(LevelGeom g, const uint2 *__restrict__ nrec,
-                             const int32_t *__restrict__ tree,
-                             Ranks rank_of, const uint64_t *__restrict__ rootoff,
-                             const int32_t *__restrict__ size, const uint64_t *__restrict__ tourscan,
+                             const int32_t *__restrict__ tree, const int32_t *__restrict__ posw,
+                             const uint64_t *__restrict__ rootoff,
+                             const uint64_t *__restrict__ tourscan, int64_t tour_len,
                              int32_t *__restrict__ depth, int32_t *__restrict__ ld,
                              int32_t *__restrict__ seq, int32_t *__restrict__ info) {
     int64_t w = gtid();
     int32_t dep = 0, l = 0;
     if (w < g.off[g.n_pairs]) {
-        // loads in dependency batches: tree and node code; root data and the
-        // slot word of the edge parent -> w; its run end; the tour prefix sum there
+        // two batches of loads: tree, node code and the tour position of the
+        // edge parent -> w (left by the tour scatter); then the root data and
+        // the tour prefix sum at that position
         const int64_t root = tree[w];
-        const int pd = code_pdir(nrec[w].x);
-        const bool nonroot = pd >= 0;
-        const int W = g.W[pair_of(g, (int)w)];
-        const int64_t p = nonroot ? nbr(w, pd, W) : -1;
-        const int d = (pd + 2) & 3;  // direction of the edge p -> w
+        const bool nonroot = code_pdir(nrec[w].x) >= 0;
+        const int32_t pos = nonroot ? posw[w] : 0;
+        const bool ok = !nonroot || (pos >= 0 && pos < tour_len);
         const uint64_t ro = rootoff[root];
-        const int32_t szr = size[root];
-        const uint64_t lwv = nonroot ? rank_of.lw[4 * p + d] : 0;
-        uint32_t toff = (uint32_t)ro, noff = (uint32_t)(ro >> 32);
+        const uint64_t P = nonroot && ok ? tourscan[pos] : 0;
+        const uint32_t toff = (uint32_t)ro, noff = (uint32_t)(ro >> 32);
         int32_t pre = (int32_t)noff;
-        if (nonroot) {
-            const uint32_t rk = (uint32_t)lwv + (uint32_t)rank_of.pr[lwv >> 32];
-            int64_t tlen = 2 * (int64_t)(szr - 1);
-            int64_t pos = (int64_t)toff + (tlen - 1 - (int64_t)rk);
-            if (pos < toff || pos >= (int64_t)toff + tlen) {
-                info[HDP_INFO_ERROR] = 3;
-                pre = 0;
-            } else {
-                uint64_t P = tourscan[pos];
-                dep = (int32_t)(P & ((1ull << kDepthBits) - 1));
-                l = (int32_t)((P >> kLdShift) & 63);
-                uint64_t down = P >> kDownShift;
-                uint32_t tidx = noff - (toff >> 1);  // trees before this one
-                pre = (int32_t)(down + tidx);
-            }
+        if (!ok) {
+            info[HDP_INFO_ERROR] = 3;
+            pre = 0;
+        } else if (nonroot) {
+            dep = (int32_t)(P & ((1ull << kDepthBits) - 1));
+            l = (int32_t)((P >> kLdShift) & 63);
+            const uint64_t down = P >> kDownShift;
+            const uint32_t tidx = noff - (toff >> 1);  // trees before this one
+            pre = (int32_t)(down + tidx);
         }
         depth[w] = dep;
         ld[w] = l;
@@ -1580,7 +1601,7 @@ struct Bump {
 
 struct TreeWs {
     int32_t *comp0, *lmin, *croot, *mnroot, *Rall, *At, *slot, *ctr, *flags;
-    int32_t *size, *ld, *seq;
+    int32_t *size, *ld, *seq, *posw;
     uint64_t *cw, *best0, *best1, *E, *Et, *lw, *pr, *rootval, *tourval, *partial64, *root_total;
     uint32_t *C;
     uint2 *nrec;
@@ -1604,6 +1625,7 @@ static TreeWs carve_tree_ws(void *ws, int64_t n, size_t *bytes) {
     t.size = b.take<int32_t>(n);
     t.ld = b.take<int32_t>(n);
     t.seq = b.take<int32_t>(n);
+    t.posw = b.take<int32_t>(n);
     t.cw = b.take<uint64_t>(n);
     t.best0 = b.take<uint64_t>(n);
     t.best1 = b.take<uint64_t>(n);
@@ -1723,16 +1745,19 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
                                              f.info);
     Ranks rk{t.lw, t.pr};
     // 5: parents, subtree sizes, heavy children
-    k_parent<<<gn, kBlock, 0, st>>>(g, im, rk, t.adj, plo, phi, f.parent, t.size, f.wgt,
-                                    t.rootval, f.lo, f.hi, t.nrec);
-    // 6: tour offsets, tour values, prefix sum, per-node depth / light depth / preorder
-    device_scan<uint64_t>(t.rootval, t.rootval, n, t.partial64, t.root_total, false, st);
-    k_tour_scatter<<<gn, kBlock, 0, st>>>(g, t.nrec, f.tree, t.size, rk,
-                                          t.rootval, t.tourval, f.info);
+    const unsigned n_scan = (unsigned)(scan_tiles(n) < 1 ? 1 : scan_tiles(n));
+    k_parent<<<n_scan, kParentThreads, 0, st>>>(g, im, rk, t.adj, plo, phi, f.parent, t.size,
+                                                f.wgt, t.rootval, f.lo, f.hi, t.nrec, t.partial64);
+    // 6: tour offsets (the root-data scan, tile sums from k_parent), tour
+    // values, prefix sum, per-node depth / light depth / preorder
+    k_scan_apply<uint64_t><<<n_scan, kBlock, 0, st>>>(t.rootval, t.rootval, n, t.partial64,
+                                                       t.root_total, 0);
+    k_tour_scatter<<<gn, kBlock, 0, st>>>(g, t.nrec, f.tree, t.size, rk, t.rootval, t.tourval,
+                                          t.posw, f.info);
     int64_t tour_len = 2 * n;  // upper bound; entries past the real length are never read
     device_scan<uint64_t>(t.tourval, t.tourval, tour_len, t.partial64, nullptr, true, st);
-    k_node_order<<<gn, kBlock, 0, st>>>(g, t.nrec, f.tree, rk, t.rootval, t.size,
-                                        t.tourval, f.depth, t.ld, t.seq, f.info);
+    k_node_order<<<gn, kBlock, 0, st>>>(g, t.nrec, f.tree, t.posw, t.rootval, t.tourval, tour_len,
+                                        f.depth, t.ld, t.seq, f.info);
     // 7: rows (stable partition of the preorder by light depth)
     {
         int64_t ntiles = scan_tiles(n);
