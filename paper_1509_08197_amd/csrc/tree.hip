@@ -448,7 +448,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
             }
             best1[v] = kNoEdge;
             lmin[v] = hk[i];
-            croot[v] = -1;
+            // an active component keeps its slot in the active list here
+            // until the roots step overwrites it (the tail numbers by it)
+            croot[v] = act ? wR + __popcll(ma & lt) : -1;
             mnroot[v] = 0x7fffffff;
         }
     }
@@ -591,7 +593,7 @@ __global__ __launch_bounds__(kBlock) void k_gbv_compact(
     uint64_t *__restrict__ Et, int32_t *__restrict__ info) {
     const int nE = ctr[CTR_E];
     const int more = flags[FLAG_BV + K - 1];
-    if (nE > kTE && more == 0) return;
+    if (nE <= kTE || more == 0) return;  // tail alone (reads the live list) or done
     for (int i = (int)gtid(); i < nE; i += gridDim.x * kBlock) {
         uint64_t k = E[i];
         bool live = false;
@@ -606,9 +608,13 @@ __global__ __launch_bounds__(kBlock) void k_gbv_compact(
 }
 
 // The remaining rounds in one workgroup.  With at most kTE edges and kTN
-// components the contracted graph is loaded into LDS (components renumbered
-// through a hash table) and finished there; otherwise the rounds run on the
-// global arrays with device-coherent loads.
+// components the contracted graph is loaded into LDS and finished there;
+// otherwise the rounds run on the global arrays with device-coherent loads.
+// After full-grid rounds the surviving components are renumbered through a
+// hash table.  Without them (a contracted graph of at most kTE edges, the
+// tail alone) nothing has hooked yet: the live list itself is read, its edges
+// join distinct active components, and a component's dense number is its slot
+// in the active list (kept in croot by the local phase).
 
 __device__ __forceinline__ int hash_slot(int key) {
     return (int)(((uint32_t)key * 2654435761u) >> 20) & (kTH - 1);
@@ -616,7 +622,8 @@ __device__ __forceinline__ int hash_slot(int key) {
 
 __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
     int K, int32_t *__restrict__ flags, const int32_t *__restrict__ ctr, LevelGeom g,
-    uint64_t *__restrict__ Et, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
+    uint64_t *__restrict__ E, uint64_t *__restrict__ Ec, const int32_t *__restrict__ comp0,
+    uint64_t *__restrict__ cw, const int32_t *__restrict__ R, const int32_t *__restrict__ ridx,
     uint64_t *__restrict__ best0, uint64_t *__restrict__ best1, uint8_t *__restrict__ intree,
     int32_t *__restrict__ info) {
     static_assert(kTailEdgesPerThread * kLocalThreads == kTE, "edges per thread");
@@ -628,13 +635,44 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
     __shared__ uint16_t lab[kTN], hk[kTN], bidx[kTN];
     __shared__ unsigned long long best[kTN];
     __shared__ int s_nodes, s_flag, s_any[3];
-    const int nLive = ctr[CTR_E], nE = ctr[CTR_ET];  // loaded together with the flag
+    // counters loaded together with the flag
+    const int nLive = ctr[CTR_E], nComp = ctr[CTR_ET], nR = ctr[CTR_RALL];
     const int prev = flags[FLAG_BV + K - 1];
     if (nLive > kTE && prev == 0) return;
     const int tid = threadIdx.x;
+    const bool alone = nLive <= kTE;  // no full-grid round has run
+    uint64_t *const Et = alone ? E : Ec;
+    const int nE = alone ? nLive : nComp;
+    const bool direct = alone && nR <= kTN;
     bool lds_mode = nE <= kTE;
     int ra[kTailEdgesPerThread], rb[kTailEdgesPerThread];  // endpoint components (pixel ids)
-    if (lds_mode) {
+    uint64_t k0[kTailEdgesPerThread];
+    if (direct) {
+        if (tid == 0) {
+            s_nodes = nR;
+            s_any[0] = s_any[1] = s_any[2] = 0;
+        }
+#pragma unroll
+        for (int q = 0; q < kTailEdgesPerThread; ++q) {
+            const int i = tid + q * kLocalThreads;
+            k0[q] = i < nE ? Et[i] : kNoEdge;
+        }
+#pragma unroll
+        for (int q = 0; q < kTailEdgesPerThread; ++q) {
+            ra[q] = rb[q] = -1;
+            if (k0[q] == kNoEdge) continue;
+            const uint32_t e = (uint32_t)k0[q];
+            ra[q] = comp0[e >> 1];
+            rb[q] = comp0[other_end(g, e)];
+        }
+        for (int j = tid; j < nR; j += kLocalThreads) rid[j] = R[j];
+#pragma unroll
+        for (int q = 0; q < kTailEdgesPerThread; ++q) {
+            if (k0[q] == kNoEdge) continue;
+            ek[tid + q * kLocalThreads] = k0[q];
+        }
+        __syncthreads();
+    } else if (lds_mode) {
         for (int h = tid; h < kTH; h += kLocalThreads) hkey[h] = -1;
         if (tid == 0) {
             s_nodes = 0;
@@ -644,7 +682,6 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
         // components of every edge (no link changes in this launch yet), into
         // the hash table of components.  A thread resolves its edges together:
         // one batch of loads per step of the link chains.
-        uint64_t k0[kTailEdgesPerThread];
 #pragma unroll
         for (int q = 0; q < kTailEdgesPerThread; ++q) {
             const int i = tid + q * kLocalThreads;
@@ -717,9 +754,14 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
             mk[q] = kNoEdge;
             ma[q] = mb[q] = 0;
             if (i >= nE) continue;
-            mk[q] = ek[i];
-            ma[q] = lookup(ra[q]);
-            mb[q] = lookup(rb[q]);
+            mk[q] = k0[q];
+            ma[q] = direct ? ridx[ra[q]] : lookup(ra[q]);
+            mb[q] = direct ? ridx[rb[q]] : lookup(rb[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < kTailEdgesPerThread; ++q) {
+            const int i = tid + q * kLocalThreads;
+            if (i >= nE) continue;
             ea[i] = (uint16_t)ma[q];
             eb[i] = (uint16_t)mb[q];
         }
@@ -1722,8 +1764,9 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     }
     k_gbv_compact<<<g_edges, kBlock, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
                                               t.Et, f.info);
-    k_gbv_tail<<<1, kLocalThreads, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.Et, t.comp0, t.cw,
-                                            t.best0, t.best1, t.intree, f.info);
+    k_gbv_tail<<<1, kLocalThreads, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.E, t.Et, t.comp0,
+                                            t.cw, t.Rall, t.croot, t.best0, t.best1, t.intree,
+                                            f.info);
     // 3: roots
     k_gbv_final<<<g_roots, kBlock, 0, st>>>(t.ctr, t.Rall, t.cw, t.lmin, t.croot, t.mnroot, f.info);
     k_set_tree<<<gn, kBlock, 0, st>>>(t.comp0, t.croot, t.lmin, t.mnroot, t.intree, g, f.tree,
