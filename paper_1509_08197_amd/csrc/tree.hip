@@ -161,6 +161,28 @@ __device__ __forceinline__ int64_t tile_pixel(const TileInfo &t, int i) {
     return t.base + (int64_t)(t.y0 + (i >> 5)) * t.W + t.x0 + (i & (kTile - 1));
 }
 
+// Per-pixel kernels whose scattered stores land in per-tile ranges (tour
+// positions, preorder) walk the image tile by tile: four kBlock-thread blocks
+// per 32x32 tile, and the blocks of one tile on one XCD (blocks are dealt to
+// the 8 XCDs in turn), so each range is written through one L2.
+constexpr int kXcds = 8;
+static_assert(kTilePx == 4 * kBlock, "four blocks per tile");
+__device__ __forceinline__ int64_t tiled_pixel(const LevelGeom &g, int n_tiles, int *W,
+                                               bool *ok) {
+    const int b = blockIdx.x, xcd = b % kXcds, k = b / kXcds;
+    const int tile = (k >> 2) * kXcds + xcd;
+    *ok = false;
+    *W = 1;
+    if (tile >= n_tiles) return 0;
+    const TileInfo t = tile_info(g, tile);
+    const int ly = (k & 3) * (kBlock / kTile) + (int)threadIdx.x / kTile;
+    const int lx = (int)threadIdx.x & (kTile - 1);
+    *ok = lx < t.tw && ly < t.th;
+    *W = t.W;
+    return tile_pixel(t, ly * kTile + lx);
+}
+inline unsigned tiled_grid(int n_tiles) { return 4u * kXcds * (unsigned)((n_tiles + kXcds - 1) / kXcds); }
+
 // Integer edge key 4^level * max_c |dI_c| (exact: level images hold dyadic means).
 __device__ __forceinline__ uint32_t edge_key(float4 a, float4 b, float scale) {
     float m = fmaxf(fmaxf(fabsf(a.x - b.x), fabsf(a.y - b.y)), fabsf(a.z - b.z));
@@ -1392,13 +1414,14 @@ __global__ void k_tour_scatter(LevelGeom g, const uint2 *__restrict__ nrec,
                                const int32_t *__restrict__ tree, const int32_t *__restrict__ size,
                                Ranks rank_of, const uint64_t *__restrict__ rootoff,
                                uint64_t *__restrict__ tourval, int32_t *__restrict__ posw,
-                               int32_t *__restrict__ info) {
-    int64_t v = gtid();
-    if (v >= g.off[g.n_pairs]) return;
+                               int n_tiles, int32_t *__restrict__ info) {
+    bool ok;
+    int W;
+    const int64_t v = tiled_pixel(g, n_tiles, &W, &ok);
+    if (!ok) return;
     const uint32_t c = nrec[v].x;
     const uint8_t a = c & 15;
     if (!a) return;
-    const int W = g.W[pair_of(g, (int)v)];
     const int pd = code_pdir(c), hd = code_hdir(c);
     // loads in three batches: the pixel's own data and slot words, then the
     // root data, the parent's code and the run-end ranks, then the stores
@@ -1452,10 +1475,12 @@ __global__ void k_node_order(LevelGeom g, const uint2 *__restrict__ nrec,
                              const uint64_t *__restrict__ rootoff,
                              const uint64_t *__restrict__ tourscan, int64_t tour_len,
                              int32_t *__restrict__ depth, int32_t *__restrict__ ld,
-                             int32_t *__restrict__ seq, int32_t *__restrict__ info) {
-    int64_t w = gtid();
+                             int32_t *__restrict__ seq, int n_tiles, int32_t *__restrict__ info) {
+    bool inside;
+    int Wt;
+    const int64_t w = tiled_pixel(g, n_tiles, &Wt, &inside);
     int32_t dep = 0, l = 0;
-    if (w < g.off[g.n_pairs]) {
+    if (inside) {
         // two batches of loads: tree, node code and the tour position of the
         // edge parent -> w (left by the tour scatter); then the root data and
         // the tour prefix sum at that position
@@ -1795,12 +1820,13 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     // values, prefix sum, per-node depth / light depth / preorder
     k_scan_apply<uint64_t><<<n_scan, kBlock, 0, st>>>(t.rootval, t.rootval, n, t.partial64,
                                                        t.root_total, 0);
-    k_tour_scatter<<<gn, kBlock, 0, st>>>(g, t.nrec, f.tree, t.size, rk, t.rootval, t.tourval,
-                                          t.posw, f.info);
+    k_tour_scatter<<<tiled_grid((int)n_tiles), kBlock, 0, st>>>(
+        g, t.nrec, f.tree, t.size, rk, t.rootval, t.tourval, t.posw, (int)n_tiles, f.info);
     int64_t tour_len = 2 * n;  // upper bound; entries past the real length are never read
     device_scan<uint64_t>(t.tourval, t.tourval, tour_len, t.partial64, nullptr, true, st);
-    k_node_order<<<gn, kBlock, 0, st>>>(g, t.nrec, f.tree, t.posw, t.rootval, t.tourval, tour_len,
-                                        f.depth, t.ld, t.seq, f.info);
+    k_node_order<<<tiled_grid((int)n_tiles), kBlock, 0, st>>>(
+        g, t.nrec, f.tree, t.posw, t.rootval, t.tourval, tour_len, f.depth, t.ld, t.seq,
+        (int)n_tiles, f.info);
     // 7: rows (stable partition of the preorder by light depth)
     {
         int64_t ntiles = scan_tiles(n);
