@@ -51,6 +51,7 @@ constexpr int kRankGridRounds = 8;
 // hash slots; endpoints and component state are 16-bit indices) and tour
 // ranking (list entries).
 constexpr int kTE = 6144, kTN = 3072, kTH = 4096;
+constexpr int64_t kTopAloneBorderPx = 2 * kTE / 3;
 constexpr int kTailEdgesPerThread = kTE / 1024;
 constexpr int kTA = 8192;
 // A contracted graph of at most kTE live edges, or a contracted tour list of
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_gbv_compact(
     const uint64_t *__restrict__ E, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
     uint64_t *__restrict__ Et, int32_t *__restrict__ info) {
     const int nE = ctr[CTR_E];
-    const int more = flags[FLAG_BV + K - 1];
+    const int more = K > 0 ? flags[FLAG_BV + K - 1] : 1;
     if (nE <= kTE || more == 0) return;  // tail alone (reads the live list) or done
     for (int i = (int)gtid(); i < nE; i += gridDim.x * kBlock) {
         uint64_t k = E[i];
@@ -659,7 +660,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
     __shared__ int s_nodes, s_flag, s_any[3];
     // counters loaded together with the flag
     const int nLive = ctr[CTR_E], nComp = ctr[CTR_ET], nR = ctr[CTR_RALL];
-    const int prev = flags[FLAG_BV + K - 1];
+    const int prev = K > 0 ? flags[FLAG_BV + K - 1] : 1;
     if (nLive > kTE && prev == 0) return;
     const int tid = threadIdx.x;
     const bool alone = nLive <= kTE;  // no full-grid round has run
@@ -1779,6 +1780,11 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     int bv_rounds = ceil_log2(border_px) + 1;
     if (bv_rounds > kBvGridRounds) bv_rounds = kBvGridRounds;
     if (bv_rounds < 1) bv_rounds = 1;
+    // A layer without intervals (one spanning tree per pair) with few tile-border
+    // pixels leaves a contracted graph that the one-workgroup tail takes whole
+    // (about 1.5 live edges per border pixel; in LDS when it fits, else in the
+    // tail's global-memory mode): no full-grid rounds are launched.
+    if (!plo && border_px <= kTopAloneBorderPx) bv_rounds = 0;
     for (int r = 0; r < bv_rounds; ++r) {
         uint64_t *bc = (r & 1) ? t.best1 : t.best0, *bn = (r & 1) ? t.best0 : t.best1;
         if (r > 0)  // round 0's minimum edges come from the tile-local phase

@@ -171,6 +171,29 @@ def test_mst_bit_exact(H, orc, Hh, Ww, seed):
     assert F["info"][2] == 1  # one tree
 
 
+def test_mst_top_layer_tail_global_mode(H, orc):
+    # A layer without intervals and with few tile-border pixels launches no
+    # full-grid rounds.  Here every pixel takes the colour of its distance to
+    # the nearest 32-pixel tile border, so pixels facing each other across a
+    # border match and most border pixels wait on their crossing edge in the
+    # tile-local phase: more live edges remain than the LDS tail holds, and the
+    # tail finishes the forest in its global-memory mode.
+    Hh, Ww = 160, 192
+    yy, xx = np.mgrid[0:Hh, 0:Ww]
+    dx = np.minimum(xx % 32, 31 - xx % 32)
+    dy = np.minimum(yy % 32, 31 - yy % 32)
+    base = np.random.default_rng(5).integers(0, 256, (16, 16, 3), dtype=np.uint8)
+    img = np.ascontiguousarray(base[dy, dx])
+    lv = H.pyramid(rgb_dev(img), [(Hh, Ww, 15)], 2, 0)
+    f = H.build_tree(lv[0], [(Hh, Ww, 15)], 0)
+    F = forest_np(f)
+    key = orc.edge_keys(img.astype(np.float64), 0)
+    in_tree, _, _, _ = orc.kruskal(Hh, Ww, key)
+    ref = orc.root_forest(Hh, Ww, in_tree, key, 0)
+    check_forest(F, ref, Hh * Ww, "MST tile-mirrored 160x192")
+    assert F["info"][H.INFO["live_edges"]] > 6144, F["info"][H.INFO["live_edges"]]
+
+
 @pytest.mark.parametrize("level", [1, 2, 3])
 def test_mst_upper_levels_bit_exact(H, orc, level):
     pair = scenes.small_scene(11, 97, 131, 31)
