@@ -547,8 +547,12 @@ __device__ __forceinline__ bool poll_cols(const float *p, float *v, int32_t *err
 
 // FUSE: the up pass computes the cost of its rows (eq. E) instead of reading a
 // cost volume, and the down pass reduces every row to its winning label.
+// The down pass of the default narrow schedule (two labels per thread, four
+// rows per group) is held to 96 VGPRs: five waves per SIMD instead of four.
 template <bool UP, int CPT, int kRPG, bool FUSE>
-__global__ void __launch_bounds__(kBlock) k_pass_s(PassArgs A) {
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu((!UP && CPT == 2 && kRPG == 4) ? 5 : 1)))
+    k_pass_s(PassArgs A) {
     constexpr bool kWta = FUSE && !UP;
     __shared__ double sP[kBlock];
     __shared__ double sX[kBlock * CPT];
