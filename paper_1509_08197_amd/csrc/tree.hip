@@ -663,7 +663,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
     const int prev = K > 0 ? flags[FLAG_BV + K - 1] : 1;
     if (nLive > kTE && prev == 0) return;
     const int tid = threadIdx.x;
-    const bool alone = nLive <= kTE;  // no full-grid round has run
+    const bool alone = K == 0 || nLive <= kTE;  // no full-grid round has run
     uint64_t *const Et = alone ? E : Ec;
     const int nE = alone ? nLive : nComp;
     const bool direct = alone && nR <= kTN;
@@ -1196,7 +1196,9 @@ __global__ __launch_bounds__(kBlock) void k_rank_compact(int K, const int32_t *_
 
 // The unfinished entries in one workgroup: renumbered into LDS (entries that
 // point at a finished entry absorb its rank) and jumped there; a larger set
-// is jumped on the global array with device-coherent loads.
+// is jumped on the global array with device-coherent loads.  A list short
+// enough that no full-grid round ran is jumped in LDS as it stands (entry j
+// at LDS slot j, no compaction or renumbering).
 __global__ __launch_bounds__(kLocalThreads) void k_rank_tail(
     int K, int32_t *__restrict__ flags, const int32_t *__restrict__ ctr,
     const int32_t *__restrict__ At, int32_t *__restrict__ slot, uint64_t *__restrict__ pr,
@@ -1207,6 +1209,31 @@ __global__ __launch_bounds__(kLocalThreads) void k_rank_tail(
     const int prev = K > 0 ? flags[FLAG_RANK + K - 1] : 1;
     if (nRuns > kTA && prev == 0) return;
     const int tid = threadIdx.x;
+    if (nRuns <= kTA) {
+        for (int j = tid; j < nRuns; j += kLocalThreads) L[j] = pr[j];
+        for (int r = K; r < 64; ++r) {
+            if (tid == 0) s_more = 0;
+            __syncthreads();
+            bool more = false;
+            for (int j = tid; j < nRuns; j += kLocalThreads) {
+                unsigned long long a = L[j];
+                int nx = (int32_t)(a >> 32);
+                if (nx < 0) continue;
+                unsigned long long b = L[nx];
+                L[j] = (b & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)a + (uint32_t)b);
+                more |= (int32_t)(b >> 32) >= 0;
+            }
+            if (more) s_more = 1;
+            __syncthreads();
+            int any = s_more;
+            __syncthreads();  // every thread has read s_more before it is cleared
+            if (!any) break;
+            if (tid == 0) flags[FLAG_RANK + r] = 1;
+        }
+        for (int j = tid; j < nRuns; j += kLocalThreads)
+            pr[j] = (0xFFFFFFFFull << 32) | (uint32_t)L[j];
+        return;
+    }
     if (nA <= kTA) {
         for (int j = tid; j < nA; j += kLocalThreads) slot[At[j]] = j;
         wg_sync();
@@ -1793,7 +1820,8 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         k_gbv_hook<<<g_roots, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Rall, t.comp0, t.cw, bc, bn,
                                                t.intree, f.info);
     }
-    k_gbv_compact<<<g_edges, kBlock, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
+    if (bv_rounds > 0)  // without rounds every listed edge is live: the tail reads the list
+        k_gbv_compact<<<g_edges, kBlock, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
                                               t.Et, f.info);
     k_gbv_tail<<<1, kLocalThreads, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.E, t.Et, t.comp0,
                                             t.cw, t.Rall, t.croot, t.best0, t.best1, t.intree,
@@ -1814,7 +1842,8 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     if (!plo && runs_bound <= kTA) rk_rounds = 0;
     for (int r = 0; r < rk_rounds; ++r)
         k_rank_round<<<g_edges, kBlock, 0, st>>>(r, t.flags, t.ctr, t.pr);
-    k_rank_compact<<<g_edges, kBlock, 0, st>>>(rk_rounds, t.flags, t.ctr, t.pr, t.At);
+    if (rk_rounds > 0)  // without rounds the tail reads the whole list itself
+        k_rank_compact<<<g_edges, kBlock, 0, st>>>(rk_rounds, t.flags, t.ctr, t.pr, t.At);
     k_rank_tail<<<1, kLocalThreads, 0, st>>>(rk_rounds, t.flags, t.ctr, t.At, t.slot, t.pr,
                                              f.info);
     Ranks rk{t.lw, t.pr};
