@@ -47,13 +47,21 @@ __device__ __forceinline__ T block_excl_scan(T x, T *total) {
     return base + inc - x;
 }
 
-template <typename T>
-__global__ void k_scan_reduce(const T *__restrict__ in, int64_t n, T *__restrict__ partial) {
+// Scan inputs may be stored narrower than the sums: wide(x) gives the value
+// of a stored element (identity by default).
+struct WidenSame {
+    template <typename X>
+    __device__ X operator()(X x) const { return x; }
+};
+
+template <typename T, typename TIn = T, typename Widen = WidenSame>
+__global__ void k_scan_reduce(const TIn *__restrict__ in, int64_t n, T *__restrict__ partial,
+                              Widen wide = Widen()) {
     int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
     T s = 0;
 #pragma unroll
     for (int i = 0; i < kScanPerThread; ++i)
-        if (base + i < n) s += in[base + i];
+        if (base + i < n) s += (T)wide(in[base + i]);
     T tot;
     block_excl_scan(s, &tot);
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
@@ -62,9 +70,10 @@ __global__ void k_scan_reduce(const T *__restrict__ in, int64_t n, T *__restrict
 // Scan of one tile; the tile's offset is the sum of the partial sums of all
 // preceding tiles, reduced by the whole workgroup (no serial pass over the
 // partials).
-template <typename T>
-__global__ void k_scan_apply(const T *__restrict__ in, T *__restrict__ out, int64_t n,
-                             const T *__restrict__ partial, T *__restrict__ grand, int inclusive) {
+template <typename T, typename TIn = T, typename Widen = WidenSame>
+__global__ void k_scan_apply(const TIn *__restrict__ in, T *__restrict__ out, int64_t n,
+                             const T *__restrict__ partial, T *__restrict__ grand, int inclusive,
+                             Widen wide = Widen()) {
     const int64_t tile = blockIdx.x;
     T pre = 0;
     for (int64_t j = threadIdx.x; j < tile; j += kBlock) pre += partial[j];
@@ -75,7 +84,7 @@ __global__ void k_scan_apply(const T *__restrict__ in, T *__restrict__ out, int6
     T s = 0;
 #pragma unroll
     for (int i = 0; i < kScanPerThread; ++i) {
-        v[i] = base + i < n ? in[base + i] : (T)0;
+        v[i] = base + i < n ? (T)wide(in[base + i]) : (T)0;
         s += v[i];
     }
     T tot;
@@ -94,13 +103,14 @@ inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 // out[i] = sum of in[0..i-1] (exclusive) or in[0..i] (inclusive); in == out allowed.
 // partial: scratch of scan_tiles(n) elements; grand (device, may be NULL) = total.
 // Two launches: per-tile sums, then every tile adds the sums before it.
-template <typename T>
-inline void device_scan(const T *in, T *out, int64_t n, T *partial, T *grand, bool inclusive,
-                        hipStream_t st) {
+template <typename T, typename TIn = T, typename Widen = WidenSame>
+inline void device_scan(const TIn *in, T *out, int64_t n, T *partial, T *grand, bool inclusive,
+                        hipStream_t st, Widen wide = Widen()) {
     int64_t nb = scan_tiles(n);
     if (nb < 1) nb = 1;
-    k_scan_reduce<T><<<(unsigned)nb, kBlock, 0, st>>>(in, n, partial);
-    k_scan_apply<T><<<(unsigned)nb, kBlock, 0, st>>>(in, out, n, partial, grand, inclusive ? 1 : 0);
+    k_scan_reduce<T, TIn, Widen><<<(unsigned)nb, kBlock, 0, st>>>(in, n, partial, wide);
+    k_scan_apply<T, TIn, Widen><<<(unsigned)nb, kBlock, 0, st>>>(in, out, n, partial, grand,
+                                                                 inclusive ? 1 : 0, wide);
 }
 
 // ---------------------------------------------------------------------------

@@ -1434,14 +1434,25 @@ __global__ __launch_bounds__(kParentThreads) void k_parent(
 
 // --- 6. tour prefix sum: depth, light depth, preorder ---------------------------------
 // Packed 64-bit tour value: bits 0-21 depth, 22-27 light depth, 28-63 down edges.
+// The tour itself is stored as one byte per step (down or up, heavy or light
+// edge) and widened to its packed value as the prefix sum reads it.
 constexpr int kDepthBits = 22;
 constexpr int kLdShift = 22;
 constexpr int kDownShift = 28;
+enum : uint8_t { kStepDownHeavy = 1, kStepDownLight = 2, kStepUpHeavy = 3, kStepUpLight = 4 };
+struct TourStep {
+    __device__ uint64_t operator()(uint8_t c) const {
+        const uint64_t light = (c == kStepDownLight || c == kStepUpLight) ? 1 : 0;
+        if (c == kStepDownHeavy || c == kStepDownLight)
+            return (1ull << kDownShift) + (light << kLdShift) + 1ull;
+        return c ? 0ull - (light << kLdShift) - 1ull : 0ull;
+    }
+};
 
 __global__ void k_tour_scatter(LevelGeom g, const uint2 *__restrict__ nrec,
                                const int32_t *__restrict__ tree, const int32_t *__restrict__ size,
                                Ranks rank_of, const uint64_t *__restrict__ rootoff,
-                               uint64_t *__restrict__ tourval, int32_t *__restrict__ posw,
+                               uint8_t *__restrict__ tourval, int32_t *__restrict__ posw,
                                int n_tiles, int32_t *__restrict__ info) {
     bool ok;
     int W;
@@ -1477,15 +1488,12 @@ __global__ void k_tour_scatter(LevelGeom g, const uint2 *__restrict__ nrec,
             info[HDP_INFO_ERROR] = 2;
             continue;
         }
-        uint64_t val;
-        if (d != pd) {  // down edge v -> child
-            uint64_t light = d != hd ? 1 : 0;
-            val = (1ull << kDownShift) + (light << kLdShift) + 1ull;
-        } else {  // up edge v -> parent
-            uint64_t light = vheavy ? 0 : 1;
-            val = 0ull - (light << kLdShift) - 1ull;
-        }
-        tourval[pos] = val;
+        uint8_t step;
+        if (d != pd)  // down edge v -> child
+            step = d != hd ? kStepDownLight : kStepDownHeavy;
+        else  // up edge v -> parent
+            step = vheavy ? kStepUpHeavy : kStepUpLight;
+        tourval[pos] = step;
     }
 }
 
@@ -1698,6 +1706,7 @@ struct TreeWs {
     int32_t *comp0, *lmin, *croot, *mnroot, *Rall, *At, *slot, *ctr, *flags;
     int32_t *size, *ld, *seq, *posw;
     uint64_t *cw, *best0, *best1, *E, *Et, *lw, *pr, *rootval, *tourval, *partial64, *root_total;
+    uint8_t *tour8;
     uint32_t *C;
     uint2 *nrec;
     uint8_t *intree, *adj;
@@ -1732,6 +1741,7 @@ static TreeWs carve_tree_ws(void *ws, int64_t n, size_t *bytes) {
     t.nrec = b.take<uint2>(n);
     t.rootval = b.take<uint64_t>(n);
     t.tourval = b.take<uint64_t>(2 * n);
+    t.tour8 = b.take<uint8_t>(2 * n);
     t.partial64 = b.take<uint64_t>(scan_tiles(2 * n) + 1);
     t.root_total = b.take<uint64_t>(1);
     t.intree = b.take<uint8_t>(2 * n);
@@ -1856,9 +1866,9 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     k_scan_apply<uint64_t><<<n_scan, kBlock, 0, st>>>(t.rootval, t.rootval, n, t.partial64,
                                                        t.root_total, 0);
     k_tour_scatter<<<tiled_grid((int)n_tiles), kBlock, 0, st>>>(
-        g, t.nrec, f.tree, t.size, rk, t.rootval, t.tourval, t.posw, (int)n_tiles, f.info);
+        g, t.nrec, f.tree, t.size, rk, t.rootval, t.tour8, t.posw, (int)n_tiles, f.info);
     int64_t tour_len = 2 * n;  // upper bound; entries past the real length are never read
-    device_scan<uint64_t>(t.tourval, t.tourval, tour_len, t.partial64, nullptr, true, st);
+    device_scan<uint64_t>(t.tour8, t.tourval, tour_len, t.partial64, nullptr, true, st, TourStep());
     k_node_order<<<tiled_grid((int)n_tiles), kBlock, 0, st>>>(
         g, t.nrec, f.tree, t.posw, t.rootval, t.tourval, tour_len, f.depth, t.ld, t.seq,
         (int)n_tiles, f.info);
