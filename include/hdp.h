@@ -72,7 +72,7 @@ enum {
     HDP_INFO_N_TREES = 2,    /* number of trees in the forest */
     HDP_INFO_WIDTH = 3,      /* row width of the volume layout (labels per row) */
     HDP_INFO_MST_ROUNDS = 4, /* hooking rounds the spanning-forest build used */
-    HDP_INFO_RANK_ROUNDS = 5,/* pointer-jumping rounds of the tour ranking */
+    HDP_INFO_RANK_ROUNDS = 5,/* tour-ranking launches and LDS-tail rounds that advanced */
     HDP_INFO_BAD_INTERVAL = 6,/* pixels whose interval was empty or wider than allowed */
     HDP_INFO_ERROR = 7,      /* nonzero if an internal consistency guard tripped */
     HDP_INFO_LIVE_EDGES = 8, /* edges still joining two components after the tile-local phase */

@@ -46,7 +46,8 @@ enum {
 
 // Rounds run by full-grid launches before one workgroup finishes the rest.
 constexpr int kBvGridRounds = 4;
-constexpr int kRankGridRounds = 8;
+constexpr int kRankGridRounds = 8;  // pointer-jumping steps on the full grid ...
+constexpr int kRankJumps = 4;        // ... taken kRankJumps per launch
 // Sizes of the one-workgroup LDS tails: spanning forest (edges, components,
 // hash slots; endpoints and component state are 16-bit indices) and tour
 // ranking (list entries).
@@ -634,10 +635,11 @@ __global__ __launch_bounds__(kBlock) void k_gbv_compact(
 // components the contracted graph is loaded into LDS and finished there;
 // otherwise the rounds run on the global arrays with device-coherent loads.
 // After full-grid rounds the surviving components are renumbered through a
-// hash table.  Without them (a contracted graph of at most kTE edges, the
-// tail alone) nothing has hooked yet: the live list itself is read, its edges
-// join distinct active components, and a component's dense number is its slot
-// in the active list (kept in croot by the local phase).
+// hash table.  Without them (none launched, or all skipped because the graph
+// has at most kTE edges) nothing has hooked yet: the live list itself is read
+// (its edges join distinct active components), and when the graph fits LDS a
+// component's dense number is its slot in the active list (kept in croot by
+// the local phase).
 
 __device__ __forceinline__ int hash_slot(int key) {
     return (int)(((uint32_t)key * 2654435761u) >> 20) & (kTH - 1);
@@ -1167,15 +1169,20 @@ __global__ __launch_bounds__(kBlock) void k_rank_round(int round, int32_t *__res
     const int prev = round > 0 ? flags[FLAG_RANK + round - 1] : 1;
     if (nC <= kTA) return;  // short lists: the one-workgroup tail alone
     if (prev == 0) return;
+    // Several jumps per launch, each published at once: an entry may read a
+    // successor that has already jumped further in this launch, which only
+    // shortens the way (every word is a valid "successor at that distance").
     bool more = false;
     for (int s = (int)gtid(); s < nC; s += gridDim.x * kBlock) {
         uint64_t P = ld_relaxed(&pr[s]);
-        int32_t nx = (int32_t)(P >> 32);
-        if (nx < 0) continue;
-        uint64_t Q = ld_relaxed(&pr[nx]);
-        int32_t nn = (int32_t)(Q >> 32);
-        st_relaxed(&pr[s], ((uint64_t)(uint32_t)nn << 32) | (uint32_t)((uint32_t)P + (uint32_t)Q));
-        more |= nn >= 0;
+        for (int j = 0; j < kRankJumps; ++j) {
+            const int32_t nx = (int32_t)(P >> 32);
+            if (nx < 0) break;
+            const uint64_t Q = ld_relaxed(&pr[nx]);
+            P = (Q & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)P + (uint32_t)Q);
+            st_relaxed(&pr[s], P);
+        }
+        more |= (int32_t)(P >> 32) >= 0;
     }
     if (__ballot(more) && (threadIdx.x & 63) == 0) flags[FLAG_RANK + round] = 1;
 }
@@ -1413,9 +1420,15 @@ __global__ __launch_bounds__(kParentThreads) void k_parent(
     const int32_t *__restrict__ plo, const int32_t *__restrict__ phi,
     int32_t *__restrict__ parent, int32_t *__restrict__ size, float *__restrict__ wgt,
     uint64_t *__restrict__ rootval, int32_t *__restrict__ lo, int32_t *__restrict__ hi,
-    uint2 *__restrict__ nrec, uint64_t *__restrict__ tile_sum) {
+    uint2 *__restrict__ nrec, uint64_t *__restrict__ tile_sum, int n_scan) {
     __shared__ uint64_t s_w[kParentThreads / 64];
-    const int64_t v = (int64_t)blockIdx.x * kParentThreads + threadIdx.x;
+    // each XCD takes a contiguous band of scan tiles (workgroups are dealt to
+    // the XCDs in turn), so the rows above and below a tile were read through
+    // the same L2
+    const int per = (n_scan + kXcds - 1) / kXcds;
+    const int tile = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    if (tile >= n_scan) return;
+    const int64_t v = (int64_t)tile * kParentThreads + threadIdx.x;
     uint64_t x = 0;
     if (v < g.off[g.n_pairs])
         x = parent_of_pixel(v, g, img, rank_of, adj, plo, phi, parent, size, wgt, rootval, lo,
@@ -1428,7 +1441,7 @@ __global__ __launch_bounds__(kParentThreads) void k_parent(
         uint64_t t = 0;
 #pragma unroll
         for (int i = 0; i < kParentThreads / 64; ++i) t += s_w[i];
-        tile_sum[blockIdx.x] = t;
+        tile_sum[tile] = t;
     }
 }
 
@@ -1850,6 +1863,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     // the contracted list is bounded by runs_bound: a list that fits the LDS
     // tail needs no full-grid rounds at all.
     if (!plo && runs_bound <= kTA) rk_rounds = 0;
+    rk_rounds = (rk_rounds + kRankJumps - 1) / kRankJumps;  // launches of kRankJumps jumps
     for (int r = 0; r < rk_rounds; ++r)
         k_rank_round<<<g_edges, kBlock, 0, st>>>(r, t.flags, t.ctr, t.pr);
     if (rk_rounds > 0)  // without rounds the tail reads the whole list itself
@@ -1859,8 +1873,9 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     Ranks rk{t.lw, t.pr};
     // 5: parents, subtree sizes, heavy children
     const unsigned n_scan = (unsigned)(scan_tiles(n) < 1 ? 1 : scan_tiles(n));
-    k_parent<<<n_scan, kParentThreads, 0, st>>>(g, im, rk, t.adj, plo, phi, f.parent, t.size,
-                                                f.wgt, t.rootval, f.lo, f.hi, t.nrec, t.partial64);
+    k_parent<<<kXcds * ((n_scan + kXcds - 1) / kXcds), kParentThreads, 0, st>>>(
+        g, im, rk, t.adj, plo, phi, f.parent, t.size, f.wgt, t.rootval, f.lo, f.hi, t.nrec,
+        t.partial64, (int)n_scan);
     // 6: tour offsets (the root-data scan, tile sums from k_parent), tour
     // values, prefix sum, per-node depth / light depth / preorder
     k_scan_apply<uint64_t><<<n_scan, kBlock, 0, st>>>(t.rootval, t.rootval, n, t.partial64,
