@@ -46,8 +46,8 @@ enum {
 
 // Rounds run by full-grid launches before one workgroup finishes the rest.
 constexpr int kBvGridRounds = 4;
-constexpr int kRankGridRounds = 8;  // pointer-jumping steps on the full grid ...
-constexpr int kRankJumps = 4;        // ... taken kRankJumps per launch
+constexpr int kRankGridRounds = 12;  // pointer-jumping steps on the full grid ...
+constexpr int kRankJumps = 12;        // ... taken kRankJumps per launch
 // Sizes of the one-workgroup LDS tails: spanning forest (edges, components,
 // hash slots; endpoints and component state are 16-bit indices) and tour
 // ranking (list entries).
