@@ -1081,14 +1081,18 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
         P[ls] = w;
     }
     __syncthreads();
-    // pointer jumping inside the tile (13 rounds reach every run end; one
-    // more confirms)
-    bool converged = false;
-    int rr = 0;
-    for (int round = 0; round < 16; ++round) {
+    // pointer jumping inside the tile, without barriers between the steps:
+    // a slot word is written by its owner only and always names a later slot
+    // of its run with the hops to it, so a word that its owner has already
+    // advanced in this pass is just as valid (the reader gets there sooner).
+    // A thread stops once its slots point at their run ends; every step
+    // advances a slot by at least one hop, which bounds the loop.
+    for (int step = 0; live && step <= 4 * kTilePx; ++step) {
         uint32_t nxt[kSlotsPerThread];
         for (int k = 0; k < kSlotsPerThread; ++k)
-            nxt[k] = ((live >> k) & 1) ? P[own[k] >> 16] : 0u;
+            nxt[k] = ((live >> k) & 1) ? __hip_atomic_load(&P[own[k] >> 16], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_WORKGROUP)
+                                       : 0u;
         for (int k = 0; k < kSlotsPerThread; ++k) {
             if (!((live >> k) & 1)) continue;
             uint32_t nx = own[k] >> 16, nn = nxt[k] >> 16;
@@ -1097,14 +1101,12 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
                 continue;
             }
             own[k] = (nn << 16) | ((own[k] & 0xFFFFu) + (nxt[k] & 0xFFFFu));
-            P[tid + k * kLocalThreads] = own[k];
-        }
-        if (!wg_any(live != 0, s_any, rr)) {
-            converged = true;
-            break;
+            __hip_atomic_store(&P[tid + k * kLocalThreads], own[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
-    if (!converged && tid == 0) info[HDP_INFO_ERROR] = 5;
+    if (live) info[HDP_INFO_ERROR] = 5;
+    __syncthreads();
     // number the run ends (one LDS atomic per wavefront and slot group)
     int wofs[kSlotsPerThread];
     uint64_t wm[kSlotsPerThread];
@@ -1217,28 +1219,45 @@ __global__ __launch_bounds__(kLocalThreads) void k_rank_tail(
     if (nRuns > kTA && prev == 0) return;
     const int tid = threadIdx.x;
     if (nRuns <= kTA) {
-        for (int j = tid; j < nRuns; j += kLocalThreads) L[j] = pr[j];
-        for (int r = K; r < 64; ++r) {
-            if (tid == 0) s_more = 0;
-            __syncthreads();
-            bool more = false;
-            for (int j = tid; j < nRuns; j += kLocalThreads) {
-                unsigned long long a = L[j];
-                int nx = (int32_t)(a >> 32);
-                if (nx < 0) continue;
-                unsigned long long b = L[nx];
-                L[j] = (b & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)a + (uint32_t)b);
-                more |= (int32_t)(b >> 32) >= 0;
-            }
-            if (more) s_more = 1;
-            __syncthreads();
-            int any = s_more;
-            __syncthreads();  // every thread has read s_more before it is cleared
-            if (!any) break;
-            if (tid == 0) flags[FLAG_RANK + r] = 1;
+        // Each thread jumps its entries (kept in registers) without barriers
+        // between the steps: an entry word is written by its owner only and
+        // is always a valid successor with the hops to it.
+        constexpr int kPer = kTA / kLocalThreads;
+        unsigned long long own[kPer];
+        uint32_t live = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int j = tid + q * kLocalThreads;
+            own[q] = j < nRuns ? pr[j] : (0xFFFFFFFFull << 32);
+            if ((int32_t)(own[q] >> 32) >= 0) live |= 1u << q;
+            if (j < nRuns) L[j] = own[q];
         }
-        for (int j = tid; j < nRuns; j += kLocalThreads)
-            pr[j] = (0xFFFFFFFFull << 32) | (uint32_t)L[j];
+        // (the vote is also the barrier after the LDS fill)
+        const int any_open = __syncthreads_or(live != 0);
+        if (tid == 0 && any_open) flags[FLAG_RANK + K] = 1;
+        for (int step = 0; live && step <= kTA; ++step) {
+            unsigned long long nb[kPer];
+#pragma unroll
+            for (int q = 0; q < kPer; ++q)
+                nb[q] = ((live >> q) & 1) ? __hip_atomic_load(&L[(int32_t)(own[q] >> 32)],
+                                                              __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_WORKGROUP)
+                                          : 0ull;
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                if (!((live >> q) & 1)) continue;
+                own[q] = (nb[q] & 0xFFFFFFFF00000000ull) | (uint32_t)((uint32_t)own[q] + (uint32_t)nb[q]);
+                __hip_atomic_store(&L[tid + q * kLocalThreads], own[q], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                if ((int32_t)(nb[q] >> 32) < 0) live &= ~(1u << q);
+            }
+        }
+        if (live) info[HDP_INFO_ERROR] = 6;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int j = tid + q * kLocalThreads;
+            if (j < nRuns) pr[j] = (0xFFFFFFFFull << 32) | (uint32_t)own[q];
+        }
         return;
     }
     if (nA <= kTA) {
