@@ -82,20 +82,6 @@ __device__ __forceinline__ void wg_sync() {
     __syncthreads();
 }
 
-// Workgroup barrier that also tells whether any thread passed true: one
-// barrier, where __syncthreads_or takes a reduction and two.  Three LDS words
-// are used in rotation (rr, the same in every thread, names this round's
-// word); the word two rounds ahead is cleared after the barrier, when no
-// thread still reads it and none writes it before the next barrier.
-__device__ __forceinline__ bool wg_any(bool p, int *w3, int &rr) {
-    if (p) w3[rr] = 1;
-    __syncthreads();
-    const bool any = w3[rr] != 0;
-    if (threadIdx.x == 0) w3[rr == 0 ? 2 : rr - 1] = 0;
-    rr = rr == 2 ? 0 : rr + 1;
-    return any;
-}
-
 // One step of a wavefront minimum: each lane takes the smaller of its value
 // and the value the DPP pattern kCtrl moves to it (rows outside kRowMask, and
 // disabled source lanes, contribute the identity ~0).
@@ -256,7 +242,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     __shared__ uint8_t tR[kTilePx], tD[kTilePx];  // tree edges taken, by owning pixel
     __shared__ int32_t pk[kPairSlots];               // component pair of a table slot
     __shared__ unsigned long long pv[kPairSlots];    // least (key, id) edge of the pair
-    __shared__ int s_flag[2], s_any[3], s_nE, s_nR, s_bE, s_bR;
+    __shared__ int s_flag[2], s_nE, s_nR, s_bE, s_bR;
     const TileInfo t = tile_info(g, blockIdx.x);
     const float scale = ldexpf(1.0f, 2 * g.level);
     const int i = threadIdx.x;
@@ -274,9 +260,6 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
         s_bR = 0;
         s_flag[0] = 0;
         s_flag[1] = 0;
-        s_any[0] = 0;
-        s_any[1] = 0;
-        s_any[2] = 0;
     }
     lab[i] = i;
     best[i] = kNoEdge;
@@ -333,7 +316,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     // and hook are written only by its thread and live in registers; the tree
     // edges are kept in LDS and stored once at the end, so that no barrier
     // waits on global stores.
-    int myl = i, rr = 0;
+    int myl = i;
     for (int iter = 0; iter < kTilePx; ++iter) {
         const int par = iter & 1;
         // every pixel offers its least edge to another component to its own
@@ -395,19 +378,19 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
             lab[i] = hook;
         }
         __syncthreads();
-        // pointer jumping until every pixel names its root (each change moves a
-        // label to a strict ancestor, so the loop ends; roots stay roots here,
-        // so a pixel whose new label is a root is done)
+        // pointer jumping until every pixel names its root, without barriers
+        // between the steps: a label only ever names an ancestor (a word its
+        // owner has already advanced is just as valid) and roots stay roots
+        // here, so a pixel is done once its label names itself; every step
+        // moves a label to a strict ancestor, which bounds the loop
         for (int it = 0; it < kTilePx; ++it) {
-            int ll = lab[myl];
-            bool more = false;
-            if (ll != myl) {
-                myl = ll;
-                lab[i] = ll;
-                more = lab[ll] != ll;
-            }
-            if (!wg_any(more, s_any, rr)) break;
+            const int ll =
+                __hip_atomic_load(&lab[myl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (ll == myl) break;
+            myl = ll;
+            __hip_atomic_store(&lab[i], ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+        __syncthreads();
     }
     // smallest pixel id of every local component (hk reused); empty pair table
     hk[i] = 0x7fffffff;
@@ -659,7 +642,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
     __shared__ int32_t rid[kTN];
     __shared__ uint16_t lab[kTN], hk[kTN], bidx[kTN];
     __shared__ unsigned long long best[kTN];
-    __shared__ int s_nodes, s_flag, s_any[3];
+    __shared__ int s_nodes, s_flag;
     // counters loaded together with the flag
     const int nLive = ctr[CTR_E], nComp = ctr[CTR_ET], nR = ctr[CTR_RALL];
     const int prev = K > 0 ? flags[FLAG_BV + K - 1] : 1;
@@ -673,10 +656,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
     int ra[kTailEdgesPerThread], rb[kTailEdgesPerThread];  // endpoint components (pixel ids)
     uint64_t k0[kTailEdgesPerThread];
     if (direct) {
-        if (tid == 0) {
-            s_nodes = nR;
-            s_any[0] = s_any[1] = s_any[2] = 0;
-        }
+        if (tid == 0) s_nodes = nR;
 #pragma unroll
         for (int q = 0; q < kTailEdgesPerThread; ++q) {
             const int i = tid + q * kLocalThreads;
@@ -699,10 +679,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
         __syncthreads();
     } else if (lds_mode) {
         for (int h = tid; h < kTH; h += kLocalThreads) hkey[h] = -1;
-        if (tid == 0) {
-            s_nodes = 0;
-            s_any[0] = s_any[1] = s_any[2] = 0;
-        }
+        if (tid == 0) s_nodes = 0;
         __syncthreads();
         // components of every edge (no link changes in this launch yet), into
         // the hash table of components.  A thread resolves its edges together:
@@ -805,7 +782,6 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
             best[j] = kNoEdge;
         }
         if (tid == 0) s_flag = 0;
-        int rr = 0;
         __syncthreads();
         for (int iter = 0; iter < kTN; ++iter) {
             // least live edge of every component (dead edges drop out for good)
@@ -865,23 +841,31 @@ __global__ __launch_bounds__(kLocalThreads) void k_gbv_tail(
                 }
             }
             __syncthreads();
-            // pointer jumping until every component names its root (labels only
-            // move to ancestors; roots stay roots, so a new root label ends it)
-            for (int it = 0; it < kTN; ++it) {
+            // pointer jumping until every component names its root, without
+            // barriers between the steps (labels only move to ancestors, roots
+            // stay roots: a node is done once its label names itself)
+            volatile uint16_t *vlab = lab;
+            uint32_t open = 0;
+#pragma unroll
+            for (int k = 0; k < kTailNodesPerThread; ++k)
+                if (tid + k * kLocalThreads < nN) open |= 1u << k;
+            for (int it = 0; open && it < kTN; ++it) {
                 int ll[kTailNodesPerThread];
 #pragma unroll
                 for (int k = 0; k < kTailNodesPerThread; ++k)
-                    ll[k] = tid + k * kLocalThreads < nN ? lab[ml[k]] : ml[k];
-                bool more = false;
+                    ll[k] = ((open >> k) & 1) ? vlab[ml[k]] : ml[k];
 #pragma unroll
                 for (int k = 0; k < kTailNodesPerThread; ++k) {
-                    if (ll[k] == ml[k]) continue;
+                    if (!((open >> k) & 1)) continue;
+                    if (ll[k] == ml[k]) {
+                        open &= ~(1u << k);
+                        continue;
+                    }
                     ml[k] = ll[k];
-                    lab[tid + k * kLocalThreads] = (uint16_t)ll[k];
-                    more |= lab[ll[k]] != ll[k];
+                    vlab[tid + k * kLocalThreads] = (uint16_t)ll[k];
                 }
-                if (!wg_any(more, s_any, rr)) break;
             }
+            __syncthreads();
         }
         // tree edges and permanent links of every merged component
         for (int j = tid; j < nN; j += kLocalThreads) {
@@ -1037,7 +1021,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
     __shared__ uint8_t sadj[kHalo * kHalo];
     __shared__ uint32_t P[4 * kTilePx];
     __shared__ int32_t tix[4 * kTilePx];
-    __shared__ int s_n, s_base, s_any[3];
+    __shared__ int s_n, s_base;
     const TileInfo t = tile_info(g, blockIdx.x);
     const int tid = threadIdx.x;
     for (int h = tid; h < kHalo * kHalo; h += kLocalThreads) {
@@ -1045,12 +1029,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
         bool in = x >= 0 && x < t.W && y >= 0 && y < t.H;
         sadj[h] = in ? adj[t.base + (int64_t)y * t.W + x] : 0;
     }
-    if (tid == 0) {
-        s_n = 0;
-        s_any[0] = 0;
-        s_any[1] = 0;
-        s_any[2] = 0;
-    }
+    if (tid == 0) s_n = 0;
     __syncthreads();
     // slot ls = 4 * (ly * kTile + lx) + d; P = next << 16 | hops (run end:
     // next = self; a run has fewer than 4 * kTilePx hops)
