@@ -54,14 +54,54 @@ struct WidenSame {
     __device__ X operator()(X x) const { return x; }
 };
 
+// A thread's kScanPerThread consecutive elements.  A full run is loaded
+// without conditions, so that all its loads are in flight together.
+template <typename T, typename TIn, typename Widen>
+__device__ __forceinline__ void load_run(const TIn *__restrict__ in, int64_t base, int64_t n,
+                                         Widen wide, T (&v)[kScanPerThread]) {
+    if (base + kScanPerThread <= n) {
+        TIn x[kScanPerThread];
+#pragma unroll
+        for (int i = 0; i < kScanPerThread; ++i) x[i] = in[base + i];
+#pragma unroll
+        for (int i = 0; i < kScanPerThread; ++i) v[i] = (T)wide(x[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kScanPerThread; ++i) v[i] = base + i < n ? (T)wide(in[base + i]) : (T)0;
+    }
+}
+
+// Sum of part[0..m) over the workgroup's threads (thread t takes t, t + kBlock,
+// ...), eight independent loads in flight per step.
+template <typename T>
+__device__ __forceinline__ T strided_sum(const T *__restrict__ part, int64_t m) {
+    T acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0;
+    int64_t j = threadIdx.x;
+    for (; j + 7 * kBlock < m; j += 8 * kBlock) {
+        T x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = part[j + u * kBlock];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += x[u];
+    }
+    for (; j < m; j += kBlock) acc[0] += part[j];
+    T s = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += acc[u];
+    return s;
+}
+
 template <typename T, typename TIn = T, typename Widen = WidenSame>
 __global__ void k_scan_reduce(const TIn *__restrict__ in, int64_t n, T *__restrict__ partial,
                               Widen wide = Widen()) {
     int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
+    T v[kScanPerThread];
+    load_run(in, base, n, wide, v);
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < kScanPerThread; ++i)
-        if (base + i < n) s += (T)wide(in[base + i]);
+    for (int i = 0; i < kScanPerThread; ++i) s += v[i];
     T tot;
     block_excl_scan(s, &tot);
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
@@ -75,18 +115,16 @@ __global__ void k_scan_apply(const TIn *__restrict__ in, T *__restrict__ out, in
                              const T *__restrict__ partial, T *__restrict__ grand, int inclusive,
                              Widen wide = Widen()) {
     const int64_t tile = blockIdx.x;
-    T pre = 0;
-    for (int64_t j = threadIdx.x; j < tile; j += kBlock) pre += partial[j];
-    T pre_all;
-    block_excl_scan(pre, &pre_all);
+    // the tile's elements and the partial sums before it, loads issued together
     const int64_t base = tile * kScanTile + threadIdx.x * kScanPerThread;
     T v[kScanPerThread];
+    load_run(in, base, n, wide, v);
+    const T pre = strided_sum(partial, tile);
+    T pre_all;
+    block_excl_scan(pre, &pre_all);
     T s = 0;
 #pragma unroll
-    for (int i = 0; i < kScanPerThread; ++i) {
-        v[i] = base + i < n ? (T)wide(in[base + i]) : (T)0;
-        s += v[i];
-    }
+    for (int i = 0; i < kScanPerThread; ++i) s += v[i];
     T tot;
     T ex = block_excl_scan(s, &tot) + pre_all;
 #pragma unroll
