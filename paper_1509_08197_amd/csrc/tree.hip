@@ -1626,9 +1626,13 @@ __global__ void k_rows(LevelGeom g, const int32_t *__restrict__ node,
                        int32_t *__restrict__ rlh, const int32_t *__restrict__ flags,
                        const int32_t *__restrict__ ctr, int32_t *__restrict__ info, int width,
                        const uint64_t *__restrict__ root_total) {
-    const int64_t r = gtid();
+    // each XCD takes a contiguous band of row blocks (neighbouring chains of
+    // the preorder, so their pixels' records come through the same L2)
+    const int per = (int)(gridDim.x / kXcds);
+    const int blk = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+    const int64_t r = (int64_t)blk * kBlock + threadIdx.x;
     const int64_t n = g.off[g.n_pairs];
-    if (blockIdx.x == 0 && threadIdx.x < 64) finish_info(flags, ctr, info, width, n, root_total);
+    if (blk == 0 && threadIdx.x < 64) finish_info(flags, ctr, info, width, n, root_total);
     if (r >= n) return;
     const int v = node[r];
     const uint2 rec = nrec[v];
@@ -1895,8 +1899,9 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         k_phase_rows<<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles, f.node,
                                                           f.row, f.phase_ptr, f.info);
     }
-    k_rows<<<gn, kBlock, 0, st>>>(g, f.node, f.row, t.nrec, f.prow, f.heavy, f.lc, f.rw, f.rx,
-                                  f.rlh, t.flags, t.ctr, f.info, width, t.root_total);
+    k_rows<<<kXcds * ((gn + kXcds - 1) / kXcds), kBlock, 0, st>>>(
+        g, f.node, f.row, t.nrec, f.prow, f.heavy, f.lc, f.rw, f.rx, f.rlh, t.flags, t.ctr, f.info,
+        width, t.root_total);
 }
 
 // 8: level order (stable LSD radix sort of ids by depth) and level_ptr
