@@ -49,6 +49,9 @@ __device__ __forceinline__ PixelPos pixel_pos(const LevelGeom &g, int v) {
     return p;
 }
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) in turn.
+constexpr int kXcds = 8;
+
 __device__ __forceinline__ int64_t gtid() {
     return (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 }

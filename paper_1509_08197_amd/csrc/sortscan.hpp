@@ -152,6 +152,18 @@ inline void device_scan(const TIn *in, T *out, int64_t n, T *partial, T *grand, 
 }
 
 // ---------------------------------------------------------------------------
+// Tile of this workgroup when the grid (band_grid(ntiles) workgroups) deals
+// contiguous bands of tiles to the XCDs, so that neighbouring tiles share an
+// L2; -1 past the last tile.
+__device__ __forceinline__ int64_t band_tile(int64_t ntiles) {
+    const int64_t per = (ntiles + kXcds - 1) / kXcds;
+    const int64_t t = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    return t < ntiles ? t : -1;
+}
+inline unsigned band_grid(int64_t ntiles) {
+    return (unsigned)(kXcds * ((ntiles + kXcds - 1) / kXcds));
+}
+
 // Stable counting sort of the sequence src[0..n) by a small key (< NB <= 256).
 // key_of(i, x) gives the key of element x = src[i].  Histogram per tile of
 // 1024 elements (bin-major so that one exclusive scan gives every tile's base),
@@ -161,9 +173,11 @@ template <int NB, typename KeyFn>
 __global__ void k_count_hist(const int32_t *__restrict__ src, int64_t n, KeyFn key_of,
                              int32_t *__restrict__ hist, int64_t ntiles) {
     __shared__ int32_t h[NB];
+    const int64_t tile = band_tile(ntiles);
+    if (tile < 0) return;
     for (int k = threadIdx.x; k < NB; k += kBlock) h[k] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t base = tile * kScanTile;
     // elements, then keys, each one batch of loads
     int32_t xs[kScanPerThread];
 #pragma unroll
@@ -181,23 +195,23 @@ __global__ void k_count_hist(const int32_t *__restrict__ src, int64_t n, KeyFn k
     for (int q = 0; q < kScanPerThread; ++q)
         if (ks[q] >= 0) atomicAdd(&h[ks[q]], 1);
     __syncthreads();
-    for (int k = threadIdx.x; k < NB; k += kBlock) hist[(int64_t)k * ntiles + blockIdx.x] = h[k];
+    for (int k = threadIdx.x; k < NB; k += kBlock) hist[(int64_t)k * ntiles + tile] = h[k];
 }
 
 template <int NB, int NBITS, typename KeyFn>
 __device__ __forceinline__ void count_scatter_tile(const int32_t *__restrict__ src, int64_t n,
                                                    KeyFn key_of, const int32_t *__restrict__ offs,
                                                    int64_t ntiles, int32_t *__restrict__ dst,
-                                                   int32_t *__restrict__ pos_of) {
+                                                   int32_t *__restrict__ pos_of, int64_t tile) {
     __shared__ int32_t run[NB];
     __shared__ int32_t wcnt[kBlock / 64][NB];
     int wv = threadIdx.x >> 6;
     for (int k = threadIdx.x; k < NB; k += kBlock) {
-        run[k] = offs[(int64_t)k * ntiles + blockIdx.x];
+        run[k] = offs[(int64_t)k * ntiles + tile];
         for (int w = 0; w < kBlock / 64; ++w) wcnt[w][k] = 0;
     }
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t base = tile * kScanTile;
     // every step's element and key loaded up front (two batches of loads)
     int32_t xs[kScanPerThread];
     int ks[kScanPerThread];
@@ -248,7 +262,9 @@ template <int NB, int NBITS, typename KeyFn>
 __global__ void k_count_scatter(const int32_t *__restrict__ src, int64_t n, KeyFn key_of,
                                 const int32_t *__restrict__ offs, int64_t ntiles,
                                 int32_t *__restrict__ dst, int32_t *__restrict__ pos_of) {
-    count_scatter_tile<NB, NBITS>(src, n, key_of, offs, ntiles, dst, pos_of);
+    const int64_t tile = band_tile(ntiles);
+    if (tile < 0) return;
+    count_scatter_tile<NB, NBITS>(src, n, key_of, offs, ntiles, dst, pos_of, tile);
 }
 
 }  // namespace hdp

@@ -153,7 +153,6 @@ __device__ __forceinline__ int64_t tile_pixel(const TileInfo &t, int i) {
 // positions, preorder) walk the image tile by tile: four kBlock-thread blocks
 // per 32x32 tile, and the blocks of one tile on one XCD (blocks are dealt to
 // the 8 XCDs in turn), so each range is written through one L2.
-constexpr int kXcds = 8;
 static_assert(kTilePx == 4 * kBlock, "four blocks per tile");
 __device__ __forceinline__ int64_t tiled_pixel(const LevelGeom &g, int n_tiles, int *W,
                                                bool *ok) {
@@ -1577,14 +1576,16 @@ __global__ void k_phase_rows(const int32_t *__restrict__ seq, int64_t n, LdKey k
                              int32_t *__restrict__ node, int32_t *__restrict__ row,
                              int32_t *__restrict__ phase_ptr, int32_t *__restrict__ info) {
     const int k = threadIdx.x;
-    if (blockIdx.x == 0 && k <= HDP_MAX_PHASES) {
+    const int64_t tile = band_tile(ntiles);
+    if (tile < 0) return;
+    if (tile == 0 && k <= HDP_MAX_PHASES) {
         int32_t v = offs[(int64_t)k * ntiles];  // rows with light depth < k
         phase_ptr[k] = v;
         // phases = 1 + largest light depth present: the first k with all rows below it
         int32_t prev = k > 0 ? offs[(int64_t)(k - 1) * ntiles] : 0;
         if (k > 0 && v == n && prev < n) info[HDP_INFO_N_PHASES] = k;
     }
-    count_scatter_tile<64, 6>(seq, n, key, offs, ntiles, node, row);
+    count_scatter_tile<64, 6>(seq, n, key, offs, ntiles, node, row, tile);
 }
 
 // Build statistics into info (one wavefront: lane r reads round r's flags).
@@ -1786,9 +1787,9 @@ static void counting_sort(const int32_t *src, int32_t *dst, int32_t *pos_of, int
                           int32_t *hist, int32_t *partial32, hipStream_t st) {
     int64_t ntiles = scan_tiles(n);
     if (ntiles < 1) ntiles = 1;
-    k_count_hist<NB><<<(unsigned)ntiles, kBlock, 0, st>>>(src, n, key, hist, ntiles);
+    k_count_hist<NB><<<band_grid(ntiles), kBlock, 0, st>>>(src, n, key, hist, ntiles);
     device_scan<int32_t>(hist, hist, (int64_t)NB * ntiles, partial32, nullptr, false, st);
-    k_count_scatter<NB, NBITS><<<(unsigned)ntiles, kBlock, 0, st>>>(src, n, key, hist, ntiles, dst,
+    k_count_scatter<NB, NBITS><<<band_grid(ntiles), kBlock, 0, st>>>(src, n, key, hist, ntiles, dst,
                                                                     pos_of);
 }
 
@@ -1894,9 +1895,9 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         int64_t ntiles = scan_tiles(n);
         if (ntiles < 1) ntiles = 1;
         LdKey key{t.ld};
-        k_count_hist<64><<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles);
+        k_count_hist<64><<<band_grid(ntiles), kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles);
         device_scan<int32_t>(t.hist, t.hist, 64 * ntiles, t.partial32, nullptr, false, st);
-        k_phase_rows<<<(unsigned)ntiles, kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles, f.node,
+        k_phase_rows<<<band_grid(ntiles), kBlock, 0, st>>>(t.seq, n, key, t.hist, ntiles, f.node,
                                                           f.row, f.phase_ptr, f.info);
     }
     k_rows<<<kXcds * ((gn + kXcds - 1) / kXcds), kBlock, 0, st>>>(
