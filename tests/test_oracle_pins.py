@@ -562,3 +562,84 @@ def test_edge_keys_constant_and_scaled(orc):
     img[:, 2:, 1] = 50.25
     k2 = orc.edge_keys(img, 2)
     assert k2[2 * 1] == 4 and k2[2 * 0] == 0 and k2[2 * 5] == 4 and k2[2 * 2] == 0
+
+
+# --- pins added for the parts that the tests above leave open -------------------------------
+
+def test_hdpf_dt_rule2_on_current_tree_intervals_golden(orc):
+    """Section 3.2, eq. DTrules with the TreeIntv union: hand-worked strips where the
+    decision depends on the tree interval as it stands after earlier merges."""
+    g = load("dt_rule2_strips.json")
+    for c in g["cases"]:
+        W = c["W"]
+        lo = np.array([c["lo"]], np.int32); hi = np.array([c["hi"]], np.int32)
+        in_tree, tlo, thi, n = orc.kruskal(1, W, np.array(c["keys"], np.int64), lo, hi,
+                                           beta=tuple(c["beta"]))
+        assert in_tree.tolist() == c["in_tree"], c["name"]
+        assert tlo.tolist() == c["tree_lo"] and thi.tolist() == c["tree_hi"], c["name"]
+        assert n == sum(c["in_tree"])
+
+
+def test_level1_forest_weights_golden(orc):
+    """Edge weights at layer 1 (eq. weight on the graph pyramid of Section 2.1):
+    the per-node weight of the rooted tree is max_c |dI_c| / 255 of the level-1
+    intensities, worked out by hand for the 3x3 fixture."""
+    g = load("pyramid_3x3.json")
+    lv = orc.pyramid(np.array(g["image_rgb_rows"], np.uint8), 2, 2)
+    key = orc.edge_keys(lv[1], 1)
+    in_tree, _, _, _ = orc.kruskal(2, 2, key)
+    ref = g["level1_forest"]
+    assert in_tree.tolist() == ref["in_tree"]
+    f = orc.root_forest(2, 2, in_tree, key, 1)
+    assert f["parent"].tolist() == ref["parent"] and f["depth"].tolist() == ref["depth"]
+    want = [float(Fraction(s)) for s in ref["wgt"]]
+    np.testing.assert_allclose(f["wgt"], want, rtol=1e-15, atol=0)
+    # the same weights reach the aggregation of a whole layer: with a cost that is 1
+    # at one pixel and 0 elsewhere, agg(v) = exp(-W(v, pixel)/sigma) (eq. W, eq. S)
+    sigma = 0.1
+    cost = np.zeros((4, 1)); cost[3, 0] = 1.0
+    agg = orc.aggregate_twopass(f["parent"], f["wgt"], f["order"], sigma, cost)
+    w1, w2, w3 = want[1], want[2], want[3]
+    np.testing.assert_allclose(agg[:, 0], np.exp(-np.array([w1 + w3, w3, w2 + w1 + w3, 0.0]) / sigma),
+                               rtol=1e-13)
+
+
+def test_hdp_loop_wiring_identical_views(orc):
+    """Hand case of the top-down loop (Section 3, Section 3.1): with identical views
+    every cost at label 0 is exactly 0 and every other cost is >= 0, so each layer's
+    winner is label 0 (lowest label on ties), and with window w the interval of every
+    pixel below is [0, S - 1 + w] clipped to [0, d_l]."""
+    img = rng_img(17, 12, 20)
+    for L, dmax, w in [(1, 7, 0), (2, 15, 1), (2, 15, 0)]:
+        res = orc.hdp_stereo(img, img, dmax, S=2, L=L, window=w, want_forest=False)
+        for l in range(L, -1, -1):
+            assert np.all(res[l]["disp"] == 0), (L, l)
+            if l < L:
+                dl = dmax >> l
+                assert np.all(res[l]["pix_lo"] == 0)
+                assert np.all(res[l]["pix_hi"] == min(1 + w, dl)), (L, w, l)
+
+
+def test_hdp_loop_is_the_composition_of_its_stages(orc):
+    """Section 3: layer L over [0, d_L] with the MST; each lower layer takes its pixel
+    intervals from the labels of the layer above (Section 3.1), then the forest, cost,
+    aggregation and WTA of that layer.  The loop must equal the stages called in this
+    order, each of which is pinned above."""
+    from paper_1509_08197_amd import scenes
+    pair = scenes.small_scene(6, 24, 40, 31)
+    S, L, w = 2, 2, 1
+    res = orc.hdp_stereo(pair.left, pair.right, 31, S=S, L=L, window=w, want_forest=True)
+    lv = orc.pyramid(pair.left, S, L); rv = orc.pyramid(pair.right, S, L)
+    Hs, Ws, ds = orc.level_dims(24, 40, 31, S, L)
+    top = orc.stereo_level(lv[L], rv[L], ds[L], L)
+    np.testing.assert_array_equal(res[L]["disp"], top["disp"])
+    up = top["disp"]
+    for l in range(L - 1, -1, -1):
+        lo, hi = orc.predict_range(up, Hs[l], Ws[l], S, w, ds[l])
+        np.testing.assert_array_equal(res[l]["pix_lo"], lo)
+        np.testing.assert_array_equal(res[l]["pix_hi"], hi)
+        assert np.all(hi - lo + 1 <= S + 2 * w)
+        r = orc.stereo_level(lv[l], rv[l], ds[l], l, lo, hi)
+        np.testing.assert_array_equal(res[l]["disp"], r["disp"])
+        np.testing.assert_array_equal(res[l]["parent"], r["parent"])
+        up = r["disp"]
