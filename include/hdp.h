@@ -180,8 +180,12 @@ HDP_API size_t hdp_build_tree_workspace_bytes(int64_t n);
  *             beta_num / beta_den > (max_width - 1) / max_width: then DT-Rule 2
  *             admits only equal intervals and the forest is the minimum
  *             spanning forest of the equal-interval edges.  Otherwise the call
- *             returns HDP_EREGIME.  Pixels that break the bound are counted in
- *             info[HDP_INFO_BAD_INTERVAL].
+ *             returns HDP_EREGIME.  The bound is checked on the device: pixels
+ *             whose interval is empty, leaves [0, dmax] or is wider than
+ *             max_width are counted in info[HDP_INFO_BAD_INTERVAL], their
+ *             interval is clamped to [0, dmax] and max_width labels (so no later
+ *             call reads or writes outside its buffers), the forest is then not
+ *             the exact one, and hdp_forest_read_info returns HDP_EREGIME.
  *   width     row width of the volume layout to prepare: at least the widest
  *             tree interval (dmax + 1 for the full range).
  */
@@ -201,8 +205,10 @@ HDP_API hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int
 HDP_API hdp_status hdp_level_order(const hdp_forest *f, void *ws, size_t ws_bytes, void *stream);
 
 /* Host copy of the forest's scalars and phase table (synchronises `stream`;
- * diagnostics only, nothing on the hot path needs it).  Either pointer may be
- * NULL; phase_ptr_host receives HDP_MAX_PHASES + 1 entries. */
+ * nothing on the hot path needs it).  Either pointer may be NULL;
+ * phase_ptr_host receives HDP_MAX_PHASES + 1 entries.  Returns HDP_EREGIME
+ * (after filling both outputs) when info[HDP_INFO_BAD_INTERVAL] > 0, i.e. the
+ * forest was built from pixel intervals that broke hdp_build_tree's bound. */
 HDP_API hdp_status hdp_forest_read_info(const hdp_forest *f, int32_t *info_host,
                                 int32_t *phase_ptr_host, void *stream);
 

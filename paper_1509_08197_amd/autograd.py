@@ -4,7 +4,10 @@
 agg(v,x) = sum_u exp(-W(v,u)/sigma) cost(u,x) and back-propagates to the cost
 volume, to sigma and (if ``wgt`` is given) to the per-pixel edge weights.  The
 tree topology is fixed (it comes from integer keys), so the weights and sigma
-are differentiated with the topology held constant.  With ``save_up`` the
+are differentiated with the topology held constant.  The weights are loaded
+into the forest only while the forward and the backward of this call run (the
+forest keeps its own weights otherwise), so several calls on one forest with
+different weights each get their own gradients.  With ``save_up`` the
 forward keeps the leaf-to-root sums U as the backward's checkpoint; without
 it the backward recomputes them from the cost.
 """
@@ -21,30 +24,54 @@ from . import hdp
 class TreeAggregate(torch.autograd.Function):
     @staticmethod
     def forward(ctx, cost, sigma, wgt, forest, save_up):
-        if wgt is not None:
-            hdp.set_weights(forest, wgt.detach().contiguous())
         s = float(sigma)
-        if save_up:
-            agg, up = hdp.aggregate(forest, cost.detach().contiguous(), s, keep_up=True,
-                                    ws=forest_ws(forest))
-        else:
-            agg, up = hdp.aggregate(forest, cost.detach().contiguous(), s, ws=forest_ws(forest)), None
+        with _weights(forest, wgt):
+            if save_up:
+                agg, up = hdp.aggregate(forest, cost.detach().contiguous(), s, keep_up=True,
+                                        ws=forest_ws(forest))
+            else:
+                agg = hdp.aggregate(forest, cost.detach().contiguous(), s, ws=forest_ws(forest))
+                up = None
         ctx.forest = forest
         ctx.sigma = s
         ctx.has_w = wgt is not None
-        ctx.save_for_backward(cost.detach(), agg, up if up is not None else torch.empty(0))
+        w_saved = wgt.detach().contiguous() if wgt is not None else torch.empty(0)
+        ctx.save_for_backward(cost.detach(), agg, up if up is not None else torch.empty(0),
+                              w_saved)
         ctx.save_up = save_up
         return agg
 
     @staticmethod
     def backward(ctx, g):
-        cost, agg, up = ctx.saved_tensors
+        cost, agg, up, w_saved = ctx.saved_tensors
         need_c, need_s, need_w = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
-        gc, gw, gs = hdp.aggregate_backward(
-            ctx.forest, cost, agg, g.contiguous(), ctx.sigma, up=up if ctx.save_up else None,
-            want_w=bool(need_w and ctx.has_w), want_sigma=bool(need_s), ws=forest_ws(ctx.forest))
+        # the adjoint reads the weights from the forest: load this call's weights
+        # (another call may have used other weights since), then restore
+        with _weights(ctx.forest, w_saved if ctx.has_w else None):
+            gc, gw, gs = hdp.aggregate_backward(
+                ctx.forest, cost, agg, g.contiguous(), ctx.sigma,
+                up=up if ctx.save_up else None, want_w=bool(need_w and ctx.has_w),
+                want_sigma=bool(need_s), ws=forest_ws(ctx.forest))
         return (gc if need_c else None, gs.reshape(()) if gs is not None else None,
                 gw if (need_w and ctx.has_w) else None, None, None)
+
+
+class _weights:
+    """Load per-pixel edge weights into the forest for the duration of a block and
+    put the forest's own weights back afterwards (no-op for wgt None)."""
+
+    def __init__(self, forest, wgt):
+        self.forest, self.wgt, self.saved = forest, wgt, None
+
+    def __enter__(self):
+        if self.wgt is not None:
+            self.saved = self.forest.array("wgt").clone()
+            hdp.set_weights(self.forest, self.wgt.detach().contiguous())
+
+    def __exit__(self, *exc):
+        if self.saved is not None:
+            hdp.set_weights(self.forest, self.saved)
+        return False
 
 
 _ws = {}

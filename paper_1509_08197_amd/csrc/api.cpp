@@ -244,15 +244,17 @@ hdp_status hdp_forest_read_info(const hdp_forest *f, int32_t *info_host, int32_t
                                 void *stream) {
     if (!f || !f->info || !f->phase_ptr) return HDP_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    if (info_host &&
-        hipMemcpyAsync(info_host, f->info, 4 * HDP_INFO_WORDS, hipMemcpyDeviceToHost, st) !=
-            hipSuccess)
+    int32_t info[HDP_INFO_WORDS];
+    if (hipMemcpyAsync(info, f->info, 4 * HDP_INFO_WORDS, hipMemcpyDeviceToHost, st) !=
+        hipSuccess)
         return HDP_EHIP;
     if (phase_ptr_host && hipMemcpyAsync(phase_ptr_host, f->phase_ptr, 4 * (HDP_MAX_PHASES + 1),
                                          hipMemcpyDeviceToHost, st) != hipSuccess)
         return HDP_EHIP;
     if (hipStreamSynchronize(st) != hipSuccess) return HDP_EHIP;
-    return HDP_OK;
+    if (info_host) memcpy(info_host, info, sizeof(info));
+    // a pixel interval that broke the caller's bound left an inexact forest
+    return info[HDP_INFO_BAD_INTERVAL] > 0 ? HDP_EREGIME : HDP_OK;
 }
 
 hdp_status hdp_forest_set_weights(const hdp_forest *f, const float *wgt, void *stream) {

@@ -1322,9 +1322,9 @@ __device__ __forceinline__ int code_hdir(uint32_t c) { return (c & kHasHeavy) ? 
 __device__ __forceinline__ uint64_t parent_of_pixel(
     int64_t v, const LevelGeom &g, const float4 *__restrict__ img, Ranks rank_of,
     const uint8_t *__restrict__ adj, const int32_t *__restrict__ plo,
-    const int32_t *__restrict__ phi, int32_t *__restrict__ parent, int32_t *__restrict__ size,
-    float *__restrict__ wgt, uint64_t *__restrict__ rootval, int32_t *__restrict__ lo,
-    int32_t *__restrict__ hi, uint2 *__restrict__ nrec) {
+    const int32_t *__restrict__ phi, int max_width, int32_t *__restrict__ parent,
+    int32_t *__restrict__ size, float *__restrict__ wgt, uint64_t *__restrict__ rootval,
+    int32_t *__restrict__ lo, int32_t *__restrict__ hi, uint2 *__restrict__ nrec) {
     const int pair = pair_of(g, (int)v);
     const int W = g.W[pair];
     const float scale = ldexpf(1.0f, 2 * g.level);
@@ -1345,8 +1345,18 @@ __device__ __forceinline__ uint64_t parent_of_pixel(
         cw[d] = e ? img[w] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     const float4 cv = img[v];
-    const int l = plo ? plo[v] : 0;
-    const int h = plo ? phi[v] : g.dmax[pair];
+    // a pixel interval outside [0, dmax] or wider than max_width (counted by
+    // the local phase in info, which makes the forest invalid) is clamped, so
+    // that no later kernel reads a label outside the image row or writes past
+    // the end of a volume row
+    const int dm = g.dmax[pair];
+    int l = plo ? plo[v] : 0;
+    int h = plo ? phi[v] : dm;
+    if (plo) {
+        l = l < 0 ? 0 : (l > dm ? dm : l);
+        h = h < l ? l : (h > dm ? dm : h);
+        h = h - l + 1 > max_width ? l + max_width - 1 : h;
+    }
     uint32_t rv[4], rw[4], kw[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
@@ -1414,7 +1424,7 @@ __device__ __forceinline__ uint64_t parent_of_pixel(
 constexpr int kParentThreads = kScanTile;
 __global__ __launch_bounds__(kParentThreads) void k_parent(
     LevelGeom g, const float4 *__restrict__ img, Ranks rank_of, const uint8_t *__restrict__ adj,
-    const int32_t *__restrict__ plo, const int32_t *__restrict__ phi,
+    const int32_t *__restrict__ plo, const int32_t *__restrict__ phi, int max_width,
     int32_t *__restrict__ parent, int32_t *__restrict__ size, float *__restrict__ wgt,
     uint64_t *__restrict__ rootval, int32_t *__restrict__ lo, int32_t *__restrict__ hi,
     uint2 *__restrict__ nrec, uint64_t *__restrict__ tile_sum, int n_scan) {
@@ -1428,8 +1438,8 @@ __global__ __launch_bounds__(kParentThreads) void k_parent(
     const int64_t v = (int64_t)tile * kParentThreads + threadIdx.x;
     uint64_t x = 0;
     if (v < g.off[g.n_pairs])
-        x = parent_of_pixel(v, g, img, rank_of, adj, plo, phi, parent, size, wgt, rootval, lo,
-                            hi, nrec);
+        x = parent_of_pixel(v, g, img, rank_of, adj, plo, phi, max_width, parent, size, wgt,
+                            rootval, lo, hi, nrec);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
     if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = x;
@@ -1877,7 +1887,8 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     // 5: parents, subtree sizes, heavy children
     const unsigned n_scan = (unsigned)(scan_tiles(n) < 1 ? 1 : scan_tiles(n));
     k_parent<<<kXcds * ((n_scan + kXcds - 1) / kXcds), kParentThreads, 0, st>>>(
-        g, im, rk, t.adj, plo, phi, f.parent, t.size, f.wgt, t.rootval, f.lo, f.hi, t.nrec,
+        g, im, rk, t.adj, plo, phi, max_width, f.parent, t.size, f.wgt, t.rootval, f.lo, f.hi,
+        t.nrec,
         t.partial64, (int)n_scan);
     // 6: tour offsets (the root-data scan, tile sums from k_parent), tour
     // values, prefix sum, per-node depth / light depth / preorder

@@ -233,9 +233,9 @@ class Forest:
         """Host copy of the scalars and the phase table (synchronises)."""
         info = (C.c_int32 * INFO_WORDS)()
         pp = (C.c_int32 * (MAX_PHASES + 1))()
-        _check("hdp_forest_read_info",
-               lib().hdp_forest_read_info(C.byref(self.st), info, pp, _stream()))
+        code = lib().hdp_forest_read_info(C.byref(self.st), info, pp, _stream())
         self.info = list(info)
+        _check("hdp_forest_read_info", code)
         npz = self.info[INFO["n_phases"]]
         self.phase_ptr = list(pp)[:npz + 1]
         return self.info

@@ -227,11 +227,39 @@ def _workload_args(args):
     return workload(*args)
 
 
-def workload_batch(cfg: int, n: int = None, processes: int = 16):
-    """All pairs of a batched workload, generated in parallel host processes."""
-    n = N_PAIRS[cfg] if n is None else n
-    if n == 1 or processes <= 1:
+def _gpu_initialised() -> bool:
+    """True once this process has made a HIP call through torch (a fork after
+    that point would hand the children the parent's device state)."""
+    import sys
+    torch = sys.modules.get("torch")
+    return bool(torch is not None and torch.cuda.is_initialized())
+
+
+_BATCHES = {}
+
+
+def prefetch(cfgs, processes: int = 16) -> None:
+    """Draw the pairs of the batched workloads ``cfgs`` now and keep them for
+    ``workload_batch``.  Called before the process's first GPU call, it draws
+    them in forked host processes; afterwards it draws them one by one here."""
+    for cfg in cfgs:
+        if cfg not in _BATCHES:
+            _BATCHES[cfg] = _draw_batch(cfg, N_PAIRS[cfg], processes)
+
+
+def _draw_batch(cfg: int, n: int, processes: int):
+    if n == 1 or processes <= 1 or _gpu_initialised():
         return [workload(cfg, i) for i in range(n)]
     from multiprocessing import get_context
     with get_context("fork").Pool(min(processes, n)) as pool:
         return pool.map(_workload_args, [(cfg, i) for i in range(n)])
+
+
+def workload_batch(cfg: int, n: int = None, processes: int = 16):
+    """All pairs of a batched workload: the prefetched ones if ``prefetch`` drew
+    them, otherwise drawn now (in forked host processes only while the process
+    has not touched the GPU)."""
+    n = N_PAIRS[cfg] if n is None else n
+    if cfg in _BATCHES and len(_BATCHES[cfg]) >= n:
+        return _BATCHES[cfg][:n]
+    return _draw_batch(cfg, n, processes)

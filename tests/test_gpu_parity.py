@@ -471,6 +471,112 @@ def test_adjoint_matches_oracle(H, orc):
     np.testing.assert_array_equal(gc2.cpu().numpy(), gc.cpu().numpy())
 
 
+def adjoint_reference(orc, par, wg, od, sigma, C, G):
+    """Oracle adjoint (two-pass, pinned to the dense gradient and FP64 finite
+    differences) and the rounding scale of each gradient: the same sums taken
+    over absolute values."""
+    dC, dw, ds = orc.aggregate_backward_twopass(par, wg, od, sigma, C, G)
+    Aabs, Uabs = orc.aggregate_twopass(par, wg, od, sigma, np.abs(G), want_up=True)
+    AC, UC = orc.aggregate_twopass(par, wg, od, sigma, C, want_up=True)
+    s = np.where(par >= 0, np.exp(-wg / sigma), 0.0)
+    pp = np.maximum(par, 0)
+    B = np.sum(Uabs * (AC[pp] + s[:, None] * UC) + UC * (Aabs[pp] + s[:, None] * Uabs), axis=1)
+    B = np.where(par >= 0, B * s / sigma, 0.0)
+    return dict(dC=dC, dw=dw, ds=ds, bC=Aabs, bw=B, bs=float(np.sum(B * wg / sigma)))
+
+
+def check_adjoint(got_c, got_w, got_s, ref, what, mask=None):
+    """Within REL of the magnitude sums (the FP32 rounding bound of a sum of
+    mixed-sign terms); also prints how the relative error behaves where the
+    reference is not small (|ref| >= 1e-3 of its largest value)."""
+    m = np.ones(ref["dC"].shape, bool) if mask is None else mask
+    ec = np.abs(got_c - ref["dC"])[m]
+    assert np.all(ec <= REL * ref["bC"][m]), f"{what} dC: {np.max(ec / ref['bC'][m]):.3g}"
+    ew = np.abs(got_w - ref["dw"])
+    assert np.all(ew <= REL * ref["bw"] + 1e-30), f"{what} dw: {np.max(ew / np.maximum(ref['bw'], 1e-30)):.3g}"
+    assert abs(got_s - ref["ds"]) <= REL * ref["bs"], (what, got_s, ref["ds"], ref["bs"])
+    for name, g_, r_ in (("dC", got_c[m], ref["dC"][m]), ("dw", got_w, ref["dw"])):
+        big = np.abs(r_) >= 1e-3 * np.max(np.abs(r_))
+        rel = np.abs(g_ - r_)[big] / np.abs(r_)[big]
+        print(f"{what} {name}: rel err where |ref| >= 1e-3 max: max {rel.max():.3g}, "
+              f"99.9% {np.quantile(rel, 0.999):.3g}, above 1e-5: {int((rel > 1e-5).sum())} of {rel.size}")
+    if ref["ds"] != 0.0:
+        print(f"{what} dsigma rel err {abs(got_s - ref['ds']) / abs(ref['ds']):.3g}")
+
+
+def test_adjoint_hdp_forest(H, orc):
+    """The adjoint on a disparity forest with many trees and narrow per-tree
+    label windows (the shape of the batched backward over HDP layers): dC inside
+    every tree interval, dw per node and dsigma against the oracle."""
+    Hh, Ww, dmax, S, w, sigma = 48, 64, 31, 2, 2, 0.1
+    pair = scenes.small_scene(88, Hh, Ww, dmax)
+    up = np.random.default_rng(8).integers(0, dmax // 2 + 1, ((Hh + 1) // 2, (Ww + 1) // 2))
+    up = np.kron(up[::3, ::3], np.ones((3, 3), int))[:up.shape[0], :up.shape[1]]
+    lo, hi = orc.predict_range(up, Hh, Ww, S, w, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lp = H.pyramid(rgb_dev(pair.left), shapes, 2, 0)
+    rp = H.pyramid(rgb_dev(pair.right), shapes, 2, 0)
+    f = H.build_tree(lp[0], shapes, 0, dev(lo.ravel(), torch.int32), dev(hi.ravel(), torch.int32),
+                     max_width=S + 2 * w, beta=(19, 20))
+    cost = H.cost_volume(lp[0], rp[0], shapes, f)
+    agg, upv = H.aggregate(f, cost, sigma, keep_up=True)
+    g = torch.from_numpy(np.random.default_rng(9).normal(size=cost.shape).astype(np.float32)).cuda()
+    gc, gw, gs = H.aggregate_backward(f, cost, agg, g, sigma, up=upv)
+    F = forest_np(f)
+    key = orc.edge_keys(pair.left.astype(np.float64), 0)
+    in_tree, tlo, thi, _ = orc.kruskal(Hh, Ww, key, lo, hi, beta=(19, 20))
+    ref_f = orc.root_forest(Hh, Ww, in_tree, key, 0)
+    check_forest(F, ref_f, Hh * Ww, "HDP forest for the adjoint")
+    assert F["info"][2] > 20, "expected a forest of many trees"
+    D = dmax + 1
+    C = np.nan_to_num(orc.cost_volume(pair.left.astype(np.float64), pair.right.astype(np.float64),
+                                      dmax, tlo, thi), nan=0.0)
+    inside = ~np.isnan(volume_to_pixels(cost.cpu().numpy(), F, D))
+    G = np.nan_to_num(volume_to_pixels(g.cpu().numpy().astype(np.float64), F, D), nan=0.0)
+    ref = adjoint_reference(orc, ref_f["parent"], ref_f["wgt"], ref_f["order"], sigma, C, G)
+    got_c = np.nan_to_num(volume_to_pixels(gc.cpu().numpy().astype(np.float64), F, D), nan=0.0)
+    check_adjoint(got_c, gw.cpu().numpy().astype(np.float64), float(gs.cpu()), ref,
+                  "HDP forest", inside)
+
+
+def test_adjoint_multi_pair_batch(H, orc):
+    """The adjoint of one batched call over pairs of different sizes and label
+    ranges (rows padded to the widest range) against per-pair oracle adjoints;
+    dsigma is the sum over the batch."""
+    shapes = [(40, 56, 7), (33, 47, 15), (24, 64, 3)]
+    sigma = 0.1
+    pairs = [scenes.small_scene(120 + i, h, w, d) for i, (h, w, d) in enumerate(shapes)]
+    lp = H.pyramid(rgb_dev(*[p.left for p in pairs]), shapes, 2, 0)
+    rp = H.pyramid(rgb_dev(*[p.right for p in pairs]), shapes, 2, 0)
+    f = H.build_tree(lp[0], shapes, 0)
+    cost = H.cost_volume(lp[0], rp[0], shapes, f)
+    agg, upv = H.aggregate(f, cost, sigma, keep_up=True)
+    g = torch.from_numpy(np.random.default_rng(10).normal(size=cost.shape).astype(np.float32)).cuda()
+    gc, gw, gs = H.aggregate_backward(f, cost, agg, g, sigma, up=upv)
+    F = forest_np(f)
+    D = max(d for _, _, d in shapes) + 1
+    gcp = volume_to_pixels(gc.cpu().numpy().astype(np.float64), F, D)
+    gp = volume_to_pixels(g.cpu().numpy().astype(np.float64), F, D)
+    gwn = gw.cpu().numpy().astype(np.float64)
+    off, ds_sum, bs_sum = 0, 0.0, 0.0
+    for p, (h, w, d) in zip(pairs, shapes):
+        n = h * w
+        key = orc.edge_keys(p.left.astype(np.float64), 0)
+        in_tree, _, _, _ = orc.kruskal(h, w, key)
+        rf = orc.root_forest(h, w, in_tree, key, 0)
+        par_g = F["parent"][off:off + n]
+        np.testing.assert_array_equal(np.where(par_g >= 0, par_g - off, -1), rf["parent"])
+        C = orc.cost_volume(p.left.astype(np.float64), p.right.astype(np.float64), d)
+        G = gp[off:off + n, :d + 1]
+        ref = adjoint_reference(orc, rf["parent"], rf["wgt"], rf["order"], sigma, C, G)
+        ref_pair = dict(ref, ds=0.0, bs=1.0)
+        check_adjoint(gcp[off:off + n, :d + 1], gwn[off:off + n], 0.0, ref_pair,
+                      f"batch pair {h}x{w} d={d}")
+        ds_sum += ref["ds"]; bs_sum += ref["bs"]
+        off += n
+    assert abs(float(gs.cpu()) - ds_sum) <= REL * bs_sum, (float(gs.cpu()), ds_sum, bs_sum)
+
+
 def test_graph_replay_matches_eager(H):
     """The whole HDP step captured once and replayed several times (with eager
     work in between) gives the eager result on every replay."""
@@ -552,3 +658,70 @@ def test_native_plan_matches_binding(H):
             np.testing.assert_array_equal(plan.layer_disp(l).cpu().numpy(),
                                           ref[l].disp.cpu().numpy())
     plan.close()
+
+
+def test_autograd_interleaved_calls_keep_their_weights(H, orc):
+    """Two tree_aggregate calls on one forest with different edge weights, both
+    forwards before either backward: each call's gradients are those of its own
+    weights, and the forest keeps its own weights afterwards."""
+    from paper_1509_08197_amd.autograd import tree_aggregate
+    Hh, Ww, dmax, sigma = 24, 40, 5, 0.1
+    pair = scenes.small_scene(79, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lp = H.pyramid(rgb_dev(pair.left), shapes, 2, 0)
+    rp = H.pyramid(rgb_dev(pair.right), shapes, 2, 0)
+    f = H.build_tree(lp[0], shapes, 0)
+    cost0 = H.cost_volume(lp[0], rp[0], shapes, f)
+    own = f.array("wgt").clone()
+    rng = np.random.default_rng(12)
+    w1 = own * torch.from_numpy(rng.uniform(0.5, 1.5, size=own.shape).astype(np.float32)).cuda()
+    w2 = own * torch.from_numpy(rng.uniform(0.5, 1.5, size=own.shape).astype(np.float32)).cuda()
+    wl = torch.from_numpy(rng.normal(size=cost0.shape).astype(np.float32)).cuda()
+    leaves, outs = [], []
+    for wv in (w1, w2):
+        c = cost0.clone().requires_grad_(True)
+        wt = wv.clone().requires_grad_(True)
+        outs.append(tree_aggregate(c, sigma, f, wt))
+        leaves.append((c, wt))
+    assert torch.equal(f.array("wgt"), own), "forward left other weights in the forest"
+    for o in outs:
+        (o * wl).sum().backward()
+    assert torch.equal(f.array("wgt"), own), "backward left other weights in the forest"
+    F = forest_np(f)
+    node = F["node"]
+    key = orc.edge_keys(pair.left.astype(np.float64), 0)
+    in_tree, _, _, _ = orc.kruskal(Hh, Ww, key)
+    ref_f = orc.root_forest(Hh, Ww, in_tree, key, 0)
+    C = orc.cost_volume(pair.left.astype(np.float64), pair.right.astype(np.float64), dmax)
+    G = np.zeros_like(C); G[node] = wl.cpu().numpy().astype(np.float64)
+    for k, (wv, (c, wt)) in enumerate(zip((w1, w2), leaves)):
+        wg = wv.cpu().numpy().astype(np.float64)
+        ref = adjoint_reference(orc, ref_f["parent"], np.where(ref_f["parent"] >= 0, wg, 0.0),
+                                ref_f["order"], sigma, C, G)
+        got_c = np.zeros_like(C); got_c[node] = c.grad.cpu().numpy()
+        check_adjoint(got_c, wt.grad.cpu().numpy().astype(np.float64), ref["ds"], ref,
+                      f"interleaved call {k}")
+
+
+def test_interval_bound_violation_is_reported(H):
+    """Pixel intervals that break the bound given to hdp_build_tree (wider than
+    max_width, or reaching outside [0, dmax]) are counted, clamped, and turn the
+    forest's info read into HDP_EREGIME; the layer still runs inside its buffers."""
+    Hh, Ww, dmax = 16, 24, 31
+    pair = scenes.small_scene(5, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lp, rp = H.pyramid_views(rgb_dev(pair.left), rgb_dev(pair.right), shapes, 2, 0)
+    lo = np.full(Hh * Ww, 4, np.int32); hi = np.full(Hh * Ww, 13, np.int32)
+    lo[7], hi[7] = 2, 17       # 16 labels > max_width 10
+    lo[40], hi[40] = -3, 5     # below label 0
+    hi[41] = 40                # above dmax
+    f = H.build_tree(lp[0], shapes, 0, dev(lo), dev(hi), max_width=10, beta=(19, 20))
+    agg, disp = H.match_layer(lp[0], rp[0], shapes, f)
+    torch.cuda.synchronize()
+    with pytest.raises(H.HdpError) as e:
+        f.read_info()
+    assert e.value.code == -4 and f.info[6] == 3
+    flo, fhi = f.array("lo").cpu().numpy(), f.array("hi").cpu().numpy()
+    assert np.all(flo >= 0) and np.all(fhi <= dmax) and np.all(fhi - flo + 1 <= 10)
+    d = disp.cpu().numpy()
+    assert np.all((d >= flo) & (d <= fhi))
