@@ -412,6 +412,10 @@ OR_API void or_predict_range(const int32_t *disp_up, int Hu, int Wu, int H, int 
  * Optional outputs (NULL to skip): parent, depth, order, level_ptr, tree_lo,
  * tree_hi, c1, c2 (see or_wta), and sampled aggregated slices
  * sample_agg[n_sample][N] at labels sample_d (NaN outside a tree interval).
+ * rank == NULL: Kruskal takes the edges by colour weight (MST, DT).  Otherwise
+ * rank[2N] holds one random number per grid edge (drawn by the caller) and the
+ * edges are taken in ascending (rank, id) order: the random spanning tree (RT)
+ * of Section 4.1 and its HDP forest.
  * Returns the number of levels of the forest. */
 
 OR_API int or_stereo_level(const double *left, const double *right, int H, int W, int dmax,
@@ -420,9 +424,11 @@ OR_API int or_stereo_level(const double *left, const double *right, int H, int W
                            int32_t *disp, double *c1, double *c2,
                            int32_t *parent_o, int32_t *depth_o, int32_t *order_o,
                            int32_t *level_ptr_o, int32_t *tree_lo_o, int32_t *tree_hi_o,
-                           int n_sample, const int32_t *sample_d, double *sample_agg) {
+                           int n_sample, const int32_t *sample_d, double *sample_agg,
+                           const int64_t *rank) {
     int N = H * W;
     int64_t *key = (int64_t *)malloc(sizeof(int64_t) * (size_t)2 * N);
+    int64_t *order_key = (int64_t *)malloc(sizeof(int64_t) * (size_t)2 * N);
     uint8_t *in_tree = (uint8_t *)malloc((size_t)2 * N);
     int32_t *tlo = (int32_t *)malloc(sizeof(int32_t) * N);
     int32_t *thi = (int32_t *)malloc(sizeof(int32_t) * N);
@@ -439,7 +445,13 @@ OR_API int or_stereo_level(const double *left, const double *right, int H, int W
     double *second = (double *)malloc(sizeof(double) * N);
 
     or_edge_keys(left, H, W, level, key);
-    or_kruskal(H, W, key, pix_lo, pix_hi, beta_num, beta_den, in_tree,
+    /* Kruskal's edge order: the colour weights (MST), or for the random
+     * spanning tree (RT, Section 4.1) the given random ranks, so that sorting
+     * the edges by (rank, id) is the random shuffle; the aggregation weights
+     * stay the colour weights of eq. weight either way */
+    for (int i = 0; i < 2 * N; ++i)
+        order_key[i] = key[i] < 0 ? -1 : (rank ? rank[i] : key[i]);
+    or_kruskal(H, W, order_key, pix_lo, pix_hi, beta_num, beta_den, in_tree,
                pix_lo ? tlo : NULL, pix_lo ? thi : NULL);
     if (!pix_lo)
         for (int v = 0; v < N; ++v) { tlo[v] = 0; thi[v] = dmax; }
@@ -479,7 +491,8 @@ OR_API int or_stereo_level(const double *left, const double *right, int H, int W
     if (level_ptr_o) memcpy(level_ptr_o, lptr, sizeof(int32_t) * (nl + 1));
     if (tree_lo_o) memcpy(tree_lo_o, tlo, sizeof(int32_t) * N);
     if (tree_hi_o) memcpy(tree_hi_o, thi, sizeof(int32_t) * N);
-    free(key); free(in_tree); free(tlo); free(thi); free(parent); free(depth); free(tree);
+    free(key); free(order_key); free(in_tree); free(tlo); free(thi); free(parent); free(depth);
+    free(tree);
     free(order); free(lptr); free(wgt); free(U); free(A); free(s); free(best); free(second);
     return nl;
 }

@@ -67,7 +67,7 @@ def _declare(L):
     L.or_wta.argtypes = [I, I, P, P, P, P, P, P]
     L.or_predict_range.argtypes = [P, I, I, I, I, I, I, I, P, P]
     L.or_stereo_level.argtypes = [P, P, I, I, I, I, P, P, I, I, D, P,
-                                  P, P, P, P, P, P, P, P, P, I, P, P]
+                                  P, P, P, P, P, P, P, P, P, I, P, P, P]
     L.or_stereo_level.restype = I
     L.or_aggregate_grad_dense.argtypes = [I, I, P, P, D, I, P, P, P, P, P]
     L.or_aggregate_backward_twopass.argtypes = [I, P, P, P, D, I, P, P, P, P, P]
@@ -211,8 +211,10 @@ def predict_range(disp_up, H, W, S, window, dmax_l):
 
 
 def stereo_level(left, right, dmax, level, pix_lo=None, pix_hi=None, beta=(19, 20),
-                 sigma=0.1, prm=COST_PARAMS, sample_d=(), want_forest=True):
-    """One layer: forest, restricted cost, two-pass aggregation, WTA."""
+                 sigma=0.1, prm=COST_PARAMS, sample_d=(), want_forest=True, rank=None):
+    """One layer: forest, restricted cost, two-pass aggregation, WTA.
+    rank: None (edges by colour weight) or one random number per grid edge
+    [2N] (the random spanning tree RT of Section 4.1: edges by (rank, id))."""
     left = _c(left, np.float64); right = _c(right, np.float64)
     H, W = left.shape[:2]
     N = H * W
@@ -233,7 +235,8 @@ def stereo_level(left, right, dmax, level, pix_lo=None, pix_hi=None, beta=(19, 2
                                _p(disp), _p(c1), _p(c2), _p(g("parent")), _p(g("depth")),
                                _p(g("order")), _p(g("level_ptr")), _p(g("tree_lo")),
                                _p(g("tree_hi")), len(sd), _p(sd if len(sd) else None),
-                               _p(sa if len(sd) else None))
+                               _p(sa if len(sd) else None),
+                               _p(None if rank is None else _c(rank, np.int64).ravel()))
     res = dict(disp=disp.reshape(H, W), c1=c1, c2=c2, n_levels=nl, sample_agg=sa)
     if want_forest:
         outs["level_ptr"] = outs["level_ptr"][:nl + 1].copy()
@@ -242,21 +245,24 @@ def stereo_level(left, right, dmax, level, pix_lo=None, pix_hi=None, beta=(19, 2
 
 
 def hdp_stereo(left_u8, right_u8, dmax, S=2, L=3, window=4, beta=(19, 20), sigma=0.1,
-               prm=COST_PARAMS, want_forest=False):
+               prm=COST_PARAMS, want_forest=False, ranks=None):
     """Top-down HDP loop (Section 3): layer L over [0, d_L], then for l = L-1..0
     interval prediction, disparity forest, restricted cost, aggregation, WTA.
+    ranks: None, or per layer l the random edge ranks [2 N_l] of HDP+RT.
     Returns a list of per-layer result dicts, index l."""
     H, W = left_u8.shape[:2]
     Hs, Ws, ds = level_dims(H, W, dmax, S, L)
     lp = pyramid(left_u8, S, L)
     rp = pyramid(right_u8, S, L)
     res = [None] * (L + 1)
-    res[L] = stereo_level(lp[L], rp[L], ds[L], L, sigma=sigma, prm=prm, want_forest=want_forest)
+    rk = (lambda l: None) if ranks is None else (lambda l: ranks[l])
+    res[L] = stereo_level(lp[L], rp[L], ds[L], L, sigma=sigma, prm=prm, want_forest=want_forest,
+                          rank=rk(L))
     res[L]["pix_lo"] = None; res[L]["pix_hi"] = None
     for l in range(L - 1, -1, -1):
         lo, hi = predict_range(res[l + 1]["disp"], Hs[l], Ws[l], S, window, ds[l])
         r = stereo_level(lp[l], rp[l], ds[l], l, lo, hi, beta=beta, sigma=sigma, prm=prm,
-                         want_forest=want_forest)
+                         want_forest=want_forest, rank=rk(l))
         r["pix_lo"] = lo; r["pix_hi"] = hi
         res[l] = r
     return res

@@ -643,3 +643,109 @@ def test_hdp_loop_is_the_composition_of_its_stages(orc):
         np.testing.assert_array_equal(res[l]["disp"], r["disp"])
         np.testing.assert_array_equal(res[l]["parent"], r["parent"])
         up = r["disp"]
+
+
+# --- random spanning tree RT (Section 4.1) -------------------------------------
+# RT shuffles the edges at random and runs union-find over them.  Reading: the
+# shuffle is given by one random number per grid edge (drawn by the caller),
+# edges taken in ascending (rank, id) order; the aggregation still uses the
+# colour weights of eq. weight on the tree edges.
+
+def edges_of_parent(parent, W):
+    """Grid edge ids (v, parent(v)) of a rooted forest."""
+    out = set()
+    for v, p in enumerate(parent):
+        if p < 0:
+            continue
+        a, b = min(v, p), max(v, p)
+        out.add(2 * a if b == a + 1 else 2 * a + 1)
+        assert b == a + 1 or b == a + W
+    return out
+
+
+def random_ranks(seed, N, hi=1 << 31):
+    return np.random.default_rng(seed).integers(0, hi, size=2 * N, dtype=np.int64)
+
+
+def test_rt_is_the_unique_spanning_tree_of_least_rank_sum_3x3(orc):
+    """Union-find over the shuffled edges keeps the spanning tree whose rank sum
+    is least (exhaustive enumeration of the 3x3 grid's spanning trees)."""
+    H, W = 3, 3
+    img = rng_img(5, H, W)
+    for seed in range(4):
+        rank = random_ranks(900 + seed, H * W, hi=1000)
+        r = orc.stereo_level(img.astype(np.float64), img.astype(np.float64), 3, 0, rank=rank)
+        got = edges_of_parent(r["parent"], W)
+        best = None
+        for sub in itertools.combinations(grid_edges(H, W), H * W - 1):
+            par = list(range(H * W))
+
+            def find(v):
+                while par[v] != v:
+                    v = par[v]
+                return v
+            ok = True
+            for e, p, q in sub:
+                a, b = find(p), find(q)
+                if a == b:
+                    ok = False; break
+                par[a] = b
+            if ok:
+                tot = sum((int(rank[e]) << 32) | e for e, _, _ in sub)
+                if best is None or tot < best[0]:
+                    best = (tot, {e for e, _, _ in sub})
+        assert got == best[1]
+
+
+@pytest.mark.parametrize("seed,H,W", [(0, 24, 24), (1, 7, 31), (2, 1, 40)])
+def test_rt_matches_scipy_mst_of_the_ranks(orc, seed, H, W):
+    """RT = minimum spanning tree of the grid weighted by (rank, id)."""
+    N = H * W
+    img = rng_img(40 + seed, H, W)
+    rank = random_ranks(seed, N, hi=1 << 19)
+    r = orc.stereo_level(img.astype(np.float64), img.astype(np.float64), 3, 0, rank=rank)
+    rows, cols, vals = [], [], []
+    for e, p, q in grid_edges(H, W):
+        rows.append(p); cols.append(q); vals.append(float((int(rank[e]) << 12) + e + 1))
+    T = minimum_spanning_tree(sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()).tocoo()
+    ref = {(int(v) - 1) & 0xFFF for v in T.data}
+    assert edges_of_parent(r["parent"], W) == ref
+    # with the colour keys as ranks RT is the MST
+    key = orc.edge_keys(img.astype(np.float64), 0)
+    a = orc.stereo_level(img.astype(np.float64), img.astype(np.float64), 3, 0, rank=key)
+    b = orc.stereo_level(img.astype(np.float64), img.astype(np.float64), 3, 0)
+    np.testing.assert_array_equal(a["parent"], b["parent"])
+
+
+def test_rt_aggregates_with_colour_weights(orc):
+    """The aggregation over RT uses the colour weights of the tree's edges, not
+    the ranks: compare with the plain definition (dense all-pairs sums)."""
+    H, W, dmax, sigma = 9, 11, 5, 0.1
+    L = rng_img(80, H, W).astype(np.float64); R = rng_img(81, H, W).astype(np.float64)
+    rank = random_ranks(7, H * W)
+    r = orc.stereo_level(L, R, dmax, 0, sigma=sigma, sample_d=list(range(dmax + 1)), rank=rank)
+    in_tree = np.zeros(2 * H * W, np.uint8)
+    in_tree[list(edges_of_parent(r["parent"], W))] = 1
+    key = orc.edge_keys(L, 0)
+    w = orc.edge_weights(key, 0)
+    G = forest_graph(H, W, in_tree, np.nan_to_num(w))
+    D = shortest_path(G, directed=False)
+    cost = orc.cost_volume(L, R, dmax)
+    ref = np.exp(-D / sigma) @ cost
+    np.testing.assert_allclose(r["sample_agg"].T, ref, rtol=1e-10)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_hdp_rt_regime_equals_filtered_msf_of_ranks(orc, seed):
+    """HDP+RT in the exact regime: the forest is the minimum spanning forest,
+    under the ranks, of the equal-interval edges."""
+    rng = np.random.default_rng(300 + seed)
+    H, W = 12, 15
+    img = rng_img(400 + seed, H, W)
+    blocks = rng.integers(0, 3, size=(H // 3 + 1, W // 3 + 1))
+    i = np.kron(blocks, np.ones((3, 3), int))[:H, :W]
+    lo = np.clip(2 * i - 4, 0, 15).astype(np.int32); hi = np.clip(2 * i + 5, 0, 15).astype(np.int32)
+    rank = random_ranks(500 + seed, H * W, hi=1 << 19)  # (rank, id) exact in float64
+    f = img.astype(np.float64)
+    r = orc.stereo_level(f, f, 15, 0, lo, hi, beta=(19, 20), rank=rank)
+    assert edges_of_parent(r["parent"], W) == msf_equal_intervals(H, W, rank, lo, hi)
