@@ -307,6 +307,30 @@ HDP_API hdp_status hdp_match_layer(const float *left, const float *right, const 
                            void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * hdp_match_layer without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments (minus ws, ws_bytes),
+ * same launches and the same results as hdp_match_layer.  Its scratch space
+ * (the workspace of hdp_match_layer: coefficients, flags, tile maps, the U
+ * volume) lives in one fixed device array of HDP_NOALLOC_SCRATCH_BYTES per
+ * GPU, held from the library's load until the process ends; the call
+ * allocates nothing.  Returns HDP_EWORKSPACE, enqueueing nothing, when
+ * hdp_aggregate_workspace_bytes(f->n, width) exceeds that size (e.g. a layer
+ * of up to about 2.6 million pixels at 10 labels per row fits).  Every call on
+ * one GPU uses the same array and the kernels reinitialise what must start
+ * clean, so calls in sequence are independent; calls that overlap on one GPU
+ * (different streams or host threads) race on the array and must not be
+ * issued.
+ */
+#define HDP_NOALLOC_SCRATCH_BYTES (256u << 20)
+HDP_API size_t hdp_match_layer_noalloc_max_bytes(void);
+HDP_API hdp_status hdp_match_layer_noalloc(const float *left, const float *right,
+                                           const hdp_shape *shapes, int32_t n_pairs,
+                                           const hdp_forest *f, int32_t width,
+                                           const hdp_cost_params *p, float sigma, float *agg,
+                                           int32_t *disp, void *stream);
+
+/*
  * Pixel interval prediction (Section 3.1) for layer l from the disparity map
  * of layer l+1:
  *   PixelIntv(x, y) = [S*i - window, S*i + S - 1 + window] intersected with

@@ -14,7 +14,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libhdp.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "plan.cpp", "pyramid.hip", "cost.hip", "tree.hip", "aggregate.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "pyramid.hip", "cost.hip", "tree.hip", "aggregate.hip",
+           "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -94,6 +94,11 @@ def _declare(L):
     L.hdp_wta.argtypes = [C.POINTER(ForestStruct), P, I32, I32, P, P, P]
     L.hdp_match_layer.argtypes = [P, P, P, I32, C.POINTER(ForestStruct), I32,
                                   C.POINTER(CostParams), F, P, P, P, SZ, P]
+    L.hdp_match_layer_noalloc.argtypes = [P, P, P, I32, C.POINTER(ForestStruct), I32,
+                                          C.POINTER(CostParams), F, P, P, P]
+    L.hdp_match_layer_noalloc.restype = I32
+    L.hdp_match_layer_noalloc_max_bytes.argtypes = []
+    L.hdp_match_layer_noalloc_max_bytes.restype = SZ
     L.hdp_forest_set_weights.argtypes = [C.POINTER(ForestStruct), P, P]
     L.hdp_forest_set_weights.restype = I32
     L.hdp_predict_range.argtypes = [P, P, P, I32, I32, I32, P, P, P]
@@ -388,6 +393,28 @@ def match_layer(left: torch.Tensor, right: torch.Tensor, shapes, forest: Forest,
         _ptr(left), _ptr(right), _shapes(shapes), len(shapes), C.byref(forest.st), int(width),
         C.byref(p), float(sigma), _ptr(agg), _ptr(disp), _ptr(w), wsb, _stream()))
     return agg, disp
+
+
+def match_layer_noalloc(left: torch.Tensor, right: torch.Tensor, shapes, forest: Forest,
+                        sigma: float = 0.1, params: Optional[CostParams] = None, agg=None,
+                        disp=None):
+    """match_layer with the library's fixed scratch array instead of a
+    workspace (the call allocates nothing on the device).  Returns (agg, disp)."""
+    n, width = forest.n, forest.width
+    if agg is None:
+        agg = torch.empty((n, width), dtype=torch.float32, device=left.device)
+    if disp is None:
+        disp = torch.empty(n, dtype=torch.int32, device=left.device)
+    p = params or cost_params()
+    _check("hdp_match_layer_noalloc", lib().hdp_match_layer_noalloc(
+        _ptr(left), _ptr(right), _shapes(shapes), len(shapes), C.byref(forest.st), int(width),
+        C.byref(p), float(sigma), _ptr(agg), _ptr(disp), _stream()))
+    return agg, disp
+
+
+def noalloc_max_bytes() -> int:
+    """Size of the fixed scratch array behind match_layer_noalloc."""
+    return int(lib().hdp_match_layer_noalloc_max_bytes())
 
 
 def predict_range(disp_upper: torch.Tensor, upper_shapes, lower_shapes, S: int = 2,

@@ -168,3 +168,27 @@ def test_workspace_sizes_grow(lib):
     b = [L.hdp_aggregate_workspace_bytes(n, 10) for n in (10, 1000, 100000)]
     assert a == sorted(a) and b == sorted(b)
     assert L.hdp_aggregate_workspace_bytes(1000, 256) > L.hdp_aggregate_workspace_bytes(1000, 10)
+
+
+def test_match_layer_noalloc_rejects_oversize(lib):
+    """The allocation-free matching call refuses, before any HIP call, a layer
+    whose scratch space exceeds its fixed array."""
+    L = lib.lib()
+    cap = lib.noalloc_max_bytes()
+    assert cap == 256 << 20
+    # a layer of 4M pixels at 32 labels per row needs more than the array holds;
+    # only the forest's size is read before the refusal
+    st = lib.ForestStruct()
+    st.n = 4 << 20
+    assert L.hdp_aggregate_workspace_bytes(st.n, 32) > cap
+    shapes = (lib.Shape * 1)(lib.Shape(2048, 2048, 255))
+    p = lib.cost_params()
+    d = C.c_void_p(256)
+    assert L.hdp_match_layer_noalloc(d, d, shapes, 1, C.byref(st), 32, C.byref(p),
+                                     C.c_float(0.1), d, d, None) == -3
+    assert L.hdp_match_layer_noalloc(d, d, shapes, 1, None, 32, C.byref(p), C.c_float(0.1), d,
+                                     d, None) == -1
+    assert L.hdp_match_layer_noalloc(d, d, shapes, 1, C.byref(st), 300, C.byref(p),
+                                     C.c_float(0.1), d, d, None) == -1
+    # the single-pair 1344x1104 layer 0 at 10 labels per row fits
+    assert L.hdp_aggregate_workspace_bytes(1344 * 1104, 10) <= cap
