@@ -405,6 +405,88 @@ OR_API void or_predict_range(const int32_t *disp_up, int Hu, int Wu, int H, int 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Bayesian pixel interval prediction (Section 2.2 eq. dpm, Section 3.1 eq.
+ * crtr), as a table over the parent's label i = 0..d_up for one layer l with
+ * labels 0..dl:
+ *   1. P(D_{l+1}=i | D_l=j) = GMM_l(i - floor(j/S)),
+ *      GMM_l(o) = sum_k pi_k N(o | mu_k, sd_k) (Section 2.2);
+ *   2. P(D_l=j | D_{l+1}=i) is proportional to P(D_{l+1}=i | D_l=j) P(D_l=j)
+ *      (eq. dpm, prior[j] = the sampled distribution P(D_l=j), any scale),
+ *      each row i normalised to sum 1 (Section 3.1);
+ *   3. the interval starts at the label of highest probability in row i and is
+ *      extended by a label j while P(i,j) / (c + P(i,j)) >= delta, c the
+ *      probability already selected (eq. crtr).
+ * Readings (the paper leaves them open): ties of the argmax go to the lowest
+ * label; the interval grows by one of its two neighbour labels at a time, the
+ * more probable one (the lower on ties), and stops at the first neighbour that
+ * fails the test (the other one, no more probable, would fail too), so the
+ * result is an interval; the test is evaluated as p >= delta * (c + p).  A row
+ * whose products are all zero carries no information from the prior: it is
+ * taken without the prior (uniform P(D_l)); a row that is still zero gets the
+ * S labels below the parent's label, [S i, S i + S - 1] clipped to [0, dl]. */
+
+static double or_gauss(double o, double mu, double sd) {
+    double z = (o - mu) / sd;
+    return exp(-0.5 * z * z) / (sd * 2.5066282746310002);  /* sqrt(2 pi) */
+}
+
+OR_API void or_gmm_interval_table(int S, int dl, int d_up, int K, const double *pi,
+                                  const double *mu, const double *sd, const double *prior,
+                                  double delta, int32_t *lo_tab, int32_t *hi_tab) {
+    double *row = (double *)malloc(sizeof(double) * (size_t)(dl + 1));
+    for (int i = 0; i <= d_up; ++i) {
+        double tot = 0.0;
+        for (int pass = 0; pass < 2 && tot == 0.0; ++pass) {
+            tot = 0.0;
+            for (int j = 0; j <= dl; ++j) {
+                double q = 0.0;
+                for (int k = 0; k < K; ++k) q += pi[k] * or_gauss((double)(i - j / S), mu[k], sd[k]);
+                row[j] = pass == 0 ? q * prior[j] : q;
+                tot += row[j];
+            }
+        }
+        if (tot == 0.0) {
+            int a = S * i > dl ? dl : S * i, b = S * i + S - 1 > dl ? dl : S * i + S - 1;
+            lo_tab[i] = a; hi_tab[i] = b;
+            continue;
+        }
+        int best = 0;
+        for (int j = 0; j <= dl; ++j) {
+            row[j] /= tot;
+            if (row[j] > row[best]) best = j;
+        }
+        int lo = best, hi = best;
+        double c = row[best];
+        for (;;) {
+            int cand = -1;
+            if (lo > 0) cand = lo - 1;
+            if (hi < dl && (cand < 0 || row[hi + 1] > row[cand])) cand = hi + 1;
+            if (cand < 0) break;
+            double p = row[cand];
+            if (!(p >= delta * (c + p))) break;
+            c += p;
+            if (cand < lo) lo = cand; else hi = cand;
+        }
+        lo_tab[i] = lo; hi_tab[i] = hi;
+    }
+    free(row);
+}
+
+/* Interval of every pixel of layer l from the table of its parent's label:
+ * PixelIntv(x, y) = [lo_tab[i], hi_tab[i]], i = D_{l+1}(floor(x/S), floor(y/S)). */
+OR_API void or_predict_range_table(const int32_t *disp_up, int Hu, int Wu, int H, int W, int S,
+                                   const int32_t *lo_tab, const int32_t *hi_tab, int32_t *lo,
+                                   int32_t *hi) {
+    (void)Hu;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int i = disp_up[(y / S) * Wu + (x / S)];
+            lo[y * W + x] = lo_tab[i];
+            hi[y * W + x] = hi_tab[i];
+        }
+}
+
+/* ------------------------------------------------------------------------ */
 /* One layer of the method (Section 3): forest over the layer's graph, E over
  * each tree interval, aggregation over the forest and winner-takes-all,
  * one label slice at a time so that memory stays O(N).

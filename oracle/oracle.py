@@ -66,6 +66,8 @@ def _declare(L):
     L.or_aggregate_twopass.argtypes = [I, P, P, P, D, I, P, P, P]
     L.or_wta.argtypes = [I, I, P, P, P, P, P, P]
     L.or_predict_range.argtypes = [P, I, I, I, I, I, I, I, P, P]
+    L.or_gmm_interval_table.argtypes = [I, I, I, I, P, P, P, P, D, P, P]
+    L.or_predict_range_table.argtypes = [P, I, I, I, I, I, P, P, P, P]
     L.or_stereo_level.argtypes = [P, P, I, I, I, I, P, P, I, I, D, P,
                                   P, P, P, P, P, P, P, P, P, I, P, P, P]
     L.or_stereo_level.restype = I
@@ -207,6 +209,27 @@ def predict_range(disp_up, H, W, S, window, dmax_l):
     Hu, Wu = disp_up.shape
     lo = np.zeros((H, W), np.int32); hi = np.zeros((H, W), np.int32)
     lib().or_predict_range(_p(disp_up), Hu, Wu, H, W, S, window, dmax_l, _p(lo), _p(hi))
+    return lo, hi
+
+
+def gmm_interval_table(S, dl, d_up, pi, mu, sd, prior, delta):
+    """Per parent label i = 0..d_up the Bayesian interval (lo, hi) of layer l
+    (Section 2.2 eq. dpm, Section 3.1 eq. crtr)."""
+    pi = _c(pi, np.float64); mu = _c(mu, np.float64); sd = _c(sd, np.float64)
+    prior = _c(prior, np.float64)
+    assert len(pi) == len(mu) == len(sd) and len(prior) == dl + 1
+    lo = np.zeros(d_up + 1, np.int32); hi = np.zeros(d_up + 1, np.int32)
+    lib().or_gmm_interval_table(int(S), int(dl), int(d_up), len(pi), _p(pi), _p(mu), _p(sd),
+                                _p(prior), float(delta), _p(lo), _p(hi))
+    return lo, hi
+
+
+def predict_range_table(disp_up, H, W, S, lo_tab, hi_tab):
+    disp_up = _c(disp_up, np.int32)
+    Hu, Wu = disp_up.shape
+    lo = np.zeros((H, W), np.int32); hi = np.zeros((H, W), np.int32)
+    lib().or_predict_range_table(_p(disp_up), Hu, Wu, H, W, S, _p(_c(lo_tab, np.int32)),
+                                 _p(_c(hi_tab, np.int32)), _p(lo), _p(hi))
     return lo, hi
 
 

@@ -749,3 +749,94 @@ def test_hdp_rt_regime_equals_filtered_msf_of_ranks(orc, seed):
     f = img.astype(np.float64)
     r = orc.stereo_level(f, f, 15, 0, lo, hi, beta=(19, 20), rank=rank)
     assert edges_of_parent(r["parent"], W) == msf_equal_intervals(H, W, rank, lo, hi)
+
+
+# --- Bayesian interval prediction (Section 2.2 eq. dpm, Section 3.1 eq. crtr) ----
+
+def test_gmm_interval_table_golden(orc):
+    g = load("gmm_interval.json")
+    for case in g["cases"]:
+        lo, hi = orc.gmm_interval_table(g["S"], g["dl"], g["d_up"], g["pi"], g["mu"], g["sd"],
+                                        g["prior"], case["delta"])
+        assert lo.tolist() == case["lo"] and hi.tolist() == case["hi"], case
+
+
+def test_gmm_interval_prior_multiplies(orc):
+    """A prior that puts all mass on one label makes that label the whole
+    interval of every parent label (every other product is zero)."""
+    dl, d_up = 31, 15
+    for j0 in (0, 7, 31):
+        prior = np.zeros(dl + 1); prior[j0] = 3.0
+        lo, hi = orc.gmm_interval_table(2, dl, d_up, [0.6, 0.4], [0.0, 1.5], [1.0, 2.0], prior,
+                                        0.004)
+        assert (lo == j0).all() and (hi == j0).all()
+
+
+def test_gmm_interval_offset_sign_and_mixture_weights(orc):
+    """Two narrow components at offsets +2 (weight 0.7) and -2 (0.3): row i puts
+    its mass on the label blocks floor(j/S) = i - 2 and i + 2, the first one
+    heavier, so the interval is the block of i - 2 where it exists (offset
+    o = i - floor(j/S) of Section 2.2), else the block of i + 2."""
+    S, dl, d_up = 2, 31, 15
+    lo, hi = orc.gmm_interval_table(S, dl, d_up, [0.7, 0.3], [2.0, -2.0], [0.1, 0.1],
+                                    np.ones(dl + 1), 0.01)
+    for i in range(d_up + 1):
+        b = i - 2 if i >= 2 else i + 2
+        assert (lo[i], hi[i]) == (S * b, S * b + S - 1), i
+
+
+@pytest.mark.parametrize("S,dl", [(2, 31), (2, 30), (3, 20)])
+def test_gmm_interval_sharp_model_is_the_child_block(orc, S, dl):
+    """A single sharp component at offset 0 with a flat prior: the interval of
+    parent label i is its S child labels [S i, S i + S - 1] clipped to [0, dl],
+    i.e. the window reading with half-width 0."""
+    d_up = dl // S
+    lo, hi = orc.gmm_interval_table(S, dl, d_up, [1.0], [0.0], [0.05], np.ones(dl + 1), 0.01)
+    i = np.arange(d_up + 1)
+    np.testing.assert_array_equal(lo, np.minimum(S * i, dl))
+    np.testing.assert_array_equal(hi, np.minimum(S * i + S - 1, dl))
+
+
+def test_gmm_interval_zero_rows(orc):
+    """A prior with no mass where the model puts its mass leaves the model
+    alone; a model that is zero everywhere gives the child block."""
+    dl, d_up = 15, 7
+    prior = np.zeros(dl + 1)
+    a = orc.gmm_interval_table(2, dl, d_up, [1.0], [0.0], [0.05], prior, 0.01)
+    b = orc.gmm_interval_table(2, dl, d_up, [1.0], [0.0], [0.05], np.ones(dl + 1), 0.01)
+    np.testing.assert_array_equal(a[0], b[0]); np.testing.assert_array_equal(a[1], b[1])
+    lo, hi = orc.gmm_interval_table(2, dl, d_up, [1.0], [500.0], [0.01], np.ones(dl + 1), 0.01)
+    np.testing.assert_array_equal(lo, 2 * np.arange(d_up + 1))
+    np.testing.assert_array_equal(hi, 2 * np.arange(d_up + 1) + 1)
+
+
+def test_gmm_interval_invariants_random_models(orc):
+    """The argmax lies inside the interval, the interval grows while labels pass
+    eq. crtr, and widens as delta falls."""
+    rng = np.random.default_rng(12)
+    for t in range(20):
+        S, dl = 2, int(rng.integers(8, 64))
+        d_up = dl // S
+        K = int(rng.integers(1, 4))
+        pi = rng.dirichlet(np.ones(K)); mu = rng.uniform(-2, 2, K); sd = rng.uniform(0.3, 2, K)
+        prior = rng.integers(0, 5, dl + 1).astype(float) + 0.1
+        prev = None
+        for delta in (0.2, 0.05, 0.004):
+            lo, hi = orc.gmm_interval_table(S, dl, d_up, pi, mu, sd, prior, delta)
+            assert (lo <= hi).all() and (lo >= 0).all() and (hi <= dl).all()
+            if prev is not None:
+                assert (lo <= prev[0]).all() and (hi >= prev[1]).all()
+            prev = (lo, hi)
+
+
+def test_predict_range_table_is_the_window_for_window_tables(orc):
+    """With the table [S i - w, S i + S - 1 + w] clipped, the table-based
+    prediction equals the window prediction pixel by pixel."""
+    rng = np.random.default_rng(4)
+    H, W, S, w, dl = 17, 23, 2, 3, 31
+    up = rng.integers(0, dl // S + 1, ((H + 1) // 2, (W + 1) // 2))
+    i = np.arange(dl // S + 1)
+    lo_t = np.clip(S * i - w, 0, dl); hi_t = np.clip(S * i + S - 1 + w, 0, dl)
+    a = orc.predict_range_table(up, H, W, S, lo_t, hi_t)
+    b = orc.predict_range(up, H, W, S, w, dl)
+    np.testing.assert_array_equal(a[0], b[0]); np.testing.assert_array_equal(a[1], b[1])
