@@ -487,6 +487,67 @@ OR_API void or_predict_range_table(const int32_t *disp_up, int Hu, int Wu, int H
 }
 
 /* ------------------------------------------------------------------------ */
+/* Left-right consistency check: the stable pixels of Section 3.1 (found "by
+ * left-to-right consistency check" as in the cited refinement method).  A
+ * left-view pixel (x, y) with label d is stable when its match x - d lies in
+ * the image and the right view's label there differs from d by at most tol.
+ * Reading: the right view's labels come from the same method run on the
+ * horizontally mirrored pair with the right image as reference; disp_r_mir is
+ * that run's output in mirrored coordinates, so the right view's label of
+ * column x is disp_r_mir at column W-1-x.  tol = 0 (equal labels) is the
+ * usual check. */
+
+OR_API void or_lr_check(const int32_t *disp_l, const int32_t *disp_r_mir, int H, int W, int tol,
+                        uint8_t *stable) {
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int d = disp_l[y * W + x], xr = x - d;
+            int ok = 0;
+            if (xr >= 0 && xr < W) {
+                int dr = disp_r_mir[y * W + (W - 1 - xr)];
+                ok = (d - dr <= tol) && (dr - d <= tol);
+            }
+            stable[y * W + x] = (uint8_t)ok;
+        }
+}
+
+/* Sampled distribution P(D_l) (Section 3.1): the layer is cut into
+ * square x square blocks and the labels of the blocks' centres that are
+ * stable are counted, prior[j] = number of such centres with label j.
+ * Reading: the centres are (square/2 + k*square) in both directions, those
+ * inside the image (a partial border block whose centre falls outside is not
+ * sampled). */
+
+OR_API void or_sample_prior(const int32_t *disp, const uint8_t *stable, int H, int W, int square,
+                            int dmax, double *prior) {
+    for (int j = 0; j <= dmax; ++j) prior[j] = 0.0;
+    for (int y = square / 2; y < H; y += square)
+        for (int x = square / 2; x < W; x += square) {
+            int p = y * W + x;
+            if (!stable[p]) continue;
+            int d = disp[p];
+            if (d >= 0 && d <= dmax) prior[d] += 1.0;
+        }
+}
+
+/* Cost of the tree-based refinement that Section 3.3 says can be added after
+ * each layer (the non-local refinement of the cited tree methods): a stable
+ * pixel p costs |x - D(p)| at label x, an unstable one costs 0, so that after
+ * aggregating over the same forest every pixel is pulled towards the labels of
+ * the stable pixels near it on the tree.  cost[N][dmax+1]; entries outside a
+ * pixel's [lo, hi] (lo/hi may be NULL for the full range) are NaN. */
+
+OR_API void or_refine_cost(const int32_t *disp, const uint8_t *stable, int N, int dmax,
+                           const int32_t *lo, const int32_t *hi, double *cost) {
+    for (int p = 0; p < N; ++p)
+        for (int x = 0; x <= dmax; ++x) {
+            double *c = cost + (size_t)p * (dmax + 1) + x;
+            if (lo && (x < lo[p] || x > hi[p])) { *c = NAN; continue; }
+            *c = stable[p] ? fabs((double)(x - disp[p])) : 0.0;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
 /* One layer of the method (Section 3): forest over the layer's graph, E over
  * each tree interval, aggregation over the forest and winner-takes-all,
  * one label slice at a time so that memory stays O(N).

@@ -68,6 +68,9 @@ def _declare(L):
     L.or_predict_range.argtypes = [P, I, I, I, I, I, I, I, P, P]
     L.or_gmm_interval_table.argtypes = [I, I, I, I, P, P, P, P, D, P, P]
     L.or_predict_range_table.argtypes = [P, I, I, I, I, I, P, P, P, P]
+    L.or_lr_check.argtypes = [P, P, I, I, I, P]
+    L.or_sample_prior.argtypes = [P, P, I, I, I, I, P]
+    L.or_refine_cost.argtypes = [P, P, I, I, P, P, P]
     L.or_stereo_level.argtypes = [P, P, I, I, I, I, P, P, I, I, D, P,
                                   P, P, P, P, P, P, P, P, P, I, P, P, P]
     L.or_stereo_level.restype = I
@@ -231,6 +234,51 @@ def predict_range_table(disp_up, H, W, S, lo_tab, hi_tab):
     lib().or_predict_range_table(_p(disp_up), Hu, Wu, H, W, S, _p(_c(lo_tab, np.int32)),
                                  _p(_c(hi_tab, np.int32)), _p(lo), _p(hi))
     return lo, hi
+
+
+def lr_check(disp_l, disp_r_mir, tol=0):
+    """Stable pixels (uint8 0/1) of the left view given the right view's labels
+    in mirrored coordinates (the left-reference output of the mirrored pair)."""
+    disp_l = _c(disp_l, np.int32); disp_r_mir = _c(disp_r_mir, np.int32)
+    H, W = disp_l.shape
+    out = np.zeros((H, W), np.uint8)
+    lib().or_lr_check(_p(disp_l), _p(disp_r_mir), H, W, int(tol), _p(out))
+    return out
+
+
+def mirrored(img):
+    """The pair's image flipped left to right (the reference for the right view)."""
+    return np.ascontiguousarray(np.asarray(img)[:, ::-1])
+
+
+def sample_prior(disp, stable, dmax, square=5):
+    disp = _c(disp, np.int32); stable = _c(stable, np.uint8)
+    H, W = disp.shape
+    prior = np.zeros(dmax + 1, np.float64)
+    lib().or_sample_prior(_p(disp), _p(stable), H, W, int(square), int(dmax), _p(prior))
+    return prior
+
+
+def refine_cost(disp, stable, dmax, lo=None, hi=None):
+    disp = _c(disp, np.int32).ravel(); stable = _c(stable, np.uint8).ravel()
+    N = disp.size
+    cost = np.zeros((N, dmax + 1), np.float64)
+    lo = None if lo is None else _c(lo, np.int32).ravel()
+    hi = None if hi is None else _c(hi, np.int32).ravel()
+    lib().or_refine_cost(_p(disp), _p(stable), N, int(dmax), _p(lo), _p(hi), _p(cost))
+    return cost
+
+
+def refine_level(forest, disp, stable, dmax, sigma=0.1, lo=None, hi=None):
+    """Tree-based refinement of one layer's labels over its forest (Section
+    3.3 closing paragraph): refinement cost, two-pass aggregation, WTA.
+    forest: dict with parent, wgt, order (root_forest / stereo_level output).
+    Returns (labels, c1, c2)."""
+    cost = refine_cost(disp, stable, dmax, lo, hi)
+    agg = aggregate_twopass(forest["parent"], forest["wgt"], forest["order"], sigma,
+                            np.nan_to_num(cost, nan=0.0))
+    agg[np.isnan(cost)] = np.inf
+    return wta(agg, lo, hi)
 
 
 def stereo_level(left, right, dmax, level, pix_lo=None, pix_hi=None, beta=(19, 20),

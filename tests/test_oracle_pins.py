@@ -840,3 +840,73 @@ def test_predict_range_table_is_the_window_for_window_tables(orc):
     a = orc.predict_range_table(up, H, W, S, lo_t, hi_t)
     b = orc.predict_range(up, H, W, S, w, dl)
     np.testing.assert_array_equal(a[0], b[0]); np.testing.assert_array_equal(a[1], b[1])
+
+
+# --- left-right check, sampled prior, tree refinement (Sections 3.1, 3.3) ---------
+
+def test_lr_check_golden(orc):
+    g = load("lr_check.json")
+    dl = np.array([g["disp_left"]], np.int32)
+    dr_mir = np.array([g["disp_right"][::-1]], np.int32)  # the mirrored run's coordinates
+    assert orc.lr_check(dl, dr_mir, 0).ravel().tolist() == g["stable_tol0"]
+    assert orc.lr_check(dl, dr_mir, 1).ravel().tolist() == g["stable_tol1"]
+
+
+def test_lr_check_of_a_shifted_pair_is_stable(orc):
+    """A textured pair whose right view is the left one shifted by d0 (constant
+    ground truth): the left run finds d0, the run on the mirrored pair (right
+    image as reference) finds d0 for the right view, and the check marks the
+    interior stable.  A wrong mirroring or a wrong match direction fails."""
+    rng = np.random.default_rng(21)
+    H, W, d0, dmax = 24, 64, 5, 9
+    wide = rng.integers(0, 256, (H, W + d0, 3)).astype(np.uint8)
+    left = np.ascontiguousarray(wide[:, :W])             # L(x) = wide(x)
+    right = np.ascontiguousarray(wide[:, d0:])           # R(x) = wide(x + d0): L(x) = R(x - d0)
+    fl, fr = left.astype(np.float64), right.astype(np.float64)
+    dL = orc.stereo_level(fl, fr, dmax, 0, sigma=0.02)["disp"]
+    dM = orc.stereo_level(orc.mirrored(fr), orc.mirrored(fl), dmax, 0, sigma=0.02)["disp"]
+    st = orc.lr_check(dL, dM, 0)
+    inner = np.s_[:, d0 + dmax + 1: W - dmax - 1]
+    assert (dL[inner] == d0).mean() > 0.95
+    assert st[inner].mean() > 0.95
+    assert st[:, :d0].sum() == 0  # matches outside the right image are never stable
+
+
+def test_sample_prior_hand_case(orc):
+    disp = np.zeros((10, 10), np.int32); st = np.ones((10, 10), np.uint8)
+    for (y, x), d, s in (((2, 2), 3, 1), ((2, 7), 3, 1), ((7, 2), 5, 1), ((7, 7), 1, 0)):
+        disp[y, x] = d; st[y, x] = s
+    disp[0, 0] = 4  # not a centre
+    assert orc.sample_prior(disp, st, 5).tolist() == [0, 0, 0, 2, 0, 1]
+    # a 7-row layer has one row of centres (y = 2; the block of rows 5..9 has its centre outside)
+    assert orc.sample_prior(disp[:7], st[:7], 5).tolist() == [0, 0, 0, 2, 0, 0]
+
+
+def test_refine_closed_forms(orc):
+    """(a) With sigma -> 0 and no zero-weight edge each pixel keeps its own
+    cost, so stable pixels keep their labels; (b) with no stable pixel every
+    cost is 0 and the lowest label wins; (c) on a constant-colour strip every
+    edge weight is 0 (s = 1), so every pixel aggregates the whole strip and
+    takes the lower median of the stable pixels' labels."""
+    H, W, dmax = 6, 9, 7
+    img = np.zeros((H, W, 3), np.float64)
+    img[..., 0] = (np.arange(H * W).reshape(H, W) * 37) % 251 + 1  # no equal neighbours
+    disp = np.random.default_rng(3).integers(0, dmax + 1, (H, W)).astype(np.int32)
+
+    def mst_forest(im):
+        h, w = im.shape[:2]
+        key = orc.edge_keys(im, 0)
+        return orc.root_forest(h, w, orc.kruskal(h, w, key)[0], key, 0)
+    f = mst_forest(img)
+    st = np.ones((H, W), np.uint8)
+    d, _, _ = orc.refine_level(f, disp, st, dmax, sigma=1e-6)
+    np.testing.assert_array_equal(d, disp.ravel())
+    d, _, _ = orc.refine_level(f, disp, np.zeros((H, W), np.uint8), dmax)
+    assert (d == 0).all()
+    strip = np.full((1, 11, 3), 80.0)
+    ds = np.array([[6, 1, 1, 7, 3, 0, 2, 6, 6, 5, 4]], np.int32)
+    ss = np.array([[1, 1, 1, 0, 1, 0, 1, 1, 0, 1, 0]], np.uint8)
+    fs = mst_forest(strip)
+    d, _, _ = orc.refine_level(fs, ds, ss, 7)
+    vals = np.sort(ds[ss == 1])  # 6 1 1 3 2 6 5 -> 1 1 2 3 5 6 6, median 3
+    assert (d == vals[(len(vals) - 1) // 2]).all()
