@@ -117,42 +117,51 @@ __global__ void k_prologue(int64_t n, const float *__restrict__ rw,
                            uint32_t *__restrict__ fill1, int width,
                            uint64_t *__restrict__ maps, int64_t map_words) {
     __shared__ int32_t sph[HDP_MAX_PHASES + 1];
-    int64_t r = gtid();
+    const int64_t r = gtid();  // the grid covers the rows and the tiles, one each per thread
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // The phase table and the row's links and weight are loaded together,
+    // before any of them is used (a thread past the last row reads the last
+    // row and drops it).
+    const int64_t rc = r < n ? r : n - 1;
+    const int tx = (int)threadIdx.x;
+    const int32_t ph = phase_ptr[tx <= HDP_MAX_PHASES ? tx : HDP_MAX_PHASES];
     int K = info[HDP_INFO_N_PHASES];
+    const int pr = prow[rc];
+    const uint8_t hv = heavy[rc];
+    const float wf = rw[rc];
     K = K < 1 ? 1 : (K > HDP_MAX_PHASES ? HDP_MAX_PHASES : K);
-    if ((int)threadIdx.x <= K) sph[threadIdx.x] = phase_ptr[threadIdx.x];
+    if (tx <= HDP_MAX_PHASES) sph[tx] = ph;
     __syncthreads();
-    // Narrow rows: mark unwritten the rows of the up passes' outputs that a
-    // tile polls (chain heads below a light edge, read by their parent's tile,
-    // and the last row of every up-pass tile, read for the next tile's carry),
-    // and the tile maps.
-    if (fill0 || fill1) {
-        for (int64_t i = r; i < n; i += stride) {
-            int lo = 0, hi = K - 1;  // phase of row i
+    if (r < n) {
+        // Narrow rows: mark unwritten the rows of the up passes' outputs that a
+        // tile polls (chain heads below a light edge, read by their parent's
+        // tile, and the last row of every up-pass tile, read for the next
+        // tile's carry).
+        if (fill0 || fill1) {
+            int lo = 0, hi = K - 1;  // phase of row r
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (sph[mid] <= i) lo = mid; else hi = mid - 1;
+                if (sph[mid] <= r) lo = mid; else hi = mid - 1;
             }
-            const bool last = (sph[lo + 1] - i) % rows == 0;
-            if (!last && (prow[i] < 0 || heavy[i])) continue;
-            for (int c = 0; c < width; ++c) {
-                if (fill0) fill0[i * width + c] = kSentF;
-                if (fill1) fill1[i * width + c] = kSentF;
+            const bool last = (sph[lo + 1] - (int)r) % rows == 0;
+            if (last || (pr >= 0 && !hv)) {
+                for (int c = 0; c < width; ++c) {
+                    if (fill0) fill0[r * width + c] = kSentF;
+                    if (fill1) fill1[r * width + c] = kSentF;
+                }
             }
         }
-    }
-    for (int64_t i = r; i < map_words; i += stride) maps[i] = kSentD;
-    if (r < n) {
-        if (prow[r] < 0) {
+        if (pr < 0) {
             s[r] = 0.0;
             om[r] = 1.0;
         } else {
-            double w = (double)rw[r];
+            const double w = (double)wf;
             s[r] = exp(-w * inv_sigma);
             om[r] = -expm1(-2.0 * w * inv_sigma);
         }
     }
+    // the tile maps, marked unpublished
+    for (int64_t i = r; i < map_words; i += stride) maps[i] = kSentD;
     if (r < tiles) {
 #pragma unroll
         for (int k = 0; k < 2 * kPassSets; ++k) flags[k * tiles + r] = 0;
@@ -584,97 +593,144 @@ __global__ void __launch_bounds__(kBlock)
     const int j0 = jl * CPT;
     const bool active = g < A.groups;
 
-    // fused matching: pixel, column and interval of every row, loaded first
+    // Stage 1: loads that do not depend on other tiles of this launch.  Every
+    // load of the stage is issued before any loaded value is used: rows past
+    // the end of the phase read a valid row of it instead and their results
+    // are dropped, and the right-image reads of labels past the interval or
+    // the image border read valid pixels whose values are not used.  So no
+    // load waits behind a branch or behind another row's loads.
+    int rr[kRPG], rc[kRPG];
+#pragma unroll
+    for (int i = 0; i < kRPG; ++i) {
+        const int li = g * kRPG + i;
+        const int r = UP ? r1 - 1 - (tl * rows + li) : r0 + tl * rows + li;
+        const bool in = active && (UP ? r >= r0 : r < r1);
+        rr[i] = in ? r : -1;
+        rc[i] = in ? r : (UP ? r1 - 1 : r0);
+    }
+    // fused matching: pixel, column and interval of every row
     int fv[kRPG], fx[kRPG], flh[kRPG];
     if (FUSE) {
 #pragma unroll
         for (int i = 0; i < kRPG; ++i) {
-            int li = g * kRPG + i;
-            int r = UP ? r1 - 1 - (tl * rows + li) : r0 + tl * rows + li;
-            bool in = active && (UP ? r >= r0 : r < r1);
-            fv[i] = in ? A.node[r] : 0;
-            fx[i] = in && UP ? A.rx[r] : 0;
-            flh[i] = in ? A.rlh[r] : 0;
+            fv[i] = A.node[rc[i]];
+            if (UP) fx[i] = A.rx[rc[i]];
+            flh[i] = A.rlh[rc[i]];
         }
     }
-
-    // stage 1: loads that do not depend on other tiles of this launch; the up
-    // pass also marks its rows of the down pass's output as unwritten
     double av[kRPG];
     double bv[kRPG][CPT];
-    int rr[kRPG], x0[kRPG], x1[kRPG], x2[kRPG];
+    int x0[kRPG], x1[kRPG], x2[kRPG];
+    {
+        float v[kRPG][CPT];
+        uint8_t hf[kRPG];
+        double sf[kRPG], of[kRPG];
+        int pf[kRPG];
+        float4 Lp[FUSE && UP ? kRPG : 1];
+        float4 Rp[FUSE && UP ? kRPG : 1][CPT];
 #pragma unroll
-    for (int i = 0; i < kRPG; ++i) {
-        int li = g * kRPG + i;
-        int r = UP ? r1 - 1 - (tl * rows + li) : r0 + tl * rows + li;
-        bool in = active && (UP ? r >= r0 : r < r1);
-        rr[i] = in ? r : -1;
-        av[i] = 1.0;
-        x0[i] = x1[i] = x2[i] = -1;
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) bv[i][c] = 0.0;
-        if (!in) continue;
-        float v[CPT];
-        if (FUSE && UP) {  // cost of labels lo + j0 .. (columns past hi hold 0)
-            const float4 Lp = A.imL[fv[i]];
-            const int a = flh[i] & 0xFFFF, b = flh[i] >> 16;
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                const int label = a + j0 + c;
-                v[c] = label <= b ? match_cost(Lp, A.imR, fv[i], fx[i], label, A.cp) : 0.f;
+        for (int i = 0; i < kRPG; ++i) {
+            const int r = rc[i];
+            if (UP) {
+                const int rn = r + 1 < r1 ? r + 1 : r;  // next row: heavy flag and coefficient
+                hf[i] = A.heavy[rn];
+                sf[i] = A.s[rn];
+                x0[i] = A.lc[r];
+                x1[i] = A.lc[A.n + r];
+                x2[i] = A.lc[2 * A.n + r];
+            } else {
+                hf[i] = A.heavy[r];
+                sf[i] = A.s[r];
+                of[i] = A.om[r];
+                pf[i] = A.prow[r];
             }
-        } else {
-            load_cols<CPT>(A.src + (int64_t)r * w + j0, v);
+            if (FUSE && UP) {
+                Lp[i] = A.imL[fv[i]];
+                const int a = flh[i] & 0xFFFF;
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) Rp[i][c] = A.imR[match_src(fv[i], fx[i], a + j0 + c)];
+            } else {
+                load_cols<CPT>(A.src + (int64_t)r * w + j0, v[i]);
+            }
         }
-        if (UP) {
-            // heavy flag and coefficient of the next row, loaded together
-            const int rn = r + 1 < r1 ? r + 1 : r;
-            const bool hn = A.heavy[rn];
-            const double sn = A.s[rn];
-            av[i] = (r + 1 < r1 && hn) ? sn : 0.0;
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) bv[i][c] = (double)v[c];
-            x0[i] = A.lc[r];
-            x1[i] = A.lc[A.n + r];
-            x2[i] = A.lc[2 * A.n + r];
-            // rows of the down pass's output that its tiles poll: parents of a
-            // chain head (a light child) and the last row of every down tile
-            if (A.fill && (x0[i] >= 0 || (r - r0 + 1) % rows == 0)) {
+        for (int i = 0; i < kRPG; ++i) {
+            const bool in = rr[i] >= 0;
+            const int r = rc[i];
+            if (FUSE && UP) {  // cost of labels lo + j0 .. (columns past hi hold 0)
+                const int a = flh[i] & 0xFFFF, b = flh[i] >> 16;
 #pragma unroll
-                for (int c = 0; c < CPT; ++c)
-                    reinterpret_cast<uint32_t *>(A.fill)[(int64_t)r * w + j0 + c] = kSentF;
+                for (int c = 0; c < CPT; ++c) {
+                    const int label = a + j0 + c;
+                    v[i][c] = label <= b ? match_cost_px(Lp[i], Rp[i][c], fx[i] - label < 0, A.cp)
+                                         : 0.f;
+                }
             }
-        } else {
-            // heavy flag, coefficients and parent row, loaded together
-            const bool hv = A.heavy[r];
-            const double sr = A.s[r], o = A.om[r];
-            const int pr = A.prow[r];
-            av[i] = hv ? sr : 0.0;
+            if (UP) {
+                av[i] = !in ? 1.0 : (r + 1 < r1 && hf[i]) ? sf[i] : 0.0;
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) bv[i][c] = o * (double)v[c];
-            x0[i] = hv ? -1 : pr;
+                for (int c = 0; c < CPT; ++c) bv[i][c] = in ? (double)v[i][c] : 0.0;
+                if (!in) x0[i] = x1[i] = x2[i] = -1;
+            } else {
+                av[i] = !in ? 1.0 : hf[i] ? sf[i] : 0.0;
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) bv[i][c] = in ? of[i] * (double)v[i][c] : 0.0;
+                x0[i] = (in && !hf[i]) ? pf[i] : -1;
+                x1[i] = x2[i] = -1;
+            }
         }
     }
+    // The up pass marks as unwritten its rows of the down pass's output that
+    // the down pass's tiles poll: parents of a chain head (a light child) and
+    // the last row of every down tile.  The marks are stored when the tile is
+    // done with everything else (the down pass is a later launch).
+    uint32_t fill_mask = 0;
+    if (UP && A.fill) {
+#pragma unroll
+        for (int i = 0; i < kRPG; ++i) {
+            const int r = rr[i];
+            if (r >= 0 && (x0[i] >= 0 || (r - r0 + 1) % rows == 0)) fill_mask |= 1u << i;
+        }
+    }
+    auto mark_fill = [&]() {
+        if (!UP || !fill_mask) return;
+#pragma unroll
+        for (int i = 0; i < kRPG; ++i) {
+            if (!(fill_mask >> i & 1u)) continue;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+                reinterpret_cast<uint32_t *>(A.fill)[(int64_t)rr[i] * w + j0 + c] = kSentF;
+        }
+    };
 
-    // stage 2: gather the rows of the previous phase, each once it is written
+    // Stage 2: gather the rows of the previous phase.  The first read of every
+    // gathered row (and its coefficient) is issued at once; a row that is
+    // still unwritten is then polled on its own.
+    {
+        constexpr int kG = UP ? 3 : 1;  // gathered rows per row
+        float gv[kRPG][kG][CPT];
+        double gs[kRPG][kG];
+        bool ok[kRPG][kG];
 #pragma unroll
-    for (int i = 0; i < kRPG; ++i) {
-        float v[CPT];
-        if (UP) {
-            int xs[3] = {x0[i], x1[i], x2[i]};
+        for (int i = 0; i < kRPG; ++i) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                if (xs[m] < 0) continue;
-                double sc = A.s[xs[m]];
-                poll_cols<CPT>(A.dst + (int64_t)xs[m] * w + j0, v, A.err, true);
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
+            for (int m = 0; m < kG; ++m) {
+                const int x = m == 0 ? x0[i] : m == 1 ? x1[i] : x2[i];
+                const int xr = x >= 0 ? x : rc[i];
+                gs[i][m] = UP ? A.s[xr] : A.s[rc[i]];
+                ok[i][m] = poll_cols<CPT>(A.dst + (int64_t)xr * w + j0, gv[i][m], A.err, false);
             }
-        } else if (x0[i] >= 0) {
-            double sc = A.s[rr[i]];
-            poll_cols<CPT>(A.dst + (int64_t)x0[i] * w + j0, v, A.err, true);
+        }
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
+        for (int i = 0; i < kRPG; ++i) {
+#pragma unroll
+            for (int m = 0; m < kG; ++m) {
+                const int x = m == 0 ? x0[i] : m == 1 ? x1[i] : x2[i];
+                if (x < 0) continue;
+                if (!ok[i][m]) poll_cols<CPT>(A.dst + (int64_t)x * w + j0, gv[i][m], A.err, true);
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) bv[i][c] += gs[i][m] * (double)gv[i][m][c];
+            }
         }
     }
 
@@ -790,7 +846,10 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
     const bool carried = !(tl == 0 || s_first == 0.0 || !active);
-    if (!kWta && !carried) return;  // every row was carry-independent
+    if (!kWta && !carried) {  // every row was carry-independent
+        mark_fill();
+        return;
+    }
 
     if (carried) {
         // Carry-in: the last row of the preceding tile, or across tiles without
@@ -889,6 +948,7 @@ __global__ void __launch_bounds__(kBlock)
             }
         }
     }
+    mark_fill();
 }
 
 // --- workspace --------------------------------------------------------------------

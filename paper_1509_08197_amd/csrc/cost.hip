@@ -25,11 +25,14 @@ __global__ void __launch_bounds__(kBlock) k_cost_volume(
     const int a = node ? lo[v] : 0;
     const int b = node ? hi[v] : g.dmax[p.pair];
     const float4 L = left[v];
+    float4 R[CPT];  // every right pixel is read before any is used
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) R[c] = right[match_src(v, p.x, a + j0 + c)];
     float out[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         int label = a + j0 + c;
-        out[c] = label <= b ? match_cost(L, right, v, p.x, label, cp) : 0.f;
+        out[c] = label <= b ? match_cost_px(L, R[c], p.x - label < 0, cp) : 0.f;
     }
     float *dst = cost + r * width + j0;
     if (CPT == 4)

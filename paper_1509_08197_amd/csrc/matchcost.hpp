@@ -11,18 +11,32 @@ struct CostParams {
     float a_c, tau_c, a_g, tau_g;
 };
 
-// Colour term from the channel differences, gradient term from the difference
-// of the gx numerators (gray gradient = gx / 6).  A label that reaches past the
-// left image border costs both truncations.
-__device__ __forceinline__ float match_cost(float4 L, const float4 *__restrict__ right, int v,
-                                            int x, int label, const CostParams &c) {
+// Right-image pixel that label `label` of pixel v (column x) is compared with.
+// A label reaching past the left border is clamped to the row's first pixel:
+// the read stays inside the image and its value is not used (see below), so
+// callers can issue the load before they know whether it is needed.
+__device__ __forceinline__ int match_src(int v, int x, int label) {
+    return v - (label < x ? label : x);
+}
+
+// Cost from the two pixels: colour term from the channel differences,
+// gradient term from the difference of the gx numerators (gray gradient =
+// gx / 6).  A label that reaches past the left image border (outside) costs
+// both truncations.
+__device__ __forceinline__ float match_cost_px(float4 L, float4 R, bool outside,
+                                               const CostParams &c) {
     // no contraction into FMAs: every kernel that inlines this computes the same floats
 #pragma clang fp contract(off)
-    if (x - label < 0) return c.a_c * c.tau_c + c.a_g * c.tau_g;
-    float4 R = right[v - label];
-    float col = (fabsf(L.x - R.x) + fabsf(L.y - R.y) + fabsf(L.z - R.z)) / 3.0f;
-    float gd = fabsf(L.w - R.w) / 6.0f;
-    return c.a_c * fminf(col, c.tau_c) + c.a_g * fminf(gd, c.tau_g);
+    const float col = (fabsf(L.x - R.x) + fabsf(L.y - R.y) + fabsf(L.z - R.z)) / 3.0f;
+    const float gd = fabsf(L.w - R.w) / 6.0f;
+    const float m = c.a_c * fminf(col, c.tau_c) + c.a_g * fminf(gd, c.tau_g);
+    const float sat = c.a_c * c.tau_c + c.a_g * c.tau_g;
+    return outside ? sat : m;
+}
+
+__device__ __forceinline__ float match_cost(float4 L, const float4 *__restrict__ right, int v,
+                                            int x, int label, const CostParams &c) {
+    return match_cost_px(L, right[match_src(v, x, label)], x - label < 0, c);
 }
 
 }  // namespace hdp
