@@ -196,6 +196,30 @@ HDP_API hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int
                           void *stream);
 
 /*
+ * Random spanning tree RT (Section 4.1: the edges are shuffled at random and
+ * union-find keeps an edge when it joins two trees), or with pixel intervals
+ * its disparity forest (HDP+RT, the DT rules applied in the shuffled order).
+ *   edge_rank  int32 [2n] on the device, one random number per grid edge,
+ *              drawn by the caller: edge_rank[2p] for the edge from pixel p
+ *              to its right neighbour, edge_rank[2p+1] for the edge to the
+ *              pixel below (entries of edges that leave the image are
+ *              ignored).  Only the low 31 bits are used.  The shuffled order
+ *              is ascending (rank, edge id); uniform random ranks give a
+ *              uniformly random order of the edges up to ties.
+ * Every other argument, the exact regime, the outputs and the errors are
+ * those of hdp_build_tree; the edge weights stored in the forest (and used by
+ * the aggregation) are still the colour weights of eq. weight.  Returns
+ * HDP_EINVAL if edge_rank is NULL.
+ */
+HDP_API hdp_status hdp_build_random_tree(const float *img, const hdp_shape *shapes,
+                                         int32_t n_pairs, int32_t level,
+                                         const int32_t *edge_rank, const int32_t *pix_lo,
+                                         const int32_t *pix_hi, int32_t max_width,
+                                         int32_t beta_num, int32_t beta_den, int32_t width,
+                                         const hdp_forest *f, void *ws, size_t ws_bytes,
+                                         void *stream);
+
+/*
  * Canonical level order of a forest built by hdp_build_tree: order (pixel ids
  * sorted by depth, ties by id), level_ptr and info[HDP_INFO_N_LEVELS].  This
  * is the breadth-first processing order of the tree passes of Section 1; the
@@ -341,6 +365,89 @@ HDP_API hdp_status hdp_match_layer_noalloc(const float *left, const float *right
 HDP_API hdp_status hdp_predict_range(const int32_t *disp_upper, const hdp_shape *upper,
                              const hdp_shape *lower, int32_t n_pairs, int32_t S,
                              int32_t window, int32_t *pix_lo, int32_t *pix_hi, void *stream);
+
+/*
+ * Bayesian pixel interval prediction (Section 2.2 eq. dpm, Section 3.1 eq.
+ * crtr) for layer l of a batch, as a table over the parent's label.
+ *   gmm        HOST pointer: the mixture model GMM_l of the offset
+ *              o = D_{l+1} - floor(D_l / S): K components (1..HDP_MAX_GMM)
+ *              with weights pi >= 0, means mu and standard deviations sd > 0
+ *              (trained parameters; the paper does not print them).
+ *   prior      device double [n_pairs][prior_stride]: the sampled
+ *              distribution P(D_l = j) of each pair, j = 0..dmax_l (any
+ *              non-negative scale; prior_stride >= every pair's dmax_l + 1).
+ *   delta      threshold delta_l of eq. crtr (the paper uses
+ *              delta_l = delta_0 * S^l), 0 < delta <= 1.
+ *   lo_tab, hi_tab  device int32 [n_pairs][tab_stride] (tab_stride >= every
+ *              pair's dmax_{l+1} + 1): the interval of parent label i.
+ *   max_width  device int32 (1 word) or NULL: receives the widest interval.
+ * Per pair and parent label i, with P(i, j) proportional to
+ * GMM_l(i - floor(j/S)) * prior[j] and normalised over j = 0..dmax_l: the
+ * interval starts at the label of highest P(i, j) (the lowest on ties) and
+ * grows by its more probable neighbour label (the lower on ties) while
+ * P / (c + P) >= delta, tested as P >= delta * (c + P) in FP64 with c the
+ * probability selected so far; it stops at the first neighbour that fails.
+ * A row whose products are all zero is taken without the prior; a row that is
+ * still zero gets [S i, S i + S - 1] clipped to [0, dmax_l].
+ * upper/lower: HOST shapes of layers l+1 and l, as hdp_predict_range.
+ */
+#define HDP_MAX_GMM 16
+typedef struct {
+    int32_t K;
+    double pi[HDP_MAX_GMM], mu[HDP_MAX_GMM], sd[HDP_MAX_GMM];
+} hdp_gmm;
+
+HDP_API hdp_status hdp_interval_table(const hdp_shape *upper, const hdp_shape *lower,
+                                      int32_t n_pairs, int32_t S, const hdp_gmm *gmm,
+                                      const double *prior, int32_t prior_stride, double delta,
+                                      int32_t *lo_tab, int32_t *hi_tab, int32_t tab_stride,
+                                      int32_t *max_width, void *stream);
+
+/*
+ * Pixel intervals of layer l from a table (hdp_interval_table): pixel (x, y)
+ * of a pair takes [lo_tab[i], hi_tab[i]] of that pair's row,
+ * i = disp_upper at (floor(x/S), floor(y/S)).  pix_lo/pix_hi: int32 [n_l].
+ */
+HDP_API hdp_status hdp_predict_range_table(const int32_t *disp_upper, const hdp_shape *upper,
+                                           const hdp_shape *lower, int32_t n_pairs, int32_t S,
+                                           const int32_t *lo_tab, const int32_t *hi_tab,
+                                           int32_t tab_stride, int32_t *pix_lo, int32_t *pix_hi,
+                                           void *stream);
+
+/*
+ * Left-right consistency check and its uses (Section 3.1: the stable pixels
+ * behind the sampled prior P(D_l); Section 3.3: the tree-based refinement that
+ * can follow each layer).  The right view's labels are those of the method run
+ * on the horizontally mirrored pair with the right image as reference.
+ *
+ * hdp_mirror: out(x, y) = rgb(W-1-x, y) for every pair, uint8 [n][3] (give it
+ *   the right image for the reference view and the left image as the second
+ *   view of the mirrored pair).
+ * hdp_lr_check: stable[v] (uint8 0/1) for every pixel (x, y) of the left view
+ *   with label d = disp_left[v]: 1 iff 0 <= x - d < W and
+ *   |d - R| <= tol, R = the right view's label at column x - d, read from
+ *   disp_right at column x - d, or at column W-1-(x-d) when right_mirrored is
+ *   nonzero (disp_right is then the mirrored run's output as it stands).
+ * hdp_sample_prior: prior (device double [n_pairs][prior_stride], overwritten)
+ *   counts, per pair and label j = 0..dmax, the stable pixels among the
+ *   centres (square/2 + k*square, square/2 + m*square) inside the image whose
+ *   label is j (Section 3.1 uses square = 5).  prior_stride >= dmax + 1.
+ * hdp_refine_cost: in the forest's volume layout float[n][width], the cost
+ *   |x - disp[v]| of label x = lo(v) + c at a stable pixel v, 0 at an
+ *   unstable one and in padding columns; hdp_aggregate + hdp_wta over the same
+ *   forest then give the refined labels.
+ * shapes: HOST shapes of the layer (n_pairs pairs).
+ */
+HDP_API hdp_status hdp_mirror(const uint8_t *rgb, const hdp_shape *shapes, int32_t n_pairs,
+                              uint8_t *out, void *stream);
+HDP_API hdp_status hdp_lr_check(const int32_t *disp_left, const int32_t *disp_right,
+                                int32_t right_mirrored, const hdp_shape *shapes, int32_t n_pairs,
+                                int32_t tol, uint8_t *stable, void *stream);
+HDP_API hdp_status hdp_sample_prior(const int32_t *disp, const uint8_t *stable,
+                                    const hdp_shape *shapes, int32_t n_pairs, int32_t square,
+                                    double *prior, int32_t prior_stride, void *stream);
+HDP_API hdp_status hdp_refine_cost(const int32_t *disp, const uint8_t *stable, const hdp_forest *f,
+                                   int32_t width, float *cost, void *stream);
 
 /*
  * Batch plan: the whole top-down loop of the method (Section 3) for a fixed

@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libhdp.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "plan.cpp", "pyramid.hip", "cost.hip", "tree.hip", "aggregate.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "interval.hip", "refine.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

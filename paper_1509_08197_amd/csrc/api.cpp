@@ -203,10 +203,11 @@ size_t hdp_build_tree_workspace_bytes(int64_t n) {
     return n < 1 ? 0 : hdp::tree_workspace_bytes(n);
 }
 
-hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int32_t n_pairs,
-                          int32_t level, const int32_t *pix_lo, const int32_t *pix_hi,
-                          int32_t max_width, int32_t beta_num, int32_t beta_den, int32_t width,
-                          const hdp_forest *f, void *ws, size_t ws_bytes, void *stream) {
+static hdp_status build_tree(const float *img, const hdp_shape *shapes, int32_t n_pairs,
+                             int32_t level, const int32_t *pix_lo, const int32_t *pix_hi,
+                             int32_t max_width, int32_t beta_num, int32_t beta_den,
+                             int32_t width, const int32_t *edge_rank, const hdp_forest *f,
+                             void *ws, size_t ws_bytes, void *stream) {
     if (!img || !ws) return HDP_EINVAL;
     if ((pix_lo == nullptr) != (pix_hi == nullptr)) return HDP_EINVAL;
     if (level < 0 || level > 8) return HDP_EINVAL;
@@ -227,8 +228,27 @@ hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int32_t n_p
     }
     if (ws_bytes < hdp::tree_workspace_bytes(n)) return HDP_EWORKSPACE;
     (void)hipGetLastError();
-    hdp::launch_build_tree(img, g, pix_lo, pix_hi, max_width, width, *f, ws, (hipStream_t)stream);
+    hdp::launch_build_tree(img, g, pix_lo, pix_hi, max_width, width, edge_rank, *f, ws,
+                           (hipStream_t)stream);
     return last_hip();
+}
+
+hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int32_t n_pairs,
+                          int32_t level, const int32_t *pix_lo, const int32_t *pix_hi,
+                          int32_t max_width, int32_t beta_num, int32_t beta_den, int32_t width,
+                          const hdp_forest *f, void *ws, size_t ws_bytes, void *stream) {
+    return build_tree(img, shapes, n_pairs, level, pix_lo, pix_hi, max_width, beta_num, beta_den,
+                      width, nullptr, f, ws, ws_bytes, stream);
+}
+
+hdp_status hdp_build_random_tree(const float *img, const hdp_shape *shapes, int32_t n_pairs,
+                                 int32_t level, const int32_t *edge_rank, const int32_t *pix_lo,
+                                 const int32_t *pix_hi, int32_t max_width, int32_t beta_num,
+                                 int32_t beta_den, int32_t width, const hdp_forest *f, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    if (!edge_rank) return HDP_EINVAL;
+    return build_tree(img, shapes, n_pairs, level, pix_lo, pix_hi, max_width, beta_num, beta_den,
+                      width, edge_rank, f, ws, ws_bytes, stream);
 }
 
 hdp_status hdp_level_order(const hdp_forest *f, void *ws, size_t ws_bytes, void *stream) {
@@ -368,6 +388,113 @@ hdp_status hdp_predict_range(const int32_t *disp_upper, const hdp_shape *upper,
     }
     (void)hipGetLastError();
     hdp::launch_predict_range(disp_upper, gu, gl, S, window, pix_lo, pix_hi, (hipStream_t)stream);
+    return last_hip();
+}
+
+static hdp_status layer_pair_geoms(const hdp_shape *upper, const hdp_shape *lower,
+                                   int32_t n_pairs, int32_t S, LevelGeom *gu, LevelGeom *gl) {
+    if (S < 2) return HDP_EINVAL;
+    hdp_status st = make_geom(upper, n_pairs, 1, gu);
+    if (st != HDP_OK) return st;
+    st = make_geom(lower, n_pairs, 0, gl);
+    if (st != HDP_OK) return st;
+    for (int i = 0; i < n_pairs; ++i) {
+        if (gu->H[i] != (gl->H[i] + S - 1) / S || gu->W[i] != (gl->W[i] + S - 1) / S ||
+            gu->dmax[i] != gl->dmax[i] / S)
+            return HDP_ESHAPE;
+    }
+    return HDP_OK;
+}
+
+hdp_status hdp_interval_table(const hdp_shape *upper, const hdp_shape *lower, int32_t n_pairs,
+                              int32_t S, const hdp_gmm *gmm, const double *prior,
+                              int32_t prior_stride, double delta, int32_t *lo_tab,
+                              int32_t *hi_tab, int32_t tab_stride, int32_t *max_width,
+                              void *stream) {
+    if (!gmm || !prior || !lo_tab || !hi_tab) return HDP_EINVAL;
+    if (!(delta > 0.0 && delta <= 1.0)) return HDP_EINVAL;
+    if (gmm->K < 1 || gmm->K > HDP_MAX_GMM) return HDP_EINVAL;
+    hdp::GmmParams m{};
+    m.K = gmm->K;
+    for (int k = 0; k < gmm->K; ++k) {
+        if (!(gmm->pi[k] >= 0.0) || !(gmm->sd[k] > 0.0) || !(gmm->mu[k] == gmm->mu[k]))
+            return HDP_EINVAL;
+        m.pi[k] = gmm->pi[k];
+        m.mu[k] = gmm->mu[k];
+        m.sd[k] = gmm->sd[k];
+    }
+    LevelGeom gu, gl;
+    hdp_status st = layer_pair_geoms(upper, lower, n_pairs, S, &gu, &gl);
+    if (st != HDP_OK) return st;
+    for (int i = 0; i < n_pairs; ++i)
+        if (prior_stride < gl.dmax[i] + 1 || tab_stride < gu.dmax[i] + 1) return HDP_EINVAL;
+    (void)hipGetLastError();
+    hdp::launch_interval_table(gu, gl, S, m, prior, prior_stride, delta, lo_tab, hi_tab,
+                               tab_stride, max_width, (hipStream_t)stream);
+    return last_hip();
+}
+
+hdp_status hdp_predict_range_table(const int32_t *disp_upper, const hdp_shape *upper,
+                                   const hdp_shape *lower, int32_t n_pairs, int32_t S,
+                                   const int32_t *lo_tab, const int32_t *hi_tab,
+                                   int32_t tab_stride, int32_t *pix_lo, int32_t *pix_hi,
+                                   void *stream) {
+    if (!disp_upper || !lo_tab || !hi_tab || !pix_lo || !pix_hi) return HDP_EINVAL;
+    LevelGeom gu, gl;
+    hdp_status st = layer_pair_geoms(upper, lower, n_pairs, S, &gu, &gl);
+    if (st != HDP_OK) return st;
+    for (int i = 0; i < n_pairs; ++i)
+        if (tab_stride < gu.dmax[i] + 1) return HDP_EINVAL;
+    (void)hipGetLastError();
+    hdp::launch_predict_range_table(disp_upper, gu, gl, S, lo_tab, hi_tab, tab_stride, pix_lo,
+                                    pix_hi, (hipStream_t)stream);
+    return last_hip();
+}
+
+hdp_status hdp_mirror(const uint8_t *rgb, const hdp_shape *shapes, int32_t n_pairs, uint8_t *out,
+                      void *stream) {
+    if (!rgb || !out || rgb == out) return HDP_EINVAL;
+    LevelGeom g;
+    hdp_status st = make_geom(shapes, n_pairs, 0, &g);
+    if (st != HDP_OK) return st;
+    (void)hipGetLastError();
+    hdp::launch_mirror(rgb, g, out, (hipStream_t)stream);
+    return last_hip();
+}
+
+hdp_status hdp_lr_check(const int32_t *disp_left, const int32_t *disp_right,
+                        int32_t right_mirrored, const hdp_shape *shapes, int32_t n_pairs,
+                        int32_t tol, uint8_t *stable, void *stream) {
+    if (!disp_left || !disp_right || !stable || tol < 0) return HDP_EINVAL;
+    LevelGeom g;
+    hdp_status st = make_geom(shapes, n_pairs, 0, &g);
+    if (st != HDP_OK) return st;
+    (void)hipGetLastError();
+    hdp::launch_lr_check(disp_left, disp_right, right_mirrored != 0, g, tol, stable,
+                         (hipStream_t)stream);
+    return last_hip();
+}
+
+hdp_status hdp_sample_prior(const int32_t *disp, const uint8_t *stable, const hdp_shape *shapes,
+                            int32_t n_pairs, int32_t square, double *prior, int32_t prior_stride,
+                            void *stream) {
+    if (!disp || !stable || !prior || square < 1) return HDP_EINVAL;
+    LevelGeom g;
+    hdp_status st = make_geom(shapes, n_pairs, 0, &g);
+    if (st != HDP_OK) return st;
+    if (prior_stride < max_dmax(g) + 1) return HDP_EINVAL;
+    (void)hipGetLastError();
+    hdp::launch_sample_prior(disp, stable, g, square, prior, prior_stride, (hipStream_t)stream);
+    return last_hip();
+}
+
+hdp_status hdp_refine_cost(const int32_t *disp, const uint8_t *stable, const hdp_forest *f,
+                           int32_t width, float *cost, void *stream) {
+    if (!disp || !stable || !cost || !f || f->n < 1 || !f->node || !f->lo || !f->hi)
+        return HDP_EINVAL;
+    if (width < 1 || width > HDP_MAX_LABELS) return HDP_EINVAL;
+    (void)hipGetLastError();
+    hdp::launch_refine_cost(disp, stable, *f, width, cost, (hipStream_t)stream);
     return last_hip();
 }
 

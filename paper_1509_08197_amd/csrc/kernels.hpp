@@ -9,6 +9,30 @@ void launch_pyramid(const uint8_t *const *rgb, int views, const LevelGeom *geoms
                     float *const *levels, hipStream_t st);
 void launch_predict_range(const int32_t *disp_up, const LevelGeom &gu, const LevelGeom &gl, int S,
                           int window, int32_t *lo, int32_t *hi, hipStream_t st);
+
+// Mixture model of one layer's label offsets, passed to kernels by value.
+struct GmmParams {
+    int K;
+    double pi[HDP_MAX_GMM], mu[HDP_MAX_GMM], sd[HDP_MAX_GMM];
+};
+void launch_interval_table(const LevelGeom &gu, const LevelGeom &gl, int S, const GmmParams &m,
+                           const double *prior, int prior_stride, double delta, int32_t *lo_tab,
+                           int32_t *hi_tab, int tab_stride, int32_t *max_width, hipStream_t st);
+// First sample centre of each pair and centres per row (sampled prior).
+struct CentreTable {
+    int64_t off[HDP_MAX_PAIRS + 1];
+    int32_t nx[HDP_MAX_PAIRS];
+};
+void launch_mirror(const uint8_t *in, const LevelGeom &g, uint8_t *out, hipStream_t st);
+void launch_lr_check(const int32_t *dl, const int32_t *dr, int right_mirrored, const LevelGeom &g,
+                     int tol, uint8_t *stable, hipStream_t st);
+void launch_sample_prior(const int32_t *disp, const uint8_t *stable, const LevelGeom &g,
+                         int square, double *prior, int prior_stride, hipStream_t st);
+void launch_refine_cost(const int32_t *disp, const uint8_t *stable, const hdp_forest &f,
+                        int width, float *cost, hipStream_t st);
+void launch_predict_range_table(const int32_t *disp_up, const LevelGeom &gu, const LevelGeom &gl,
+                                int S, const int32_t *lo_tab, const int32_t *hi_tab,
+                                int tab_stride, int32_t *lo, int32_t *hi, hipStream_t st);
 void launch_cost_volume(const float *left, const float *right, const LevelGeom &g,
                         const int32_t *node, const int32_t *lo, const int32_t *hi, int width,
                         const hdp_cost_params &p, float *cost, hipStream_t st);
@@ -16,8 +40,8 @@ void launch_wta(const LevelGeom &g, const int32_t *node, const int32_t *lo, cons
                 int width, const float *agg, int32_t *disp, hipStream_t st);
 size_t tree_workspace_bytes(int64_t n);
 void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
-                       const int32_t *phi, int max_width, int width, const hdp_forest &f,
-                       void *ws, hipStream_t st);
+                       const int32_t *phi, int max_width, int width, const int32_t *rank,
+                       const hdp_forest &f, void *ws, hipStream_t st);
 void launch_level_order(const hdp_forest &f, void *ws, hipStream_t st);
 void launch_set_weights(const hdp_forest &f, const float *w, hipStream_t st);
 size_t aggregate_workspace_bytes(int64_t n, int width);

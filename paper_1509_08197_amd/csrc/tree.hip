@@ -230,7 +230,8 @@ __device__ __forceinline__ int pair_min(int32_t *pk, unsigned long long *pv, int
 
 __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
     const float4 *__restrict__ img, LevelGeom g, const int32_t *__restrict__ plo,
-    const int32_t *__restrict__ phi, int max_width, int32_t *__restrict__ comp0,
+    const int32_t *__restrict__ phi, int max_width, const int32_t *__restrict__ rank,
+    int32_t *__restrict__ comp0,
     uint64_t *__restrict__ cw, uint64_t *__restrict__ best0, uint64_t *__restrict__ best1,
     int32_t *__restrict__ lmin, int32_t *__restrict__ croot, int32_t *__restrict__ mnroot,
     uint8_t *__restrict__ intree, uint64_t *__restrict__ E, int32_t *__restrict__ R,
@@ -277,6 +278,15 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
         const int64_t vr = hr ? v + 1 : v, vd = hd ? v + t.W : v;
         const int64_t vl = hl ? v - 1 : v, vu = hu ? v - t.W : v;
         const float4 a = img[v], ar = img[vr], ad = img[vd], al = img[vl], au = img[vu];
+        // random spanning tree: Kruskal's order is the edges' random ranks
+        // (31 bits, so no rank is the absent-edge marker) instead of the colour key
+        uint32_t qr = 0, qd = 0, ql = 0, qu = 0;
+        if (rank) {
+            qr = (uint32_t)rank[2 * v] & 0x7fffffffu;
+            qd = (uint32_t)rank[2 * v + 1] & 0x7fffffffu;
+            ql = (uint32_t)rank[2 * vl] & 0x7fffffffu;
+            qu = (uint32_t)rank[2 * vu + 1] & 0x7fffffffu;
+        }
         bool sr = true, sd = true, sl = true, su = true;
         if (plo) {
             const int lo = plo[v], hi = phi[v];
@@ -289,10 +299,10 @@ __global__ __launch_bounds__(kLocalThreads) void k_local_msf(
             sl = lo == lol && hi == hil;
             su = lo == lou && hi == hiu;
         }
-        if (hr && sr) kr = edge_key(a, ar, scale);
-        if (hd && sd) kd = edge_key(a, ad, scale);
-        if (hl && sl) kL[ly] = edge_key(al, a, scale);
-        if (hu && su) kU[lx] = edge_key(au, a, scale);
+        if (hr && sr) kr = rank ? qr : edge_key(a, ar, scale);
+        if (hd && sd) kd = rank ? qd : edge_key(a, ad, scale);
+        if (hl && sl) kL[ly] = rank ? ql : edge_key(al, a, scale);
+        if (hu && su) kU[lx] = rank ? qu : edge_key(au, a, scale);
     }
     kR[i] = kr;
     kD[i] = kd;
@@ -1804,8 +1814,8 @@ static void counting_sort(const int32_t *src, int32_t *dst, int32_t *pos_of, int
 }
 
 void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
-                       const int32_t *phi, int max_width, int width, const hdp_forest &f,
-                       void *ws, hipStream_t st) {
+                       const int32_t *phi, int max_width, int width, const int32_t *rank,
+                       const hdp_forest &f, void *ws, hipStream_t st) {
     int64_t n = g.off[g.n_pairs];
     size_t bytes;
     TreeWs t = carve_tree_ws(ws, n, &bytes);
@@ -1837,7 +1847,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
 
     // 1-2: spanning forest (tile-local phase, full-grid rounds, one-workgroup tail)
     k_tree_init<<<1, FLAG_WORDS, 0, st>>>(t.flags, t.ctr, f.info);
-    k_local_msf<<<n_tiles, kLocalThreads, 0, st>>>(im, g, plo, phi, max_width, t.comp0, t.cw,
+    k_local_msf<<<n_tiles, kLocalThreads, 0, st>>>(im, g, plo, phi, max_width, rank, t.comp0, t.cw,
                                                    t.best0, t.best1, t.lmin, t.croot, t.mnroot,
                                                    t.intree, t.E, t.Rall, t.ctr, f.info);
     int bv_rounds = ceil_log2(border_px) + 1;

@@ -51,6 +51,25 @@ class Params(C.Structure):
                 ("cost", CostParams)]
 
 
+MAX_GMM = 16
+
+
+class Gmm(C.Structure):
+    _fields_ = [("K", C.c_int32), ("pi", C.c_double * MAX_GMM), ("mu", C.c_double * MAX_GMM),
+                ("sd", C.c_double * MAX_GMM)]
+
+
+def make_gmm(pi, mu, sd) -> Gmm:
+    """Mixture model GMM_l of the label offsets of one layer (Section 2.2)."""
+    K = len(pi)
+    assert 1 <= K <= MAX_GMM and len(mu) == K and len(sd) == K
+    g = Gmm()
+    g.K = K
+    for k in range(K):
+        g.pi[k], g.mu[k], g.sd[k] = float(pi[k]), float(mu[k]), float(sd[k])
+    return g
+
+
 class ForestStruct(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in (
         "parent", "depth", "tree", "lo", "hi", "row", "wgt", "order", "level_ptr", "node",
@@ -82,6 +101,9 @@ def _declare(L):
     L.hdp_build_tree_workspace_bytes.argtypes = [I64]; L.hdp_build_tree_workspace_bytes.restype = SZ
     L.hdp_build_tree.argtypes = [P, P, I32, I32, P, P, I32, I32, I32, I32,
                                  C.POINTER(ForestStruct), P, SZ, P]
+    L.hdp_build_random_tree.argtypes = [P, P, I32, I32, P, P, P, I32, I32, I32, I32,
+                                        C.POINTER(ForestStruct), P, SZ, P]
+    L.hdp_build_random_tree.restype = I32
     L.hdp_forest_read_info.argtypes = [C.POINTER(ForestStruct), P, P, P]
     L.hdp_level_order.argtypes = [C.POINTER(ForestStruct), P, SZ, P]
     L.hdp_cost_volume.argtypes = [P, P, P, I32, C.POINTER(ForestStruct), I32,
@@ -99,6 +121,17 @@ def _declare(L):
     L.hdp_match_layer_noalloc.restype = I32
     L.hdp_match_layer_noalloc_max_bytes.argtypes = []
     L.hdp_match_layer_noalloc_max_bytes.restype = SZ
+    L.hdp_interval_table.argtypes = [P, P, I32, I32, C.POINTER(Gmm), P, I32, C.c_double, P, P,
+                                     I32, P, P]
+    L.hdp_interval_table.restype = I32
+    L.hdp_predict_range_table.argtypes = [P, P, P, I32, I32, P, P, I32, P, P, P]
+    L.hdp_predict_range_table.restype = I32
+    L.hdp_mirror.argtypes = [P, P, I32, P, P]
+    L.hdp_lr_check.argtypes = [P, P, I32, P, I32, I32, P, P]
+    L.hdp_sample_prior.argtypes = [P, P, P, I32, I32, P, I32, P]
+    L.hdp_refine_cost.argtypes = [P, P, C.POINTER(ForestStruct), I32, P, P]
+    for name in ("hdp_mirror", "hdp_lr_check", "hdp_sample_prior", "hdp_refine_cost"):
+        getattr(L, name).restype = I32
     L.hdp_forest_set_weights.argtypes = [C.POINTER(ForestStruct), P, P]
     L.hdp_forest_set_weights.restype = I32
     L.hdp_predict_range.argtypes = [P, P, P, I32, I32, I32, P, P, P]
@@ -273,8 +306,10 @@ _ws_agg = Workspace()
 def build_tree(img: torch.Tensor, shapes, level: int, pix_lo=None, pix_hi=None,
                max_width: int = 0, beta=(19, 20), width: Optional[int] = None,
                read_info: bool = False, forest: Optional[Forest] = None, ws=None,
-               level_order: bool = True) -> Forest:
+               level_order: bool = True, rank: Optional[torch.Tensor] = None) -> Forest:
     """Minimum spanning tree (pix_lo None) or disparity forest of one layer.
+    rank: None, or int32 [2n] random edge ranks: the random spanning tree RT
+    (and its disparity forest) instead of the MST.
     level_order: also fill the canonical (depth, id) order and level_ptr."""
     n = n_pixels(shapes)
     assert img.shape == (n, 4) and img.dtype == torch.float32 and img.is_contiguous()
@@ -290,9 +325,17 @@ def build_tree(img: torch.Tensor, shapes, level: int, pix_lo=None, pix_hi=None,
         forest.level = level
     wsb = lib().hdp_build_tree_workspace_bytes(n)
     w = (ws or _ws_tree).get(wsb, dev)
-    _check("hdp_build_tree", lib().hdp_build_tree(
-        _ptr(img), _shapes(shapes), len(shapes), level, _ptr(pix_lo), _ptr(pix_hi), int(max_width),
-        int(beta[0]), int(beta[1]), int(width), C.byref(forest.st), _ptr(w), wsb, _stream()))
+    if rank is None:
+        _check("hdp_build_tree", lib().hdp_build_tree(
+            _ptr(img), _shapes(shapes), len(shapes), level, _ptr(pix_lo), _ptr(pix_hi),
+            int(max_width), int(beta[0]), int(beta[1]), int(width), C.byref(forest.st), _ptr(w),
+            wsb, _stream()))
+    else:
+        assert rank.shape == (2 * n,) and rank.dtype == torch.int32 and rank.is_contiguous()
+        _check("hdp_build_random_tree", lib().hdp_build_random_tree(
+            _ptr(img), _shapes(shapes), len(shapes), level, _ptr(rank), _ptr(pix_lo),
+            _ptr(pix_hi), int(max_width), int(beta[0]), int(beta[1]), int(width),
+            C.byref(forest.st), _ptr(w), wsb, _stream()))
     if level_order:
         _check("hdp_level_order",
                lib().hdp_level_order(C.byref(forest.st), _ptr(w), wsb, _stream()))
@@ -431,6 +474,89 @@ def predict_range(disp_upper: torch.Tensor, upper_shapes, lower_shapes, S: int =
     return lo, hi
 
 
+def interval_table(upper_shapes, lower_shapes, S: int, gmm: Gmm, prior: torch.Tensor,
+                   delta: float):
+    """Bayesian interval table of one layer (Section 2.2 eq. dpm, Section 3.1
+    eq. crtr).  prior: float64 [n_pairs, stride] on the GPU (P(D_l = j) per
+    pair).  Returns (lo_tab, hi_tab, max_width) with the tables int32
+    [n_pairs, d_up + 1] and max_width a 1-element device tensor."""
+    assert prior.dtype == torch.float64 and prior.is_cuda and prior.is_contiguous()
+    n = len(lower_shapes)
+    assert prior.shape[0] == n
+    tab_stride = max(d for _, _, d in upper_shapes) + 1
+    lo = torch.empty((n, tab_stride), dtype=torch.int32, device=prior.device)
+    hi = torch.empty_like(lo)
+    mw = torch.empty(1, dtype=torch.int32, device=prior.device)
+    _check("hdp_interval_table", lib().hdp_interval_table(
+        _shapes(upper_shapes), _shapes(lower_shapes), n, S, C.byref(gmm), _ptr(prior),
+        int(prior.shape[1]), float(delta), _ptr(lo), _ptr(hi), tab_stride, _ptr(mw), _stream()))
+    return lo, hi, mw
+
+
+def predict_range_table(disp_upper: torch.Tensor, upper_shapes, lower_shapes, S: int,
+                        lo_tab: torch.Tensor, hi_tab: torch.Tensor, out=None):
+    n = n_pixels(lower_shapes)
+    if out is None:
+        lo = torch.empty(n, dtype=torch.int32, device=disp_upper.device)
+        hi = torch.empty(n, dtype=torch.int32, device=disp_upper.device)
+    else:
+        lo, hi = out
+    _check("hdp_predict_range_table", lib().hdp_predict_range_table(
+        _ptr(disp_upper), _shapes(upper_shapes), _shapes(lower_shapes), len(lower_shapes), S,
+        _ptr(lo_tab), _ptr(hi_tab), int(lo_tab.shape[1]), _ptr(lo), _ptr(hi), _stream()))
+    return lo, hi
+
+
+# --- left-right check, sampled prior, refinement (Sections 3.1, 3.3) ------------------
+
+def mirror(rgb: torch.Tensor, shapes) -> torch.Tensor:
+    """Every pair's image flipped left to right (uint8 [n, 3])."""
+    assert rgb.is_cuda and rgb.dtype == torch.uint8 and rgb.is_contiguous()
+    out = torch.empty_like(rgb)
+    _check("hdp_mirror", lib().hdp_mirror(_ptr(rgb), _shapes(shapes), len(shapes), _ptr(out),
+                                          _stream()))
+    return out
+
+
+def right_view(left_rgb, right_rgb, shapes, **kw):
+    """The method run on the mirrored pair with the right image as reference:
+    the right view's labels, in mirrored coordinates (see lr_check)."""
+    return hdp_stereo(mirror(right_rgb, shapes), mirror(left_rgb, shapes), shapes, **kw)
+
+
+def lr_check(disp_left: torch.Tensor, disp_right: torch.Tensor, shapes, tol: int = 0,
+             right_mirrored: bool = True) -> torch.Tensor:
+    """Stable pixels (uint8 0/1) of the left view (left-right consistency)."""
+    out = torch.empty(disp_left.shape, dtype=torch.uint8, device=disp_left.device)
+    _check("hdp_lr_check", lib().hdp_lr_check(_ptr(disp_left), _ptr(disp_right),
+                                              1 if right_mirrored else 0, _shapes(shapes),
+                                              len(shapes), int(tol), _ptr(out), _stream()))
+    return out
+
+
+def sample_prior(disp: torch.Tensor, stable: torch.Tensor, shapes, square: int = 5,
+                 stride: Optional[int] = None) -> torch.Tensor:
+    """P(D_l) per pair: counts of the labels of the stable block centres
+    (float64 [n_pairs, stride], Section 3.1)."""
+    stride = stride or max(d for _, _, d in shapes) + 1
+    out = torch.empty((len(shapes), stride), dtype=torch.float64, device=disp.device)
+    _check("hdp_sample_prior", lib().hdp_sample_prior(
+        _ptr(disp), _ptr(stable), _shapes(shapes), len(shapes), int(square), _ptr(out), stride,
+        _stream()))
+    return out
+
+
+def refine(forest: Forest, disp: torch.Tensor, stable: torch.Tensor, sigma: float = 0.1,
+           ws=None):
+    """Tree-based refinement of one layer's labels over its forest (Section 3.3):
+    refinement cost, aggregation, winner-takes-all.  Returns (agg, labels)."""
+    cost = torch.empty((forest.n, forest.width), dtype=torch.float32, device=disp.device)
+    _check("hdp_refine_cost", lib().hdp_refine_cost(_ptr(disp), _ptr(stable), C.byref(forest.st),
+                                                    int(forest.width), _ptr(cost), _stream()))
+    agg = aggregate(forest, cost, sigma, ws=ws)
+    return agg, wta(agg, forest.shapes, forest)
+
+
 # --- diagnostics -----------------------------------------------------------------------
 
 TIMER = dict(up_pass=0, down_pass=1, cost=2)
@@ -470,13 +596,15 @@ class LevelResult:
 
 
 def stereo_level(left_img, right_img, shapes, level, pix_lo=None, pix_hi=None, max_width=0,
-                 beta=(19, 20), sigma=0.1, params=None, keep=False, ws=None) -> LevelResult:
+                 beta=(19, 20), sigma=0.1, params=None, keep=False, ws=None,
+                 rank=None) -> LevelResult:
     """One layer (Section 3): forest, restricted cost, aggregation, WTA.
     keep: run the three steps apart and also return the cost and aggregated
-    volumes (and fill the forest's level order); otherwise one fused call."""
+    volumes (and fill the forest's level order); otherwise one fused call.
+    rank: random edge ranks of the layer (random spanning tree RT) or None."""
     ws = ws or {}
     f = build_tree(left_img, shapes, level, pix_lo, pix_hi, max_width=max_width, beta=beta,
-                   read_info=False, ws=ws.get("tree"), level_order=keep)
+                   read_info=False, ws=ws.get("tree"), level_order=keep, rank=rank)
     if not keep:
         agg, disp = match_layer(left_img, right_img, shapes, f, sigma, params, ws=ws.get("agg"))
         return LevelResult(level=level, shapes=list(shapes), forest=f, disp=disp, pix_lo=pix_lo,
@@ -489,28 +617,60 @@ def stereo_level(left_img, right_img, shapes, level, pix_lo=None, pix_hi=None, m
 
 
 def hdp_stereo(left_rgb: torch.Tensor, right_rgb: torch.Tensor, shapes, S=2, L=3, window=4,
-               beta=(19, 20), sigma=0.1, params=None, keep=False, ws=None) -> List[LevelResult]:
+               beta=(19, 20), sigma=0.1, params=None, keep=False, ws=None,
+               ranks=None, gmm=None, priors=None, delta0=0.004,
+               gmm_max_width=None) -> List[LevelResult]:
     """Top-down HDP (Section 3): layer L over [0, d_L] with the MST, then for
     l = L-1..0 interval prediction -> disparity forest -> cost -> aggregation
-    -> WTA.  left_rgb/right_rgb: uint8 [n0, 3].  Returns results indexed by layer."""
+    -> WTA.  left_rgb/right_rgb: uint8 [n0, 3].  ranks: None (MST), or per
+    layer the random edge ranks of HDP+RT (see draw_edge_ranks).
+
+    Interval prediction: the window [S i - window, S i + S - 1 + window] by
+    default; with gmm (per layer l < L a Gmm, see make_gmm) and priors (per
+    layer l < L a float64 [n_pairs, stride] device tensor of P(D_l)), the
+    Bayesian table with delta_l = delta0 * S^l.  gmm_max_width: a bound on the
+    table's widths (then nothing synchronises); None reads the widest interval
+    back from the device.  Returns results indexed by layer."""
     lv = level_shapes(shapes, S, L)
     lp, rp = pyramid_views(left_rgb, right_rgb, shapes, S, L)
+    rk = (lambda l: None) if ranks is None else (lambda l: ranks[l])
     res: List[Optional[LevelResult]] = [None] * (L + 1)
-    res[L] = stereo_level(lp[L], rp[L], lv[L], L, sigma=sigma, params=params, keep=keep, ws=ws)
+    res[L] = stereo_level(lp[L], rp[L], lv[L], L, sigma=sigma, params=params, keep=keep, ws=ws,
+                          rank=rk(L))
     for l in range(L - 1, -1, -1):
-        lo, hi = predict_range(res[l + 1].disp, lv[l + 1], lv[l], S, window)
-        mw = min(S + 2 * window, max(d for _, _, d in lv[l]) + 1)
+        dl = max(d for _, _, d in lv[l])
+        if gmm is None:
+            lo, hi = predict_range(res[l + 1].disp, lv[l + 1], lv[l], S, window)
+            mw = min(S + 2 * window, dl + 1)
+        else:
+            lo_t, hi_t, mwt = interval_table(lv[l + 1], lv[l], S, gmm[l], priors[l],
+                                             delta0 * S ** l)
+            lo, hi = predict_range_table(res[l + 1].disp, lv[l + 1], lv[l], S, lo_t, hi_t)
+            mw = int(mwt.item()) if gmm_max_width is None else min(int(gmm_max_width), dl + 1)
         res[l] = stereo_level(lp[l], rp[l], lv[l], l, lo, hi, max_width=mw, beta=beta,
-                              sigma=sigma, params=params, keep=keep, ws=ws)
+                              sigma=sigma, params=params, keep=keep, ws=ws, rank=rk(l))
     return res
 
 
+def draw_edge_ranks(shapes, S: int = 2, L: int = 3, generator=None, device="cuda"):
+    """One random int32 rank in [0, 2^31) per grid edge (2 per pixel) of every
+    layer: the random shuffle of the random spanning tree RT (Section 4.1).
+    Returns a list indexed by layer."""
+    out = []
+    for lvl in level_shapes(shapes, S, L):
+        n = n_pixels(lvl)
+        out.append(torch.randint(0, 2 ** 31 - 1, (2 * n,), dtype=torch.int32, device=device,
+                                 generator=generator))
+    return out
+
+
 def full_range(left_rgb, right_rgb, shapes, sigma=0.1, params=None, keep=False,
-               ws=None) -> LevelResult:
-    """Full-range MST aggregation + WTA at the input resolution (the baseline
-    the method speeds up)."""
+               ws=None, rank=None) -> LevelResult:
+    """Full-range MST (or, with rank, RT) aggregation + WTA at the input
+    resolution (the baseline the method speeds up)."""
     lp, rp = pyramid_views(left_rgb, right_rgb, shapes, 2, 0)
-    return stereo_level(lp[0], rp[0], shapes, 0, sigma=sigma, params=params, keep=keep, ws=ws)
+    return stereo_level(lp[0], rp[0], shapes, 0, sigma=sigma, params=params, keep=keep, ws=ws,
+                        rank=rank)
 
 
 class CapturedStep:

@@ -217,6 +217,37 @@ def small_scene(seed: int, H: int, W: int, dmax: int, sigma_noise: float = 2.0) 
     return planes_scene(seed, H=H, W=W, dmax=dmax, sigma_noise=sigma_noise)
 
 
+def gmm_params(seed: int, L: int, K: int = 3, sd_range=(0.3, 0.7)):
+    """Stand-ins for the trained mixture models GMM_l (Section 2.2) of the label
+    offset o = D_{l+1} - floor(D_l / S), one per layer l < L: K components with
+    weights from a flat Dirichlet draw, means uniform in [-0.5, 0.5] and
+    standard deviations uniform in sd_range.  (The paper trains them by EM on
+    Middlebury ground truth and does not print them.)  Returns a list of
+    (pi, mu, sd) arrays."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(L):
+        pi = rng.dirichlet(np.ones(K))
+        mu = rng.uniform(-0.5, 0.5, K)
+        sd = rng.uniform(sd_range[0], sd_range[1], K)
+        out.append((pi, mu, sd))
+    return out
+
+
+def label_prior(gt: np.ndarray, S: int, level: int, dmax_l: int, square: int = 5) -> np.ndarray:
+    """Stand-in for the sampled distribution P(D_l) of Section 3.1: the paper
+    takes the disparities of the centres of 5x5 squares of layer l (computed
+    and checked for left-right consistency); here the ground truth at those
+    centres, in layer-l labels floor(d / S^l), counted per label 0..dmax_l."""
+    f = S ** level
+    Hl, Wl = -(-gt.shape[0] // f), -(-gt.shape[1] // f)
+    ys = np.arange(square // 2, Hl, square)
+    xs = np.arange(square // 2, Wl, square)
+    d = gt[np.minimum(ys * f, gt.shape[0] - 1)][:, np.minimum(xs * f, gt.shape[1] - 1)]
+    lab = np.clip(np.floor(d / f).astype(np.int64), 0, dmax_l)
+    return np.bincount(lab.ravel(), minlength=dmax_l + 1).astype(np.float64)
+
+
 def random_cost(seed: int, n_rows: int, width: int) -> np.ndarray:
     """Non-negative float32 cost rows (exactly representable values)."""
     rng = np.random.default_rng(seed)

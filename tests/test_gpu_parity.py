@@ -725,3 +725,362 @@ def test_interval_bound_violation_is_reported(H):
     assert np.all(flo >= 0) and np.all(fhi <= dmax) and np.all(fhi - flo + 1 <= 10)
     d = disp.cpu().numpy()
     assert np.all((d >= flo) & (d <= fhi))
+
+
+# --- random spanning tree RT (Section 4.1) -------------------------------------------
+
+def rank_np(seed, n):
+    return np.random.default_rng(seed).integers(0, 2 ** 31 - 1, 2 * n).astype(np.int32)
+
+
+def rt_reference(orc, img, Hh, Ww, level, rank, lo=None, hi=None, beta=(19, 20)):
+    """Oracle RT (or HDP+RT forest): Kruskal in (rank, id) order, colour weights."""
+    key = orc.edge_keys(img.astype(np.float64), level)
+    okey = np.where(key >= 0, rank.astype(np.int64), -1)
+    in_tree, tlo, thi, _ = orc.kruskal(Hh, Ww, okey, lo, hi, beta=beta)
+    return orc.root_forest(Hh, Ww, in_tree, key, level), tlo, thi
+
+
+@pytest.mark.parametrize("Hh,Ww,seed", [(120, 160, 1), (31, 47, 2), (1, 64, 3), (64, 1, 4),
+                                        (1, 1, 5), (2, 2, 6), (200, 300, 7)])
+def test_rt_bit_exact(H, orc, Hh, Ww, seed):
+    pair = scenes.small_scene(seed, Hh, Ww, 15)
+    shapes = [(Hh, Ww, 15)]
+    lv = H.pyramid(rgb_dev(pair.left), shapes, 2, 0)
+    rank = rank_np(seed, Hh * Ww)
+    f = H.build_tree(lv[0], shapes, 0, rank=dev(rank))
+    F = forest_np(f)
+    ref, _, _ = rt_reference(orc, pair.left, Hh, Ww, 0, rank)
+    check_forest(F, ref, Hh * Ww, f"RT {Hh}x{Ww}")
+    assert F["info"][2] == 1  # one tree
+    # a random tree is not the MST (weights ignored by the order)
+    if Hh * Ww > 100:
+        m = H.build_tree(lv[0], shapes, 0)
+        assert not np.array_equal(forest_np(m)["parent"], F["parent"])
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_rt_upper_levels_bit_exact(H, orc, level):
+    pair = scenes.small_scene(13, 97, 131, 31)
+    lv = H.pyramid(rgb_dev(pair.left), [(97, 131, 31)], 2, 2)
+    shp = H.level_shapes([(97, 131, 31)], 2, 2)[level]
+    n = shp[0][0] * shp[0][1]
+    rank = rank_np(50 + level, n)
+    f = H.build_tree(lv[level], shp, level, rank=dev(rank))
+    F = forest_np(f)
+    img = orc.pyramid(pair.left, 2, 2)[level]
+    ref, _, _ = rt_reference(orc, img, shp[0][0], shp[0][1], level, rank)
+    check_forest(F, ref, n, f"RT level {level}")
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_hdp_rt_forest_bit_exact(H, orc, seed):
+    """HDP+RT: the DT rules over the shuffled order, in the exact regime."""
+    Hh, Ww, dmax, S, w = 96, 128, 63, 2, 4
+    pair = scenes.small_scene(60 + seed, Hh, Ww, dmax)
+    up = np.random.default_rng(seed).integers(0, dmax // 2 + 1, ((Hh + 1) // 2, (Ww + 1) // 2))
+    up = np.kron(up[::4, ::4], np.ones((4, 4), int))[:up.shape[0], :up.shape[1]]
+    lo, hi = orc.predict_range(up, Hh, Ww, S, w, dmax)
+    lv = H.pyramid(rgb_dev(pair.left), [(Hh, Ww, dmax)], 2, 0)
+    rank = rank_np(70 + seed, Hh * Ww)
+    f = H.build_tree(lv[0], [(Hh, Ww, dmax)], 0, dev(lo.ravel(), torch.int32),
+                     dev(hi.ravel(), torch.int32), max_width=S + 2 * w, beta=(19, 20),
+                     rank=dev(rank))
+    F = forest_np(f)
+    ref, tlo, thi = rt_reference(orc, pair.left, Hh, Ww, 0, rank, lo, hi)
+    check_forest(F, ref, Hh * Ww, "HDP+RT forest")
+    np.testing.assert_array_equal(F["lo"], tlo)
+    np.testing.assert_array_equal(F["hi"], thi)
+
+
+def test_hdp_rt_loop_stagewise(H, orc):
+    """The whole HDP+RT loop: every layer's forest and aggregation against the
+    oracle's loop with the same ranks (layer l fed the oracle's layer l+1
+    labels), and the fused matching equal to the three separate steps."""
+    Hh, Ww, dmax, S, w, L = 96, 128, 63, 2, 4, 3
+    pair = scenes.small_scene(90, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lvs = H.level_shapes(shapes, S, L)
+    ranks = [rank_np(900 + l, lvs[l][0][0] * lvs[l][0][1]) for l in range(L + 1)]
+    ores = orc.hdp_stereo(pair.left, pair.right, dmax, S=S, L=L, window=w, want_forest=True,
+                          ranks=[r.astype(np.int64) for r in ranks])
+    lp = H.pyramid(rgb_dev(pair.left), shapes, S, L)
+    rp = H.pyramid(rgb_dev(pair.right), shapes, S, L)
+    for level in range(L, -1, -1):
+        dl = lvs[level][0][2]
+        lo = hi = None
+        if level < L:
+            up = dev(ores[level + 1]["disp"].ravel(), torch.int32)
+            lo, hi = H.predict_range(up, lvs[level + 1], lvs[level], S, w)
+        r = H.stereo_level(lp[level], rp[level], lvs[level], level, lo, hi,
+                           max_width=min(S + 2 * w, dl + 1), keep=True, rank=dev(ranks[level]))
+        F = forest_np(r.forest)
+        assert F["info"][7] == 0
+        np.testing.assert_array_equal(F["parent"], ores[level]["parent"])
+        np.testing.assert_array_equal(F["lo"], ores[level]["tree_lo"])
+        np.testing.assert_array_equal(F["hi"], ores[level]["tree_hi"])
+        Lf = orc.pyramid(pair.left, S, L)[level]; Rf = orc.pyramid(pair.right, S, L)[level]
+        ref, tlo, thi = rt_reference(orc, Lf, lvs[level][0][0], lvs[level][0][1], level,
+                                     ranks[level],
+                                     None if lo is None else ores[level]["pix_lo"],
+                                     None if lo is None else ores[level]["pix_hi"])
+        if lo is None:
+            tlo = np.zeros(F["lo"].shape, np.int32); thi = np.full(F["hi"].shape, dl, np.int32)
+        cost = orc.cost_volume(Lf, Rf, dl, tlo, thi)
+        agg = orc.aggregate_twopass(ref["parent"], ref["wgt"], ref["order"], 0.1,
+                                    np.nan_to_num(cost, nan=0.0))
+        agg[np.isnan(cost)] = np.nan
+        assert_rel(volume_to_pixels(r.agg.cpu().numpy(), F, dl + 1), agg, REL,
+                   f"HDP+RT aggregate layer {level}")
+        nm, nt = check_wta(r.disp.cpu().numpy(), agg, tlo, thi, f"HDP+RT WTA layer {level}")
+        fused = H.stereo_level(lp[level], rp[level], lvs[level], level, lo, hi,
+                               max_width=min(S + 2 * w, dl + 1), rank=dev(ranks[level]))
+        assert torch.equal(fused.disp, r.disp), f"layer {level}: fused labels differ"
+        print(f"HDP+RT layer {level}: WTA mismatches {nm} (near-ties {nt})")
+
+
+# --- Bayesian interval prediction (Section 2.2 eq. dpm, Section 3.1 eq. crtr) -------
+
+GMM_LOW = [(50, 70, 255), (33, 41, 191), (17, 9, 63), (5, 6, 1)]
+
+
+def gmm_case(seed):
+    rng = np.random.default_rng(seed)
+    K = 1 + seed % 4
+    pi = rng.dirichlet(np.ones(K)); mu = rng.uniform(-1.5, 1.5, K); sd = rng.uniform(0.3, 2.0, K)
+    prior = np.zeros((len(GMM_LOW), 256))
+    for p, (_, _, d) in enumerate(GMM_LOW):
+        prior[p, :d + 1] = rng.integers(0, 4, d + 1) * (rng.random(d + 1) < 0.6)
+    prior[2, :] = 0.0  # a pair without prior mass: the model alone
+    return pi, mu, sd, prior
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_interval_table_bit_exact(H, orc, seed):
+    S = 2
+    upper = [((h + 1) // 2, (w + 1) // 2, d // 2) for h, w, d in GMM_LOW]
+    pi, mu, sd, prior = gmm_case(seed)
+    g = H.make_gmm(pi, mu, sd)
+    for delta in (0.004, 0.016, 0.2, 1.0):
+        lo_t, hi_t, mw = H.interval_table(upper, GMM_LOW, S, g, dev(prior), delta)
+        lo_t, hi_t = lo_t.cpu().numpy(), hi_t.cpu().numpy()
+        widest = 0
+        for p, (_, _, d) in enumerate(GMM_LOW):
+            olo, ohi = orc.gmm_interval_table(S, d, d // 2, pi, mu, sd, prior[p, :d + 1], delta)
+            np.testing.assert_array_equal(lo_t[p, :d // 2 + 1], olo, err_msg=f"pair {p} {delta}")
+            np.testing.assert_array_equal(hi_t[p, :d // 2 + 1], ohi, err_msg=f"pair {p} {delta}")
+            widest = max(widest, int((ohi - olo + 1).max()))
+        assert int(mw.item()) == widest
+        if delta == 1.0:  # nothing passes eq. crtr: single labels
+            for p, (_, _, d) in enumerate(GMM_LOW):
+                assert (lo_t[p, :d // 2 + 1] == hi_t[p, :d // 2 + 1]).all()
+
+
+def test_interval_table_degenerate_models(H, orc):
+    """A model that underflows everywhere gives the child blocks; a sharp model
+    at offset 0 with a flat prior gives them too."""
+    S = 2
+    upper = [((h + 1) // 2, (w + 1) // 2, d // 2) for h, w, d in GMM_LOW]
+    prior = np.ones((len(GMM_LOW), 256))
+    for mu, sd in ((500.0, 0.01), (0.0, 0.05)):
+        lo_t, hi_t, _ = H.interval_table(upper, GMM_LOW, S, H.make_gmm([1.0], [mu], [sd]),
+                                         dev(prior), 0.01)
+        for p, (_, _, d) in enumerate(GMM_LOW):
+            i = np.arange(d // 2 + 1)
+            np.testing.assert_array_equal(lo_t[p, :d // 2 + 1].cpu().numpy(), np.minimum(2 * i, d))
+            np.testing.assert_array_equal(hi_t[p, :d // 2 + 1].cpu().numpy(),
+                                          np.minimum(2 * i + 1, d))
+
+
+def test_predict_range_table_bit_exact(H, orc):
+    S = 2
+    upper = [((h + 1) // 2, (w + 1) // 2, d // 2) for h, w, d in GMM_LOW]
+    pi, mu, sd, prior = gmm_case(5)
+    lo_t, hi_t, _ = H.interval_table(upper, GMM_LOW, S, H.make_gmm(pi, mu, sd), dev(prior), 0.004)
+    rng = np.random.default_rng(6)
+    ups = [rng.integers(0, d + 1, (h, w)).astype(np.int32) for h, w, d in upper]
+    up = dev(np.concatenate([u.ravel() for u in ups]))
+    lo, hi = H.predict_range_table(up, upper, GMM_LOW, S, lo_t, hi_t)
+    lo, hi = lo.cpu().numpy(), hi.cpu().numpy()
+    off = 0
+    for p, (h, w, d) in enumerate(GMM_LOW):
+        olo, ohi = orc.predict_range_table(ups[p], h, w, S, lo_t[p].cpu().numpy(),
+                                           hi_t[p].cpu().numpy())
+        np.testing.assert_array_equal(lo[off:off + h * w], olo.ravel())
+        np.testing.assert_array_equal(hi[off:off + h * w], ohi.ravel())
+        off += h * w
+
+
+def test_hdp_gmm_loop_stagewise(H, orc):
+    """The HDP loop with Bayesian intervals: every layer fed the oracle's
+    layer-(l+1) labels gives the oracle's table, pixel intervals, disparity
+    forest and aggregation; the GPU loop then runs end to end."""
+    Hh, Ww, dmax, S, L = 96, 128, 63, 2, 3
+    pair = scenes.small_scene(77, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lvs = H.level_shapes(shapes, S, L)
+    gm = scenes.gmm_params(3, L)
+    priors = [scenes.label_prior(pair.gt, S, l, lvs[l][0][2]) for l in range(L)]
+    delta0 = 0.004
+    lp = H.pyramid(rgb_dev(pair.left), shapes, S, L)
+    rp = H.pyramid(rgb_dev(pair.right), shapes, S, L)
+    Lf = orc.pyramid(pair.left, S, L); Rf = orc.pyramid(pair.right, S, L)
+    o_up = orc.stereo_level(Lf[L], Rf[L], lvs[L][0][2], L)
+    for level in range(L - 1, -1, -1):
+        dl = lvs[level][0][2]
+        Hl, Wl = lvs[level][0][:2]
+        olo_t, ohi_t = orc.gmm_interval_table(S, dl, lvs[level + 1][0][2], *gm[level],
+                                              priors[level], delta0 * S ** level)
+        olo, ohi = orc.predict_range_table(o_up["disp"], Hl, Wl, S, olo_t, ohi_t)
+        lo_t, hi_t, mw = H.interval_table(lvs[level + 1], lvs[level], S, H.make_gmm(*gm[level]),
+                                          dev(priors[level][None, :]), delta0 * S ** level)
+        np.testing.assert_array_equal(lo_t[0].cpu().numpy(), olo_t)
+        np.testing.assert_array_equal(hi_t[0].cpu().numpy(), ohi_t)
+        up = dev(o_up["disp"].ravel(), torch.int32)
+        lo, hi = H.predict_range_table(up, lvs[level + 1], lvs[level], S, lo_t, hi_t)
+        np.testing.assert_array_equal(lo.cpu().numpy(), olo.ravel())
+        np.testing.assert_array_equal(hi.cpu().numpy(), ohi.ravel())
+        mwi = int(mw.item())
+        assert 19 * mwi > 20 * (mwi - 1), "test case left the exact regime"
+        r = H.stereo_level(lp[level], rp[level], lvs[level], level, lo, hi, max_width=mwi,
+                           keep=True)
+        o = orc.stereo_level(Lf[level], Rf[level], dl, level, olo, ohi)
+        F = forest_np(r.forest)
+        assert F["info"][7] == 0 and F["info"][6] == 0
+        np.testing.assert_array_equal(F["parent"], o["parent"])
+        np.testing.assert_array_equal(F["lo"], o["tree_lo"])
+        np.testing.assert_array_equal(F["hi"], o["tree_hi"])
+        ref = run_level_oracle(orc, Lf[level], Rf[level], dl, level, olo, ohi)
+        assert_rel(volume_to_pixels(r.agg.cpu().numpy(), F, dl + 1), ref["agg"], REL,
+                   f"GMM aggregate layer {level}")
+        nm, nt = check_wta(r.disp.cpu().numpy(), ref["agg"], ref["tlo"], ref["thi"],
+                           f"GMM WTA layer {level}")
+        print(f"GMM layer {level}: widest interval {mwi}, WTA mismatches {nm} (near-ties {nt})")
+        o_up = o
+    # the whole loop on the GPU with these models runs and labels every pixel
+    res = H.hdp_stereo(rgb_dev(pair.left), rgb_dev(pair.right), shapes, S=S, L=L,
+                       gmm=[H.make_gmm(*g) for g in gm],
+                       priors=[dev(p[None, :]) for p in priors], delta0=delta0)
+    d0 = res[0].disp.cpu().numpy()
+    assert d0.min() >= 0 and d0.max() <= dmax
+
+
+# --- left-right check, sampled prior, refinement (Sections 3.1, 3.3) ----------------
+
+LR_SHAPES = [(37, 53, 31), (20, 9, 7), (1, 1, 3), (64, 96, 63)]
+
+
+def test_mirror_and_lr_check_bit_exact(H, orc):
+    rng = np.random.default_rng(8)
+    imgs = [rng.integers(0, 256, (h, w, 3)).astype(np.uint8) for h, w, _ in LR_SHAPES]
+    m = H.mirror(rgb_dev(*imgs), LR_SHAPES).cpu().numpy()
+    off = 0
+    for im, (h, w, _) in zip(imgs, LR_SHAPES):
+        np.testing.assert_array_equal(m[off:off + h * w].reshape(h, w, 3), im[:, ::-1])
+        off += h * w
+    dls = [rng.integers(0, d + 1, (h, w)).astype(np.int32) for h, w, d in LR_SHAPES]
+    # right labels equal to the left ones at the match for about half the pixels
+    drs = []
+    for dl, (h, w, d) in zip(dls, LR_SHAPES):
+        dr = rng.integers(0, d + 1, (h, w)).astype(np.int32)
+        for y in range(h):
+            for x in range(w):
+                if x - dl[y, x] >= 0 and rng.random() < 0.5:
+                    dr[y, x - dl[y, x]] = dl[y, x]
+        drs.append(dr)
+    cat = lambda a: dev(np.concatenate([x.ravel() for x in a]))
+    for tol in (0, 1):
+        st_m = H.lr_check(cat(dls), cat([d[:, ::-1] for d in drs]), LR_SHAPES, tol).cpu().numpy()
+        st_n = H.lr_check(cat(dls), cat(drs), LR_SHAPES, tol, right_mirrored=False).cpu().numpy()
+        np.testing.assert_array_equal(st_m, st_n)
+        off = 0
+        for dl, dr, (h, w, _) in zip(dls, drs, LR_SHAPES):
+            ref = orc.lr_check(dl, np.ascontiguousarray(dr[:, ::-1]), tol)
+            np.testing.assert_array_equal(st_m[off:off + h * w], ref.ravel())
+            off += h * w
+
+
+def test_sample_prior_bit_exact(H, orc):
+    rng = np.random.default_rng(9)
+    dls = [rng.integers(0, d + 1, (h, w)).astype(np.int32) for h, w, d in LR_SHAPES]
+    sts = [(rng.random((h, w)) < 0.7).astype(np.uint8) for h, w, _ in LR_SHAPES]
+    cat = lambda a: dev(np.concatenate([x.ravel() for x in a]))
+    for square in (5, 3):
+        pr = H.sample_prior(cat(dls), cat(sts), LR_SHAPES, square, stride=70).cpu().numpy()
+        for p, (dl, s, (h, w, d)) in enumerate(zip(dls, sts, LR_SHAPES)):
+            ref = orc.sample_prior(dl, s, d, square)
+            np.testing.assert_array_equal(pr[p, :d + 1], ref)
+            assert (pr[p, d + 1:] == 0).all()
+
+
+@pytest.mark.parametrize("hdp_layer", [False, True])
+def test_refine_matches_oracle(H, orc, hdp_layer):
+    """Refinement over a layer's forest with the oracle's labels and stable
+    pixels as input: aggregated refinement cost within 1e-5 of FP64, labels
+    equal except at near-ties."""
+    Hh, Ww, dmax = 72, 96, 31
+    pair = scenes.small_scene(33, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lp = H.pyramid(rgb_dev(pair.left), shapes, 2, 0)
+    Lf = pair.left.astype(np.float64)
+    lo = hi = None
+    kw = {}
+    if hdp_layer:
+        up = np.random.default_rng(2).integers(0, dmax // 2 + 1, (Hh // 2, Ww // 2))
+        up = np.kron(up[::4, ::4], np.ones((4, 4), int))[:Hh // 2, :Ww // 2]
+        lo, hi = orc.predict_range(up, Hh, Ww, 2, 4, dmax)
+        kw = dict(pix_lo=dev(lo.ravel(), torch.int32), pix_hi=dev(hi.ravel(), torch.int32),
+                  max_width=10)
+    f = H.build_tree(lp[0], shapes, 0, **kw)
+    ref = run_level_oracle(orc, Lf, pair.right.astype(np.float64), dmax, 0, lo, hi)
+    rng = np.random.default_rng(4)
+    disp = np.clip(np.rint(pair.gt).astype(np.int32), 0, dmax)
+    if hdp_layer:
+        disp = np.clip(disp, ref["tlo"].reshape(Hh, Ww), ref["thi"].reshape(Hh, Ww))
+    stable = (rng.random((Hh, Ww)) < 0.6).astype(np.uint8)
+    agg, lab = H.refine(f, dev(disp.ravel()), dev(stable.ravel()))
+    F = forest_np(f)
+    cost = orc.refine_cost(disp, stable, dmax, ref["tlo"], ref["thi"])
+    oagg = orc.aggregate_twopass(ref["ref"]["parent"], ref["ref"]["wgt"], ref["ref"]["order"],
+                                 0.1, np.nan_to_num(cost, nan=0.0))
+    oagg[np.isnan(cost)] = np.nan
+    got = volume_to_pixels(agg.cpu().numpy(), F, dmax + 1)
+    # entries whose exact value is 0 (no stable pixel contributes) must be 0
+    zero = oagg == 0
+    assert (got[zero] == 0).all()
+    assert_rel(got[~zero], oagg[~zero], REL, "refinement aggregate")
+    nm, nt = check_wta(lab.cpu().numpy(), oagg, ref["tlo"], ref["thi"], "refinement WTA")
+    print(f"refinement ({'HDP' if hdp_layer else 'MST'}): mismatches {nm} (near-ties {nt})")
+
+
+def test_right_view_and_check_end_to_end(H, orc):
+    """Left run, run on the mirrored pair and the check on the GPU, against the
+    same chain in the oracle: labels equal except at near-ties, and the stable
+    mask equal wherever both views' labels agree with the oracle's."""
+    pair = scenes.workload(1)
+    Hh, Ww = pair.shape
+    shapes = [(Hh, Ww, pair.dmax)]
+    L8, R8 = rgb_dev(pair.left), rgb_dev(pair.right)
+    left = H.full_range(L8, R8, shapes)
+    right = H.full_range(H.mirror(R8, shapes), H.mirror(L8, shapes), shapes)
+    st = H.lr_check(left.disp, right.disp, shapes).cpu().numpy()
+    fl, fr = pair.left.astype(np.float64), pair.right.astype(np.float64)
+    ol = orc.stereo_level(fl, fr, pair.dmax, 0)
+    orr = orc.stereo_level(orc.mirrored(fr), orc.mirrored(fl), pair.dmax, 0)
+    ost = orc.lr_check(ol["disp"], orr["disp"], 0).ravel()
+    gl, gr = left.disp.cpu().numpy(), right.disp.cpu().numpy()
+    for g, o, what in ((gl, ol, "left"), (gr, orr, "mirrored right")):
+        mism = g != o["disp"].ravel()
+        near = (o["c2"] - o["c1"]) <= REL * np.abs(o["c1"])
+        assert np.all(near[mism]), f"{what}: mismatches off near-ties"
+    same = (gl == ol["disp"].ravel()) & (gr == orr["disp"].ravel())
+    assert same.mean() > 0.99
+    # where both label maps agree everywhere the check reads, the masks agree
+    x = np.arange(Hh * Ww) % Ww
+    y = np.arange(Hh * Ww) // Ww
+    xr = x - gl
+    inside = (xr >= 0) & (xr < Ww)
+    j = y * Ww + (Ww - 1 - np.clip(xr, 0, Ww - 1))
+    ok = same & same[j]
+    np.testing.assert_array_equal(st[ok | ~inside], ost[ok | ~inside])
+    assert st.mean() > 0.5
