@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in tile schedule")
     ap.add_argument("--parts", action="store_true",
                     help="also time every part of the HDP step as its own captured graph")
+    ap.add_argument("--workload", default="all", choices=["all", "uneven32", "road64"],
+                    help="profiling aid for --mode batched: run one batched workload only "
+                         "(and not the adjoint workload)")
     return ap.parse_args()
 
 
@@ -203,7 +206,7 @@ def main():
     pair = scenes.workload(2)
     extras = not args.no_extra and args.mode in ("both", "batched")
     if extras:
-        scenes.prefetch([3, 4, 5])
+        scenes.prefetch({"all": [3, 4, 5], "uneven32": [3], "road64": [5]}[args.workload])
 
     import torch
 
@@ -291,7 +294,8 @@ def main():
     if extras:
         use(hdp_sched)
         out["batched"] = bench_batched(hdp, scenes, args)
-        out["adjoint"] = bench_adjoint(hdp, scenes, args)
+        if args.workload == "all":
+            out["adjoint"] = bench_adjoint(hdp, scenes, args)
 
     if not args.no_cpu_baseline and args.mode == "both":
         from oracle import oracle
@@ -371,6 +375,16 @@ def bench_batched(hdp, scenes, args):
     adjoint.  Each with the roofline of its fused passes (eager runs)."""
     import torch
     res = {}
+    if args.workload in ("all", "uneven32"):
+        res["uneven32_hdp_fwd"] = bench_uneven32(hdp, scenes, args)
+    if args.workload in ("all", "road64"):
+        res["road64_hdp_fwd_bwd"] = bench_road64(hdp, scenes, args)
+    return res
+
+
+def bench_uneven32(hdp, scenes, args):
+    """32 uneven pairs (320-1392 x 240-1110, 64-256 labels), HDP forward."""
+    import torch
     pairs = scenes.workload_batch(3)
     L, R, shapes = upload(pairs)
     P3 = scenes.HDP_PARAMS[3]
@@ -385,17 +399,23 @@ def bench_batched(hdp, scenes, args):
     torch.cuda.synchronize()
     alg3 = sum(layer_entries(r.forest) for r in r3)
     full3 = sum(h * w * (d + 1) for h, w, d in shapes)
-    res["uneven32_hdp_fwd"] = {
+    res = {
         "pairs": len(shapes), "Mpix": sum(h * w for h, w, _ in shapes) / 1e6,
         "ms_per_step": t3 * 1e3, "Mpix_disp_per_s": alg3 / t3 / 1e6,
         "entries_per_step": alg3,
         "Mpix_disp_per_s_full_range_equiv": full3 / t3 / 1e6,
         "layers": per_layer_stats(r3),
         "roofline": rooflines(pass_roofline(hdp, step3, reps=3), "uneven32")}
-    res["uneven32_hdp_fwd"]["roofline"]["working_set_MB"] = working_set_mb(r3)
+    res["roofline"]["working_set_MB"] = working_set_mb(r3)
     del r3, L, R
     torch.cuda.empty_cache()
+    return res
 
+
+def bench_road64(hdp, scenes, args):
+    """64 road pairs 1242x375, labels 0..191: HDP forward, and forward +
+    adjoint (against the fused forward and the forward keeping its volumes)."""
+    import torch
     pairs = scenes.workload_batch(5)
     L, R, shapes = upload(pairs)
     P5 = scenes.HDP_PARAMS[5]
@@ -429,7 +449,7 @@ def bench_batched(hdp, scenes, args):
     r5 = fwd5()
     torch.cuda.synchronize()
     alg5 = sum(layer_entries(r.forest) for r in r5)
-    res["road64_hdp_fwd_bwd"] = {
+    res = {
         "pairs": len(shapes), "Mpix": sum(h * w for h, w, _ in shapes) / 1e6,
         "fwd_ms": times["fwd"] * 1e3, "fwd_keep_ms": times["fwd_keep"] * 1e3,
         "fwd_bwd_ms": times["fwd_bwd"] * 1e3,
@@ -439,7 +459,7 @@ def bench_batched(hdp, scenes, args):
         "Mpix_disp_per_s_full_range_equiv_fwd": full5 / times["fwd"] / 1e6,
         "layers": per_layer_stats(r5),
         "roofline": rooflines(pass_roofline(hdp, fwd5, reps=3), "road64")}
-    res["road64_hdp_fwd_bwd"]["roofline"]["working_set_MB"] = working_set_mb(r5)
+    res["roofline"]["working_set_MB"] = working_set_mb(r5)
     del r5, L, R
     torch.cuda.empty_cache()
     return res
