@@ -30,6 +30,7 @@
 namespace hdp {
 
 constexpr int kRPGDefault = 8;  // rows per thread group of a tile
+constexpr int kSumBlocks = 512;  // blocks of the first summing launch of the adjoint
 
 // Narrow rows (at most kSentMaxWidth labels) use rows as signals: unwritten
 // values hold signalling-NaN patterns that no arithmetic produces.
@@ -117,12 +118,13 @@ __global__ void k_prologue(int64_t n, const float *__restrict__ rw,
                            uint32_t *__restrict__ fill1, int width,
                            uint64_t *__restrict__ maps, int64_t map_words) {
     __shared__ int32_t sph[HDP_MAX_PHASES + 1];
-    const int64_t r = gtid();  // the grid covers the rows and the tiles, one each per thread
+    // One thread per row (the grid covers the rows and the tiles).
+    const int64_t t = gtid();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // The phase table and the row's links and weight are loaded together,
     // before any of them is used (a thread past the last row reads the last
     // row and drops it).
-    const int64_t rc = r < n ? r : n - 1;
+    const int64_t rc = t < n ? t : n - 1;
     const int tx = (int)threadIdx.x;
     const int32_t ph = phase_ptr[tx <= HDP_MAX_PHASES ? tx : HDP_MAX_PHASES];
     int K = info[HDP_INFO_N_PHASES];
@@ -132,42 +134,60 @@ __global__ void k_prologue(int64_t n, const float *__restrict__ rw,
     K = K < 1 ? 1 : (K > HDP_MAX_PHASES ? HDP_MAX_PHASES : K);
     if (tx <= HDP_MAX_PHASES) sph[tx] = ph;
     __syncthreads();
-    if (r < n) {
-        // Narrow rows: mark unwritten the rows of the up passes' outputs that a
-        // tile polls (chain heads below a light edge, read by their parent's
-        // tile, and the last row of every up-pass tile, read for the next
-        // tile's carry).
-        if (fill0 || fill1) {
-            int lo = 0, hi = K - 1;  // phase of row r
+    // Narrow rows: mark unwritten the rows of the up passes' outputs that a
+    // tile polls (chain heads below a light edge, read by their parent's
+    // tile, and the last row of every up-pass tile, read for the next tile's
+    // carry).  The 64 rows of a wavefront are consecutive: the wavefront
+    // stores the words of its marked rows together, lane j taking words
+    // j, j + 64, ... of the block, so each store covers consecutive words.
+    if (fill0 || fill1) {
+        bool mark = false;
+        if (t < n) {
+            int lo = 0, hi = K - 1;  // phase of row t
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (sph[mid] <= r) lo = mid; else hi = mid - 1;
+                if (sph[mid] <= t) lo = mid; else hi = mid - 1;
             }
-            const bool last = (sph[lo + 1] - (int)r) % rows == 0;
-            if (last || (pr >= 0 && !hv)) {
-                for (int c = 0; c < width; ++c) {
-                    if (fill0) fill0[r * width + c] = kSentF;
-                    if (fill1) fill1[r * width + c] = kSentF;
-                }
+            const bool last = (sph[lo + 1] - (int)t) % rows == 0;
+            mark = last || (pr >= 0 && !hv);
+        }
+        const uint64_t mm = __ballot(mark);
+        const int lane = tx & 63;
+        const int64_t r0w = t - lane;  // first row of the wavefront's block
+        const bool even = (width & 1) == 0;
+        const int hw = even ? width / 2 : width;  // words per row
+        for (int idx = lane; idx < 64 * hw; idx += 64) {
+            const int j = idx / hw;
+            if (!((mm >> j) & 1ull)) continue;
+            if (even) {
+                const int64_t i = r0w * hw + idx;
+                if (fill0) reinterpret_cast<uint64_t *>(fill0)[i] = kSent64;
+                if (fill1) reinterpret_cast<uint64_t *>(fill1)[i] = kSent64;
+            } else {
+                const int64_t i = r0w * width + idx;
+                if (fill0) fill0[i] = kSentF;
+                if (fill1) fill1[i] = kSentF;
             }
         }
+    }
+    if (t < n) {
         if (pr < 0) {
-            s[r] = 0.0;
-            om[r] = 1.0;
+            s[t] = 0.0;
+            om[t] = 1.0;
         } else {
             const double w = (double)wf;
-            s[r] = exp(-w * inv_sigma);
-            om[r] = -expm1(-2.0 * w * inv_sigma);
+            s[t] = exp(-w * inv_sigma);
+            om[t] = -expm1(-2.0 * w * inv_sigma);
         }
     }
     // the tile maps, marked unpublished
-    for (int64_t i = r; i < map_words; i += stride) maps[i] = kSentD;
-    if (r < tiles) {
+    for (int64_t i = t; i < map_words; i += stride) maps[i] = kSentD;
+    if (t < tiles && width > kSentMaxWidth) {  // tile flags: wide rows only (narrow rows signal by rows)
 #pragma unroll
-        for (int k = 0; k < 2 * kPassSets; ++k) flags[k * tiles + r] = 0;
+        for (int k = 0; k < 2 * kPassSets; ++k) flags[k * tiles + t] = 0;
     }
-    if (r < kPassSets) ticket[r] = 0;
-    if (r != 0) return;
+    if (t < kPassSets) ticket[t] = 0;
+    if (t != 0) return;
     plan[P_NPH] = K;
     plan[P_ROWS] = rows;
     for (int k = 0; k <= K; ++k) plan[P_ROW0 + k] = phase_ptr[k];
@@ -203,7 +223,7 @@ struct PassArgs {
     int32_t *err;        // nonzero: a bounded wait timed out / inconsistent input
     // narrow-row mode (rows as signals)
     float *fill;         // up pass: rows of the following down pass's output to mark unwritten
-    double *tPs, *tXs;   // this pass's tile maps (tiles without a chain break), marked unwritten
+    double *tPs, *tXs;   // this pass's tile maps (tiles without a chain break); tPs marked unwritten
     // fused matching (narrow rows): the up pass computes its cost rows from the
     // level images, the down pass writes each row's winning label
     const float4 *imL, *imR;
@@ -806,6 +826,10 @@ __global__ void __launch_bounds__(kBlock)
         for (int c = 0; c < CPT; ++c)
             st_dev(reinterpret_cast<uint64_t *>(&A.tXs[(int64_t)T * w + j0 + c]),
                    (uint64_t)__double_as_longlong(Xt[c]));
+        // The product word doubles as the map's flag, so it is stored after
+        // every word of the map has completed (group 0 is in one wavefront,
+        // whose outstanding stores all complete at this wait).
+        stores_complete();
         if (jl == 0)
             st_dev(reinterpret_cast<uint64_t *>(&A.tPs[T]), (uint64_t)__double_as_longlong(Pt));
     }
@@ -883,11 +907,9 @@ __global__ void __launch_bounds__(kBlock)
                     break;
                 }
                 if (pred > lim) {  // map of tile pred published: look one tile further back
-                    bool ok = ld_dev(reinterpret_cast<const uint64_t *>(&A.tPs[pred])) != kSentD;
-#pragma unroll
-                    for (int c = 0; c < CPT; ++c)
-                        ok = ok && ld_dev(reinterpret_cast<const uint64_t *>(
-                                       &A.tXs[(int64_t)pred * w + j0 + c])) != kSentD;
+                    // (its product word is stored once the whole map is written)
+                    const bool ok =
+                        ld_dev(reinterpret_cast<const uint64_t *>(&A.tPs[pred])) != kSentD;
                     if (ok) {
                         --pred;
                         continue;
@@ -994,7 +1016,9 @@ static AggWs carve_agg_ws(void *ws, int64_t n, int width, size_t *bytes) {
     a.tXs = a.tPs + (narrow ? kPassSets * nt : 0);
     a.up = reinterpret_cast<float *>(take(sizeof(float) * n * width));
     a.ug = reinterpret_cast<float *>(take(sizeof(float) * n * width));
-    a.red = reinterpret_cast<double *>(take(sizeof(double) * (n / 4 + 64)));
+    // partial sums of the adjoint: one per block of the edge gradients (at most
+    // n / 4 + 1 with 4 lanes per row and 256 threads), then one per summing block
+    a.red = reinterpret_cast<double *>(take(sizeof(double) * (n / 4 + 64 + kSumBlocks)));
     *bytes = off + 256;
     return a;
 }
@@ -1064,9 +1088,10 @@ static PassArgs pass_args(const hdp_forest &f, int width, const AggWs &w, const 
 // fill0 / fill1: outputs of the up passes of this call (narrow rows only).
 static void prologue(const hdp_forest &f, int width, float sigma, const AggWs &w, hipStream_t st,
                      float *fill0 = nullptr, float *fill1 = nullptr) {
-    int64_t m = f.n > w.tiles ? f.n : w.tiles;
     const bool narrow = width <= kSentMaxWidth;
-    int64_t map_words = narrow ? (int64_t)kPassSets * w.tiles * (width + 1) : 0;
+    int64_t m = f.n > w.tiles ? f.n : w.tiles;
+    // narrow rows: the product words of the tile maps, marked unpublished
+    int64_t map_words = narrow ? (int64_t)kPassSets * w.tiles : 0;
     k_prologue<<<grid_for(m), kBlock, 0, st>>>(
         f.n, f.rw, f.prow, f.heavy, 1.0 / (double)sigma, w.s, w.om, w.flags, w.tiles, w.ticket,
         f.phase_ptr, f.info, tile_geom(width).rows, w.plan,
@@ -1143,7 +1168,11 @@ void launch_match(const float *left, const float *right, const LevelGeom &g, con
 // --- adjoint ----------------------------------------------------------------------------
 
 // Per row (edge to the parent): acc = sum_x [Ug (Ac(p) - s Uc) + Uc (Ag(p) - s Ug)];
-// grad_w = -(s/sigma) acc; per-block partial of acc * s * w / sigma^2.
+// grad_w = -(s/sigma) acc; per-block partial of acc * s * w / sigma^2.  LPR
+// consecutive lanes take one row (lane j reads labels j, j + LPR, ...: the
+// row's labels are read by consecutive lanes), so a wavefront covers 64 / LPR
+// rows; the row sum is a butterfly over its LPR lanes.
+template <int LPR>
 __global__ void __launch_bounds__(kBlock) k_edge_grad(int64_t n, int width,
                                                       const int32_t *__restrict__ prow,
                                                       const int32_t *__restrict__ node,
@@ -1156,26 +1185,34 @@ __global__ void __launch_bounds__(kBlock) k_edge_grad(int64_t n, int width,
                                                       float *__restrict__ grad_w,
                                                       double *__restrict__ red) {
     __shared__ double part[kBlock / 64];
-    int64_t r = gtid() >> 6;
-    int lane = threadIdx.x & 63;
+    const int64_t r = gtid() / LPR;
+    const int j = (int)(threadIdx.x & (LPR - 1));
     double contrib = 0.0;
+    int p = -1;
+    double sr = 0.0;
+    double acc = 0.0;
     if (r < n) {
-        int p = prow[r];
-        double acc = 0.0;
-        double sr = s[r];
+        p = prow[r];
+        sr = s[r];
         if (p >= 0) {
             const float *ucr = uc + r * width, *ugr = ug + r * width;
             const float *acp = ac + (int64_t)p * width, *agp = ag + (int64_t)p * width;
-            for (int j = lane; j < width; j += 64) {
-                double u1 = ucr[j], u2 = ugr[j];
-                acc += u2 * ((double)acp[j] - sr * u1) + u1 * ((double)agp[j] - sr * u2);
+            for (int x = j; x < width; x += LPR) {
+                const double u1 = ucr[x], u2 = ugr[x];
+                acc += u2 * ((double)acp[x] - sr * u1) + u1 * ((double)agp[x] - sr * u2);
             }
         }
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (lane == 0 && grad_w) grad_w[node[r]] = p >= 0 ? (float)(-(sr * inv_sigma) * acc) : 0.f;
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (r < n && j == 0) {
+        if (grad_w) grad_w[node[r]] = p >= 0 ? (float)(-(sr * inv_sigma) * acc) : 0.f;
         if (p >= 0) contrib = acc * sr * (double)rw[r] * inv_sigma * inv_sigma;
     }
-    if (lane == 0) part[threadIdx.x >> 6] = contrib;
+    // block partial in a fixed order: rows of a wavefront, then wavefronts
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = contrib;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
@@ -1184,17 +1221,51 @@ __global__ void __launch_bounds__(kBlock) k_edge_grad(int64_t n, int width,
     }
 }
 
-__global__ void k_sum_red(const double *__restrict__ red, int64_t nb, float *__restrict__ out) {
+// Sum of nb partials: every block sums a strided share (fixed order), the
+// last launch has one block and writes the float result.
+__global__ void __launch_bounds__(kBlock) k_sum_red(const double *__restrict__ red, int64_t nb,
+                                                    double *__restrict__ out2,
+                                                    float *__restrict__ out) {
     __shared__ double sh[kBlock];
     double t = 0.0;
-    for (int64_t i = threadIdx.x; i < nb; i += kBlock) t += red[i];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = gtid(); i < nb; i += stride) t += red[i];
     sh[threadIdx.x] = t;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = (float)sh[0];
+    if (threadIdx.x == 0) {
+        if (out) *out = (float)sh[0];
+        else out2[blockIdx.x] = sh[0];
+    }
+}
+
+// Launch of the edge gradients with the row width's lanes per row.
+static int64_t launch_edge_grad(const hdp_forest &f, int width, const double *s, const float *uc,
+                                const float *ac, const float *ug, const float *ag,
+                                double inv_sigma, float *grad_w, double *red, hipStream_t st) {
+    const int lpr = width <= 8 ? 4 : width <= 16 ? 8 : width <= 32 ? 16 : width <= 64 ? 32 : 64;
+    const int64_t nb = (f.n * lpr + kBlock - 1) / kBlock;
+#define HDP_EDGE_GRAD(L)                                                                           \
+    k_edge_grad<L><<<(unsigned)nb, kBlock, 0, st>>>(f.n, width, f.prow, f.node, f.rw, s, uc, ac,  \
+                                                    ug, ag, inv_sigma, grad_w, red)
+    if (lpr == 4) HDP_EDGE_GRAD(4);
+    else if (lpr == 8) HDP_EDGE_GRAD(8);
+    else if (lpr == 16) HDP_EDGE_GRAD(16);
+    else if (lpr == 32) HDP_EDGE_GRAD(32);
+    else HDP_EDGE_GRAD(64);
+#undef HDP_EDGE_GRAD
+    return nb;
+}
+
+// Partial sums of the edge gradients -> dL/dsigma (two launches, fixed order).
+static void launch_sum(const double *red, int64_t nb, double *red2, float *out, hipStream_t st) {
+    const int64_t blocks = (nb + kBlock - 1) / kBlock < kSumBlocks ? (nb + kBlock - 1) / kBlock
+                                                                   : kSumBlocks;
+    k_sum_red<<<(unsigned)blocks, kBlock, 0, st>>>(red, nb, red2, nullptr);
+    k_sum_red<<<1, kBlock, 0, st>>>(red2, blocks, nullptr, out);
 }
 
 void launch_aggregate_backward(const hdp_forest &f, int width, const float *cost, const float *agg,
@@ -1215,11 +1286,9 @@ void launch_aggregate_backward(const hdp_forest &f, int width, const float *cost
     }
     two_pass(f, width, grad_agg, w.ug, grad_cost, w, 0, st);
     if (grad_w || grad_sigma) {
-        int64_t nb = (f.n * 64 + kBlock - 1) / kBlock;
-        k_edge_grad<<<(unsigned)nb, kBlock, 0, st>>>(f.n, width, f.prow, f.node, f.rw, w.s, uc, agg,
-                                                    w.ug, grad_cost, 1.0 / (double)sigma, grad_w,
-                                                    w.red);
-        if (grad_sigma) k_sum_red<<<1, kBlock, 0, st>>>(w.red, nb, grad_sigma);
+        const int64_t nb = launch_edge_grad(f, width, w.s, uc, agg, w.ug, grad_cost,
+                                            1.0 / (double)sigma, grad_w, w.red, st);
+        if (grad_sigma) launch_sum(w.red, nb, w.red + nb, grad_sigma, st);
     }
 }
 

@@ -43,63 +43,45 @@ __global__ void __launch_bounds__(kBlock) k_cost_volume(
         dst[0] = out[0];
 }
 
-// Winner-takes-all, one thread per row (narrow rows).
-__global__ void k_wta_thread(LevelGeom g, const int32_t *__restrict__ node,
-                             const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
-                             int width, const float *__restrict__ agg, int32_t *__restrict__ disp,
-                             int64_t n) {
-    int64_t r = gtid();
-    if (r >= n) return;
-    int v = node ? node[r] : (int)r;
-    int a = node ? lo[v] : 0;
-    int b = node ? hi[v] : g.dmax[pair_of(g, v)];
-    const float *row = agg + r * width;
-    int nl = b - a + 1 < width ? b - a + 1 : width;
-    float best = row[0];
-    int bj = 0;
-    // the loop runs over the whole row (its loads do not wait for the
-    // interval); columns past the interval are skipped
-    if ((width & 1) == 0) {  // rows start 8-byte aligned: pairs of labels
-        const float2 *row2 = reinterpret_cast<const float2 *>(row);
-        for (int h = 0; 2 * h < width; ++h) {
-            float2 x = row2[h];
-            if (2 * h < nl && x.x < best) { best = x.x; bj = 2 * h; }
-            if (2 * h + 1 < nl && x.y < best) { best = x.y; bj = 2 * h + 1; }
-        }
-    } else {
-        for (int j = 1; j < width; ++j) {
-            float x = row[j];
-            if (j < nl && x < best) { best = x; bj = j; }
-        }
-    }
-    disp[v] = a + bj;
-}
-
-// Winner-takes-all, one wavefront per row (wide rows).
-__global__ void k_wta_wave(LevelGeom g, const int32_t *__restrict__ node,
-                           const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
-                           int width, const float *__restrict__ agg, int32_t *__restrict__ disp,
-                           int64_t n) {
-    int64_t r = gtid() >> 6;
-    int lane = threadIdx.x & 63;
-    if (r >= n) return;
-    int v = node ? node[r] : (int)r;
-    int a = node ? lo[v] : 0;
-    int b = node ? hi[v] : g.dmax[pair_of(g, v)];
-    int nl = b - a + 1 < width ? b - a + 1 : width;
-    const float *row = agg + r * width;
+// Winner-takes-all: LPR consecutive lanes take one row (lane j reads columns
+// j, j + LPR, ..., so the row is read by consecutive lanes); each lane keeps
+// its least value and column (first of equal values), then a butterfly over
+// the row's lanes keeps the least value, the lower column on ties.
+template <int LPR>
+__global__ void __launch_bounds__(kBlock) k_wta(LevelGeom g, const int32_t *__restrict__ node,
+                                                const int32_t *__restrict__ lo,
+                                                const int32_t *__restrict__ hi, int width,
+                                                const float *__restrict__ agg,
+                                                int32_t *__restrict__ disp, int64_t n) {
+    const int64_t r = gtid() / LPR;
+    const int j = (int)(threadIdx.x & (LPR - 1));
     float best = __builtin_inff();
     int bj = 0x7fffffff;
-    for (int j = lane; j < nl; j += 64) {
-        float x = row[j];
-        if (x < best) { best = x; bj = j; }
+    int v = 0, a = 0;
+    if (r < n) {
+        v = node ? node[r] : (int)r;
+        a = node ? lo[v] : 0;
+        const int b = node ? hi[v] : g.dmax[pair_of(g, v)];
+        const int nl = b - a + 1 < width ? b - a + 1 : width;
+        const float *row = agg + r * width;
+        for (int x = j; x < nl; x += LPR) {
+            const float y = row[x];
+            if (y < best) {
+                best = y;
+                bj = x;
+            }
+        }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        float ob = __shfl_xor(best, off, 64);
-        int oj = __shfl_xor(bj, off, 64);
-        if (ob < best || (ob == best && oj < bj)) { best = ob; bj = oj; }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+        const float ob = __shfl_xor(best, off, 64);
+        const int oj = __shfl_xor(bj, off, 64);
+        if (ob < best || (ob == best && oj < bj)) {
+            best = ob;
+            bj = oj;
+        }
     }
-    if (lane == 0) disp[v] = a + bj;
+    if (r < n && j == 0) disp[v] = a + (bj == 0x7fffffff ? 0 : bj);
 }
 
 void launch_cost_volume(const float *left, const float *right, const LevelGeom &g,
@@ -125,11 +107,15 @@ void launch_cost_volume(const float *left, const float *right, const LevelGeom &
 
 void launch_wta(const LevelGeom &g, const int32_t *node, const int32_t *lo, const int32_t *hi,
                 int width, const float *agg, int32_t *disp, hipStream_t st) {
-    int64_t n = g.off[g.n_pairs];
-    if (width >= 64)
-        k_wta_wave<<<grid_for(n * 64), kBlock, 0, st>>>(g, node, lo, hi, width, agg, disp, n);
-    else
-        k_wta_thread<<<grid_for(n), kBlock, 0, st>>>(g, node, lo, hi, width, agg, disp, n);
+    const int64_t n = g.off[g.n_pairs];
+    const int lpr = width <= 16 ? 4 : width <= 32 ? 8 : width <= 64 ? 16 : width <= 128 ? 32 : 64;
+#define HDP_WTA(L) k_wta<L><<<grid_for(n * L), kBlock, 0, st>>>(g, node, lo, hi, width, agg, disp, n)
+    if (lpr == 4) HDP_WTA(4);
+    else if (lpr == 8) HDP_WTA(8);
+    else if (lpr == 16) HDP_WTA(16);
+    else if (lpr == 32) HDP_WTA(32);
+    else HDP_WTA(64);
+#undef HDP_WTA
 }
 
 }  // namespace hdp
