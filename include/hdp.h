@@ -77,7 +77,9 @@ enum {
     HDP_INFO_ERROR = 7,      /* nonzero if an internal consistency guard tripped */
     HDP_INFO_LIVE_EDGES = 8, /* edges still joining two components after the tile-local phase */
     HDP_INFO_ACTIVE_COMPONENTS = 9, /* components with an edge left after the tile-local phase */
-    HDP_INFO_TOUR_RUNS = 10  /* entries of the contracted Euler-tour list */
+    HDP_INFO_TOUR_RUNS = 10, /* entries of the contracted Euler-tour list */
+    HDP_INFO_LIST_EDGES = 11 /* edges still live after the full-grid rounds of the spanning
+                                forest (0 when none ran or they finished it) */
 };
 
 /*

@@ -46,6 +46,9 @@ enum {
 
 // Rounds run by full-grid launches before one workgroup finishes the rest.
 constexpr int kBvGridRounds = 4;
+// Further rounds on the compacted list of live edges (cheap: a pass over the
+// few edges still live), before the one-workgroup tail takes what is left.
+constexpr int kBvListRounds = 8;
 constexpr int kRankGridRounds = 12;  // pointer-jumping steps on the full grid ...
 constexpr int kRankJumps = 12;        // ... taken kRankJumps per launch
 // Sizes of the one-workgroup LDS tails: spanning forest (edges, components,
@@ -546,13 +549,17 @@ __device__ __forceinline__ void offer_min(uint64_t *best, int x, uint64_t k, uin
     if (seen > k) atomicMin((unsigned long long *)&best[x], (unsigned long long)k);
 }
 
+// kList: a round on the compacted list of live edges (the rounds after the
+// compaction) instead of the whole list left by the tile-local phase.
+template <bool kList>
 __global__ __launch_bounds__(kBlock) void k_gbv_minedge(
     int round, const int32_t *__restrict__ flags, const int32_t *__restrict__ ctr, LevelGeom g,
     uint64_t *__restrict__ E, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
     uint64_t *__restrict__ best, int32_t *__restrict__ info) {
-    const int nE = ctr[CTR_E];  // loaded together with the round's flag
+    // counters loaded together with the round's flag
+    const int nLive = ctr[CTR_E], nE = kList ? ctr[CTR_ET] : nLive;
     const int more = round > 0 ? flags[FLAG_BV + round - 1] : 1;
-    if (nE <= kTE) return;  // small contracted graph: the tail alone
+    if (nLive <= kTE) return;  // small contracted graph: the tail alone
     if (more == 0) return;
     for (int i = (int)gtid(); i < nE; i += gridDim.x * kBlock) {
         uint64_t k = E[i];
@@ -621,6 +628,45 @@ __global__ __launch_bounds__(kBlock) void k_gbv_compact(
         int pos = wave_append(live, &ctr[CTR_ET]);
         if (live) Et[pos] = k;
     }
+}
+
+// Hooking of a round on the compacted list, driven by the edges: a component
+// hooks along the one live edge equal to its minimum (mutual choice: the
+// smaller id stays the root), and the next round's minima of both ends are
+// cleared (every component of the next round is an end of a live edge).  The
+// components are those at the start of the round: links stored in this launch
+// carry round + 1 and are not followed.
+__global__ __launch_bounds__(kBlock) void k_gbv_lhook(
+    int round, int32_t *__restrict__ flags, const int32_t *__restrict__ ctr, LevelGeom g,
+    const uint64_t *__restrict__ Et, const int32_t *__restrict__ comp0, uint64_t *__restrict__ cw,
+    const uint64_t *__restrict__ best, uint64_t *__restrict__ best_next,
+    uint8_t *__restrict__ intree, int32_t *__restrict__ info) {
+    const int nLive = ctr[CTR_E], nE = ctr[CTR_ET];  // loaded together with the flag
+    const int more = flags[FLAG_BV + round - 1];
+    if (nLive <= kTE || more == 0) return;
+    bool hooked = false;
+    for (int i = (int)gtid(); i < nE; i += gridDim.x * kBlock) {
+        const uint64_t k = Et[i];
+        if (k == kNoEdge) continue;
+        const uint32_t e = (uint32_t)k;
+        int a = comp0[e >> 1], b = comp0[other_end(g, e)];
+        find_comp2(cw, a, b, round, info);
+        if (a == b) continue;
+        best_next[a] = kNoEdge;
+        best_next[b] = kNoEdge;
+        const uint64_t ba = best[a], bb = best[b];
+        const uint64_t link = (uint64_t)(round + 1) << 32;
+        if (ba == k && !(bb == k && a < b)) {
+            st_relaxed(&cw[a], link | (uint32_t)b);
+            intree[e] = 1;
+            hooked = true;
+        } else if (bb == k && !(ba == k && b < a)) {
+            st_relaxed(&cw[b], link | (uint32_t)a);
+            intree[e] = 1;
+            hooked = true;
+        }
+    }
+    if (__ballot(hooked) && (threadIdx.x & 63) == 0) flags[FLAG_BV + round] = 1;
 }
 
 // The remaining rounds in one workgroup.  With at most kTE edges and kTN
@@ -1620,6 +1666,7 @@ __device__ __forceinline__ void finish_info(const int32_t *__restrict__ flags,
     info[HDP_INFO_LIVE_EDGES] = ctr[CTR_E];
     info[HDP_INFO_ACTIVE_COMPONENTS] = ctr[CTR_RALL];
     info[HDP_INFO_TOUR_RUNS] = ctr[CTR_RUNS];
+    info[HDP_INFO_LIST_EDGES] = ctr[CTR_ET];
     // every tree of sz nodes has a tour of 2(sz - 1) slots
     info[HDP_INFO_N_TREES] = (int32_t)(n - (int64_t)((uint32_t)*root_total >> 1));
     info[HDP_INFO_MST_ROUNDS] = __popcll(bv);
@@ -1861,7 +1908,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     for (int r = 0; r < bv_rounds; ++r) {
         uint64_t *bc = (r & 1) ? t.best1 : t.best0, *bn = (r & 1) ? t.best0 : t.best1;
         if (r > 0)  // round 0's minimum edges come from the tile-local phase
-            k_gbv_minedge<<<g_edges, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
+            k_gbv_minedge<false><<<g_edges, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
                                                       bc, f.info);
         k_gbv_hook<<<g_roots, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Rall, t.comp0, t.cw, bc, bn,
                                                t.intree, f.info);
@@ -1869,9 +1916,19 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     if (bv_rounds > 0)  // without rounds every listed edge is live: the tail reads the list
         k_gbv_compact<<<g_edges, kBlock, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
                                               t.Et, f.info);
-    k_gbv_tail<<<1, kLocalThreads, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.E, t.Et, t.comp0,
-                                            t.cw, t.Rall, t.croot, t.best0, t.best1, t.intree,
-                                            f.info);
+    // rounds on the compacted list (each skipped once a round hooked nothing)
+    const int list_rounds = bv_rounds > 0 ? kBvListRounds : 0;
+    const unsigned g_list = g_edges < 512u ? g_edges : 512u;
+    for (int r = bv_rounds; r < bv_rounds + list_rounds; ++r) {
+        uint64_t *bc = (r & 1) ? t.best1 : t.best0, *bn = (r & 1) ? t.best0 : t.best1;
+        k_gbv_minedge<true><<<g_list, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Et, t.comp0, t.cw,
+                                                       bc, f.info);
+        k_gbv_lhook<<<g_list, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Et, t.comp0, t.cw, bc, bn,
+                                               t.intree, f.info);
+    }
+    k_gbv_tail<<<1, kLocalThreads, 0, st>>>(bv_rounds + list_rounds, t.flags, t.ctr, g, t.E, t.Et,
+                                            t.comp0, t.cw, t.Rall, t.croot, t.best0, t.best1,
+                                            t.intree, f.info);
     // 3: roots
     k_gbv_final<<<g_roots, kBlock, 0, st>>>(t.ctr, t.Rall, t.cw, t.lmin, t.croot, t.mnroot, f.info);
     k_set_tree<<<gn, kBlock, 0, st>>>(t.comp0, t.croot, t.lmin, t.mnroot, t.intree, g, f.tree,

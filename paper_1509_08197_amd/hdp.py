@@ -23,7 +23,8 @@ MAX_LABELS = 256
 MAX_PHASES = 40
 INFO_WORDS = 16
 INFO = dict(n_levels=0, n_phases=1, n_trees=2, width=3, mst_rounds=4, rank_rounds=5,
-            bad_interval=6, error=7, live_edges=8, active_components=9, tour_runs=10)
+            bad_interval=6, error=7, live_edges=8, active_components=9, tour_runs=10,
+            list_edges=11)
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "invalid shape or batch",
           -3: "workspace too small", -4: "outside the exact disparity-forest regime",

@@ -793,6 +793,54 @@ def test_hdp_rt_forest_bit_exact(H, orc, seed):
     np.testing.assert_array_equal(F["hi"], thi)
 
 
+def ruler_path_ranks(n_tiles, rng):
+    """Edge ranks of a 2 x (32 n_tiles) image whose 32 x 2 tiles form a path:
+    edges inside a tile rank 0 (each tile becomes one component in the
+    tile-local phase) and the two edges crossing from tile t to t + 1 rank
+    2 (1 + v2(t + 1)) plus a random bit, so that every spanning-forest round
+    merges the components in pairs only: log2(n_tiles) + 1 hooking rounds."""
+    W = 32 * n_tiles
+    rank = np.zeros((2, W, 2), np.int64)  # [y, x, dir]: dir 0 joins x + 1, dir 1 joins y + 1
+    t = np.arange(n_tiles - 1)
+    v2 = np.array([(int(k) & -int(k)).bit_length() - 1 for k in t + 1])
+    for y in range(2):
+        rank[y, 32 * t + 31, 0] = 2 * (1 + v2) + rng.integers(0, 2, n_tiles - 1)
+    return rank.reshape(-1).astype(np.int32)
+
+
+@pytest.mark.parametrize("n_pairs,tail_mode", [(2, "lds"), (8, "global")])
+def test_rt_ruler_path_many_rounds(H, orc, n_pairs, tail_mode):
+    """Spanning-forest rounds past the full-grid and compacted-list rounds: a
+    batch of 2 x 262144 pairs of 8192 tiles each needs 13 hooking rounds, so
+    the one-workgroup tail finishes the last one, in LDS (2 pairs: 2044 live
+    edges after the full-grid rounds) or in global memory (8 pairs: 8176).
+    Every pair's tree against the oracle's Kruskal in (rank, id) order."""
+    n_tiles, Hh = 8192, 2
+    Ww = 32 * n_tiles
+    rng = np.random.default_rng(40 + n_pairs)
+    imgs = [rng.integers(0, 256, (Hh, Ww, 3), dtype=np.uint8) for _ in range(n_pairs)]
+    ranks = [ruler_path_ranks(n_tiles, rng) for _ in range(n_pairs)]
+    shapes = [(Hh, Ww, 15)] * n_pairs
+    lv = H.pyramid(rgb_dev(*imgs), shapes, 2, 0)
+    f = H.build_tree(lv[0], shapes, 0, rank=dev(np.concatenate(ranks)))
+    F = forest_np(f)
+    info = F["info"]
+    assert info[H.INFO["error"]] == 0
+    assert info[H.INFO["n_trees"]] == n_pairs
+    assert info[H.INFO["mst_rounds"]] == 13, info[H.INFO["mst_rounds"]]
+    assert info[H.INFO["live_edges"]] == n_pairs * 2 * (n_tiles - 1)
+    assert info[H.INFO["list_edges"]] == n_pairs * 2 * (n_tiles // 16 - 1)
+    assert (info[H.INFO["list_edges"]] > 6144) == (tail_mode == "global")
+    n = Hh * Ww
+    for i in range(n_pairs):
+        ref, _, _ = rt_reference(orc, imgs[i], Hh, Ww, 0, ranks[i])
+        par = F["parent"][i * n:(i + 1) * n]
+        np.testing.assert_array_equal(np.where(par >= 0, par - i * n, -1), ref["parent"],
+                                      err_msg=f"pair {i} parent")
+        np.testing.assert_array_equal(F["depth"][i * n:(i + 1) * n], ref["depth"],
+                                      err_msg=f"pair {i} depth")
+
+
 def test_hdp_rt_loop_stagewise(H, orc):
     """The whole HDP+RT loop: every layer's forest and aggregation against the
     oracle's loop with the same ranks (layer l fed the oracle's layer l+1
