@@ -26,18 +26,18 @@ __device__ __forceinline__ T wave_incl_scan(T x) {
     return x;
 }
 
-// Exclusive scan of one value per thread across the 256-thread workgroup.
+// Exclusive scan of one value per thread across a workgroup of NT threads.
 // Returns the exclusive prefix; *total receives the workgroup sum.
-template <typename T>
-__device__ __forceinline__ T block_excl_scan(T x, T *total) {
-    __shared__ T wsum[kBlock / 64];
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan_n(T x, T *total) {
+    __shared__ T wsum[NT / 64];
     int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     T inc = wave_incl_scan(x);
     if (lane == 63) wsum[wv] = inc;
     __syncthreads();
     T base = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         T s = wsum[w];
         if (w < wv) base += s;
         tot += s;
@@ -45,6 +45,11 @@ __device__ __forceinline__ T block_excl_scan(T x, T *total) {
     __syncthreads();
     *total = tot;
     return base + inc - x;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T x, T *total) {
+    return block_excl_scan_n<kBlock>(x, total);
 }
 
 // Scan inputs may be stored narrower than the sums: wide(x) gives the value
@@ -71,28 +76,6 @@ __device__ __forceinline__ void load_run(const TIn *__restrict__ in, int64_t bas
     }
 }
 
-// Sum of part[0..m) over the workgroup's threads (thread t takes t, t + kBlock,
-// ...), eight independent loads in flight per step.
-template <typename T>
-__device__ __forceinline__ T strided_sum(const T *__restrict__ part, int64_t m) {
-    T acc[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] = 0;
-    int64_t j = threadIdx.x;
-    for (; j + 7 * kBlock < m; j += 8 * kBlock) {
-        T x[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = part[j + u * kBlock];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] += x[u];
-    }
-    for (; j < m; j += kBlock) acc[0] += part[j];
-    T s = 0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s += acc[u];
-    return s;
-}
-
 template <typename T, typename TIn = T, typename Widen = WidenSame>
 __global__ void k_scan_reduce(const TIn *__restrict__ in, int64_t n, T *__restrict__ partial,
                               Widen wide = Widen()) {
@@ -107,47 +90,64 @@ __global__ void k_scan_reduce(const TIn *__restrict__ in, int64_t n, T *__restri
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// Scan of one tile; the tile's offset is the sum of the partial sums of all
-// preceding tiles, reduced by the whole workgroup (no serial pass over the
-// partials).
+// In-place exclusive scan of the nb tile sums in one workgroup: thread t sums
+// its contiguous chunk, the workgroup scans the chunk sums, and the thread
+// rewrites its chunk as running prefixes.  grand (may be NULL) = the total.
+constexpr int kPartThreads = 1024;
+template <typename T>
+__global__ __launch_bounds__(kPartThreads) void k_scan_partials(T *__restrict__ part, int64_t nb,
+                                                                T *__restrict__ grand) {
+    const int64_t c = (nb + kPartThreads - 1) / kPartThreads;
+    const int64_t lo = (int64_t)threadIdx.x * c;
+    const int64_t hi = lo + c < nb ? lo + c : nb;
+    T s = 0;
+#pragma unroll 8
+    for (int64_t j = lo; j < hi; ++j) s += part[j];
+    T tot;
+    T ex = block_excl_scan_n<kPartThreads>(s, &tot);
+    for (int64_t j = lo; j < hi; ++j) {
+        const T x = part[j];
+        part[j] = ex;
+        ex += x;
+    }
+    if (grand && threadIdx.x == 0) *grand = tot;
+}
+
+// Scan of one tile, offset by its entry of the scanned tile sums.
 template <typename T, typename TIn = T, typename Widen = WidenSame>
 __global__ void k_scan_apply(const TIn *__restrict__ in, T *__restrict__ out, int64_t n,
-                             const T *__restrict__ partial, T *__restrict__ grand, int inclusive,
-                             Widen wide = Widen()) {
+                             const T *__restrict__ partial, int inclusive, Widen wide = Widen()) {
     const int64_t tile = blockIdx.x;
-    // the tile's elements and the partial sums before it, loads issued together
     const int64_t base = tile * kScanTile + threadIdx.x * kScanPerThread;
     T v[kScanPerThread];
     load_run(in, base, n, wide, v);
-    const T pre = strided_sum(partial, tile);
-    T pre_all;
-    block_excl_scan(pre, &pre_all);
+    const T pre = partial[tile];
     T s = 0;
 #pragma unroll
     for (int i = 0; i < kScanPerThread; ++i) s += v[i];
     T tot;
-    T ex = block_excl_scan(s, &tot) + pre_all;
+    T ex = block_excl_scan(s, &tot) + pre;
 #pragma unroll
     for (int i = 0; i < kScanPerThread; ++i) {
         T nx = ex + v[i];
         if (base + i < n) out[base + i] = inclusive ? nx : ex;
         ex = nx;
     }
-    if (grand && tile == gridDim.x - 1 && threadIdx.x == 0) *grand = pre_all + tot;
 }
 
 inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
 // out[i] = sum of in[0..i-1] (exclusive) or in[0..i] (inclusive); in == out allowed.
 // partial: scratch of scan_tiles(n) elements; grand (device, may be NULL) = total.
-// Two launches: per-tile sums, then every tile adds the sums before it.
+// Three launches: per-tile sums, their scan, then every tile's own scan.
 template <typename T, typename TIn = T, typename Widen = WidenSame>
 inline void device_scan(const TIn *in, T *out, int64_t n, T *partial, T *grand, bool inclusive,
                         hipStream_t st, Widen wide = Widen()) {
     int64_t nb = scan_tiles(n);
     if (nb < 1) nb = 1;
     k_scan_reduce<T, TIn, Widen><<<(unsigned)nb, kBlock, 0, st>>>(in, n, partial, wide);
-    k_scan_apply<T, TIn, Widen><<<(unsigned)nb, kBlock, 0, st>>>(in, out, n, partial, grand,
+    k_scan_partials<T><<<1, kPartThreads, 0, st>>>(partial, nb, grand);
+    k_scan_apply<T, TIn, Widen><<<(unsigned)nb, kBlock, 0, st>>>(in, out, n, partial,
                                                                  inclusive ? 1 : 0, wide);
 }
 

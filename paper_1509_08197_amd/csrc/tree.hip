@@ -1959,8 +1959,8 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         t.partial64, (int)n_scan);
     // 6: tour offsets (the root-data scan, tile sums from k_parent), tour
     // values, prefix sum, per-node depth / light depth / preorder
-    k_scan_apply<uint64_t><<<n_scan, kBlock, 0, st>>>(t.rootval, t.rootval, n, t.partial64,
-                                                       t.root_total, 0);
+    k_scan_partials<uint64_t><<<1, kPartThreads, 0, st>>>(t.partial64, n_scan, t.root_total);
+    k_scan_apply<uint64_t><<<n_scan, kBlock, 0, st>>>(t.rootval, t.rootval, n, t.partial64, 0);
     k_tour_scatter<<<tiled_grid((int)n_tiles), kBlock, 0, st>>>(
         g, t.nrec, f.tree, t.size, rk, t.rootval, t.tour8, t.posw, (int)n_tiles, f.info);
     int64_t tour_len = 2 * n;  // upper bound; entries past the real length are never read
