@@ -23,13 +23,19 @@ struct LevelGeom {
 
 constexpr int kTile = 32;  // side of the square pixel tiles of the tree builder's local phases
 
-// Pair that holds global pixel v (binary search over the offsets).
+// Pair that holds global pixel v: a binary search for the first active lane's
+// pixel, uniform over the wavefront (scalar loads of the offsets), then every
+// lane steps to its own pair (no steps when the wavefront's pixels lie in one
+// pair).
 __device__ __forceinline__ int pair_of(const LevelGeom &g, int v) {
+    const int v0 = __builtin_amdgcn_readfirstlane(v);
     int lo = 0, hi = g.n_pairs - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (g.off[mid] <= v) lo = mid; else hi = mid - 1;
+        if (g.off[mid] <= v0) lo = mid; else hi = mid - 1;
     }
+    while (lo > 0 && g.off[lo] > v) --lo;
+    while (lo + 1 < g.n_pairs && g.off[lo + 1] <= v) ++lo;
     return lo;
 }
 

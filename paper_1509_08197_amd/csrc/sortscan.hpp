@@ -90,38 +90,49 @@ __global__ void k_scan_reduce(const TIn *__restrict__ in, int64_t n, T *__restri
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// In-place exclusive scan of the nb tile sums in one workgroup: thread t sums
-// its contiguous chunk, the workgroup scans the chunk sums, and the thread
-// rewrites its chunk as running prefixes.  grand (may be NULL) = the total.
-constexpr int kPartThreads = 1024;
+// Tile sums are scanned in blocks of kScanTile: every workgroup scans one
+// block in place (exclusive) and writes the block's total to sup[block]; a
+// tile's offset is then its scanned sum plus the totals of the blocks before
+// its own (few: one per kScanTile tiles), summed by its workgroup.
 template <typename T>
-__global__ __launch_bounds__(kPartThreads) void k_scan_partials(T *__restrict__ part, int64_t nb,
-                                                                T *__restrict__ grand) {
-    const int64_t c = (nb + kPartThreads - 1) / kPartThreads;
-    const int64_t lo = (int64_t)threadIdx.x * c;
-    const int64_t hi = lo + c < nb ? lo + c : nb;
+__global__ void k_scan_partials(T *__restrict__ part, int64_t nb, T *__restrict__ sup) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanPerThread;
+    T v[kScanPerThread];
+    load_run(part, base, nb, WidenSame(), v);
     T s = 0;
-#pragma unroll 8
-    for (int64_t j = lo; j < hi; ++j) s += part[j];
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) s += v[i];
     T tot;
-    T ex = block_excl_scan_n<kPartThreads>(s, &tot);
-    for (int64_t j = lo; j < hi; ++j) {
-        const T x = part[j];
-        part[j] = ex;
-        ex += x;
+    T ex = block_excl_scan(s, &tot);
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) {
+        if (base + i < nb) part[base + i] = ex;
+        ex += v[i];
     }
-    if (grand && threadIdx.x == 0) *grand = tot;
+    if (threadIdx.x == 0) sup[blockIdx.x] = tot;
 }
 
-// Scan of one tile, offset by its entry of the scanned tile sums.
+// Sum of sup[0..m) over the workgroup (every thread receives it).
+template <typename T>
+__device__ __forceinline__ T block_sum_prefix(const T *__restrict__ sup, int64_t m) {
+    T a = 0;
+    for (int64_t j = threadIdx.x; j < m; j += kBlock) a += sup[j];
+    T tot;
+    block_excl_scan(a, &tot);
+    return tot;
+}
+
+// Scan of one tile, offset by its scanned tile sum and the block totals
+// before it.  grand (may be NULL) receives the total from the last tile.
 template <typename T, typename TIn = T, typename Widen = WidenSame>
 __global__ void k_scan_apply(const TIn *__restrict__ in, T *__restrict__ out, int64_t n,
-                             const T *__restrict__ partial, int inclusive, Widen wide = Widen()) {
+                             const T *__restrict__ partial, const T *__restrict__ sup,
+                             T *__restrict__ grand, int inclusive, Widen wide = Widen()) {
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * kScanTile + threadIdx.x * kScanPerThread;
     T v[kScanPerThread];
     load_run(in, base, n, wide, v);
-    const T pre = partial[tile];
+    const T pre = partial[tile] + block_sum_prefix(sup, tile / kScanTile);
     T s = 0;
 #pragma unroll
     for (int i = 0; i < kScanPerThread; ++i) s += v[i];
@@ -133,22 +144,35 @@ __global__ void k_scan_apply(const TIn *__restrict__ in, T *__restrict__ out, in
         if (base + i < n) out[base + i] = inclusive ? nx : ex;
         ex = nx;
     }
+    if (grand && tile == gridDim.x - 1 && threadIdx.x == 0) *grand = pre + tot;
 }
 
 inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+// Scratch elements of a scan of n elements: the tile sums, then the block totals.
+inline int64_t scan_scratch(int64_t n) {
+    const int64_t nb = scan_tiles(n) < 1 ? 1 : scan_tiles(n);
+    return nb + scan_tiles(nb) + 1;
+}
+// Scan of the tile sums part[0..nb) (blockwise) and the tiles of in.
+template <typename T, typename TIn, typename Widen>
+inline void scan_sums_and_apply(const TIn *in, T *out, int64_t n, T *part, int64_t nb, T *grand,
+                                bool inclusive, hipStream_t st, Widen wide) {
+    const int64_t nsup = scan_tiles(nb);
+    k_scan_partials<T><<<(unsigned)nsup, kBlock, 0, st>>>(part, nb, part + nb);
+    k_scan_apply<T, TIn, Widen><<<(unsigned)nb, kBlock, 0, st>>>(in, out, n, part, part + nb,
+                                                                 grand, inclusive ? 1 : 0, wide);
+}
 
 // out[i] = sum of in[0..i-1] (exclusive) or in[0..i] (inclusive); in == out allowed.
-// partial: scratch of scan_tiles(n) elements; grand (device, may be NULL) = total.
-// Three launches: per-tile sums, their scan, then every tile's own scan.
+// partial: scratch of scan_scratch(n) elements; grand (device, may be NULL) = total.
+// Three launches: per-tile sums, their blockwise scan, then every tile's own scan.
 template <typename T, typename TIn = T, typename Widen = WidenSame>
 inline void device_scan(const TIn *in, T *out, int64_t n, T *partial, T *grand, bool inclusive,
                         hipStream_t st, Widen wide = Widen()) {
     int64_t nb = scan_tiles(n);
     if (nb < 1) nb = 1;
     k_scan_reduce<T, TIn, Widen><<<(unsigned)nb, kBlock, 0, st>>>(in, n, partial, wide);
-    k_scan_partials<T><<<1, kPartThreads, 0, st>>>(partial, nb, grand);
-    k_scan_apply<T, TIn, Widen><<<(unsigned)nb, kBlock, 0, st>>>(in, out, n, partial,
-                                                                 inclusive ? 1 : 0, wide);
+    scan_sums_and_apply(in, out, n, partial, nb, grand, inclusive, st, wide);
 }
 
 // ---------------------------------------------------------------------------

@@ -1825,11 +1825,11 @@ static TreeWs carve_tree_ws(void *ws, int64_t n, size_t *bytes) {
     t.rootval = b.take<uint64_t>(n);
     t.tourval = b.take<uint64_t>(2 * n);
     t.tour8 = b.take<uint8_t>(2 * n);
-    t.partial64 = b.take<uint64_t>(scan_tiles(2 * n) + 1);
+    t.partial64 = b.take<uint64_t>(scan_scratch(2 * n));
     t.root_total = b.take<uint64_t>(1);
     t.intree = b.take<uint8_t>(2 * n);
     t.adj = b.take<uint8_t>(n);
-    t.partial32 = b.take<int32_t>(scan_tiles(256 * ntiles) + 1);
+    t.partial32 = b.take<int32_t>(scan_scratch(256 * ntiles));
     t.hist = b.take<int32_t>(256 * ntiles);
     t.sortA = b.take<int32_t>(n);
     t.sortB = b.take<int32_t>(n);
@@ -1959,8 +1959,8 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         t.partial64, (int)n_scan);
     // 6: tour offsets (the root-data scan, tile sums from k_parent), tour
     // values, prefix sum, per-node depth / light depth / preorder
-    k_scan_partials<uint64_t><<<1, kPartThreads, 0, st>>>(t.partial64, n_scan, t.root_total);
-    k_scan_apply<uint64_t><<<n_scan, kBlock, 0, st>>>(t.rootval, t.rootval, n, t.partial64, 0);
+    scan_sums_and_apply(t.rootval, t.rootval, n, t.partial64, (int64_t)n_scan, t.root_total,
+                        false, st, WidenSame());
     k_tour_scatter<<<tiled_grid((int)n_tiles), kBlock, 0, st>>>(
         g, t.nrec, f.tree, t.size, rk, t.rootval, t.tour8, t.posw, (int)n_tiles, f.info);
     int64_t tour_len = 2 * n;  // upper bound; entries past the real length are never read
