@@ -111,7 +111,10 @@ enum {
  *   node    row -> pixel id.
  *   prow    row of the parent, -1 at roots.
  *   heavy   1 if the row's pixel is its parent's heavy child (same chain).
- *   lc      [3][n] rows of the light children, -1 where absent.
+ *   lc      [2][n] rows of the light children, -1 where absent (a node has
+ *           at most two: a tree is rooted at its smallest pixel id, whose
+ *           upper and left neighbours lie outside its tree, so a root has at
+ *           most two children and any other node at most three).
  *   rw      weight of the row's edge to its parent (= wgt[node]).
  *   rx      column (x) of the row's pixel in its image.
  *   rlh     interval of the row's pixel, lo | hi << 16 (= lo[node], hi[node]).

@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
     // stage 1: loads that do not depend on other tiles of this launch
     double av[kRPG];
     double bv[kRPG][CPT];
-    int rr[kRPG], x0[kRPG], x1[kRPG], x2[kRPG];
+    int rr[kRPG], x0[kRPG], x1[kRPG];
 #pragma unroll
     for (int i = 0; i < kRPG; ++i) {
         int li = g * kRPG + i;
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
         bool in = active && (UP ? r >= r0 : r < r1);
         rr[i] = in ? r : -1;
         av[i] = 1.0;
-        x0[i] = x1[i] = x2[i] = -1;
+        x0[i] = x1[i] = -1;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) bv[i][c] = 0.0;
         if (!in) continue;
@@ -366,7 +366,6 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
             for (int c = 0; c < CPT; ++c) bv[i][c] = (double)v[c];
             x0[i] = A.lc[r];
             x1[i] = A.lc[A.n + r];
-            x2[i] = A.lc[2 * A.n + r];
         } else {
             // heavy flag, coefficients and parent row, loaded together
             const bool hv = A.heavy[r];
@@ -392,10 +391,7 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
 #pragma unroll
     for (int i = 0; i < kRPG; ++i) {
         wait_row(x0[i]);
-        if (UP) {
-            wait_row(x1[i]);
-            wait_row(x2[i]);
-        }
+        if (UP) wait_row(x1[i]);
     }
 #pragma unroll
     for (int i = 0; i < kRPG; ++i) {
@@ -410,12 +406,6 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
             if (x1[i] >= 0) {
                 double sc = A.s[x1[i]];
                 load_cols_dev<CPT>(A.dst + (int64_t)x1[i] * w + j0, v);
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
-            }
-            if (x2[i] >= 0) {
-                double sc = A.s[x2[i]];
-                load_cols_dev<CPT>(A.dst + (int64_t)x2[i] * w + j0, v);
 #pragma unroll
                 for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
             }
@@ -633,70 +623,84 @@ __global__ void __launch_bounds__(kBlock)
     if (FUSE) {
 #pragma unroll
         for (int i = 0; i < kRPG; ++i) {
-            fv[i] = A.node[rc[i]];
-            if (UP) fx[i] = A.rx[rc[i]];
-            flh[i] = A.rlh[rc[i]];
+            fv[i] = at32(A.node, rc[i]);
+            if (UP) fx[i] = at32(A.rx, rc[i]);
+            flh[i] = at32(A.rlh, rc[i]);
         }
     }
+    // Row maps x -> av * x + bv.  The constant terms are sums of non-negative
+    // terms (costs, or coefficients times stored rows), so holding them in
+    // FP32 adds one relative rounding of at most 2^-24 per row; the maps are
+    // composed in FP64.  At most two light children per row are gathered (a
+    // tree's root, its smallest pixel, has no upper or left tree neighbour).
     double av[kRPG];
-    double bv[kRPG][CPT];
-    int x0[kRPG], x1[kRPG], x2[kRPG];
+    float bv[kRPG][CPT];
+    int x0[kRPG], x1[kRPG];
     {
         float v[kRPG][CPT];
         uint8_t hf[kRPG];
         double sf[kRPG], of[kRPG];
         int pf[kRPG];
-        float4 Lp[FUSE && UP ? kRPG : 1];
-        float4 Rp[FUSE && UP ? kRPG : 1][CPT];
 #pragma unroll
         for (int i = 0; i < kRPG; ++i) {
             const int r = rc[i];
             if (UP) {
                 const int rn = r + 1 < r1 ? r + 1 : r;  // next row: heavy flag and coefficient
-                hf[i] = A.heavy[rn];
-                sf[i] = A.s[rn];
-                x0[i] = A.lc[r];
-                x1[i] = A.lc[A.n + r];
-                x2[i] = A.lc[2 * A.n + r];
+                hf[i] = at32(A.heavy, rn);
+                sf[i] = at32(A.s, rn);
+                x0[i] = at32(A.lc, r);
+                x1[i] = at32(A.lc, A.n + r);
             } else {
-                hf[i] = A.heavy[r];
-                sf[i] = A.s[r];
-                of[i] = A.om[r];
-                pf[i] = A.prow[r];
+                hf[i] = at32(A.heavy, r);
+                sf[i] = at32(A.s, r);
+                of[i] = at32(A.om, r);
+                pf[i] = at32(A.prow, r);
             }
-            if (FUSE && UP) {
-                Lp[i] = A.imL[fv[i]];
-                const int a = flh[i] & 0xFFFF;
+            if (!(FUSE && UP)) load_cols<CPT>(A.src + (int64_t)r * w + j0, v[i]);
+        }
+        if (FUSE && UP) {  // cost of labels lo + j0 .. (columns past hi hold 0), half of the rows at a time
+            constexpr int kH = kRPG >= 2 ? 2 : 1;
+            constexpr int kR2 = kRPG / kH;
 #pragma unroll
-                for (int c = 0; c < CPT; ++c) Rp[i][c] = A.imR[match_src(fv[i], fx[i], a + j0 + c)];
-            } else {
-                load_cols<CPT>(A.src + (int64_t)r * w + j0, v[i]);
+            for (int h = 0; h < kH; ++h) {
+                float4 Lp[kR2], Rp[kR2][CPT];
+#pragma unroll
+                for (int ii = 0; ii < kR2; ++ii) {
+                    const int i = h * kR2 + ii;
+                    Lp[ii] = at32(A.imL, fv[i]);
+                    const int a = flh[i] & 0xFFFF;
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c)
+                        Rp[ii][c] = at32(A.imR, match_src(fv[i], fx[i], a + j0 + c));
+                }
+#pragma unroll
+                for (int ii = 0; ii < kR2; ++ii) {
+                    const int i = h * kR2 + ii;
+                    const int a = flh[i] & 0xFFFF, b = flh[i] >> 16;
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) {
+                        const int label = a + j0 + c;
+                        v[i][c] = label <= b ? match_cost_px(Lp[ii], Rp[ii][c], fx[i] - label < 0, A.cp)
+                                             : 0.f;
+                    }
+                }
             }
         }
 #pragma unroll
         for (int i = 0; i < kRPG; ++i) {
             const bool in = rr[i] >= 0;
             const int r = rc[i];
-            if (FUSE && UP) {  // cost of labels lo + j0 .. (columns past hi hold 0)
-                const int a = flh[i] & 0xFFFF, b = flh[i] >> 16;
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) {
-                    const int label = a + j0 + c;
-                    v[i][c] = label <= b ? match_cost_px(Lp[i], Rp[i][c], fx[i] - label < 0, A.cp)
-                                         : 0.f;
-                }
-            }
             if (UP) {
                 av[i] = !in ? 1.0 : (r + 1 < r1 && hf[i]) ? sf[i] : 0.0;
 #pragma unroll
-                for (int c = 0; c < CPT; ++c) bv[i][c] = in ? (double)v[i][c] : 0.0;
-                if (!in) x0[i] = x1[i] = x2[i] = -1;
+                for (int c = 0; c < CPT; ++c) bv[i][c] = in ? v[i][c] : 0.f;
+                if (!in) x0[i] = x1[i] = -1;
             } else {
                 av[i] = !in ? 1.0 : hf[i] ? sf[i] : 0.0;
 #pragma unroll
-                for (int c = 0; c < CPT; ++c) bv[i][c] = in ? of[i] * (double)v[i][c] : 0.0;
+                for (int c = 0; c < CPT; ++c) bv[i][c] = in ? (float)(of[i] * (double)v[i][c]) : 0.f;
                 x0[i] = (in && !hf[i]) ? pf[i] : -1;
-                x1[i] = x2[i] = -1;
+                x1[i] = -1;
             }
         }
     }
@@ -723,33 +727,42 @@ __global__ void __launch_bounds__(kBlock)
         }
     };
 
-    // Stage 2: gather the rows of the previous phase.  The first read of every
-    // gathered row (and its coefficient) is issued at once; a row that is
-    // still unwritten is then polled on its own.
+    // Stage 2: gather the rows of the previous phase, half of the rows at a
+    // time (fewer registers in flight).  The first read of every gathered row
+    // (and its coefficient) of the half is issued at once; a row that is still
+    // unwritten is then polled on its own.
     {
-        constexpr int kG = UP ? 3 : 1;  // gathered rows per row
-        float gv[kRPG][kG][CPT];
-        double gs[kRPG][kG];
-        bool ok[kRPG][kG];
+        constexpr int kG = UP ? 2 : 1;  // gathered rows per row
+        constexpr int kH = kRPG >= 2 ? 2 : 1;
+        constexpr int kR2 = kRPG / kH;
 #pragma unroll
-        for (int i = 0; i < kRPG; ++i) {
+        for (int h = 0; h < kH; ++h) {
+            float gv[kR2][kG][CPT];
+            double gs[kR2][kG];
+            bool ok[kR2][kG];
 #pragma unroll
-            for (int m = 0; m < kG; ++m) {
-                const int x = m == 0 ? x0[i] : m == 1 ? x1[i] : x2[i];
-                const int xr = x >= 0 ? x : rc[i];
-                gs[i][m] = UP ? A.s[xr] : A.s[rc[i]];
-                ok[i][m] = poll_cols<CPT>(A.dst + (int64_t)xr * w + j0, gv[i][m], A.err, false);
+            for (int ii = 0; ii < kR2; ++ii) {
+                const int i = h * kR2 + ii;
+#pragma unroll
+                for (int m = 0; m < kG; ++m) {
+                    const int x = m == 0 ? x0[i] : x1[i];
+                    const int xr = x >= 0 ? x : rc[i];
+                    gs[ii][m] = UP ? at32(A.s, xr) : at32(A.s, rc[i]);
+                    ok[ii][m] = poll_cols<CPT>(A.dst + (int64_t)xr * w + j0, gv[ii][m], A.err, false);
+                }
             }
-        }
 #pragma unroll
-        for (int i = 0; i < kRPG; ++i) {
+            for (int ii = 0; ii < kR2; ++ii) {
+                const int i = h * kR2 + ii;
 #pragma unroll
-            for (int m = 0; m < kG; ++m) {
-                const int x = m == 0 ? x0[i] : m == 1 ? x1[i] : x2[i];
-                if (x < 0) continue;
-                if (!ok[i][m]) poll_cols<CPT>(A.dst + (int64_t)x * w + j0, gv[i][m], A.err, true);
+                for (int m = 0; m < kG; ++m) {
+                    const int x = m == 0 ? x0[i] : x1[i];
+                    if (x < 0) continue;
+                    if (!ok[ii][m]) poll_cols<CPT>(A.dst + (int64_t)x * w + j0, gv[ii][m], A.err, true);
 #pragma unroll
-                for (int c = 0; c < CPT; ++c) bv[i][c] += gs[i][m] * (double)gv[i][m][c];
+                    for (int c = 0; c < CPT; ++c)
+                        bv[i][c] = (float)((double)bv[i][c] + gs[ii][m] * (double)gv[ii][m][c]);
+                }
             }
         }
     }
@@ -807,6 +820,7 @@ __global__ void __launch_bounds__(kBlock)
     for (int c = 0; c < CPT; ++c) Xt[c] = 0.0;
     if (active) {
         const int nseg = (A.groups + seg_len - 1) / seg_len;
+#pragma unroll 1
         for (int q2 = 0; q2 < nseg; ++q2) {
             if (q2 == sg) {  // segments before this one, then this group's offset in it
 #pragma unroll

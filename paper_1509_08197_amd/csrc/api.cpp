@@ -34,6 +34,8 @@ namespace {
 
 constexpr int64_t kMaxPixels = (int64_t(1) << 30) - 1;  // tour slot ids 4v+d below 2^32 - 1
 constexpr int64_t kMaxPairPixels = (int64_t(1) << 22) - 1;  // packed depth field
+// per-pixel arrays of up to 16-byte elements are addressed with 32-bit byte offsets
+static_assert(HDP_MAX_PAIRS * kMaxPairPixels * 16 < (int64_t(1) << 32), "32-bit pixel offsets");
 
 hdp_status last_hip() {
     hipError_t e = hipGetLastError();
@@ -99,7 +101,7 @@ FLayout forest_layout(int64_t n) {
     L.level_ptr = take(4 * (n + 1));
     L.node = take(4 * n);
     L.prow = take(4 * n);
-    L.lc = take(4 * 3 * n);
+    L.lc = take(4 * 2 * n);
     L.heavy = take(n);
     L.rw = take(4 * n);
     L.phase_ptr = take(4 * (HDP_MAX_PHASES + 1));

@@ -39,6 +39,17 @@ __device__ __forceinline__ int pair_of(const LevelGeom &g, int v) {
     return lo;
 }
 
+// Element idx of an array of less than 4 GiB, addressed by a 32-bit byte
+// offset from the base: the load takes the scalar-base + 32-bit vector-offset
+// form (one address register instead of two).  Every per-pixel and per-row
+// array of a batch qualifies: a batch holds at most 64 pairs of fewer than
+// 2^22 pixels, so fewer than 2^28 elements of at most 16 bytes.
+template <typename T>
+__device__ __forceinline__ T at32(const T *base, uint32_t idx) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                        (uint64_t)(idx * (uint32_t)sizeof(T)));
+}
+
 struct PixelPos {
     int pair, x, y, W, H, base;
 };

@@ -1727,10 +1727,11 @@ __global__ void k_rows(LevelGeom g, const int32_t *__restrict__ node,
     for (int i = 0; i < 4; ++i) {
         const int d = order[i];
         if (!((c >> d) & 1) || d == pd || d == hd) continue;  // parent or heavy child
-        if (k < 3) lc[(int64_t)k * n + r] = rn[i];
+        if (k < 2) lc[(int64_t)k * n + r] = rn[i];
         ++k;
     }
-    for (; k < 3; ++k) lc[(int64_t)k * n + r] = -1;
+    if (k > 2) info[HDP_INFO_ERROR] = 1;  // a root that is not its tree's smallest pixel
+    for (; k < 2; ++k) lc[(int64_t)k * n + r] = -1;
 }
 
 // --- 8. canonical level order ------------------------------------------------------------
@@ -1916,8 +1917,13 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     if (bv_rounds > 0)  // without rounds every listed edge is live: the tail reads the list
         k_gbv_compact<<<g_edges, kBlock, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
                                               t.Et, f.info);
-    // rounds on the compacted list (each skipped once a round hooked nothing)
-    const int list_rounds = bv_rounds > 0 ? kBvListRounds : 0;
+    // Rounds on the compacted list (each skipped once a round hooked nothing),
+    // launched where the tail would otherwise take more live edges than its
+    // LDS holds: after the full-grid rounds about one live edge per 6 border
+    // pixels is left on a layer without intervals, one per 64 with intervals
+    // (measured).  Elsewhere their launches would cost more than they save.
+    const int64_t est_left = plo ? border_px / 64 : border_px / 6;
+    const int list_rounds = bv_rounds > 0 && est_left > kTE / 2 ? kBvListRounds : 0;
     const unsigned g_list = g_edges < 512u ? g_edges : 512u;
     for (int r = bv_rounds; r < bv_rounds + list_rounds; ++r) {
         uint64_t *bc = (r & 1) ? t.best1 : t.best0, *bn = (r & 1) ? t.best0 : t.best1;

@@ -259,7 +259,7 @@ class Forest:
         if name == "heavy":
             return self._view(name, n, torch.uint8)
         if name == "lc":
-            return self._view(name, 3 * n, torch.int32).view(3, n)
+            return self._view(name, 2 * n, torch.int32).view(2, n)
         if name == "level_ptr":
             return self._view(name, n + 1, torch.int32)
         if name == "phase_ptr":
