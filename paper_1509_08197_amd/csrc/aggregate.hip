@@ -38,6 +38,12 @@ constexpr int kSentMaxWidth = 32;
 constexpr uint32_t kSentF = 0x7fa00001u;
 constexpr uint64_t kSent64 = 0x7fa000017fa00001ull;
 constexpr uint64_t kSentD = 0x7ff4000000000001ull;
+// A narrow-row tile is one workgroup of kNarrowThreads threads; its map is
+// scanned in kNarrowSegs segments of thread groups.  (512-thread tiles, half
+// the tickets per row, measured slower on batches: the longer in-tile scan
+// costs more than the ticket counter saves.)
+constexpr int kNarrowThreads = 256;
+constexpr int kNarrowSegs = kNarrowThreads / 64;
 
 
 // Layout of the device-side pass plan (int32 words).
@@ -77,7 +83,7 @@ static TileGeom make_geom(int width, int cpt, int rpg) {
     t.cpt = cpt;
     t.rpg = rpg;
     t.lpr = (width + cpt - 1) / cpt;
-    t.groups = kBlock / t.lpr;
+    t.groups = (width <= kSentMaxWidth ? kNarrowThreads : kBlock) / t.lpr;
     if (t.groups < 1) t.groups = 1;
     t.rows = t.groups * rpg;
     return t;
@@ -246,6 +252,12 @@ __device__ __forceinline__ void st_dev(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0); }
+// ld_dev of element idx of an array of less than 4 GiB (32-bit byte offset)
+template <typename T>
+__device__ __forceinline__ T ld_dev32(const T *base, uint32_t idx) {
+    return ld_dev(reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                              (uint64_t)(idx * (uint32_t)sizeof(T))));
+}
 
 constexpr int64_t kSpinLimit = int64_t(1) << 20;
 
@@ -567,21 +579,24 @@ __device__ __forceinline__ bool poll_cols(const float *p, float *v, int32_t *err
 // FUSE: the up pass computes the cost of its rows (eq. E) instead of reading a
 // cost volume, and the down pass reduces every row to its winning label.
 // The down pass of the default narrow schedule (two labels per thread, four
-// rows per group) is held to 96 VGPRs: five waves per SIMD instead of four.
+// rows per group) is held to 80 VGPRs, as the up pass is by itself: six waves
+// per SIMD, three tiles per compute unit.
 template <bool UP, int CPT, int kRPG, bool FUSE>
-__global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu((!UP && CPT == 2 && kRPG == 4) ? 5 : 1)))
+__global__ void __launch_bounds__(kNarrowThreads)
+    __attribute__((amdgpu_waves_per_eu((!UP && CPT == 2 && kRPG == 4) ? 6 : 1)))
     k_pass_s(PassArgs A) {
     constexpr bool kWta = FUSE && !UP;
-    __shared__ double sP[kBlock];
-    __shared__ double sX[kBlock * CPT];
-    __shared__ double sSegP[4 * kSentMaxWidth];  // 4 segments x (threads per row <= width)
-    __shared__ double sSegX[4 * kSentMaxWidth * CPT];
+    constexpr int kSeg = kNarrowSegs;
+    __shared__ double sP[kNarrowThreads];
+    __shared__ double sX[kNarrowThreads * CPT];
+    __shared__ double sSegP[kSeg * kSentMaxWidth];  // segments x (threads per row <= width)
+    __shared__ double sSegX[kSeg * kSentMaxWidth * CPT];
     __shared__ int s_ticket;
     __shared__ double s_first;
     __shared__ int32_t s_plan[P_WORDS];
-    __shared__ float sWb[kWta ? kBlock * kRPG : 1];  // fused winner-takes-all candidates
-    __shared__ int sWj[kWta ? kBlock * kRPG : 1];
+    __shared__ float sWb[kWta ? kNarrowThreads * kRPG : 1];  // fused winner-takes-all candidates
+    __shared__ int sWj[kWta ? kNarrowThreads * kRPG : 1];
+    __shared__ int sWv[kWta ? kNarrowThreads * kRPG : 1];     // pixel of each row (lead threads)
     const int tid = threadIdx.x;
     // the ticket, and meanwhile the whole plan into LDS (one word per thread)
     if (tid == 0) s_ticket = atomicAdd(A.ticket, 1);
@@ -729,8 +744,9 @@ __global__ void __launch_bounds__(kBlock)
 
     // Stage 2: gather the rows of the previous phase, half of the rows at a
     // time (fewer registers in flight).  The first read of every gathered row
-    // (and its coefficient) of the half is issued at once; a row that is still
-    // unwritten is then polled on its own.
+    // (and its coefficient) of the half is issued at once, for the rows that
+    // exist only (device-coherent reads are not spent on absent children); a
+    // row that is still unwritten is then polled on its own.
     {
         constexpr int kG = UP ? 2 : 1;  // gathered rows per row
         constexpr int kH = kRPG >= 2 ? 2 : 1;
@@ -746,9 +762,14 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
                 for (int m = 0; m < kG; ++m) {
                     const int x = m == 0 ? x0[i] : x1[i];
-                    const int xr = x >= 0 ? x : rc[i];
-                    gs[ii][m] = UP ? at32(A.s, xr) : at32(A.s, rc[i]);
-                    ok[ii][m] = poll_cols<CPT>(A.dst + (int64_t)xr * w + j0, gv[ii][m], A.err, false);
+                    ok[ii][m] = true;
+                    gs[ii][m] = 0.0;
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) gv[ii][m][c] = 0.f;
+                    if (x >= 0) {
+                        gs[ii][m] = UP ? at32(A.s, x) : at32(A.s, rc[i]);
+                        ok[ii][m] = poll_cols<CPT>(A.dst + (int64_t)x * w + j0, gv[ii][m], A.err, false);
+                    }
                 }
             }
 #pragma unroll
@@ -785,7 +806,6 @@ __global__ void __launch_bounds__(kBlock)
     // Exclusive map of the groups before this thread's group (Pg, Xg) and the
     // tile map (Pt, Xt), in two levels: the groups are cut into kSeg segments
     // scanned at the same time, then the segment maps are combined.
-    constexpr int kSeg = 4;
     const int seg_len = (A.groups + kSeg - 1) / kSeg;
     const int sg = g / seg_len;
     double Pg = 1.0, Xg[CPT];
@@ -848,24 +868,37 @@ __global__ void __launch_bounds__(kBlock)
             st_dev(reinterpret_cast<uint64_t *>(&A.tPs[T]), (uint64_t)__double_as_longlong(Pt));
     }
     // fused winner-takes-all: per row, this thread's least value and its column
-    // (first of equal values), taken as the row is stored
-    float wb[kRPG];
-    int wj[kRPG];
+    // (first of equal values), taken into LDS as the row is stored (every row
+    // of the tile is stored exactly once).  Each row's interval is kept
+    // packed, lo | hi << 8, two rows per register.
+    uint32_t lh2[(kRPG + 1) / 2];
+    if (kWta) {
+        if (jl == 0) {
 #pragma unroll
-    for (int i = 0; i < kRPG; ++i) {
-        wb[i] = __builtin_inff();
-        wj[i] = 0x7fffffff;
+            for (int i = 0; i < kRPG; ++i) sWv[tid * kRPG + i] = fv[i];
+        }
+#pragma unroll
+        for (int i = 0; i < (kRPG + 1) / 2; ++i) lh2[i] = 0;
+#pragma unroll
+        for (int i = 0; i < kRPG; ++i)
+            lh2[i >> 1] |= ((uint32_t)(flh[i] & 0xFF) | (uint32_t)((flh[i] >> 16) & 0xFF) << 8)
+                           << (16 * (i & 1));
     }
     auto take = [&](int i, const double *cv) {
-        const int nl = (flh[i] >> 16) - (flh[i] & 0xFFFF);  // last valid column
+        const uint32_t lh = (lh2[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+        const int nl = (int)(lh >> 8) - (int)(lh & 0xFF);  // last valid column
+        float best = __builtin_inff();
+        int bj = 0x7fffffff;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const float x = (float)cv[c];
-            if (j0 + c <= nl && x < wb[i]) {
-                wb[i] = x;
-                wj[i] = j0 + c;
+            if (j0 + c <= nl && x < best) {
+                best = x;
+                bj = j0 + c;
             }
         }
+        sWb[tid * kRPG + i] = best;
+        sWj[tid * kRPG + i] = bj;
     };
     // rows at or after the tile's first chain break do not depend on the carry-in
     if (active) {
@@ -909,12 +942,13 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
                     for (int c = 0; c < CPT; ++c) carry[c] = (double)v[c];
                     for (int tk = pred + 1; tk < T; ++tk) {
-                        const double pk = __longlong_as_double(
-                            (long long)ld_dev(reinterpret_cast<const uint64_t *>(&A.tPs[tk])));
+                        // (a batch's tile maps take far less than 4 GiB)
+                        const double pk = __longlong_as_double((long long)ld_dev32(
+                            reinterpret_cast<const uint64_t *>(A.tPs), (uint32_t)tk));
 #pragma unroll
                         for (int c = 0; c < CPT; ++c) {
-                            const double xk = __longlong_as_double((long long)ld_dev(
-                                reinterpret_cast<const uint64_t *>(&A.tXs[(int64_t)tk * w + j0 + c])));
+                            const double xk = __longlong_as_double((long long)ld_dev32(
+                                reinterpret_cast<const uint64_t *>(A.tXs), (uint32_t)(tk * w + j0 + c)));
                             carry[c] = (double)(float)fma(pk, carry[c], xk);
                         }
                     }
@@ -961,13 +995,9 @@ __global__ void __launch_bounds__(kBlock)
     }
 
     if (kWta) {  // the row's threads are consecutive: combine their candidates in LDS
-#pragma unroll
-        for (int i = 0; i < kRPG; ++i) {
-            sWb[tid * kRPG + i] = wb[i];
-            sWj[tid * kRPG + i] = wj[i];
-        }
+        const bool lead = active && jl == 0;
         __syncthreads();
-        if (active && jl == 0) {
+        if (lead) {
 #pragma unroll
             for (int i = 0; i < kRPG; ++i) {
                 if (rr[i] < 0) continue;
@@ -980,7 +1010,7 @@ __global__ void __launch_bounds__(kBlock)
                         bj = sWj[(tid + o) * kRPG + i];
                     }
                 }
-                A.disp[fv[i]] = (flh[i] & 0xFFFF) + bj;
+                A.disp[sWv[tid * kRPG + i]] = (int)((lh2[i >> 1] >> (16 * (i & 1))) & 0xFF) + bj;
             }
         }
     }
@@ -1048,7 +1078,7 @@ template <bool UP, int CPT, int RPG, bool FUSE>
 static void launch_pass(const PassArgs &A, int64_t tiles, hipStream_t st) {
     timer_before(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
     if (FUSE || A.width <= kSentMaxWidth)
-        k_pass_s<UP, CPT, RPG, FUSE><<<(unsigned)tiles, kBlock, 0, st>>>(A);
+        k_pass_s<UP, CPT, RPG, FUSE><<<(unsigned)tiles, kNarrowThreads, 0, st>>>(A);
     else
         k_pass<UP, CPT, RPG><<<(unsigned)tiles, kBlock, 0, st>>>(A);
     timer_after(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
