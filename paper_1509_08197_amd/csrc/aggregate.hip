@@ -259,11 +259,11 @@ __device__ __forceinline__ T ld_dev32(const T *base, uint32_t idx) {
                                               (uint64_t)(idx * (uint32_t)sizeof(T))));
 }
 
-constexpr int64_t kSpinLimit = int64_t(1) << 20;
+constexpr int kSpinLimit = 1 << 20;
 
 __device__ __forceinline__ int wait_nonzero(const int32_t *p, int32_t *err, int code) {
     int f = ld_dev(p);
-    int64_t it = 0;
+    int it = 0;
     while (f == 0) {
         __builtin_amdgcn_s_sleep(1);
         f = ld_dev(p);
@@ -351,41 +351,48 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
     const int j0 = jl * CPT;
     const bool active = g < A.groups;
 
-    // stage 1: loads that do not depend on other tiles of this launch
+    // stage 1: loads that do not depend on other tiles of this launch.  Row
+    // maps x -> av * x + bv; the constant terms are sums of non-negative terms
+    // held in FP32 (one relative rounding of at most 2^-24 per term added),
+    // the maps are composed in FP64.
     double av[kRPG];
-    double bv[kRPG][CPT];
-    int rr[kRPG], x0[kRPG], x1[kRPG];
+    float bv[kRPG][CPT];
+    // row i of this thread's group (-1 past the phase), recomputed where used
+    auto row_of = [&](int i) {
+        const int li = g * kRPG + i;
+        const int r = UP ? r1 - 1 - (tl * rows + li) : r0 + tl * rows + li;
+        return active && (UP ? r >= r0 : r < r1) ? r : -1;
+    };
+    int x0[kRPG], x1[kRPG];
 #pragma unroll
     for (int i = 0; i < kRPG; ++i) {
-        int li = g * kRPG + i;
-        int r = UP ? r1 - 1 - (tl * rows + li) : r0 + tl * rows + li;
-        bool in = active && (UP ? r >= r0 : r < r1);
-        rr[i] = in ? r : -1;
+        const int r = row_of(i);
+        const bool in = r >= 0;
         av[i] = 1.0;
         x0[i] = x1[i] = -1;
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) bv[i][c] = 0.0;
+        for (int c = 0; c < CPT; ++c) bv[i][c] = 0.f;
         if (!in) continue;
         float v[CPT];
         load_cols<CPT>(A.src + (int64_t)r * w + j0, v);
         if (UP) {
             // heavy flag and coefficient of the next row, loaded together
             const int rn = r + 1 < r1 ? r + 1 : r;
-            const bool hn = A.heavy[rn];
-            const double sn = A.s[rn];
+            const bool hn = at32(A.heavy, rn);
+            const double sn = at32(A.s, rn);
             av[i] = (r + 1 < r1 && hn) ? sn : 0.0;
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) bv[i][c] = (double)v[c];
-            x0[i] = A.lc[r];
-            x1[i] = A.lc[A.n + r];
+            for (int c = 0; c < CPT; ++c) bv[i][c] = v[c];
+            x0[i] = at32(A.lc, r);
+            x1[i] = at32(A.lc, A.n + r);
         } else {
             // heavy flag, coefficients and parent row, loaded together
-            const bool hv = A.heavy[r];
-            const double sr = A.s[r], o = A.om[r];
-            const int pr = A.prow[r];
+            const bool hv = at32(A.heavy, r);
+            const double sr = at32(A.s, r), o = at32(A.om, r);
+            const int pr = at32(A.prow, r);
             av[i] = hv ? sr : 0.0;
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) bv[i][c] = o * (double)v[c];
+            for (int c = 0; c < CPT; ++c) bv[i][c] = (float)(o * (double)v[c]);
             x0[i] = hv ? -1 : pr;
         }
     }
@@ -410,22 +417,22 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
         float v[CPT];
         if (UP) {
             if (x0[i] >= 0) {
-                double sc = A.s[x0[i]];
+                double sc = at32(A.s, x0[i]);
                 load_cols_dev<CPT>(A.dst + (int64_t)x0[i] * w + j0, v);
 #pragma unroll
-                for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
+                for (int c = 0; c < CPT; ++c) bv[i][c] = (float)((double)bv[i][c] + sc * (double)v[c]);
             }
             if (x1[i] >= 0) {
-                double sc = A.s[x1[i]];
+                double sc = at32(A.s, x1[i]);
                 load_cols_dev<CPT>(A.dst + (int64_t)x1[i] * w + j0, v);
 #pragma unroll
-                for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
+                for (int c = 0; c < CPT; ++c) bv[i][c] = (float)((double)bv[i][c] + sc * (double)v[c]);
             }
         } else if (x0[i] >= 0) {
-            double sc = A.s[rr[i]];
+            double sc = at32(A.s, row_of(i));
             load_cols_dev<CPT>(A.dst + (int64_t)x0[i] * w + j0, v);
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) bv[i][c] += sc * (double)v[c];
+            for (int c = 0; c < CPT; ++c) bv[i][c] = (float)((double)bv[i][c] + sc * (double)v[c]);
         }
     }
 
@@ -448,6 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
 #pragma unroll
     for (int c = 0; c < CPT; ++c) Xt[c] = 0.0;
     if (active) {
+#pragma unroll 1
         for (int q2 = 0; q2 < A.groups; ++q2) {
             int o = q2 * A.lpr + jl;
             double pq = sP[o];
@@ -514,6 +522,7 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
         double cv[CPT];
 #pragma unroll
         for (int c = 0; c < CPT; ++c) cv[c] = carry[c];
+#pragma unroll 1
         for (int q2 = 0; q2 < g; ++q2) {
             int o = q2 * A.lpr + jl;
             double pq = sP[o];
@@ -524,7 +533,8 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
         for (int i = 0; i < kRPG; ++i) {
 #pragma unroll
             for (int c = 0; c < CPT; ++c) cv[c] = av[i] * cv[c] + bv[i][c];
-            if (rr[i] >= 0) store_cols_dev<CPT>(A.dst + (int64_t)rr[i] * w + j0, cv);
+            const int r = row_of(i);
+            if (r >= 0) store_cols_dev<CPT>(A.dst + (int64_t)r * w + j0, cv);
         }
         if (!incl_now && g == A.groups - 1) {  // value after the tile: its map applied to the carry
 #pragma unroll
@@ -552,7 +562,7 @@ __global__ void __launch_bounds__(kBlock) k_pass(PassArgs A) {
 // CPT labels of a row, once written (device-coherent loads, bounded poll).
 template <int CPT>
 __device__ __forceinline__ bool poll_cols(const float *p, float *v, int32_t *err, bool wait) {
-    for (int64_t it = 0;; ++it) {
+    for (int it = 0;; ++it) {
         bool ok = true;
         if (CPT == 1) {
             uint32_t u = ld_dev(reinterpret_cast<const uint32_t *>(p));
@@ -562,7 +572,8 @@ __device__ __forceinline__ bool poll_cols(const float *p, float *v, int32_t *err
 #pragma unroll
             for (int h = 0; h < CPT / 2; ++h) {
                 uint64_t u = ld_dev(reinterpret_cast<const uint64_t *>(p) + h);
-                ok = ok && u != kSent64;
+                // unwritten: both halves hold the pattern (compared as 32-bit words)
+                ok = ok && ((uint32_t)u != kSentF || (uint32_t)(u >> 32) != kSentF);
                 v[2 * h] = __uint_as_float((uint32_t)u);
                 v[2 * h + 1] = __uint_as_float((uint32_t)(u >> 32));
             }
@@ -933,7 +944,7 @@ __global__ void __launch_bounds__(kNarrowThreads)
         {
             const int lim = t0[q];
             int pred = T - 1;
-            for (int64_t it = 0;; ++it) {
+            for (int it = 0;; ++it) {
                 // row processed just before tile pred + 1 of this phase
                 const int nxt = pred + 1 - lim;
                 const int lr = UP ? r1 - nxt * rows : r0 + nxt * rows - 1;
