@@ -124,6 +124,34 @@ def test_pyramid_exact(H, orc, Hh, Ww):
         np.testing.assert_array_equal(got, ref[l].astype(np.float32))
 
 
+def test_pyramid_unaligned_input_and_batch_rows(H, orc):
+    """Layer 0 read four pixels per thread from 32-bit words, and pixel by
+    pixel where the buffer is not 4-byte aligned or the words would leave it:
+    both give the oracle's layer (gx included) on a batch whose pairs start at
+    every offset modulo 4 and rows of odd widths."""
+    shapes = [(5, 7, 15), (3, 13, 15), (6, 1, 15), (4, 9, 15), (2, 3, 15)]
+    rng = np.random.default_rng(77)
+    imgs = [rng.integers(0, 256, (h, w, 3)).astype(np.uint8) for h, w, _ in shapes]
+    flat = np.concatenate([im.reshape(-1, 3) for im in imgs])
+    base = torch.zeros(flat.size + 8, dtype=torch.uint8, device="cuda")
+    for shift in (0, 1, 2, 3):
+        view = base[shift:shift + flat.size]
+        view.copy_(torch.from_numpy(flat.ravel()).cuda())
+        lv = H.pyramid(view.view(-1, 3), shapes, 2, 0)
+        got = lv[0].cpu().numpy()
+        off = 0
+        for im in imgs:
+            h, w = im.shape[:2]
+            g = got[off:off + h * w].reshape(h, w, 4)
+            off += h * w
+            np.testing.assert_array_equal(g[..., :3], im.astype(np.float32), err_msg=f"shift {shift}")
+            S = im.astype(np.int64).sum(axis=2)
+            right = np.concatenate([S[:, 1:], S[:, -1:]], axis=1)
+            left = np.concatenate([S[:, :1], S[:, :-1]], axis=1)
+            np.testing.assert_array_equal(g[..., 3], (right - left).astype(np.float32),
+                                          err_msg=f"shift {shift}")
+
+
 def test_pyramid_views_and_gradient(H, orc):
     """Both views in one call equal two single-view calls; the gx channel of
     every layer is S(x+1) - S(x-1) of the channel sums S (replicated border),
