@@ -1068,9 +1068,12 @@ __device__ __forceinline__ int turn(uint8_t aw, int d) {
 }
 
 constexpr uint32_t kTourEnd = 0xFFFFFFFFu;
-constexpr int kSlotsPerThread = 4 * kTilePx / kLocalThreads;
+// The tile-local tour ranking runs 512 threads per tile (eight slots each):
+// four tiles fit a compute unit at once instead of two.
+constexpr int kTourThreads = 512;
+constexpr int kTourSlots = 4 * kTilePx / kTourThreads;
 
-__global__ __launch_bounds__(kLocalThreads) void k_tour_local(
+__global__ __launch_bounds__(kTourThreads) void k_tour_local(
     LevelGeom g, const uint8_t *__restrict__ adj, uint64_t *__restrict__ lw,
     uint32_t *__restrict__ C, int32_t *__restrict__ ctr, int32_t *__restrict__ info) {
     __shared__ uint8_t sadj[kHalo * kHalo];
@@ -1079,7 +1082,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
     __shared__ int s_n, s_base;
     const TileInfo t = tile_info(g, blockIdx.x);
     const int tid = threadIdx.x;
-    for (int h = tid; h < kHalo * kHalo; h += kLocalThreads) {
+    for (int h = tid; h < kHalo * kHalo; h += kTourThreads) {
         int x = t.x0 + (h % kHalo) - 1, y = t.y0 + (h / kHalo) - 1;
         bool in = x >= 0 && x < t.W && y >= 0 && y < t.H;
         sadj[h] = in ? adj[t.base + (int64_t)y * t.W + x] : 0;
@@ -1091,10 +1094,10 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
     constexpr uint32_t kInvalid = ~0u;
     // Only the owning thread writes a slot, so each thread keeps its slots in
     // registers; a pointer-jumping round is one batch of independent loads.
-    uint32_t own[kSlotsPerThread];
+    uint32_t own[kTourSlots];
     uint32_t live = 0;
-    for (int k = 0; k < kSlotsPerThread; ++k) {
-        int ls = tid + k * kLocalThreads;
+    for (int k = 0; k < kTourSlots; ++k) {
+        int ls = tid + k * kTourThreads;
         int i = ls >> 2, d = ls & 3;
         int lx = i & (kTile - 1), ly = i >> 5;
         uint32_t w = kInvalid;
@@ -1122,12 +1125,12 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
     // A thread stops once its slots point at their run ends; every step
     // advances a slot by at least one hop, which bounds the loop.
     for (int step = 0; live && step <= 4 * kTilePx; ++step) {
-        uint32_t nxt[kSlotsPerThread];
-        for (int k = 0; k < kSlotsPerThread; ++k)
+        uint32_t nxt[kTourSlots];
+        for (int k = 0; k < kTourSlots; ++k)
             nxt[k] = ((live >> k) & 1) ? __hip_atomic_load(&P[own[k] >> 16], __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_WORKGROUP)
                                        : 0u;
-        for (int k = 0; k < kSlotsPerThread; ++k) {
+        for (int k = 0; k < kTourSlots; ++k) {
             if (!((live >> k) & 1)) continue;
             uint32_t nx = own[k] >> 16, nn = nxt[k] >> 16;
             if (nn == nx) {  // next is its run's end: done
@@ -1135,18 +1138,18 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
                 continue;
             }
             own[k] = (nn << 16) | ((own[k] & 0xFFFFu) + (nxt[k] & 0xFFFFu));
-            __hip_atomic_store(&P[tid + k * kLocalThreads], own[k], __ATOMIC_RELAXED,
+            __hip_atomic_store(&P[tid + k * kTourThreads], own[k], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
     if (live) info[HDP_INFO_ERROR] = 5;
     __syncthreads();
     // number the run ends (one LDS atomic per wavefront and slot group)
-    int wofs[kSlotsPerThread];
-    uint64_t wm[kSlotsPerThread];
+    int wofs[kTourSlots];
+    uint64_t wm[kTourSlots];
     const int lane = tid & 63;
-    for (int k = 0; k < kSlotsPerThread; ++k) {
-        int ls = tid + k * kLocalThreads;
+    for (int k = 0; k < kTourSlots; ++k) {
+        int ls = tid + k * kTourThreads;
         bool term = own[k] != kInvalid && (int)(own[k] >> 16) == ls;
         wm[k] = __ballot(term);
         wofs[k] = 0;
@@ -1156,8 +1159,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
     if (tid == 0) s_base = s_n ? atomicAdd(&ctr[CTR_RUNS], s_n) : 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
-    for (int k = 0; k < kSlotsPerThread; ++k) {
-        int ls = tid + k * kLocalThreads;
+    for (int k = 0; k < kTourSlots; ++k) {
+        int ls = tid + k * kTourThreads;
         int base = __shfl(wofs[k], 0, 64) + s_base;
         if (!((wm[k] >> lane) & 1)) continue;
         int idx = base + __popcll(wm[k] & lt);
@@ -1172,8 +1175,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_tour_local(
         C[idx] = end ? kTourEnd : (uint32_t)(4 * wg + d2);
     }
     __syncthreads();
-    for (int k = 0; k < kSlotsPerThread; ++k) {
-        int ls = tid + k * kLocalThreads;
+    for (int k = 0; k < kTourSlots; ++k) {
+        int ls = tid + k * kTourThreads;
         uint32_t a = own[k];
         if (a == kInvalid) continue;
         int64_t v = tile_pixel(t, ls >> 2);
@@ -1940,7 +1943,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     k_set_tree<<<gn, kBlock, 0, st>>>(t.comp0, t.croot, t.lmin, t.mnroot, t.intree, g, f.tree,
                                       t.adj, f.info);
     // 4: Euler tour ranks
-    k_tour_local<<<n_tiles, kLocalThreads, 0, st>>>(g, t.adj, t.lw, t.C, t.ctr, f.info);
+    k_tour_local<<<n_tiles, kTourThreads, 0, st>>>(g, t.adj, t.lw, t.C, t.ctr, f.info);
     k_tour_link<<<g_edges, kBlock, 0, st>>>(t.ctr, t.C, t.lw, t.pr);
     int rk_rounds = ceil_log2(max_list) + 1;
     if (rk_rounds > kRankGridRounds) rk_rounds = kRankGridRounds;
