@@ -316,7 +316,7 @@ HDP_API hdp_status hdp_wta(const hdp_forest *f, const hdp_shape *shapes, int32_t
  * One layer's matching after the forest is built: restricted cost (Section
  * 3.3, eq. E), tree aggregation (eq. W, eq. S, eq. C) and winner-takes-all,
  * with the same results as hdp_cost_volume + hdp_aggregate + hdp_wta.  For
- * rows of at most 32 labels the up pass computes each row's cost from the
+ * rows of at most 64 labels the up pass computes each row's cost from the
  * level images as it goes (no cost volume in memory) and the down pass writes
  * each row's winning label as its row is finished (no separate WTA read of the
  * aggregated volume); wider rows run the three steps one after another with

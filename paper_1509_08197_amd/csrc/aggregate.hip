@@ -34,7 +34,7 @@ constexpr int kSumBlocks = 512;  // blocks of the first summing launch of the ad
 
 // Narrow rows (at most kSentMaxWidth labels) use rows as signals: unwritten
 // values hold signalling-NaN patterns that no arithmetic produces.
-constexpr int kSentMaxWidth = 32;
+constexpr int kSentMaxWidth = 64;
 constexpr uint32_t kSentF = 0x7fa00001u;
 constexpr uint64_t kSent64 = 0x7fa000017fa00001ull;
 constexpr uint64_t kSentD = 0x7ff4000000000001ull;
@@ -92,7 +92,7 @@ static TileGeom make_geom(int width, int cpt, int rpg) {
 static TileGeom tile_geom(int width) {
     int cpt = g_sched_cpt[width], rpg = g_sched_rpg[width];
     if (!cpt || !schedule_valid(width, cpt, rpg)) {
-        cpt = (width >= 64 && width % 4 == 0) ? 4 : (width % 2 == 0 && width >= 8) ? 2 : 1;
+        cpt = (width >= 48 && width % 4 == 0) ? 4 : (width % 2 == 0 && width >= 8) ? 2 : 1;
         rpg = width <= kSentMaxWidth ? 4 : kRPGDefault;  // narrow rows: shorter tiles measured faster
     }
     return make_geom(width, cpt, rpg);
