@@ -316,11 +316,12 @@ HDP_API hdp_status hdp_wta(const hdp_forest *f, const hdp_shape *shapes, int32_t
  * One layer's matching after the forest is built: restricted cost (Section
  * 3.3, eq. E), tree aggregation (eq. W, eq. S, eq. C) and winner-takes-all,
  * with the same results as hdp_cost_volume + hdp_aggregate + hdp_wta.  For
- * rows of at most 64 labels the up pass computes each row's cost from the
- * level images as it goes (no cost volume in memory) and the down pass writes
- * each row's winning label as its row is finished (no separate WTA read of the
- * aggregated volume); wider rows run the three steps one after another with
- * the cost volume in the workspace.
+ * rows of at most 64 labels, or of up to 256 labels in multiples of four, the
+ * up pass computes each row's cost from the level images as it goes (no cost
+ * volume in memory) and the down pass writes each row's winning label as its
+ * row is finished (no separate WTA read of the aggregated volume); other rows
+ * run the three steps one after another with the cost volume in the
+ * workspace.
  *   left, right, shapes, n_pairs, f, width, p: as hdp_cost_volume (f required).
  *   sigma       > 0, as hdp_aggregate.
  *   agg         float[n][width], receives the aggregated volume (volume layout).

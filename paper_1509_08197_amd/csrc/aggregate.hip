@@ -32,9 +32,14 @@ namespace hdp {
 constexpr int kRPGDefault = 8;  // rows per thread group of a tile
 constexpr int kSumBlocks = 512;  // blocks of the first summing launch of the adjoint
 
-// Narrow rows (at most kSentMaxWidth labels) use rows as signals: unwritten
-// values hold signalling-NaN patterns that no arithmetic produces.
-constexpr int kSentMaxWidth = 64;
+// Narrow rows use rows as signals: unwritten values hold signalling-NaN
+// patterns that no arithmetic produces.  Rows of at most 64 labels, and rows
+// of up to kSentMaxWidth labels that split into four labels per thread, are
+// narrow; the others take the wide-row kernel with tile flags.
+constexpr int kSentMaxWidth = 256;
+__host__ __device__ inline bool narrow_rows(int width) {
+    return width <= 64 || (width <= kSentMaxWidth && width % 4 == 0);
+}
 constexpr uint32_t kSentF = 0x7fa00001u;
 constexpr uint64_t kSent64 = 0x7fa000017fa00001ull;
 constexpr uint64_t kSentD = 0x7ff4000000000001ull;
@@ -83,7 +88,7 @@ static TileGeom make_geom(int width, int cpt, int rpg) {
     t.cpt = cpt;
     t.rpg = rpg;
     t.lpr = (width + cpt - 1) / cpt;
-    t.groups = (width <= kSentMaxWidth ? kNarrowThreads : kBlock) / t.lpr;
+    t.groups = (narrow_rows(width) ? kNarrowThreads : kBlock) / t.lpr;
     if (t.groups < 1) t.groups = 1;
     t.rows = t.groups * rpg;
     return t;
@@ -93,7 +98,7 @@ static TileGeom tile_geom(int width) {
     int cpt = g_sched_cpt[width], rpg = g_sched_rpg[width];
     if (!cpt || !schedule_valid(width, cpt, rpg)) {
         cpt = (width >= 48 && width % 4 == 0) ? 4 : (width % 2 == 0 && width >= 8) ? 2 : 1;
-        rpg = width <= kSentMaxWidth ? 4 : kRPGDefault;  // narrow rows: shorter tiles measured faster
+        rpg = narrow_rows(width) ? 4 : kRPGDefault;  // narrow rows: shorter tiles measured faster
     }
     return make_geom(width, cpt, rpg);
 }
@@ -188,7 +193,7 @@ __global__ void k_prologue(int64_t n, const float *__restrict__ rw,
     }
     // the tile maps, marked unpublished
     for (int64_t i = t; i < map_words; i += stride) maps[i] = kSentD;
-    if (t < tiles && width > kSentMaxWidth) {  // tile flags: wide rows only (narrow rows signal by rows)
+    if (t < tiles && !narrow_rows(width)) {  // tile flags: wide rows only (narrow rows signal by rows)
 #pragma unroll
         for (int k = 0; k < 2 * kPassSets; ++k) flags[k * tiles + t] = 0;
     }
@@ -600,8 +605,11 @@ __global__ void __launch_bounds__(kNarrowThreads)
     constexpr int kSeg = kNarrowSegs;
     __shared__ double sP[kNarrowThreads];
     __shared__ double sX[kNarrowThreads * CPT];
-    __shared__ double sSegP[kSeg * kSentMaxWidth];  // segments x (threads per row <= width)
-    __shared__ double sSegX[kSeg * kSentMaxWidth * CPT];
+    // segment maps: kSeg x (threads per row) products, then their columns
+    // (sized by the launch for the row width)
+    extern __shared__ double s_seg[];
+    double *const sSegP = s_seg;
+    double *const sSegX = s_seg + kSeg * A.lpr;
     __shared__ int s_ticket;
     __shared__ double s_first;
     __shared__ int32_t s_plan[P_WORDS];
@@ -1065,7 +1073,7 @@ static AggWs carve_agg_ws(void *ws, int64_t n, int width, size_t *bytes) {
     a.tP = reinterpret_cast<double *>(take(sizeof(double) * nt));
     a.tX = reinterpret_cast<double *>(take(sizeof(double) * nt * width));
     a.tI = reinterpret_cast<double *>(take(sizeof(double) * nt * width));
-    const bool narrow = width <= kSentMaxWidth;  // one block: the prologue marks it in one sweep
+    const bool narrow = narrow_rows(width);  // one block: the prologue marks it in one sweep
     a.tPs = reinterpret_cast<double *>(
         take(narrow ? sizeof(double) * kPassSets * nt * (width + 1) : 8));
     a.tXs = a.tPs + (narrow ? kPassSets * nt : 0);
@@ -1088,10 +1096,12 @@ size_t aggregate_workspace_bytes(int64_t n, int width) {
 template <bool UP, int CPT, int RPG, bool FUSE>
 static void launch_pass(const PassArgs &A, int64_t tiles, hipStream_t st) {
     timer_before(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
-    if (FUSE || A.width <= kSentMaxWidth)
-        k_pass_s<UP, CPT, RPG, FUSE><<<(unsigned)tiles, kNarrowThreads, 0, st>>>(A);
-    else
+    if (FUSE || narrow_rows(A.width)) {
+        const size_t seg = sizeof(double) * kNarrowSegs * A.lpr * (1 + CPT);
+        k_pass_s<UP, CPT, RPG, FUSE><<<(unsigned)tiles, kNarrowThreads, seg, st>>>(A);
+    } else {
         k_pass<UP, CPT, RPG><<<(unsigned)tiles, kBlock, 0, st>>>(A);
+    }
     timer_after(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
 }
 
@@ -1143,7 +1153,7 @@ static PassArgs pass_args(const hdp_forest &f, int width, const AggWs &w, const 
 // fill0 / fill1: outputs of the up passes of this call (narrow rows only).
 static void prologue(const hdp_forest &f, int width, float sigma, const AggWs &w, hipStream_t st,
                      float *fill0 = nullptr, float *fill1 = nullptr) {
-    const bool narrow = width <= kSentMaxWidth;
+    const bool narrow = narrow_rows(width);
     int64_t m = f.n > w.tiles ? f.n : w.tiles;
     // narrow rows: the product words of the tile maps, marked unpublished
     int64_t map_words = narrow ? (int64_t)kPassSets * w.tiles : 0;
@@ -1190,7 +1200,7 @@ void launch_match(const float *left, const float *right, const LevelGeom &g, con
                   void *ws, hipStream_t st) {
     size_t bytes;
     AggWs w = carve_agg_ws(ws, f.n, width, &bytes);
-    if (width > kSentMaxWidth) {
+    if (!narrow_rows(width)) {
         launch_cost_volume(left, right, g, f.node, f.lo, f.hi, width, p, w.ug, st);
         prologue(f, width, sigma, w, st, w.up);
         two_pass(f, width, w.ug, w.up, agg, w, 0, st);

@@ -424,7 +424,8 @@ def match_layer(left: torch.Tensor, right: torch.Tensor, shapes, forest: Forest,
                 sigma: float = 0.1, params: Optional[CostParams] = None, agg=None, disp=None,
                 ws=None):
     """Cost, aggregation and WTA of one layer in one call (fused passes for
-    rows of at most 64 labels).  Returns (agg, disp)."""
+    rows of at most 64 labels, or up to 256 in multiples of four).  Returns
+    (agg, disp)."""
     n, width = forest.n, forest.width
     if agg is None:
         agg = torch.empty((n, width), dtype=torch.float32, device=left.device)
