@@ -49,8 +49,11 @@ constexpr int kBvGridRounds = 4;
 // Further rounds on the compacted list of live edges (cheap: a pass over the
 // few edges still live), before the one-workgroup tail takes what is left.
 constexpr int kBvListRounds = 8;
-constexpr int kRankGridRounds = 12;  // pointer-jumping steps on the full grid ...
-constexpr int kRankJumps = 12;        // ... taken kRankJumps per launch
+// Pointer-jumping steps on the full grid are taken kRankJumps per launch, as
+// many launches as the longest possible list needs: entries stay open until
+// their pointer reaches the list end, so a short-cut to the one-workgroup tail
+// would leave it nearly the whole list of a large tree.
+constexpr int kRankJumps = 12;
 // Sizes of the one-workgroup LDS tails: spanning forest (edges, components,
 // hash slots; endpoints and component state are 16-bit indices) and tour
 // ranking (list entries).
@@ -1946,7 +1949,6 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     k_tour_local<<<n_tiles, kTourThreads, 0, st>>>(g, t.adj, t.lw, t.C, t.ctr, f.info);
     k_tour_link<<<g_edges, kBlock, 0, st>>>(t.ctr, t.C, t.lw, t.pr);
     int rk_rounds = ceil_log2(max_list) + 1;
-    if (rk_rounds > kRankGridRounds) rk_rounds = kRankGridRounds;
     if (rk_rounds < 1) rk_rounds = 1;
     // Without intervals every pair's forest is one spanning tree (one tour), so
     // the contracted list is bounded by runs_bound: a list that fits the LDS
