@@ -1013,24 +1013,32 @@ __global__ void __launch_bounds__(kNarrowThreads)
         }
     }
 
-    if (kWta) {  // the row's threads are consecutive: combine their candidates in LDS
-        const bool lead = active && jl == 0;
+    if (kWta) {
+        // The row's threads are consecutive and later threads hold later
+        // columns: a tree over them in LDS (at step s, thread jl with jl a
+        // multiple of 2s takes the candidate of thread jl + s only if it is
+        // strictly smaller) leaves each row's first least value with its lead
+        // thread.  Every row of the tile is combined at each step.
         __syncthreads();
-        if (lead) {
+        for (int s2 = 1; s2 < A.lpr; s2 <<= 1) {
+            if (active && (jl & (2 * s2 - 1)) == 0 && jl + s2 < A.lpr) {
 #pragma unroll
-            for (int i = 0; i < kRPG; ++i) {
-                if (rr[i] < 0) continue;
-                float best = sWb[tid * kRPG + i];
-                int bj = sWj[tid * kRPG + i];
-                for (int o = 1; o < A.lpr; ++o) {  // later threads hold later columns
-                    const float x = sWb[(tid + o) * kRPG + i];
-                    if (x < best) {
-                        best = x;
-                        bj = sWj[(tid + o) * kRPG + i];
+                for (int i = 0; i < kRPG; ++i) {
+                    const float x = sWb[(tid + s2) * kRPG + i];
+                    if (x < sWb[tid * kRPG + i]) {
+                        sWb[tid * kRPG + i] = x;
+                        sWj[tid * kRPG + i] = sWj[(tid + s2) * kRPG + i];
                     }
                 }
-                A.disp[sWv[tid * kRPG + i]] = (int)((lh2[i >> 1] >> (16 * (i & 1))) & 0xFF) + bj;
             }
+            __syncthreads();
+        }
+        if (active && jl == 0) {
+#pragma unroll
+            for (int i = 0; i < kRPG; ++i)
+                if (rr[i] >= 0)
+                    A.disp[sWv[tid * kRPG + i]] =
+                        (int)((lh2[i >> 1] >> (16 * (i & 1))) & 0xFF) + sWj[tid * kRPG + i];
         }
     }
     mark_fill();
