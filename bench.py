@@ -12,8 +12,9 @@ over the layers of one step and over their pixels, of the width of the
 pixel's tree interval (the (pixel, label) entries the method aggregates),
 divided by the step time, in Mpix*disp/s.  Beside it: the
 full-range-equivalent rate N*(dmax+1)/step time, the per-layer search ratio,
-the full-range MST path on the same pair, the roofline of the dominant
-kernel (the fused up pass), the batched workloads with their own rooflines,
+the full-range MST path on the same pair (with the roofline of its passes),
+the roofline of the dominant kernel (the fused up pass), the batched
+workloads with their own rooflines,
 the adjoint ratios, and the FP64 CPU oracle timed on the host together with
 the label agreement between the two.
 """
@@ -290,6 +291,9 @@ def main():
         if args.mode == "both":
             out["full_range"]["speedup_hdp_over_full"] = t_full / (out["ms_per_step"] * 1e-3)
         del fstep
+        # the full-range step runs the same fused passes on one 256-label layer
+        out["full_range"]["roofline"] = rooflines(
+            pass_roofline(hdp, lambda: [full_eager()], reps=3), "full_1344x1104")
 
     if extras:
         use(hdp_sched)
