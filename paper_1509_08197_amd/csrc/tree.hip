@@ -49,10 +49,11 @@ constexpr int kBvGridRounds = 4;
 // Further rounds on the compacted list of live edges (cheap: a pass over the
 // few edges still live), before the one-workgroup tail takes what is left.
 constexpr int kBvListRounds = 8;
-// Pointer-jumping steps on the full grid are taken kRankJumps per launch, as
-// many launches as the longest possible list needs: entries stay open until
-// their pointer reaches the list end, so a short-cut to the one-workgroup tail
-// would leave it nearly the whole list of a large tree.
+// Pointer-jumping steps on the full grid are taken kRankJumps per launch.  A
+// layer without intervals (one spanning tree per pair) gets as many launches
+// as its longest possible list needs: entries stay open until their pointer
+// reaches the list end, so stopping early would leave the one-workgroup tail
+// nearly the whole list of a large tree.
 constexpr int kRankJumps = 12;
 // Sizes of the one-workgroup LDS tails: spanning forest (edges, components,
 // hash slots; endpoints and component state are 16-bit indices) and tour
@@ -1950,6 +1951,10 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     k_tour_link<<<g_edges, kBlock, 0, st>>>(t.ctr, t.C, t.lw, t.pr);
     int rk_rounds = ceil_log2(max_list) + 1;
     if (rk_rounds < 1) rk_rounds = 1;
+    // With intervals the trees are small (the longest contracted list of the
+    // 1344x1104 pair's level 0 has under a thousand entries): one launch, and
+    // the tail finishes any longer list.
+    if (plo && rk_rounds > kRankJumps) rk_rounds = kRankJumps;
     // Without intervals every pair's forest is one spanning tree (one tour), so
     // the contracted list is bounded by runs_bound: a list that fits the LDS
     // tail needs no full-grid rounds at all.
