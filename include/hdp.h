@@ -346,7 +346,7 @@ HDP_API hdp_status hdp_match_layer(const float *left, const float *right, const 
  * GPU, held from the library's load until the process ends; the call
  * allocates nothing.  Returns HDP_EWORKSPACE, enqueueing nothing, when
  * hdp_aggregate_workspace_bytes(f->n, width) exceeds that size (e.g. a layer
- * of up to about 2.6 million pixels at 10 labels per row fits).  Every call on
+ * of up to about 2.4 million pixels at 10 labels per row fits).  Every call on
  * one GPU uses the same array and the kernels reinitialise what must start
  * clean, so calls in sequence are independent; calls that overlap on one GPU
  * (different streams or host threads) race on the array and must not be

@@ -127,7 +127,9 @@ __global__ void k_prologue(int64_t n, const float *__restrict__ rw,
                            const int32_t *__restrict__ phase_ptr, const int32_t *__restrict__ info,
                            int rows, int32_t *__restrict__ plan, uint32_t *__restrict__ fill0,
                            uint32_t *__restrict__ fill1, int width,
-                           uint64_t *__restrict__ maps, int64_t map_words) {
+                           uint64_t *__restrict__ maps, int64_t map_words,
+                           const float4 *__restrict__ imR, uint2 *__restrict__ imRp,
+                           float rscale) {
     __shared__ int32_t sph[HDP_MAX_PHASES + 1];
     // One thread per row (the grid covers the rows and the tiles).
     const int64_t t = gtid();
@@ -142,6 +144,9 @@ __global__ void k_prologue(int64_t n, const float *__restrict__ rw,
     const int pr = prow[rc];
     const uint8_t hv = heavy[rc];
     const float wf = rw[rc];
+    // fused matching: the right image packed for the up pass (one pixel per
+    // row: a layer has as many pixels as rows)
+    const float4 rpx = imRp ? imR[rc] : make_float4(0.f, 0.f, 0.f, 0.f);
     K = K < 1 ? 1 : (K > HDP_MAX_PHASES ? HDP_MAX_PHASES : K);
     if (tx <= HDP_MAX_PHASES) sph[tx] = ph;
     __syncthreads();
@@ -181,6 +186,7 @@ __global__ void k_prologue(int64_t n, const float *__restrict__ rw,
             }
         }
     }
+    if (imRp && t < n) imRp[t] = pack_right(rpx, rscale);
     if (t < n) {
         if (pr < 0) {
             s[t] = 0.0;
@@ -238,6 +244,8 @@ struct PassArgs {
     // fused matching (narrow rows): the up pass computes its cost rows from the
     // level images, the down pass writes each row's winning label
     const float4 *imL, *imR;
+    const uint2 *imRp;  // right image packed by the prologue (8 bytes a pixel)
+    float rinv;         // 4^-l: scale of the packed pixels
     CostParams cp;
     const int32_t *node, *rx, *rlh;
     int32_t *disp;
@@ -592,16 +600,20 @@ __device__ __forceinline__ bool poll_cols(const float *p, float *v, int32_t *err
     }
 }
 
+// Variants of the narrow-row pass: plain, fused matching, fused matching whose
+// up pass reads the right image packed (8 bytes a pixel).
+constexpr int kFuse = 1, kFusePacked = 2;
+
 // FUSE: the up pass computes the cost of its rows (eq. E) instead of reading a
 // cost volume, and the down pass reduces every row to its winning label.
 // The down pass of the default narrow schedule (two labels per thread, four
 // rows per group) is held to 80 VGPRs, as the up pass is by itself: six waves
 // per SIMD, three tiles per compute unit.
-template <bool UP, int CPT, int kRPG, bool FUSE>
+template <bool UP, int CPT, int kRPG, int FUSE>
 __global__ void __launch_bounds__(kNarrowThreads)
     __attribute__((amdgpu_waves_per_eu((!UP && CPT == 2 && kRPG == 4) ? 6 : 1)))
     k_pass_s(PassArgs A) {
-    constexpr bool kWta = FUSE && !UP;
+    constexpr bool kWta = FUSE != 0 && !UP;
     constexpr int kSeg = kNarrowSegs;
     __shared__ double sP[kNarrowThreads];
     __shared__ double sX[kNarrowThreads * CPT];
@@ -697,25 +709,55 @@ __global__ void __launch_bounds__(kNarrowThreads)
             constexpr int kR2 = kRPG / kH;
 #pragma unroll
             for (int h = 0; h < kH; ++h) {
-                float4 Lp[kR2], Rp[kR2][CPT];
+                // right pixels packed (wide rows) or as FP32; each side
+                // issues all its loads of the half before it uses any
+                float4 Lp[kR2];
 #pragma unroll
-                for (int ii = 0; ii < kR2; ++ii) {
-                    const int i = h * kR2 + ii;
-                    Lp[ii] = at32(A.imL, fv[i]);
-                    const int a = flh[i] & 0xFFFF;
+                for (int ii = 0; ii < kR2; ++ii) Lp[ii] = at32(A.imL, fv[h * kR2 + ii]);
+                if (FUSE == kFusePacked) {
+                    uint2 Rq[kR2][CPT];
 #pragma unroll
-                    for (int c = 0; c < CPT; ++c)
-                        Rp[ii][c] = at32(A.imR, match_src(fv[i], fx[i], a + j0 + c));
-                }
+                    for (int ii = 0; ii < kR2; ++ii) {
+                        const int i = h * kR2 + ii;
+                        const int a = flh[i] & 0xFFFF;
 #pragma unroll
-                for (int ii = 0; ii < kR2; ++ii) {
-                    const int i = h * kR2 + ii;
-                    const int a = flh[i] & 0xFFFF, b = flh[i] >> 16;
+                        for (int c = 0; c < CPT; ++c)
+                            Rq[ii][c] = at32(A.imRp, match_src(fv[i], fx[i], a + j0 + c));
+                    }
 #pragma unroll
-                    for (int c = 0; c < CPT; ++c) {
-                        const int label = a + j0 + c;
-                        v[i][c] = label <= b ? match_cost_px(Lp[ii], Rp[ii][c], fx[i] - label < 0, A.cp)
-                                             : 0.f;
+                    for (int ii = 0; ii < kR2; ++ii) {
+                        const int i = h * kR2 + ii;
+                        const int a = flh[i] & 0xFFFF, b = flh[i] >> 16;
+#pragma unroll
+                        for (int c = 0; c < CPT; ++c) {
+                            const int label = a + j0 + c;
+                            const float4 Rp = packed_fallback(Rq[ii][c])
+                                                  ? at32(A.imR, match_src(fv[i], fx[i], label))
+                                                  : unpack_right(Rq[ii][c], A.rinv);
+                            v[i][c] = label <= b ? match_cost_px(Lp[ii], Rp, fx[i] - label < 0, A.cp)
+                                                 : 0.f;
+                        }
+                    }
+                } else {
+                    float4 Rp[kR2][CPT];
+#pragma unroll
+                    for (int ii = 0; ii < kR2; ++ii) {
+                        const int i = h * kR2 + ii;
+                        const int a = flh[i] & 0xFFFF;
+#pragma unroll
+                        for (int c = 0; c < CPT; ++c)
+                            Rp[ii][c] = at32(A.imR, match_src(fv[i], fx[i], a + j0 + c));
+                    }
+#pragma unroll
+                    for (int ii = 0; ii < kR2; ++ii) {
+                        const int i = h * kR2 + ii;
+                        const int a = flh[i] & 0xFFFF, b = flh[i] >> 16;
+#pragma unroll
+                        for (int c = 0; c < CPT; ++c) {
+                            const int label = a + j0 + c;
+                            v[i][c] = label <= b ? match_cost_px(Lp[ii], Rp[ii][c], fx[i] - label < 0, A.cp)
+                                                 : 0.f;
+                        }
                     }
                 }
             }
@@ -1050,6 +1092,7 @@ struct AggWs {
     int32_t *plan, *ticket, *flags;  // flags: kPassSets x (flag[tiles], flagw[tiles])
     double *s, *om, *tP, *tX, *tI;
     double *tPs, *tXs;  // narrow rows: kPassSets x tile maps (tiles, tiles x width)
+    uint2 *imRp;    // right image packed for the fused up pass
     float *up;      // U when the caller does not keep it
     float *ug;      // U of the gradient (backward)
     double *red;    // per-block partial sums (backward)
@@ -1085,6 +1128,7 @@ static AggWs carve_agg_ws(void *ws, int64_t n, int width, size_t *bytes) {
     a.tPs = reinterpret_cast<double *>(
         take(narrow ? sizeof(double) * kPassSets * nt * (width + 1) : 8));
     a.tXs = a.tPs + (narrow ? kPassSets * nt : 0);
+    a.imRp = reinterpret_cast<uint2 *>(take(sizeof(uint2) * n));
     a.up = reinterpret_cast<float *>(take(sizeof(float) * n * width));
     a.ug = reinterpret_cast<float *>(take(sizeof(float) * n * width));
     // partial sums of the adjoint: one per block of the edge gradients (at most
@@ -1100,8 +1144,9 @@ size_t aggregate_workspace_bytes(int64_t n, int width) {
     return b;
 }
 
-// FUSE (narrow rows only): the fused matching variant of the narrow-row pass.
-template <bool UP, int CPT, int RPG, bool FUSE>
+// FUSE (narrow rows only): the fused matching variant of the narrow-row pass
+// (kFusePacked: its up pass reads the packed right image).
+template <bool UP, int CPT, int RPG, int FUSE>
 static void launch_pass(const PassArgs &A, int64_t tiles, hipStream_t st) {
     timer_before(UP ? HDP_TIMER_UP_PASS : HDP_TIMER_DOWN_PASS, st);
     if (FUSE || narrow_rows(A.width)) {
@@ -1114,7 +1159,7 @@ static void launch_pass(const PassArgs &A, int64_t tiles, hipStream_t st) {
 }
 
 // One pass with flag set `set` (cleared by the prologue of this call).
-template <bool UP, bool FUSE = false>
+template <bool UP, int FUSE = 0>
 static void run_pass(PassArgs A, const AggWs &w, const TileGeom &tg, int set, hipStream_t st,
                      float *fill = nullptr) {
     int64_t tiles = A.n / tg.rows + HDP_MAX_PHASES + 2;  // >= the plan's tile count
@@ -1160,7 +1205,8 @@ static PassArgs pass_args(const hdp_forest &f, int width, const AggWs &w, const 
 // Coefficients and the plan of both passes (device side, no host sync).
 // fill0 / fill1: outputs of the up passes of this call (narrow rows only).
 static void prologue(const hdp_forest &f, int width, float sigma, const AggWs &w, hipStream_t st,
-                     float *fill0 = nullptr, float *fill1 = nullptr) {
+                     float *fill0 = nullptr, float *fill1 = nullptr,
+                     const float *right = nullptr, float rscale = 1.f) {
     const bool narrow = narrow_rows(width);
     int64_t m = f.n > w.tiles ? f.n : w.tiles;
     // narrow rows: the product words of the tile maps, marked unpublished
@@ -1170,7 +1216,8 @@ static void prologue(const hdp_forest &f, int width, float sigma, const AggWs &w
         f.phase_ptr, f.info, tile_geom(width).rows, w.plan,
         narrow ? reinterpret_cast<uint32_t *>(fill0) : nullptr,
         narrow ? reinterpret_cast<uint32_t *>(fill1) : nullptr, width,
-        reinterpret_cast<uint64_t *>(w.tPs), map_words);
+        reinterpret_cast<uint64_t *>(w.tPs), map_words, reinterpret_cast<const float4 *>(right),
+        right ? w.imRp : nullptr, rscale);
 }
 
 // Two passes of `src` over the forest: U -> up, A -> out (flag sets up_set, up_set + 1).
@@ -1195,6 +1242,9 @@ void launch_aggregate(const hdp_forest &f, int width, const float *cost, float s
     two_pass(f, width, cost, U, agg, w, 0, st);
 }
 
+// Rows of at least this many labels take the right image packed in the fused up pass.
+constexpr int kPackRightMinWidth = 64;
+
 // Layers of at least this many rows take the winner-takes-all inside the down
 // pass; smaller ones (whose passes are bound by the phase dependency chain)
 // run it as its own kernel.
@@ -1215,11 +1265,19 @@ void launch_match(const float *left, const float *right, const LevelGeom &g, con
         launch_wta(g, f.node, f.lo, f.hi, width, agg, disp, st);
         return;
     }
-    prologue(f, width, sigma, w, st, w.up);
+    // Rows of many labels read the right image packed (8 bytes a pixel), so
+    // that the right-pixel reads, most of the up pass's traffic there, take
+    // half the bytes; the narrow HDP windows (where the pass is bound by its
+    // dependency chain, not by these reads) read it as it is (measured).
+    const bool pack = width >= kPackRightMinWidth;
+    const float rscale = ldexpf(1.0f, 2 * g.level);
+    prologue(f, width, sigma, w, st, w.up, nullptr, pack ? right : nullptr, rscale);
     TileGeom tg = tile_geom(width);
     PassArgs A = pass_args(f, width, w, tg);
     A.imL = reinterpret_cast<const float4 *>(left);
     A.imR = reinterpret_cast<const float4 *>(right);
+    A.imRp = pack ? w.imRp : nullptr;
+    A.rinv = 1.0f / rscale;
     A.cp = CostParams{p.a_c, p.tau_c, p.a_g, p.tau_g};
     A.node = f.node;
     A.rx = f.rx;
@@ -1227,13 +1285,16 @@ void launch_match(const float *left, const float *right, const LevelGeom &g, con
     A.disp = disp;
     A.src = nullptr;
     A.dst = w.up;
-    run_pass<true, true>(A, w, tg, 0, st, agg);
+    if (pack)
+        run_pass<true, kFusePacked>(A, w, tg, 0, st, agg);
+    else
+        run_pass<true, kFuse>(A, w, tg, 0, st, agg);
     A.src = w.up;
     A.dst = agg;
     if (f.n >= kFusedWtaMinRows) {
-        run_pass<false, true>(A, w, tg, 1, st);
+        run_pass<false, kFuse>(A, w, tg, 1, st);
     } else {
-        run_pass<false, false>(A, w, tg, 1, st);
+        run_pass<false, 0>(A, w, tg, 1, st);
         launch_wta(g, f.node, f.lo, f.hi, width, agg, disp, st);
     }
 }

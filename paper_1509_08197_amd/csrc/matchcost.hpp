@@ -36,6 +36,32 @@ __device__ __forceinline__ float match_cost_px(float4 L, float4 R, bool outside,
     return outside ? sat : m;
 }
 
+// Right-image pixel in 8 bytes for the fused up pass: R, G and B times 4^l
+// in 14 bits each and the gradient numerator times 4^l in 22 bits (two's
+// complement), l the pyramid layer.  Exact for the pixels of a pyramid of 2x2
+// means at layers 0..3 (multiples of 4^-l, channels at most 255, |gx| at most
+// 765): unpacking gives back the same floats.  Any other pixel is stored as
+// all ones (a red field of 16383, which no packed pixel has) and is read as
+// its FP32 value instead.
+__device__ __forceinline__ uint2 pack_right(float4 p, float scale) {
+    const float r = p.x * scale, g = p.y * scale, b = p.z * scale, x = p.w * scale;
+    const bool ok = r >= 0.f && r < 16383.f && r == rintf(r) && g >= 0.f && g < 16383.f &&
+                    g == rintf(g) && b >= 0.f && b < 16383.f && b == rintf(b) &&
+                    fabsf(x) < 2097152.f && x == rintf(x);
+    if (!ok) return make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+    const uint32_t R = (uint32_t)r, G = (uint32_t)g, B = (uint32_t)b;
+    const uint32_t X = (uint32_t)(int32_t)x & 0x3FFFFFu;
+    return make_uint2(R | (G << 14) | (B << 28), (B >> 4) | (X << 10));
+}
+__device__ __forceinline__ bool packed_fallback(uint2 q) { return (q.x & 0x3FFFu) == 0x3FFFu; }
+// inv = 4^-l
+__device__ __forceinline__ float4 unpack_right(uint2 q, float inv) {
+    const float R = (float)(q.x & 0x3FFFu), G = (float)((q.x >> 14) & 0x3FFFu);
+    const float B = (float)((q.x >> 28) | ((q.y & 0x3FFu) << 4));
+    const float X = (float)((int32_t)q.y >> 10);
+    return make_float4(R * inv, G * inv, B * inv, X * inv);
+}
+
 __device__ __forceinline__ float match_cost(float4 L, const float4 *__restrict__ right, int v,
                                             int x, int label, const CostParams &c) {
     return match_cost_px(L, right[match_src(v, x, label)], x - label < 0, c);

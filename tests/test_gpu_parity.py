@@ -361,10 +361,11 @@ def _three_steps(H, lp, rp, shapes, f, sigma=0.1):
 
 @pytest.mark.parametrize("case", ["hdp_layer0", "hdp_layer1_batch", "top_width32", "wide_width64"])
 def test_fused_match_layer_equals_three_steps(H, case):
-    """hdp_match_layer (fused cost in the up pass, fused WTA in the down pass for
-    rows of <= 32 labels; the three steps apart for wider rows) gives bit for bit
-    the aggregated volume and the labels of hdp_cost_volume + hdp_aggregate +
-    hdp_wta on the same forest."""
+    """hdp_match_layer (fused cost in the up pass for rows of at most 64 labels
+    or up to 256 in fours, the right image packed from 64 labels on; the
+    winner-takes-all fused into the down pass on layers of >= 2^18 rows) gives
+    bit for bit the aggregated volume and the labels of hdp_cost_volume +
+    hdp_aggregate + hdp_wta on the same forest."""
     S, L, w = 2, 3, 4
     if case == "hdp_layer1_batch":
         shapes = [(96, 128, 63), (37, 53, 31), (1, 40, 15)]
@@ -389,6 +390,37 @@ def test_fused_match_layer_equals_three_steps(H, case):
         lp, rp, lv = lps[level], rps[level], lvs[level]
         mw = min(S + 2 * w, max(d for _, _, d in lv) + 1)
     f = H.build_tree(lp, lv, level, lo, hi, max_width=mw)
+    agg3, disp3 = _three_steps(H, lp, rp, lv, f)
+    aggf, dispf = H.match_layer(lp, rp, lv, f)
+    torch.cuda.synchronize()
+    assert f.read_info()[7] == 0
+    assert torch.equal(aggf, agg3), f"{case}: aggregated volumes differ"
+    assert torch.equal(dispf, disp3), f"{case}: labels differ"
+
+
+@pytest.mark.parametrize("case", ["w256_layer0", "w64_layer2", "w256_fallback"])
+def test_packed_right_image_equals_three_steps(H, case):
+    """Rows of >= 64 labels: the fused up pass reads the right image packed in
+    8 bytes a pixel (exact for pyramid pixels: multiples of 4^-l).  Its results
+    equal those of the three separate steps bit for bit: at layer 0 (256
+    labels), at layer 2 (64 labels, pixels in sixteenths), and with pixels that
+    do not pack (fractional or out-of-range values: read as FP32 instead)."""
+    if case == "w64_layer2":
+        shapes, level = [(120, 200, 255)], 2
+    else:
+        shapes, level = [(40, 300, 255)], 0
+    pairs = [scenes.small_scene(520 + i, h, wd, d) for i, (h, wd, d) in enumerate(shapes)]
+    Lr, Rr = rgb_dev(*[p.left for p in pairs]), rgb_dev(*[p.right for p in pairs])
+    lps, rps = H.pyramid_views(Lr, Rr, shapes, 2, level)
+    lv = H.level_shapes(shapes, 2, level)[level]
+    lp, rp = lps[level], rps[level]
+    if case == "w256_fallback":
+        rp = rp.clone()
+        px = rp.view(-1, 4)
+        px[::5, 0] += 0.25       # not a whole number: no exact packing
+        px[7, 1] = 20000.0       # beyond the packed field
+    f = H.build_tree(lp, lv, level)
+    assert f.width >= 64
     agg3, disp3 = _three_steps(H, lp, rp, lv, f)
     aggf, dispf = H.match_layer(lp, rp, lv, f)
     torch.cuda.synchronize()
