@@ -33,9 +33,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 NEAR_TIE_REL = 1e-5
 
-# Layers of at least this many rows take the winner-takes-all inside the down
-# pass (kFusedWtaMinRows in aggregate.hip); smaller ones run it as its own kernel.
-FUSED_WTA_MIN_ROWS = 1 << 18
 
 
 def parse():
@@ -82,11 +79,12 @@ def pass_bytes_alg(forest, up: bool) -> float:
     """Algorithmic HBM bytes of one fused matching pass: 4 B per entry for the up
     pass (the cost is computed in place: write U), 8 B per entry for the down pass
     (read U, write the aggregated cost), 12 B of tree metadata per node and pass,
-    and with the fused winner-takes-all 4 B per pixel for its label."""
+    and in the down pass 4 B per pixel for its label (the winner-takes-all is
+    fused into it)."""
     e, n = layer_entries(forest), forest.n
     if up:
         return 4.0 * e + 12.0 * n
-    return 8.0 * e + 12.0 * n + (4.0 * n if n >= FUSED_WTA_MIN_ROWS else 0.0)
+    return 8.0 * e + 12.0 * n + 4.0 * n
 
 
 def pass_bytes_kernel(forest, up: bool) -> float:
@@ -96,7 +94,7 @@ def pass_bytes_kernel(forest, up: bool) -> float:
     links; the up pass writes U (4 B per entry), reads the row's pixel, column and
     interval (12 B) and its left and right image pixels (32 B) and 8 B per light
     child; the down pass reads U and writes the aggregated volume (8 B per entry)
-    and, with the fused winner-takes-all, the row's pixel and interval (8 B) and
+    and, for the fused winner-takes-all, the row's pixel and interval (8 B) and
     its label (4 B)."""
     import torch
     n, w = forest.n, forest.width
@@ -106,8 +104,7 @@ def pass_bytes_kernel(forest, up: bool) -> float:
     common = 4.0 * heads * w + 21.0 * n
     if up:
         return common + 4.0 * n * w + (12.0 + 32.0) * n + 8.0 * heads
-    wta = 12.0 * n if n >= FUSED_WTA_MIN_ROWS else 0.0
-    return common + 8.0 * n * w + wta
+    return common + 8.0 * n * w + 12.0 * n
 
 
 def measured_traffic(workload: str):
@@ -159,7 +156,7 @@ def rooflines(rl, traffic_key):
     up = roofline_entry(rl["up_pass"], "k_pass_s<up, fused cost> (leaf-to-root pass, cost "
                                        "computed in the pass)", tr and tr.get("up_pass"))
     down = roofline_entry(rl["down_pass"], "k_pass_s<down> (root-to-leaf pass, winner-takes-all "
-                                           "fused on layers of >= 2^18 rows)",
+                                           "fused)",
                           tr and tr.get("down_pass"))
     both = {k: rl["up_pass"][k] + rl["down_pass"][k] for k in ("secs", "launches", "alg", "ker")}
     b = roofline_entry(both, "k_pass_s, both passes", None)

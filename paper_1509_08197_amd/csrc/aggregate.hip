@@ -1245,11 +1245,6 @@ void launch_aggregate(const hdp_forest &f, int width, const float *cost, float s
 // Rows of at least this many labels take the right image packed in the fused up pass.
 constexpr int kPackRightMinWidth = 64;
 
-// Layers of at least this many rows take the winner-takes-all inside the down
-// pass; smaller ones (whose passes are bound by the phase dependency chain)
-// run it as its own kernel.
-constexpr int64_t kFusedWtaMinRows = int64_t(1) << 18;
-
 // Cost, aggregation and winner-takes-all of one layer.  Narrow rows: the two
 // fused passes (no cost volume in memory, no separate WTA launch).  Wide rows:
 // the cost volume is built in the workspace and the three steps run apart.
@@ -1291,12 +1286,7 @@ void launch_match(const float *left, const float *right, const LevelGeom &g, con
         run_pass<true, kFuse>(A, w, tg, 0, st, agg);
     A.src = w.up;
     A.dst = agg;
-    if (f.n >= kFusedWtaMinRows) {
-        run_pass<false, kFuse>(A, w, tg, 1, st);
-    } else {
-        run_pass<false, 0>(A, w, tg, 1, st);
-        launch_wta(g, f.node, f.lo, f.hi, width, agg, disp, st);
-    }
+    run_pass<false, kFuse>(A, w, tg, 1, st);
 }
 
 // --- adjoint ----------------------------------------------------------------------------

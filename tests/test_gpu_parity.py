@@ -363,9 +363,9 @@ def _three_steps(H, lp, rp, shapes, f, sigma=0.1):
 def test_fused_match_layer_equals_three_steps(H, case):
     """hdp_match_layer (fused cost in the up pass for rows of at most 64 labels
     or up to 256 in fours, the right image packed from 64 labels on; the
-    winner-takes-all fused into the down pass on layers of >= 2^18 rows) gives
-    bit for bit the aggregated volume and the labels of hdp_cost_volume +
-    hdp_aggregate + hdp_wta on the same forest."""
+    winner-takes-all fused into the down pass) gives bit for bit the aggregated
+    volume and the labels of hdp_cost_volume + hdp_aggregate + hdp_wta on the
+    same forest."""
     S, L, w = 2, 3, 4
     if case == "hdp_layer1_batch":
         shapes = [(96, 128, 63), (37, 53, 31), (1, 40, 15)]
