@@ -31,6 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# Rows of at least this many labels read the right image packed in 8 bytes a
+# pixel in the fused up pass (kPackRightMinWidth in aggregate.hip).
+PACK_RIGHT_MIN_WIDTH = 64
 NEAR_TIE_REL = 1e-5
 
 
@@ -92,10 +95,10 @@ def pass_bytes_kernel(forest, up: bool) -> float:
     of `width` labels, padding included): both passes read the previous-phase row
     of every chain head (4 B per label) and 21 B per row of coefficients and
     links; the up pass writes U (4 B per entry), reads the row's pixel, column and
-    interval (12 B) and its left and right image pixels (32 B) and 8 B per light
-    child; the down pass reads U and writes the aggregated volume (8 B per entry)
-    and, for the fused winner-takes-all, the row's pixel and interval (8 B) and
-    its label (4 B)."""
+    interval (12 B), its left and right image pixels (32 B; 24 B where the
+    right image is read packed) and 8 B per light child; the down pass reads U
+    and writes the aggregated volume (8 B per entry) and, for the fused
+    winner-takes-all, the row's pixel and interval (8 B) and its label (4 B)."""
     import torch
     n, w = forest.n, forest.width
     heavy = forest.array("heavy")
@@ -103,7 +106,8 @@ def pass_bytes_kernel(forest, up: bool) -> float:
     heads = int(torch.count_nonzero((heavy == 0) & (prow >= 0)).item())
     common = 4.0 * heads * w + 21.0 * n
     if up:
-        return common + 4.0 * n * w + (12.0 + 32.0) * n + 8.0 * heads
+        img = 16.0 + (8.0 if w >= PACK_RIGHT_MIN_WIDTH else 16.0)
+        return common + 4.0 * n * w + (12.0 + img) * n + 8.0 * heads
     return common + 8.0 * n * w + 12.0 * n
 
 
