@@ -398,15 +398,18 @@ def test_fused_match_layer_equals_three_steps(H, case):
     assert torch.equal(dispf, disp3), f"{case}: labels differ"
 
 
-@pytest.mark.parametrize("case", ["w256_layer0", "w64_layer2", "w256_fallback"])
+@pytest.mark.parametrize("case", ["w256_layer0", "w64_layer2", "w256_fallback", "w128_batch2"])
 def test_packed_right_image_equals_three_steps(H, case):
     """Rows of >= 64 labels: the fused up pass reads the right image packed in
     8 bytes a pixel (exact for pyramid pixels: multiples of 4^-l).  Its results
     equal those of the three separate steps bit for bit: at layer 0 (256
-    labels), at layer 2 (64 labels, pixels in sixteenths), and with pixels that
-    do not pack (fractional or out-of-range values: read as FP32 instead)."""
+    labels), at layer 2 (64 labels, pixels in sixteenths), on a batch of two
+    pairs, and with pixels that do not pack (fractional or out-of-range values:
+    read as FP32 instead)."""
     if case == "w64_layer2":
         shapes, level = [(120, 200, 255)], 2
+    elif case == "w128_batch2":
+        shapes, level = [(30, 150, 127), (25, 90, 127)], 0
     else:
         shapes, level = [(40, 300, 255)], 0
     pairs = [scenes.small_scene(520 + i, h, wd, d) for i, (h, wd, d) in enumerate(shapes)]

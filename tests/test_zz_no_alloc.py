@@ -2,7 +2,7 @@
 hdp_match_layer on the same forests: aggregated volumes and labels must be
 identical bit for bit, over consecutive calls that reuse the library's fixed
 scratch array with different sizes (largest first), on the fused narrow-row
-path and on the wide-row path."""
+path (right image as FP32 and packed) and on the wide-row path."""
 
 import numpy as np
 import pytest
@@ -77,11 +77,16 @@ def test_noalloc_matches_workspace_call(H):
     for level in (0, 2):
         left, right, shapes, f = _layer(H, small, level, L=2, window=2)
         _compare(H, left, right, shapes, f, f"160x120 layer {level}")
-    # 3) wide rows (labels 0..63: cost volume in the scratch array), smaller again
+    # 3) 64-label rows (fused passes, right image packed in the scratch array)
     wide = scenes.small_scene(77, 48, 64, 63)
     left, right, shapes, f = _full(H, wide)
     assert f.width == 64
     _compare(H, left, right, shapes, f, "64x48 full range, 64 labels")
+    # 4) wide rows (66 labels, not in fours: cost volume in the scratch array)
+    wide = scenes.small_scene(78, 40, 60, 65)
+    left, right, shapes, f = _full(H, wide)
+    assert f.width == 66
+    _compare(H, left, right, shapes, f, "60x40 full range, 66 labels")
 
 
 def test_noalloc_rejects_oversize(H):
