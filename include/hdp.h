@@ -318,10 +318,12 @@ HDP_API hdp_status hdp_wta(const hdp_forest *f, const hdp_shape *shapes, int32_t
  * with the same results as hdp_cost_volume + hdp_aggregate + hdp_wta.  For
  * rows of at most 64 labels, or of up to 256 labels in multiples of four, the
  * up pass computes each row's cost from the level images as it goes (no cost
- * volume in memory) and the down pass writes each row's winning label as its
- * row is finished (no separate WTA read of the aggregated volume); other rows
- * run the three steps one after another with the cost volume in the
- * workspace.
+ * volume in memory; from 64 labels on it reads the right image packed in
+ * 8 bytes a pixel, which the workspace holds, exactly where the pixels are
+ * those of a pyramid of 2x2 means and as FP32 elsewhere) and the down pass
+ * writes each row's winning label as its row is finished (no separate WTA
+ * read of the aggregated volume); other rows run the three steps one after
+ * another with the cost volume in the workspace.
  *   left, right, shapes, n_pairs, f, width, p: as hdp_cost_volume (f required).
  *   sigma       > 0, as hdp_aggregate.
  *   agg         float[n][width], receives the aggregated volume (volume layout).
