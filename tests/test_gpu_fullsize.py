@@ -143,6 +143,32 @@ def test_fused_hdp_step_1344x1104(H):
         assert torch.equal(res[l].disp, disp3), f"layer {l}: step labels differ"
 
 
+def test_fused_full_range_1344x1104(H):
+    """The full-range step as benchmarked (fused matching on 256-label rows:
+    the cost in the up pass with the right image packed, the winner-takes-all
+    in the down pass, the built-in schedule) against the three separate steps
+    (validated against the oracle above) on the same forest: aggregated volume
+    and labels bit for bit, and the step's own labels."""
+    pair = scenes.workload(2)
+    Hh, Ww = pair.shape
+    shapes = [(Hh, Ww, 255)]
+    Lr, Rr = rgb_dev(pair.left), rgb_dev(pair.right)
+    step = H.full_range(Lr, Rr, shapes)
+    lp, rp = H.pyramid_views(Lr, Rr, shapes, 2, 0)
+    f = step.forest
+    assert f.width == 256
+    cost = H.cost_volume(lp[0], rp[0], shapes, f)
+    agg3 = H.aggregate(f, cost, 0.1)
+    del cost
+    disp3 = H.wta(agg3, shapes, f)
+    aggf, dispf = H.match_layer(lp[0], rp[0], shapes, f)
+    torch.cuda.synchronize()
+    assert f.read_info()[7] == 0
+    assert torch.equal(aggf, agg3), "aggregated volumes differ"
+    assert torch.equal(dispf, disp3), "labels differ"
+    assert torch.equal(step.disp, disp3), "step labels differ"
+
+
 def tree_roots(parent):
     n = len(parent)
     root = np.where(parent >= 0, parent, np.arange(n))
