@@ -148,7 +148,7 @@ def test_fused_full_range_1344x1104(H):
     the cost in the up pass with the right image packed, the winner-takes-all
     in the down pass, the built-in schedule) against the three separate steps
     (validated against the oracle above) on the same forest: aggregated volume
-    and labels bit for bit, and the step's own labels."""
+    and labels bit for bit, the step's own labels, and a second run."""
     pair = scenes.workload(2)
     Hh, Ww = pair.shape
     shapes = [(Hh, Ww, 255)]
@@ -167,6 +167,11 @@ def test_fused_full_range_1344x1104(H):
     assert torch.equal(aggf, agg3), "aggregated volumes differ"
     assert torch.equal(dispf, disp3), "labels differ"
     assert torch.equal(step.disp, disp3), "step labels differ"
+    # a second run (the tiles of the long chains find other finished
+    # predecessors from run to run) gives the same bits
+    agg2, disp2 = H.match_layer(lp[0], rp[0], shapes, f)
+    torch.cuda.synchronize()
+    assert torch.equal(agg2, aggf) and torch.equal(disp2, dispf), "runs differ"
 
 
 def tree_roots(parent):
