@@ -180,17 +180,25 @@ HDP_API size_t hdp_build_tree_workspace_bytes(int64_t n);
  *             exact integers at 4^level scale).
  *   pix_lo/hi pixel intervals PixelIntv (int32 [n]) or NULL for [0, dmax].
  *   max_width upper bound the caller guarantees on hi - lo + 1 (ignored when
- *             pix_lo is NULL).  The forest is built exactly (the same forest
- *             as the sequential Kruskal process with both DT rules) when
- *             beta_num / beta_den > (max_width - 1) / max_width: then DT-Rule 2
- *             admits only equal intervals and the forest is the minimum
- *             spanning forest of the equal-interval edges.  Otherwise the call
- *             returns HDP_EREGIME.  The bound is checked on the device: pixels
+ *             pix_lo is NULL).  When beta_num / beta_den > (max_width - 1) /
+ *             max_width, DT-Rule 2 admits only equal intervals and the forest
+ *             (the same as the sequential Kruskal process with both DT rules)
+ *             is built as the minimum spanning forest of the equal-interval
+ *             edges, in parallel.  The bound is checked on the device: pixels
  *             whose interval is empty, leaves [0, dmax] or is wider than
  *             max_width are counted in info[HDP_INFO_BAD_INTERVAL], their
  *             interval is clamped to [0, dmax] and max_width labels (so no later
  *             call reads or writes outside its buffers), the forest is then not
  *             the exact one, and hdp_forest_read_info returns HDP_EREGIME.
+ *             Otherwise (outside that regime, e.g. beta = 3/5) the result
+ *             depends on the order of the edges, and the sequential process
+ *             itself runs on the device: the edges are sorted by (weight, id)
+ *             and one workgroup takes them in that order (slow: one edge after
+ *             another; meant for the small images that setting is used on).
+ *             A tree's interval can then grow past max_width: `width` must
+ *             hold the widest tree interval (dmax + 1 always does); a tree
+ *             wider than `width`, or an empty or out-of-range pixel interval,
+ *             is counted in info[HDP_INFO_BAD_INTERVAL].
  *   width     row width of the volume layout to prepare: at least the widest
  *             tree interval (dmax + 1 for the full range).
  */
@@ -212,9 +220,11 @@ HDP_API hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int
  *              is ascending (rank, edge id); uniform random ranks give a
  *              uniformly random order of the edges up to ties.
  * Every other argument, the exact regime, the outputs and the errors are
- * those of hdp_build_tree; the edge weights stored in the forest (and used by
- * the aggregation) are still the colour weights of eq. weight.  Returns
- * HDP_EINVAL if edge_rank is NULL.
+ * those of hdp_build_tree, except that outside the exact regime this call
+ * returns HDP_EREGIME (the sequential process is built for the colour order
+ * only); the edge weights stored in the forest (and used by the aggregation)
+ * are still the colour weights of eq. weight.  Returns HDP_EINVAL if
+ * edge_rank is NULL.
  */
 HDP_API hdp_status hdp_build_random_tree(const float *img, const hdp_shape *shapes,
                                          int32_t n_pairs, int32_t level,

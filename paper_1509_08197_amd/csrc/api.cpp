@@ -219,19 +219,23 @@ static hdp_status build_tree(const float *img, const hdp_shape *shapes, int32_t 
     int64_t n = total_pixels(g);
     if (!forest_ok(f, n)) return HDP_EINVAL;
     if (width < 1 || width > HDP_MAX_LABELS) return HDP_EINVAL;
+    bool literal = false;
     if (pix_lo) {
         if (max_width < 1 || width < max_width) return HDP_EINVAL;
-        // exact regime: two distinct intervals of width <= w have IoU <= (w-1)/w < beta
         if (beta_num < 1 || beta_den < 1 || beta_num > beta_den) return HDP_EINVAL;
-        if ((int64_t)beta_num * max_width <= (int64_t)beta_den * (max_width - 1))
-            return HDP_EREGIME;
+        // exact regime: two distinct intervals of width <= w have IoU <= (w-1)/w < beta;
+        // outside it the sequential process itself runs (random ranks: not built there)
+        if ((int64_t)beta_num * max_width <= (int64_t)beta_den * (max_width - 1)) {
+            if (edge_rank) return HDP_EREGIME;
+            literal = true;
+        }
     } else if (width < max_dmax(g) + 1) {
         return HDP_EINVAL;
     }
     if (ws_bytes < hdp::tree_workspace_bytes(n)) return HDP_EWORKSPACE;
     (void)hipGetLastError();
     hdp::launch_build_tree(img, g, pix_lo, pix_hi, max_width, width, edge_rank, *f, ws,
-                           (hipStream_t)stream);
+                           (hipStream_t)stream, literal, beta_num, beta_den);
     return last_hip();
 }
 

@@ -39,9 +39,12 @@ void launch_cost_volume(const float *left, const float *right, const LevelGeom &
 void launch_wta(const LevelGeom &g, const int32_t *node, const int32_t *lo, const int32_t *hi,
                 int width, const float *agg, int32_t *disp, hipStream_t st);
 size_t tree_workspace_bytes(int64_t n);
+// literal: outside the exact regime, the sequential Kruskal process with both
+// DT rules (beta_num / beta_den) instead of the minimum spanning forest.
 void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
                        const int32_t *phi, int max_width, int width, const int32_t *rank,
-                       const hdp_forest &f, void *ws, hipStream_t st);
+                       const hdp_forest &f, void *ws, hipStream_t st, bool literal = false,
+                       int beta_num = 1, int beta_den = 1);
 void launch_level_order(const hdp_forest &f, void *ws, hipStream_t st);
 void launch_set_weights(const hdp_forest &f, const float *w, hipStream_t st);
 size_t aggregate_workspace_bytes(int64_t n, int width);

@@ -1044,6 +1044,152 @@ __global__ void k_set_tree(const int32_t *__restrict__ comp0, const int32_t *__r
     adj[v] = a;
 }
 
+// --- literal disparity forest (outside the exact regime) -------------------------
+// Section 3.2 as written: Kruskal over the grid edges in ascending (weight,
+// edge id) with Rule 2 (union-find), DT-Rule 1 (eq. cri1: skip an edge whose
+// two pixel intervals are disjoint) and DT-Rule 2 (eq. DTrules on the current
+// tree intervals, tested exactly as beta_den * |n| >= beta_num * |u|; a merge
+// gives the tree the union of the two intervals).  Outside the regime of
+// equal intervals the result depends on the order, so the edges are sorted by
+// (key, id) and one workgroup takes them in that order.
+
+// Keys and the DT-Rule 1 filter of the two edges a pixel owns (sentinel:
+// absent or filtered, sorted last), and the start state of the union-find.
+__global__ void k_seq_edges(const float4 *__restrict__ img, LevelGeom g,
+                            const int32_t *__restrict__ plo, const int32_t *__restrict__ phi,
+                            uint32_t sentinel, uint32_t *__restrict__ ekey,
+                            int32_t *__restrict__ uf, int32_t *__restrict__ usz,
+                            int32_t *__restrict__ tlo, int32_t *__restrict__ thi,
+                            int32_t *__restrict__ croot, int32_t *__restrict__ lmin,
+                            uint8_t *__restrict__ intree, int32_t *__restrict__ info) {
+    const int64_t v = gtid();
+    if (v >= g.off[g.n_pairs]) return;
+    const PixelPos p = pixel_pos(g, (int)v);
+    const bool hr = p.x + 1 < p.W, hd = p.y + 1 < p.H;
+    const int64_t vr = hr ? v + 1 : v, vd = hd ? v + p.W : v;
+    const float4 a = img[v], ar = img[vr], ad = img[vd];
+    const int dm = g.dmax[p.pair];
+    int l = plo[v], h = phi[v];
+    const int lr = plo[vr], hrr = phi[vr], ld = plo[vd], hdd = phi[vd];
+    const float scale = ldexpf(1.0f, 2 * g.level);
+    // an interval that is empty or leaves [0, dmax] makes the forest invalid
+    if (l < 0 || h > dm || l > h) atomicAdd(&info[HDP_INFO_BAD_INTERVAL], 1);
+    const bool kr = hr && (l > lr ? l : lr) <= (h < hrr ? h : hrr);
+    const bool kd = hd && (l > ld ? l : ld) <= (h < hdd ? h : hdd);
+    ekey[2 * v] = kr ? edge_key(a, ar, scale) : sentinel;
+    ekey[2 * v + 1] = kd ? edge_key(a, ad, scale) : sentinel;
+    l = l < 0 ? 0 : (l > dm ? dm : l);
+    h = h < l ? l : (h > dm ? dm : h);
+    uf[v] = (int32_t)v;
+    usz[v] = 1;
+    tlo[v] = l;
+    thi[v] = h;
+    croot[v] = -1;
+    lmin[v] = 0x7fffffff;
+    intree[2 * v] = 0;
+    intree[2 * v + 1] = 0;
+}
+
+// digit of an edge's key for the stable counting sort of the edge ids
+struct EdgeDigit {
+    const uint32_t *key;
+    int shift;
+    __device__ int operator()(int64_t, int32_t e) const { return (key[e] >> shift) & 255; }
+};
+
+__device__ __forceinline__ int32_t uf_find_halving(int32_t *uf, int32_t v) {
+    while (uf[v] != v) {
+        const int32_t gp = uf[uf[v]];
+        uf[v] = gp;
+        v = gp;
+    }
+    return v;
+}
+
+constexpr int kSeqThreads = 256;
+constexpr int kSeqChunk = 2048;  // edges staged in LDS per step
+
+// The sequential process: the workgroup stages the next kSeqChunk edges of
+// the sorted list (ids and far ends) in LDS, then one thread takes them in
+// order.  Every edge is decided exactly as in the definition above.
+__global__ __launch_bounds__(kSeqThreads) void k_seq_kruskal(
+    const int32_t *__restrict__ sorted, const uint32_t *__restrict__ ekey, int64_t m,
+    uint32_t sentinel, LevelGeom g, int beta_num, int beta_den, int32_t *__restrict__ uf,
+    int32_t *__restrict__ usz, int32_t *__restrict__ tlo, int32_t *__restrict__ thi,
+    uint8_t *__restrict__ intree) {
+    __shared__ int32_t se[kSeqChunk], sq[kSeqChunk];
+    __shared__ int s_stop;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_stop = 0;
+    for (int64_t base = 0; base < m; base += kSeqChunk) {
+        __syncthreads();
+        if (s_stop) break;
+        for (int j = tid; j < kSeqChunk; j += kSeqThreads) {
+            const int64_t i = base + j;
+            int32_t e = -1, q = 0;
+            if (i < m) {
+                e = sorted[i];
+                if (ekey[e] == sentinel) {
+                    e = -1;  // absent or filtered: every later edge is too
+                } else {
+                    const int32_t pv = e >> 1;
+                    q = (e & 1) ? pv + g.W[pair_of(g, pv)] : pv + 1;
+                }
+            }
+            se[j] = e;
+            sq[j] = q;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int j = 0; j < kSeqChunk; ++j) {
+                const int32_t e = se[j];
+                if (e < 0) {
+                    s_stop = 1;
+                    break;
+                }
+                int32_t rp = uf_find_halving(uf, e >> 1), rq = uf_find_halving(uf, sq[j]);
+                if (rp == rq) continue;  // Rule 2
+                // DT-Rule 2 on the current tree intervals
+                const int32_t lp = tlo[rp], hp = thi[rp], lq = tlo[rq], hq = thi[rq];
+                const int32_t ilo = lp > lq ? lp : lq, ihi = hp < hq ? hp : hq;
+                const int64_t inter = ihi >= ilo ? (int64_t)(ihi - ilo + 1) : 0;
+                const int64_t uni = (int64_t)(hp - lp + 1) + (hq - lq + 1) - inter;
+                if ((int64_t)beta_den * inter < (int64_t)beta_num * uni) continue;
+                // merge (union by size); the tree takes the union of the intervals
+                if (usz[rp] < usz[rq]) {
+                    const int32_t t = rp;
+                    rp = rq;
+                    rq = t;
+                }
+                uf[rq] = rp;
+                usz[rp] += usz[rq];
+                tlo[rp] = lp < lq ? lp : lq;
+                thi[rp] = hp > hq ? hp : hq;
+                intree[e] = 1;
+            }
+        }
+    }
+}
+
+// Per pixel: its tree (union-find root), the tree's smallest pixel and the
+// tree's interval; trees wider than the row width are counted as bad.
+__global__ void k_seq_roots(const int32_t *__restrict__ uf, const int32_t *__restrict__ tlo,
+                            const int32_t *__restrict__ thi, int64_t n, int width,
+                            int32_t *__restrict__ comp0, int32_t *__restrict__ lmin,
+                            int32_t *__restrict__ plo2, int32_t *__restrict__ phi2,
+                            int32_t *__restrict__ info) {
+    const int64_t v = gtid();
+    if (v >= n) return;
+    int32_t r = (int32_t)v;
+    while (uf[r] != r) r = uf[r];
+    comp0[v] = r;
+    atomicMin(&lmin[r], (int32_t)v);
+    const int32_t l = tlo[r], h = thi[r];
+    plo2[v] = l;
+    phi2[v] = h;
+    if (h - l + 1 > width) atomicAdd(&info[HDP_INFO_BAD_INTERVAL], 1);
+}
+
 // --- 4. Euler tour ranking ---------------------------------------------------------
 // Slot 4v+d = directed tree edge from v in direction d (0 right, 1 down, 2 left,
 // 3 up); its successor turns to the next tree edge of the far pixel, and the
@@ -1802,6 +1948,7 @@ struct TreeWs {
     uint2 *nrec;
     uint8_t *intree, *adj;
     int32_t *partial32, *hist, *sortA, *sortB;
+    int32_t *hist2, *part2;  // counting sort of the 2n edge ids (literal forest)
 };
 
 static TreeWs carve_tree_ws(void *ws, int64_t n, size_t *bytes) {
@@ -1841,6 +1988,9 @@ static TreeWs carve_tree_ws(void *ws, int64_t n, size_t *bytes) {
     t.hist = b.take<int32_t>(256 * ntiles);
     t.sortA = b.take<int32_t>(n);
     t.sortB = b.take<int32_t>(n);
+    const int64_t etiles = scan_tiles(2 * n) + 1;
+    t.hist2 = b.take<int32_t>(256 * etiles);
+    t.part2 = b.take<int32_t>(scan_scratch(256 * etiles));
     *bytes = b.off + 256;
     return t;
 }
@@ -1870,7 +2020,8 @@ static void counting_sort(const int32_t *src, int32_t *dst, int32_t *pos_of, int
 
 void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
                        const int32_t *phi, int max_width, int width, const int32_t *rank,
-                       const hdp_forest &f, void *ws, hipStream_t st) {
+                       const hdp_forest &f, void *ws, hipStream_t st, bool literal, int beta_num,
+                       int beta_den) {
     int64_t n = g.off[g.n_pairs];
     size_t bytes;
     TreeWs t = carve_tree_ws(ws, n, &bytes);
@@ -1900,50 +2051,84 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     unsigned g_edges = grid_for(2 * n) < (unsigned)kGridCap ? grid_for(2 * n) : kGridCap;
     unsigned g_roots = grid_for(border_px) < (unsigned)kGridCap ? grid_for(border_px) : kGridCap;
 
-    // 1-2: spanning forest (tile-local phase, full-grid rounds, one-workgroup tail)
+    // intervals and bound the layout kernels see: the pixel intervals (in the
+    // regime every tree keeps its pixels' interval), or the trees' intervals
+    const int32_t *plo_f = plo, *phi_f = phi;
+    int mw_f = max_width;
     k_tree_init<<<1, FLAG_WORDS, 0, st>>>(t.flags, t.ctr, f.info);
-    k_local_msf<<<n_tiles, kLocalThreads, 0, st>>>(im, g, plo, phi, max_width, rank, t.comp0, t.cw,
-                                                   t.best0, t.best1, t.lmin, t.croot, t.mnroot,
-                                                   t.intree, t.E, t.Rall, t.ctr, f.info);
-    int bv_rounds = ceil_log2(border_px) + 1;
-    if (bv_rounds > kBvGridRounds) bv_rounds = kBvGridRounds;
-    if (bv_rounds < 1) bv_rounds = 1;
-    // A layer without intervals (one spanning tree per pair) with few tile-border
-    // pixels leaves a contracted graph that the one-workgroup tail takes whole
-    // (about 1.5 live edges per border pixel; in LDS when it fits, else in the
-    // tail's global-memory mode): no full-grid rounds are launched.
-    if (!plo && border_px <= kTopAloneBorderPx) bv_rounds = 0;
-    for (int r = 0; r < bv_rounds; ++r) {
-        uint64_t *bc = (r & 1) ? t.best1 : t.best0, *bn = (r & 1) ? t.best0 : t.best1;
-        if (r > 0)  // round 0's minimum edges come from the tile-local phase
-            k_gbv_minedge<false><<<g_edges, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
-                                                      bc, f.info);
-        k_gbv_hook<<<g_roots, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Rall, t.comp0, t.cw, bc, bn,
-                                               t.intree, f.info);
+    if (literal) {
+        // 1-3 (literal forest): keys and filter, stable sort of the edge ids by
+        // key (8 bits a pass; ids ascending among equal keys), the sequential
+        // process, then each pixel's tree, smallest pixel and tree interval
+        uint32_t *ekey = reinterpret_cast<uint32_t *>(t.cw);
+        int32_t *uf = t.Rall, *usz = t.slot;
+        int32_t *tlo = reinterpret_cast<int32_t *>(t.best0), *thi = tlo + n;
+        int32_t *plo2 = reinterpret_cast<int32_t *>(t.best1), *phi2 = plo2 + n;
+        const int passes = (255ll << (2 * g.level)) < 0xFFFF ? 2 : 3;
+        const uint32_t sentinel = (1u << (8 * passes)) - 1u;
+        k_seq_edges<<<gn, kBlock, 0, st>>>(im, g, plo, phi, sentinel, ekey, uf, usz, tlo, thi,
+                                           t.croot, t.lmin, t.intree, f.info);
+        int32_t *src = reinterpret_cast<int32_t *>(t.E), *dst = src + 2 * n;
+        k_iota<<<grid_for(2 * n), kBlock, 0, st>>>(src, 2 * n);
+        for (int pass = 0; pass < passes; ++pass) {
+            counting_sort<256, 8>(src, dst, nullptr, 2 * n, EdgeDigit{ekey, 8 * pass}, t.hist2,
+                                  t.part2, st);
+            int32_t *tmp = src;
+            src = dst;
+            dst = tmp;
+        }
+        k_seq_kruskal<<<1, kSeqThreads, 0, st>>>(src, ekey, 2 * n, sentinel, g, beta_num,
+                                                  beta_den, uf, usz, tlo, thi, t.intree);
+        k_seq_roots<<<gn, kBlock, 0, st>>>(uf, tlo, thi, n, width, t.comp0, t.lmin, plo2, phi2,
+                                           f.info);
+        plo_f = plo2;
+        phi_f = phi2;
+        mw_f = width;
+    } else {
+        // 1-2: spanning forest (tile-local phase, full-grid rounds, one-workgroup tail)
+        k_local_msf<<<n_tiles, kLocalThreads, 0, st>>>(im, g, plo, phi, max_width, rank, t.comp0, t.cw,
+                                                       t.best0, t.best1, t.lmin, t.croot, t.mnroot,
+                                                       t.intree, t.E, t.Rall, t.ctr, f.info);
+        int bv_rounds = ceil_log2(border_px) + 1;
+        if (bv_rounds > kBvGridRounds) bv_rounds = kBvGridRounds;
+        if (bv_rounds < 1) bv_rounds = 1;
+        // A layer without intervals (one spanning tree per pair) with few tile-border
+        // pixels leaves a contracted graph that the one-workgroup tail takes whole
+        // (about 1.5 live edges per border pixel; in LDS when it fits, else in the
+        // tail's global-memory mode): no full-grid rounds are launched.
+        if (!plo && border_px <= kTopAloneBorderPx) bv_rounds = 0;
+        for (int r = 0; r < bv_rounds; ++r) {
+            uint64_t *bc = (r & 1) ? t.best1 : t.best0, *bn = (r & 1) ? t.best0 : t.best1;
+            if (r > 0)  // round 0's minimum edges come from the tile-local phase
+                k_gbv_minedge<false><<<g_edges, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
+                                                          bc, f.info);
+            k_gbv_hook<<<g_roots, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Rall, t.comp0, t.cw, bc, bn,
+                                                   t.intree, f.info);
+        }
+        if (bv_rounds > 0)  // without rounds every listed edge is live: the tail reads the list
+            k_gbv_compact<<<g_edges, kBlock, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
+                                                  t.Et, f.info);
+        // Rounds on the compacted list (each skipped once a round hooked nothing),
+        // launched where the tail would otherwise take more live edges than its
+        // LDS holds: after the full-grid rounds about one live edge per 6 border
+        // pixels is left on a layer without intervals, one per 64 with intervals
+        // (measured).  Elsewhere their launches would cost more than they save.
+        const int64_t est_left = plo ? border_px / 64 : border_px / 6;
+        const int list_rounds = bv_rounds > 0 && est_left > kTE / 2 ? kBvListRounds : 0;
+        const unsigned g_list = g_edges < 512u ? g_edges : 512u;
+        for (int r = bv_rounds; r < bv_rounds + list_rounds; ++r) {
+            uint64_t *bc = (r & 1) ? t.best1 : t.best0, *bn = (r & 1) ? t.best0 : t.best1;
+            k_gbv_minedge<true><<<g_list, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Et, t.comp0, t.cw,
+                                                           bc, f.info);
+            k_gbv_lhook<<<g_list, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Et, t.comp0, t.cw, bc, bn,
+                                                   t.intree, f.info);
+        }
+        k_gbv_tail<<<1, kLocalThreads, 0, st>>>(bv_rounds + list_rounds, t.flags, t.ctr, g, t.E, t.Et,
+                                                t.comp0, t.cw, t.Rall, t.croot, t.best0, t.best1,
+                                                t.intree, f.info);
+        // 3: roots
+        k_gbv_final<<<g_roots, kBlock, 0, st>>>(t.ctr, t.Rall, t.cw, t.lmin, t.croot, t.mnroot, f.info);
     }
-    if (bv_rounds > 0)  // without rounds every listed edge is live: the tail reads the list
-        k_gbv_compact<<<g_edges, kBlock, 0, st>>>(bv_rounds, t.flags, t.ctr, g, t.E, t.comp0, t.cw,
-                                              t.Et, f.info);
-    // Rounds on the compacted list (each skipped once a round hooked nothing),
-    // launched where the tail would otherwise take more live edges than its
-    // LDS holds: after the full-grid rounds about one live edge per 6 border
-    // pixels is left on a layer without intervals, one per 64 with intervals
-    // (measured).  Elsewhere their launches would cost more than they save.
-    const int64_t est_left = plo ? border_px / 64 : border_px / 6;
-    const int list_rounds = bv_rounds > 0 && est_left > kTE / 2 ? kBvListRounds : 0;
-    const unsigned g_list = g_edges < 512u ? g_edges : 512u;
-    for (int r = bv_rounds; r < bv_rounds + list_rounds; ++r) {
-        uint64_t *bc = (r & 1) ? t.best1 : t.best0, *bn = (r & 1) ? t.best0 : t.best1;
-        k_gbv_minedge<true><<<g_list, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Et, t.comp0, t.cw,
-                                                       bc, f.info);
-        k_gbv_lhook<<<g_list, kBlock, 0, st>>>(r, t.flags, t.ctr, g, t.Et, t.comp0, t.cw, bc, bn,
-                                               t.intree, f.info);
-    }
-    k_gbv_tail<<<1, kLocalThreads, 0, st>>>(bv_rounds + list_rounds, t.flags, t.ctr, g, t.E, t.Et,
-                                            t.comp0, t.cw, t.Rall, t.croot, t.best0, t.best1,
-                                            t.intree, f.info);
-    // 3: roots
-    k_gbv_final<<<g_roots, kBlock, 0, st>>>(t.ctr, t.Rall, t.cw, t.lmin, t.croot, t.mnroot, f.info);
     k_set_tree<<<gn, kBlock, 0, st>>>(t.comp0, t.croot, t.lmin, t.mnroot, t.intree, g, f.tree,
                                       t.adj, f.info);
     // 4: Euler tour ranks
@@ -1951,10 +2136,10 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     k_tour_link<<<g_edges, kBlock, 0, st>>>(t.ctr, t.C, t.lw, t.pr);
     int rk_rounds = ceil_log2(max_list) + 1;
     if (rk_rounds < 1) rk_rounds = 1;
-    // With intervals the trees are small (the longest contracted list of the
-    // 1344x1104 pair's level 0 has under a thousand entries): one launch, and
-    // the tail finishes any longer list.
-    if (plo && rk_rounds > kRankJumps) rk_rounds = kRankJumps;
+    // With intervals (in the regime) the trees are small (the longest
+    // contracted list of the 1344x1104 pair's level 0 has under a thousand
+    // entries): one launch, and the tail finishes any longer list.
+    if (plo && !literal && rk_rounds > kRankJumps) rk_rounds = kRankJumps;
     // Without intervals every pair's forest is one spanning tree (one tour), so
     // the contracted list is bounded by runs_bound: a list that fits the LDS
     // tail needs no full-grid rounds at all.
@@ -1970,7 +2155,7 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
     // 5: parents, subtree sizes, heavy children
     const unsigned n_scan = (unsigned)(scan_tiles(n) < 1 ? 1 : scan_tiles(n));
     k_parent<<<kXcds * ((n_scan + kXcds - 1) / kXcds), kParentThreads, 0, st>>>(
-        g, im, rk, t.adj, plo, phi, max_width, f.parent, t.size, f.wgt, t.rootval, f.lo, f.hi,
+        g, im, rk, t.adj, plo_f, phi_f, mw_f, f.parent, t.size, f.wgt, t.rootval, f.lo, f.hi,
         t.nrec,
         t.partial64, (int)n_scan);
     // 6: tour offsets (the root-data scan, tile sums from k_parent), tour

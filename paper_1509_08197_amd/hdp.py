@@ -315,7 +315,15 @@ def build_tree(img: torch.Tensor, shapes, level: int, pix_lo=None, pix_hi=None,
     n = n_pixels(shapes)
     assert img.shape == (n, 4) and img.dtype == torch.float32 and img.is_contiguous()
     if width is None:
-        width = max_width if pix_lo is not None else max(d for _, _, d in shapes) + 1
+        dfull = max(d for _, _, d in shapes) + 1
+        if pix_lo is None:
+            width = dfull
+        elif beta[0] * max_width <= beta[1] * (max_width - 1):
+            # outside the exact regime the sequential process runs and merges
+            # can widen a tree's interval up to the full range
+            width = dfull
+        else:
+            width = max_width
     dev = img.device
     if forest is None:
         buf, st = alloc_forest(n, dev)

@@ -257,12 +257,85 @@ def test_hdpf_bit_exact(H, orc, seed):
     assert F["info"][6] == 0
 
 
-def test_regime_rejected(H):
+def test_regime_rejected_random_tree(H):
+    """Outside the exact regime the random spanning tree's disparity forest is
+    not built: HDP_EREGIME before any launch."""
     lv = H.pyramid(rgb_dev(np.zeros((8, 8, 3), np.uint8)), [(8, 8, 63)], 2, 0)
     lo = dev(np.zeros(64, np.int32)); hi = dev(np.full(64, 9, np.int32))
+    rank = dev(np.arange(128, dtype=np.int32))
     with pytest.raises(H.HdpError) as e:
-        H.build_tree(lv[0], [(8, 8, 63)], 0, lo, hi, max_width=10, beta=(3, 5))
+        H.build_tree(lv[0], [(8, 8, 63)], 0, lo, hi, max_width=10, beta=(3, 5), rank=rank)
     assert e.value.code == -4
+
+
+@pytest.mark.parametrize("case", ["beta35_w4", "beta35_w8", "beta12_batch2"])
+def test_hdpf_literal_outside_regime(H, orc, case):
+    """Outside the exact regime (beta = 3/5, the small-image setting of
+    Section 4.1; wide windows) the forest is the one of the sequential Kruskal
+    process with both DT rules on the current tree intervals: parents, trees,
+    depths, level order, weights and each pixel's tree interval bit-exact
+    against the oracle's literal process."""
+    S, dmax = 2, 63
+    if case == "beta12_batch2":
+        shapes, w, beta = [(40, 56, dmax), (23, 31, dmax)], 4, (1, 2)
+    else:
+        shapes, w, beta = [(48, 64, dmax)], (4 if case == "beta35_w4" else 8), (3, 5)
+    pairs = [scenes.small_scene(610 + i, h, wd, d) for i, (h, wd, d) in enumerate(shapes)]
+    los, his, refs = [], [], []
+    for i, (pair, (h, wd, _)) in enumerate(zip(pairs, shapes)):
+        up = np.random.default_rng(30 + i).integers(0, dmax // 2 + 1, ((h + 1) // 2, (wd + 1) // 2))
+        up = np.kron(up[::3, ::3], np.ones((3, 3), int))[:up.shape[0], :up.shape[1]]
+        lo, hi = orc.predict_range(up, h, wd, S, w, dmax)
+        key = orc.edge_keys(pairs[i].left.astype(np.float64), 0)
+        in_tree, tlo, thi, _ = orc.kruskal(h, wd, key, lo, hi, beta=beta)
+        refs.append((orc.root_forest(h, wd, in_tree, key, 0), tlo, thi))
+        los.append(lo.ravel()); his.append(hi.ravel())
+    lv = H.pyramid(rgb_dev(*[p.left for p in pairs]), shapes, 2, 0)
+    lo_d = dev(np.concatenate(los), torch.int32); hi_d = dev(np.concatenate(his), torch.int32)
+    mw = S + 2 * w
+    assert beta[0] * mw <= beta[1] * (mw - 1)  # outside the regime
+    f = H.build_tree(lv[0], shapes, 0, lo_d, hi_d, max_width=mw, beta=beta)
+    assert f.width == dmax + 1
+    F = forest_np(f)
+    assert F["info"][6] == 0
+    off = 0
+    for i, ((h, wd, _), (ref, tlo, thi)) in enumerate(zip(shapes, refs)):
+        n = h * wd
+        sl = slice(off, off + n)
+        # pixel ids of pair i are offset by the pixels of the pairs before it
+        np.testing.assert_array_equal(F["parent"][sl], np.where(ref["parent"] >= 0,
+                                                                ref["parent"] + off, -1))
+        np.testing.assert_array_equal(F["tree"][sl], ref["tree"] + off)
+        np.testing.assert_array_equal(F["depth"][sl], ref["depth"])
+        assert_rel(F["wgt"][sl], ref["wgt"], 1e-6, f"{case} pair {i} wgt")
+        np.testing.assert_array_equal(F["lo"][sl], tlo)
+        np.testing.assert_array_equal(F["hi"][sl], thi)
+        if len(shapes) == 1:
+            check_forest(F, ref, n, f"literal HDPF {case}")
+        off += n
+    # some trees merged across different intervals (the case the regime excludes)
+    assert np.any(F["hi"] - F["lo"] + 1 > mw) or np.any(
+        (F["lo"] != np.concatenate(los)) | (F["hi"] != np.concatenate(his)))
+
+
+def test_hdp_literal_end_to_end_small(H, orc):
+    """The whole loop with beta = 3/5 (outside the regime at every layer below
+    the top) on the GPU against the oracle's literal loop: labels identical
+    except at near-ties or where an interval upstream differs."""
+    pair = scenes.small_scene(640, 48, 64, 31)
+    res = H.hdp_stereo(rgb_dev(pair.left), rgb_dev(pair.right), [(48, 64, 31)], S=2, L=2,
+                       window=2, beta=(3, 5))
+    ores = orc.hdp_stereo(pair.left, pair.right, 31, S=2, L=2, window=2, beta=(3, 5))
+    for l in (2, 1, 0):
+        g = res[l].disp.cpu().numpy(); o = ores[l]["disp"].ravel()
+        gap = (ores[l]["c2"] - ores[l]["c1"]) / ores[l]["c1"]
+        mism = g != o
+        if l < 2:
+            same_int = ((res[l].pix_lo.cpu().numpy() == ores[l]["pix_lo"].ravel()) &
+                        (res[l].pix_hi.cpu().numpy() == ores[l]["pix_hi"].ravel()))
+        else:
+            same_int = np.ones_like(mism)
+        assert np.all(gap[mism & same_int] <= REL), f"layer {l}: unexplained mismatches"
 
 
 # --- cost, aggregation, WTA ------------------------------------------------------------
