@@ -219,12 +219,11 @@ HDP_API hdp_status hdp_build_tree(const float *img, const hdp_shape *shapes, int
  *              ignored).  Only the low 31 bits are used.  The shuffled order
  *              is ascending (rank, edge id); uniform random ranks give a
  *              uniformly random order of the edges up to ties.
- * Every other argument, the exact regime, the outputs and the errors are
- * those of hdp_build_tree, except that outside the exact regime this call
- * returns HDP_EREGIME (the sequential process is built for the colour order
- * only); the edge weights stored in the forest (and used by the aggregation)
- * are still the colour weights of eq. weight.  Returns HDP_EINVAL if
- * edge_rank is NULL.
+ * Every other argument, the exact regime (outside it the sequential process
+ * in the shuffled order), the outputs and the errors are those of
+ * hdp_build_tree; the edge weights stored in the forest (and used by the
+ * aggregation) are still the colour weights of eq. weight.  Returns
+ * HDP_EINVAL if edge_rank is NULL.
  */
 HDP_API hdp_status hdp_build_random_tree(const float *img, const hdp_shape *shapes,
                                          int32_t n_pairs, int32_t level,

@@ -224,11 +224,8 @@ static hdp_status build_tree(const float *img, const hdp_shape *shapes, int32_t 
         if (max_width < 1 || width < max_width) return HDP_EINVAL;
         if (beta_num < 1 || beta_den < 1 || beta_num > beta_den) return HDP_EINVAL;
         // exact regime: two distinct intervals of width <= w have IoU <= (w-1)/w < beta;
-        // outside it the sequential process itself runs (random ranks: not built there)
-        if ((int64_t)beta_num * max_width <= (int64_t)beta_den * (max_width - 1)) {
-            if (edge_rank) return HDP_EREGIME;
-            literal = true;
-        }
+        // outside it the sequential process itself runs
+        if ((int64_t)beta_num * max_width <= (int64_t)beta_den * (max_width - 1)) literal = true;
     } else if (width < max_dmax(g) + 1) {
         return HDP_EINVAL;
     }

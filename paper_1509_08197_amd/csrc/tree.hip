@@ -1057,7 +1057,8 @@ __global__ void k_set_tree(const int32_t *__restrict__ comp0, const int32_t *__r
 // absent or filtered, sorted last), and the start state of the union-find.
 __global__ void k_seq_edges(const float4 *__restrict__ img, LevelGeom g,
                             const int32_t *__restrict__ plo, const int32_t *__restrict__ phi,
-                            uint32_t sentinel, uint32_t *__restrict__ ekey,
+                            const int32_t *__restrict__ rank, uint32_t sentinel,
+                            uint32_t *__restrict__ ekey,
                             int32_t *__restrict__ uf, int32_t *__restrict__ usz,
                             int32_t *__restrict__ tlo, int32_t *__restrict__ thi,
                             int32_t *__restrict__ croot, int32_t *__restrict__ lmin,
@@ -1076,8 +1077,11 @@ __global__ void k_seq_edges(const float4 *__restrict__ img, LevelGeom g,
     if (l < 0 || h > dm || l > h) atomicAdd(&info[HDP_INFO_BAD_INTERVAL], 1);
     const bool kr = hr && (l > lr ? l : lr) <= (h < hrr ? h : hrr);
     const bool kd = hd && (l > ld ? l : ld) <= (h < hdd ? h : hdd);
-    ekey[2 * v] = kr ? edge_key(a, ar, scale) : sentinel;
-    ekey[2 * v + 1] = kd ? edge_key(a, ad, scale) : sentinel;
+    // random spanning tree: the edges' random ranks (31 bits) order them instead
+    const uint32_t qr = rank ? (uint32_t)rank[2 * v] & 0x7fffffffu : edge_key(a, ar, scale);
+    const uint32_t qd = rank ? (uint32_t)rank[2 * v + 1] & 0x7fffffffu : edge_key(a, ad, scale);
+    ekey[2 * v] = kr ? qr : sentinel;
+    ekey[2 * v + 1] = kd ? qd : sentinel;
     l = l < 0 ? 0 : (l > dm ? dm : l);
     h = h < l ? l : (h > dm ? dm : h);
     uf[v] = (int32_t)v;
@@ -2064,10 +2068,11 @@ void launch_build_tree(const float *img, const LevelGeom &g, const int32_t *plo,
         int32_t *uf = t.Rall, *usz = t.slot;
         int32_t *tlo = reinterpret_cast<int32_t *>(t.best0), *thi = tlo + n;
         int32_t *plo2 = reinterpret_cast<int32_t *>(t.best1), *phi2 = plo2 + n;
-        const int passes = (255ll << (2 * g.level)) < 0xFFFF ? 2 : 3;
-        const uint32_t sentinel = (1u << (8 * passes)) - 1u;
-        k_seq_edges<<<gn, kBlock, 0, st>>>(im, g, plo, phi, sentinel, ekey, uf, usz, tlo, thi,
-                                           t.croot, t.lmin, t.intree, f.info);
+        // keys below 2^16 (colour keys to layer 4), 2^24, or 31-bit ranks
+        const int passes = rank ? 4 : (255ll << (2 * g.level)) < 0xFFFF ? 2 : 3;
+        const uint32_t sentinel = passes == 4 ? 0xFFFFFFFFu : (1u << (8 * passes)) - 1u;
+        k_seq_edges<<<gn, kBlock, 0, st>>>(im, g, plo, phi, rank, sentinel, ekey, uf, usz, tlo,
+                                           thi, t.croot, t.lmin, t.intree, f.info);
         int32_t *src = reinterpret_cast<int32_t *>(t.E), *dst = src + 2 * n;
         k_iota<<<grid_for(2 * n), kBlock, 0, st>>>(src, 2 * n);
         for (int pass = 0; pass < passes; ++pass) {

@@ -83,12 +83,9 @@ def test_build_tree_validation(lib):
     # empty batch
     assert L.hdp_build_tree(dummy, shapes, 0, 0, None, None, 0, 19, 20, 64, C.byref(st),
                             dummy, ws, None) == -2
-    # outside the exact regime (width 10 with beta 3/5) the random tree's forest
-    # is refused before any launch (the colour-order forest runs the sequential
-    # process instead, which needs a device)
-    assert L.hdp_build_random_tree(dummy, shapes, 1, 0, dummy, dummy, dummy, 10, 3, 5, 64,
-                                   C.byref(st), dummy, ws, None) == -4
-    # outside the exact regime the row width must hold a tree's interval: at
+    # (outside the exact regime, width 10 with beta 3/5, the call runs the
+    # sequential process on the device: not callable here)
+    # the row width must hold a tree's interval: at
     # least max_width
     assert L.hdp_build_tree(dummy, shapes, 1, 0, dummy, dummy, 10, 3, 5, 9, C.byref(st),
                             dummy, ws, None) == -1

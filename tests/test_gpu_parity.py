@@ -257,17 +257,6 @@ def test_hdpf_bit_exact(H, orc, seed):
     assert F["info"][6] == 0
 
 
-def test_regime_rejected_random_tree(H):
-    """Outside the exact regime the random spanning tree's disparity forest is
-    not built: HDP_EREGIME before any launch."""
-    lv = H.pyramid(rgb_dev(np.zeros((8, 8, 3), np.uint8)), [(8, 8, 63)], 2, 0)
-    lo = dev(np.zeros(64, np.int32)); hi = dev(np.full(64, 9, np.int32))
-    rank = dev(np.arange(128, dtype=np.int32))
-    with pytest.raises(H.HdpError) as e:
-        H.build_tree(lv[0], [(8, 8, 63)], 0, lo, hi, max_width=10, beta=(3, 5), rank=rank)
-    assert e.value.code == -4
-
-
 @pytest.mark.parametrize("case", ["beta35_w4", "beta35_w8", "beta12_batch2"])
 def test_hdpf_literal_outside_regime(H, orc, case):
     """Outside the exact regime (beta = 3/5, the small-image setting of
@@ -907,6 +896,27 @@ def test_rt_upper_levels_bit_exact(H, orc, level):
     img = orc.pyramid(pair.left, 2, 2)[level]
     ref, _, _ = rt_reference(orc, img, shp[0][0], shp[0][1], level, rank)
     check_forest(F, ref, n, f"RT level {level}")
+
+
+def test_hdp_rt_forest_literal_outside_regime(H, orc):
+    """HDP+RT outside the exact regime (beta = 3/5): the sequential process in
+    the shuffled (rank, id) order, bit-exact against the oracle's."""
+    Hh, Ww, dmax, S, w = 48, 64, 63, 2, 4
+    pair = scenes.small_scene(66, Hh, Ww, dmax)
+    up = np.random.default_rng(5).integers(0, dmax // 2 + 1, ((Hh + 1) // 2, (Ww + 1) // 2))
+    up = np.kron(up[::3, ::3], np.ones((3, 3), int))[:up.shape[0], :up.shape[1]]
+    lo, hi = orc.predict_range(up, Hh, Ww, S, w, dmax)
+    lv = H.pyramid(rgb_dev(pair.left), [(Hh, Ww, dmax)], 2, 0)
+    rank = rank_np(77, Hh * Ww)
+    f = H.build_tree(lv[0], [(Hh, Ww, dmax)], 0, dev(lo.ravel(), torch.int32),
+                     dev(hi.ravel(), torch.int32), max_width=S + 2 * w, beta=(3, 5),
+                     rank=dev(rank))
+    F = forest_np(f)
+    ref, tlo, thi = rt_reference(orc, pair.left, Hh, Ww, 0, rank, lo, hi, beta=(3, 5))
+    check_forest(F, ref, Hh * Ww, "literal HDP+RT forest")
+    np.testing.assert_array_equal(F["lo"], tlo)
+    np.testing.assert_array_equal(F["hi"], thi)
+    assert F["info"][6] == 0
 
 
 @pytest.mark.parametrize("seed", [0, 1])
