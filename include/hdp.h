@@ -51,7 +51,7 @@ typedef enum {
     HDP_EINVAL = -1,      /* null pointer or out-of-range scalar */
     HDP_ESHAPE = -2,      /* bad image shape, dmax, or batch size */
     HDP_EWORKSPACE = -3,  /* workspace smaller than required */
-    HDP_EREGIME = -4,     /* beta / interval width outside the exact regime */
+    HDP_EREGIME = -4,     /* forest not exact: a pixel interval broke the bound given */
     HDP_EHIP = -5         /* HIP runtime error */
 } hdp_status;
 

@@ -27,7 +27,7 @@ INFO = dict(n_levels=0, n_phases=1, n_trees=2, width=3, mst_rounds=4, rank_round
             list_edges=11)
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "invalid shape or batch",
-          -3: "workspace too small", -4: "outside the exact disparity-forest regime",
+          -3: "workspace too small", -4: "disparity forest not exact (an interval broke the bound given)",
           -5: "HIP runtime error"}
 
 
