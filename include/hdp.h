@@ -246,7 +246,8 @@ HDP_API hdp_status hdp_level_order(const hdp_forest *f, void *ws, size_t ws_byte
  * nothing on the hot path needs it).  Either pointer may be NULL;
  * phase_ptr_host receives HDP_MAX_PHASES + 1 entries.  Returns HDP_EREGIME
  * (after filling both outputs) when info[HDP_INFO_BAD_INTERVAL] > 0, i.e. the
- * forest was built from pixel intervals that broke hdp_build_tree's bound. */
+ * forest was built from pixel intervals that broke hdp_build_tree's bounds (or,
+ * outside the exact regime, a tree's interval outgrew the row width). */
 HDP_API hdp_status hdp_forest_read_info(const hdp_forest *f, int32_t *info_host,
                                 int32_t *phase_ptr_host, void *stream);
 
