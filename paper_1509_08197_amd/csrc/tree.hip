@@ -1101,27 +1101,30 @@ struct EdgeDigit {
     __device__ int operator()(int64_t, int32_t e) const { return (key[e] >> shift) & 255; }
 };
 
-__device__ __forceinline__ int32_t uf_find_halving(int32_t *uf, int32_t v) {
-    while (uf[v] != v) {
-        const int32_t gp = uf[uf[v]];
-        uf[v] = gp;
-        v = gp;
+constexpr int kSeqThreads = 256;
+constexpr int kSeqChunk = 2048;  // edges staged in LDS per step
+
+__device__ __forceinline__ int32_t uf_root_ro(const int32_t *uf, int32_t v) {
+    int32_t u = uf[v];
+    while (u != v) {
+        v = u;
+        u = uf[v];
     }
     return v;
 }
 
-constexpr int kSeqThreads = 256;
-constexpr int kSeqChunk = 2048;  // edges staged in LDS per step
-
 // The sequential process: the workgroup stages the next kSeqChunk edges of
-// the sorted list (ids and far ends) in LDS, then one thread takes them in
-// order.  Every edge is decided exactly as in the definition above.
+// the sorted list in LDS with the roots of both ends as the chunk starts
+// (found in parallel; roots only ever merge, so ends that share a root then
+// are certainly a Rule 2 skip, and a root then is an ancestor of the root
+// now), then one thread takes the edges in order and decides each exactly as
+// in the definition above.
 __global__ __launch_bounds__(kSeqThreads) void k_seq_kruskal(
     const int32_t *__restrict__ sorted, const uint32_t *__restrict__ ekey, int64_t m,
     uint32_t sentinel, LevelGeom g, int beta_num, int beta_den, int32_t *__restrict__ uf,
     int32_t *__restrict__ usz, int32_t *__restrict__ tlo, int32_t *__restrict__ thi,
     uint8_t *__restrict__ intree) {
-    __shared__ int32_t se[kSeqChunk], sq[kSeqChunk];
+    __shared__ int32_t se[kSeqChunk], sp[kSeqChunk], sq[kSeqChunk];
     __shared__ int s_stop;
     const int tid = threadIdx.x;
     if (tid == 0) s_stop = 0;
@@ -1130,18 +1133,21 @@ __global__ __launch_bounds__(kSeqThreads) void k_seq_kruskal(
         if (s_stop) break;
         for (int j = tid; j < kSeqChunk; j += kSeqThreads) {
             const int64_t i = base + j;
-            int32_t e = -1, q = 0;
+            int32_t e = -1, hp = 0, hq = 0;
             if (i < m) {
                 e = sorted[i];
                 if (ekey[e] == sentinel) {
                     e = -1;  // absent or filtered: every later edge is too
                 } else {
                     const int32_t pv = e >> 1;
-                    q = (e & 1) ? pv + g.W[pair_of(g, pv)] : pv + 1;
+                    const int32_t q = (e & 1) ? pv + g.W[pair_of(g, pv)] : pv + 1;
+                    hp = uf_root_ro(uf, pv);
+                    hq = uf_root_ro(uf, q);
                 }
             }
             se[j] = e;
-            sq[j] = q;
+            sp[j] = hp;
+            sq[j] = hq;
         }
         __syncthreads();
         if (tid == 0) {
@@ -1151,22 +1157,31 @@ __global__ __launch_bounds__(kSeqThreads) void k_seq_kruskal(
                     s_stop = 1;
                     break;
                 }
-                int32_t rp = uf_find_halving(uf, e >> 1), rq = uf_find_halving(uf, sq[j]);
+                int32_t rp = sp[j], rq = sq[j];
+                if (rp == rq) continue;  // Rule 2 (one tree since the chunk began)
+                // the roots now: both chains (merges of this chunk) walked together
+                for (;;) {
+                    const int32_t up = uf[rp], uq = uf[rq];
+                    if (up == rp && uq == rq) break;
+                    rp = up;
+                    rq = uq;
+                }
                 if (rp == rq) continue;  // Rule 2
                 // DT-Rule 2 on the current tree intervals
                 const int32_t lp = tlo[rp], hp = thi[rp], lq = tlo[rq], hq = thi[rq];
+                const int32_t zp = usz[rp], zq = usz[rq];
                 const int32_t ilo = lp > lq ? lp : lq, ihi = hp < hq ? hp : hq;
                 const int64_t inter = ihi >= ilo ? (int64_t)(ihi - ilo + 1) : 0;
                 const int64_t uni = (int64_t)(hp - lp + 1) + (hq - lq + 1) - inter;
                 if ((int64_t)beta_den * inter < (int64_t)beta_num * uni) continue;
                 // merge (union by size); the tree takes the union of the intervals
-                if (usz[rp] < usz[rq]) {
+                if (zp < zq) {
                     const int32_t t = rp;
                     rp = rq;
                     rq = t;
                 }
                 uf[rq] = rp;
-                usz[rp] += usz[rq];
+                usz[rp] = zp + zq;
                 tlo[rp] = lp < lq ? lp : lq;
                 thi[rp] = hp > hq ? hp : hq;
                 intree[e] = 1;
