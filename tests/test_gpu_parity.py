@@ -1159,6 +1159,58 @@ def test_hdp_gmm_loop_stagewise(H, orc):
     assert d0.min() >= 0 and d0.max() <= dmax
 
 
+def test_hdp_gmm_layers_literal_forest(H, orc):
+    """Bayesian intervals with beta = 3/5 (outside the exact regime): every
+    layer fed the oracle's layer-(l+1) labels gives the oracle's literal
+    disparity forest (parents and tree intervals bit for bit), aggregation
+    (within 1e-5) and labels (up to near-ties)."""
+    Hh, Ww, dmax, S, L = 64, 80, 63, 2, 2
+    beta = (3, 5)
+    pair = scenes.small_scene(79, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    lvs = H.level_shapes(shapes, S, L)
+    gm = scenes.gmm_params(3, L)
+    priors = [scenes.label_prior(pair.gt, S, l, lvs[l][0][2]) for l in range(L)]
+    delta0 = 0.004
+    lp = H.pyramid(rgb_dev(pair.left), shapes, S, L)
+    rp = H.pyramid(rgb_dev(pair.right), shapes, S, L)
+    Lf = orc.pyramid(pair.left, S, L); Rf = orc.pyramid(pair.right, S, L)
+    o_up = orc.stereo_level(Lf[L], Rf[L], lvs[L][0][2], L)
+    for level in range(L - 1, -1, -1):
+        dl = lvs[level][0][2]
+        Hl, Wl = lvs[level][0][:2]
+        olo_t, ohi_t = orc.gmm_interval_table(S, dl, lvs[level + 1][0][2], *gm[level],
+                                              priors[level], delta0 * S ** level)
+        olo, ohi = orc.predict_range_table(o_up["disp"], Hl, Wl, S, olo_t, ohi_t)
+        lo_t, hi_t, mw = H.interval_table(lvs[level + 1], lvs[level], S, H.make_gmm(*gm[level]),
+                                          dev(priors[level][None, :]), delta0 * S ** level)
+        up = dev(o_up["disp"].ravel(), torch.int32)
+        lo, hi = H.predict_range_table(up, lvs[level + 1], lvs[level], S, lo_t, hi_t)
+        mwi = int(mw.item())
+        assert beta[0] * mwi <= beta[1] * (mwi - 1), "test case is inside the exact regime"
+        r = H.stereo_level(lp[level], rp[level], lvs[level], level, lo, hi, max_width=mwi,
+                           beta=beta, keep=True)
+        o = orc.stereo_level(Lf[level], Rf[level], dl, level, olo, ohi, beta=beta)
+        F = forest_np(r.forest)
+        assert F["info"][7] == 0 and F["info"][6] == 0
+        np.testing.assert_array_equal(F["parent"], o["parent"])
+        np.testing.assert_array_equal(F["lo"], o["tree_lo"])
+        np.testing.assert_array_equal(F["hi"], o["tree_hi"])
+        key = orc.edge_keys(Lf[level], level)
+        in_tree, tlo, thi, _ = orc.kruskal(Hl, Wl, key, olo, ohi, beta=beta)
+        ref_f = orc.root_forest(Hl, Wl, in_tree, key, level)
+        cost = orc.cost_volume(Lf[level], Rf[level], dl, tlo, thi)
+        agg = orc.aggregate_twopass(ref_f["parent"], ref_f["wgt"], ref_f["order"], 0.1,
+                                    np.nan_to_num(cost, nan=0.0))
+        agg[np.isnan(cost)] = np.nan
+        assert_rel(volume_to_pixels(r.agg.cpu().numpy(), F, dl + 1), agg, REL,
+                   f"literal GMM aggregate layer {level}")
+        nm, nt = check_wta(r.disp.cpu().numpy(), agg, tlo, thi, f"literal GMM WTA layer {level}")
+        print(f"literal GMM layer {level}: widest pixel interval {mwi}, widest tree interval "
+              f"{int((F['hi'] - F['lo']).max()) + 1}, WTA mismatches {nm} (near-ties {nt})")
+        o_up = o
+
+
 # --- left-right check, sampled prior, refinement (Sections 3.1, 3.3) ----------------
 
 LR_SHAPES = [(37, 53, 31), (20, 9, 7), (1, 1, 3), (64, 96, 63)]
