@@ -307,6 +307,31 @@ def test_hdpf_literal_outside_regime(H, orc, case):
         (F["lo"] != np.concatenate(los)) | (F["hi"] != np.concatenate(his)))
 
 
+@pytest.mark.parametrize("Hh,Ww", [(1, 1), (1, 17), (17, 1), (2, 2), (3, 40)])
+def test_hdpf_literal_degenerate_shapes(H, orc, Hh, Ww):
+    """The literal disparity forest on degenerate grids (a single pixel, one
+    row, one column, 2x2, a thin strip) with random intervals and beta = 1/2:
+    bit-exact against the oracle's literal process."""
+    dmax = 15
+    rng = np.random.default_rng(Hh * 100 + Ww)
+    img = rng.integers(0, 256, (Hh, Ww, 3)).astype(np.uint8)
+    lo = rng.integers(0, 10, Hh * Ww).astype(np.int32)
+    hi = np.minimum(lo + rng.integers(0, 6, Hh * Ww), dmax).astype(np.int32)
+    shapes = [(Hh, Ww, dmax)]
+    lv = H.pyramid(rgb_dev(img), shapes, 2, 0)
+    f = H.build_tree(lv[0], shapes, 0, dev(lo, torch.int32), dev(hi, torch.int32),
+                     max_width=6, beta=(1, 2))
+    F = forest_np(f)
+    key = orc.edge_keys(img.astype(np.float64), 0)
+    in_tree, tlo, thi, _ = orc.kruskal(Hh, Ww, key, lo.reshape(Hh, Ww), hi.reshape(Hh, Ww),
+                                       beta=(1, 2))
+    ref = orc.root_forest(Hh, Ww, in_tree, key, 0)
+    check_forest(F, ref, Hh * Ww, f"literal {Hh}x{Ww}")
+    np.testing.assert_array_equal(F["lo"], tlo)
+    np.testing.assert_array_equal(F["hi"], thi)
+    assert F["info"][6] == 0
+
+
 def test_hdp_literal_end_to_end_small(H, orc):
     """The whole loop with beta = 3/5 (outside the regime at every layer below
     the top) on the GPU against the oracle's literal loop: labels identical
