@@ -76,9 +76,11 @@ OR_API void or_pyramid(const uint8_t *rgb, int H, int W, int S, int L, double *o
  *   M = a_c * min(mean_c |I^L_c(x,y) - I^R_c(x-d,y)|, tau_c)
  *     + a_g * min(|gx^L(x,y) - gx^R(x-d,y)|, tau_g),
  *   gray g = (R+G+B)/3, gx(x) = (g(x+1) - g(x-1)) / 2 with replicated borders,
- *   and M = a_c*tau_c + a_g*tau_g when x-d falls outside the image.
- * prm = {a_c, tau_c, a_g, tau_g}.  The gray difference is formed from the
- * channel sums, (sum(x+1) - sum(x-1)) / 6, which is the same quantity. */
+ *   and, when x-d falls left of the image, M = a_c*tau_c + a_g*tau_g (border
+ *   policy 0, the reading used by default) or M against the row's first
+ *   pixel (policy 1).
+ * prm = {a_c, tau_c, a_g, tau_g, border}.  The gray difference is formed from
+ * the channel sums, (sum(x+1) - sum(x-1)) / 6, which is the same quantity. */
 
 static double chan_sum(const double *img, int W, int x, int y) {
     const double *p = img + ((size_t)y * W + x) * 3;
@@ -95,7 +97,10 @@ OR_API double or_matching_cost(const double *left, const double *right, int H, i
                                int x, int y, int d, const double *prm) {
     (void)H;
     int xr = x - d;
-    if (xr < 0) return prm[0] * prm[1] + prm[2] * prm[3];
+    if (xr < 0) {
+        if (prm[4] == 0.0) return prm[0] * prm[1] + prm[2] * prm[3];
+        xr = 0;
+    }
     const double *pl = left + ((size_t)y * W + x) * 3;
     const double *pr = right + ((size_t)y * W + xr) * 3;
     double col = (fabs(pl[0] - pr[0]) + fabs(pl[1] - pr[1]) + fabs(pl[2] - pr[2])) / 3.0;

@@ -23,6 +23,14 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 COST_PARAMS = (0.89, 7.0, 0.11, 2.0)
 
 
+def _prm(prm):
+    """Cost constants (a_c, tau_c, a_g, tau_g[, border]) as the C array; border
+    0 (default): a label past the left image border costs both truncations;
+    1: it is compared with the row's first pixel."""
+    pr = [float(x) for x in prm]
+    return np.array(pr + [0.0] * (5 - len(pr)), np.float64)
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (single-threaded, -O2, IEEE semantics)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -113,7 +121,7 @@ def pyramid(rgb, S, L):
 def matching_cost(left, right, x, y, d, prm=COST_PARAMS):
     left = _c(left, np.float64); right = _c(right, np.float64)
     H, W = left.shape[:2]
-    pr = np.array(prm, np.float64)
+    pr = _prm(prm)
     return lib().or_matching_cost(_p(left), _p(right), H, W, x, y, d, _p(pr))
 
 
@@ -122,7 +130,7 @@ def cost_volume(left, right, dmax, lo=None, hi=None, prm=COST_PARAMS):
     left = _c(left, np.float64); right = _c(right, np.float64)
     H, W = left.shape[:2]
     out = np.zeros((H * W, dmax + 1), np.float64)
-    pr = np.array(prm, np.float64)
+    pr = _prm(prm)
     lo = None if lo is None else _c(lo, np.int32).ravel()
     hi = None if hi is None else _c(hi, np.int32).ravel()
     lib().or_cost_volume(_p(left), _p(right), H, W, dmax, _p(lo), _p(hi), _p(pr), _p(out))
@@ -299,7 +307,7 @@ def stereo_level(left, right, dmax, level, pix_lo=None, pix_hi=None, beta=(19, 2
         pix_lo = _c(pix_lo, np.int32).ravel(); pix_hi = _c(pix_hi, np.int32).ravel()
     sd = np.array(sample_d, np.int32)
     sa = np.zeros((len(sd), N), np.float64)
-    pr = np.array(prm, np.float64)
+    pr = _prm(prm)
     g = outs.get
     nl = lib().or_stereo_level(_p(left), _p(right), H, W, dmax, level, _p(pix_lo), _p(pix_hi),
                                int(beta[0]), int(beta[1]), float(sigma), _p(pr),

@@ -1276,7 +1276,7 @@ void launch_match(const float *left, const float *right, const LevelGeom &g, con
     A.imR = reinterpret_cast<const float4 *>(right);
     A.imRp = pack ? w.imRp : nullptr;
     A.rinv = 1.0f / rscale;
-    A.cp = CostParams{p.a_c, p.tau_c, p.a_g, p.tau_g};
+    A.cp = CostParams{p.a_c, p.tau_c, p.a_g, p.tau_g, p.border};
     A.node = f.node;
     A.rx = f.rx;
     A.rlh = f.rlh;

@@ -291,6 +291,7 @@ hdp_status hdp_cost_volume(const float *left, const float *right, const hdp_shap
                            int32_t n_pairs, const hdp_forest *f, int32_t width,
                            const hdp_cost_params *p, float *cost, void *stream) {
     if (!left || !right || !p || !cost) return HDP_EINVAL;
+    if (p->border != 0 && p->border != 1) return HDP_EINVAL;
     LevelGeom g;
     hdp_status st = make_geom(shapes, n_pairs, 0, &g);
     if (st != HDP_OK) return st;
@@ -332,6 +333,7 @@ hdp_status hdp_match_layer(const float *left, const float *right, const hdp_shap
                            const hdp_cost_params *p, float sigma, float *agg, int32_t *disp,
                            void *ws, size_t ws_bytes, void *stream) {
     if (!left || !right || !p || !agg || !disp || !ws || !(sigma > 0.f)) return HDP_EINVAL;
+    if (p->border != 0 && p->border != 1) return HDP_EINVAL;
     LevelGeom g;
     hdp_status st = make_geom(shapes, n_pairs, 0, &g);
     if (st != HDP_OK) return st;

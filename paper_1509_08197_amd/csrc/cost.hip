@@ -88,7 +88,7 @@ void launch_cost_volume(const float *left, const float *right, const LevelGeom &
                         const int32_t *node, const int32_t *lo, const int32_t *hi, int width,
                         const hdp_cost_params &p, float *cost, hipStream_t st) {
     int64_t n = g.off[g.n_pairs];
-    CostParams cp{p.a_c, p.tau_c, p.a_g, p.tau_g};
+    CostParams cp{p.a_c, p.tau_c, p.a_g, p.tau_g, p.border};
     const float4 *L = reinterpret_cast<const float4 *>(left);
     const float4 *R = reinterpret_cast<const float4 *>(right);
     int cpt = (width % 4 == 0 && width / 4 <= kBlock) ? 4 : (width % 2 == 0 ? 2 : 1);

@@ -9,6 +9,7 @@ namespace hdp {
 
 struct CostParams {
     float a_c, tau_c, a_g, tau_g;
+    int border;  // 0: a match past the left border costs both truncations; 1: row's first pixel
 };
 
 // Right-image pixel that label `label` of pixel v (column x) is compared with.
@@ -33,7 +34,7 @@ __device__ __forceinline__ float match_cost_px(float4 L, float4 R, bool outside,
     const float gd = fabsf(L.w - R.w) * (1.0f / 6.0f);
     const float m = c.a_c * fminf(col, c.tau_c) + c.a_g * fminf(gd, c.tau_g);
     const float sat = c.a_c * c.tau_c + c.a_g * c.tau_g;
-    return outside ? sat : m;
+    return outside && c.border == 0 ? sat : m;
 }
 
 // Right-image pixel in 8 bytes for the fused up pass: R, G and B times 4^l

@@ -43,7 +43,7 @@ class Shape(C.Structure):
 
 class CostParams(C.Structure):
     _fields_ = [("a_c", C.c_float), ("tau_c", C.c_float), ("a_g", C.c_float),
-                ("tau_g", C.c_float)]
+                ("tau_g", C.c_float), ("border", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -362,8 +362,10 @@ def set_weights(forest: Forest, wgt: torch.Tensor):
 
 # --- cost, aggregation, WTA ---------------------------------------------------------
 
-def cost_params(a_c=0.89, tau_c=7.0, a_g=0.11, tau_g=2.0) -> CostParams:
-    return CostParams(a_c, tau_c, a_g, tau_g)
+def cost_params(a_c=0.89, tau_c=7.0, a_g=0.11, tau_g=2.0, border=0) -> CostParams:
+    """border 0: a label past the left image border costs both truncations;
+    1: it is compared with the row's first pixel."""
+    return CostParams(a_c, tau_c, a_g, tau_g, border)
 
 
 def cost_volume(left: torch.Tensor, right: torch.Tensor, shapes, forest: Optional[Forest] = None,

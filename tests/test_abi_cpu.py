@@ -163,6 +163,10 @@ def test_match_layer_validation(lib):
     other = (lib.Shape * 1)(lib.Shape(H, W + 1, 15))  # forest does not match the batch
     assert call(shapes=other) == -1
     assert call(n_pairs=0) == -2
+    bad = lib.cost_params(border=2)  # border policy is 0 or 1
+    assert call(p=C.byref(bad)) == -1
+    assert L.hdp_cost_volume(dummy, dummy, shapes, 1, C.byref(st), 10, C.byref(bad), dummy,
+                             None) == -1
 
 
 def test_workspace_sizes_grow(lib):

@@ -519,6 +519,48 @@ def test_packed_right_image_equals_three_steps(H, case):
     assert torch.equal(dispf, disp3), f"{case}: labels differ"
 
 
+@pytest.mark.parametrize("width_case", ["hdp_w10", "full_w64"])
+def test_border_policy_clamp(H, orc, width_case):
+    """Border policy 1 (a label past the left border compared with the row's
+    first pixel): the cost volume within 1e-5 of the oracle's with the same
+    policy, and the fused matching bit for bit equal to the three separate
+    steps (FP32 right pixels on HDP windows, packed ones on 64-label rows)."""
+    Hh, Ww, dmax = 40, 56, 63
+    pair = scenes.small_scene(91, Hh, Ww, dmax)
+    shapes = [(Hh, Ww, dmax)]
+    Lr, Rr = rgb_dev(pair.left), rgb_dev(pair.right)
+    lp, rp = H.pyramid_views(Lr, Rr, shapes, 2, 0)
+    if width_case == "hdp_w10":
+        lo = np.clip(np.arange(Hh * Ww) % 37 - 4, 0, dmax).astype(np.int32)
+        hi = np.minimum(lo + 9, dmax).astype(np.int32)
+        f = H.build_tree(lp[0], shapes, 0, dev(lo, torch.int32), dev(hi, torch.int32),
+                         max_width=10)
+    else:
+        lo = np.zeros(Hh * Ww, np.int32); hi = np.full(Hh * Ww, dmax, np.int32)
+        f = H.build_tree(lp[0], shapes, 0)
+    p = H.cost_params(border=1)
+    cost = H.cost_volume(lp[0], rp[0], shapes, f, params=p)
+    F = forest_np(f)
+    got = volume_to_pixels(cost.cpu().numpy(), F, dmax + 1)
+    tlo, thi = F["lo"], F["hi"]
+    ref = orc.cost_volume(pair.left.astype(np.float64), pair.right.astype(np.float64), dmax,
+                          tlo.reshape(Hh, Ww), thi.reshape(Hh, Ww), prm=orc.COST_PARAMS + (1,))
+    m = ~np.isnan(ref)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    assert_rel(got[m], ref[m], REL, f"border 1 cost {width_case}")
+    # the policies differ exactly where the label passes the left border
+    ref0 = orc.cost_volume(pair.left.astype(np.float64), pair.right.astype(np.float64), dmax,
+                           tlo.reshape(Hh, Ww), thi.reshape(Hh, Ww))
+    x = np.arange(Hh * Ww) % Ww
+    past = np.arange(dmax + 1)[None, :] > x[:, None]
+    assert np.array_equal(ref0[m & ~past], ref[m & ~past])
+    agg = H.aggregate(f, cost, 0.1)
+    disp = H.wta(agg, shapes, f)
+    aggf, dispf = H.match_layer(lp[0], rp[0], shapes, f, params=p)
+    torch.cuda.synchronize()
+    assert torch.equal(aggf, agg) and torch.equal(dispf, disp)
+
+
 def test_workspace_reuse_no_stale_rows(H):
     """Only the rows a tile polls are marked unwritten before a pass; a call on
     a workspace that holds another input's rows must still give the results of

@@ -103,6 +103,39 @@ def test_cost_golden(orc):
         assert abs(got - want) < 1e-12, c
 
 
+def test_cost_border_policy(orc):
+    """Border policy 1 (Section 3.3 leaves the image border open): a label that
+    reaches past the left border is compared with the row's first pixel, so
+    its cost equals that of label d = x, computed here from the definition by
+    hand on the golden strip; inside the image both policies agree, and
+    policy 0 gives the saturated value a_c tau_c + a_g tau_g."""
+    g = load("cost_4x3.json")
+    H, W = g["H"], g["W"]
+    L = np.zeros((H, W, 3)); R = np.zeros((H, W, 3))
+    L[1] = np.array(g["left_row1"]); R[1] = np.array(g["right_row1"])
+    a_c, tau_c, a_g, tau_g = g["params"]
+    clamp = list(g["params"]) + [1]
+
+    def by_hand(x, y):
+        # pixel (x, y) of the left image against column 0 of the right image
+        gl = lambda img, xx: img[y, min(xx + 1, W - 1)].sum() - img[y, max(xx - 1, 0)].sum()
+        col = np.abs(L[y, x] - R[y, 0]).sum() / 3.0
+        gd = abs(gl(L, x) - gl(R, 0)) / 6.0
+        return a_c * min(col, tau_c) + a_g * min(gd, tau_g)
+
+    for y in range(H):
+        for x in range(W):
+            for d in range(W + 2):
+                c0 = orc.matching_cost(L, R, x, y, d, g["params"])
+                c1 = orc.matching_cost(L, R, x, y, d, clamp)
+                if d <= x:
+                    assert c1 == c0
+                else:
+                    assert c0 == a_c * tau_c + a_g * tau_g
+                    assert abs(c1 - by_hand(x, y)) < 1e-12
+                    assert c1 == orc.matching_cost(L, R, x, y, x, clamp)
+
+
 def test_cost_volume_nan_outside_interval(orc):
     img_l = rng_img(2, 5, 9).astype(np.float64); img_r = rng_img(3, 5, 9).astype(np.float64)
     lo = np.random.default_rng(0).integers(0, 4, size=(5, 9)); hi = lo + 3
