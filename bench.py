@@ -114,12 +114,13 @@ def pass_bytes_kernel(forest, up: bool) -> float:
 def measured_traffic(workload: str):
     """HBM bytes per launch of the up and down passes from the committed counter
     runs (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain copy
-    of known size), or None once the kernel source has changed since."""
+    of known size), or None once the kernel's sources (the pass and the matching
+    cost it inlines) have changed since."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "k_pass_traffic.json")))
         w = rec["workloads"][workload]
-        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])
     except (OSError, ValueError, KeyError):
         return None
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
