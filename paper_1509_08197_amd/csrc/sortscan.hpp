@@ -122,17 +122,42 @@ __device__ __forceinline__ T block_sum_prefix(const T *__restrict__ sup, int64_t
     return tot;
 }
 
+// Lists of at most kDirectTiles tile sums are not scanned by a launch of
+// their own: every tile sums the unscanned sums before it, kDirectPer loads
+// per thread issued together (the sums are a few KB, served from L2).
+constexpr int kDirectPer = 16;
+constexpr int64_t kDirectTiles = (int64_t)kBlock * kDirectPer;
+
+template <typename T>
+__device__ __forceinline__ T block_sum_direct(const T *__restrict__ part, int64_t m) {
+    T v[kDirectPer];
+#pragma unroll
+    for (int i = 0; i < kDirectPer; ++i) {
+        const int64_t j = (int64_t)i * kBlock + threadIdx.x;
+        v[i] = j < m ? part[j] : (T)0;
+    }
+    T a = 0;
+#pragma unroll
+    for (int i = 0; i < kDirectPer; ++i) a += v[i];
+    T tot;
+    block_excl_scan(a, &tot);
+    return tot;
+}
+
 // Scan of one tile, offset by its scanned tile sum and the block totals
-// before it.  grand (may be NULL) receives the total from the last tile.
+// before it, or (direct) by the sum of the unscanned tile sums before it.
+// grand (may be NULL) receives the total from the last tile.
 template <typename T, typename TIn = T, typename Widen = WidenSame>
 __global__ void k_scan_apply(const TIn *__restrict__ in, T *__restrict__ out, int64_t n,
                              const T *__restrict__ partial, const T *__restrict__ sup,
-                             T *__restrict__ grand, int inclusive, Widen wide = Widen()) {
+                             T *__restrict__ grand, int inclusive, int direct,
+                             Widen wide = Widen()) {
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * kScanTile + threadIdx.x * kScanPerThread;
     T v[kScanPerThread];
     load_run(in, base, n, wide, v);
-    const T pre = partial[tile] + block_sum_prefix(sup, tile / kScanTile);
+    const T pre = direct ? block_sum_direct(partial, tile)
+                         : partial[tile] + block_sum_prefix(sup, tile / kScanTile);
     T s = 0;
 #pragma unroll
     for (int i = 0; i < kScanPerThread; ++i) s += v[i];
@@ -153,19 +178,25 @@ inline int64_t scan_scratch(int64_t n) {
     const int64_t nb = scan_tiles(n) < 1 ? 1 : scan_tiles(n);
     return nb + scan_tiles(nb) + 1;
 }
-// Scan of the tile sums part[0..nb) (blockwise) and the tiles of in.
+// Scan of the tile sums part[0..nb) (blockwise; skipped for at most
+// kDirectTiles sums, which every tile then adds up itself) and the tiles of
+// in.  part is left unscanned in the direct case.
 template <typename T, typename TIn, typename Widen>
 inline void scan_sums_and_apply(const TIn *in, T *out, int64_t n, T *part, int64_t nb, T *grand,
                                 bool inclusive, hipStream_t st, Widen wide) {
-    const int64_t nsup = scan_tiles(nb);
-    k_scan_partials<T><<<(unsigned)nsup, kBlock, 0, st>>>(part, nb, part + nb);
-    k_scan_apply<T, TIn, Widen><<<(unsigned)nb, kBlock, 0, st>>>(in, out, n, part, part + nb,
-                                                                 grand, inclusive ? 1 : 0, wide);
+    const bool direct = nb <= kDirectTiles;
+    if (!direct) {
+        const int64_t nsup = scan_tiles(nb);
+        k_scan_partials<T><<<(unsigned)nsup, kBlock, 0, st>>>(part, nb, part + nb);
+    }
+    k_scan_apply<T, TIn, Widen><<<(unsigned)nb, kBlock, 0, st>>>(
+        in, out, n, part, part + nb, grand, inclusive ? 1 : 0, direct ? 1 : 0, wide);
 }
 
 // out[i] = sum of in[0..i-1] (exclusive) or in[0..i] (inclusive); in == out allowed.
 // partial: scratch of scan_scratch(n) elements; grand (device, may be NULL) = total.
-// Three launches: per-tile sums, their blockwise scan, then every tile's own scan.
+// Three launches (two for at most kDirectTiles tiles): per-tile sums, their
+// blockwise scan, then every tile's own scan.
 template <typename T, typename TIn = T, typename Widen = WidenSame>
 inline void device_scan(const TIn *in, T *out, int64_t n, T *partial, T *grand, bool inclusive,
                         hipStream_t st, Widen wide = Widen()) {
