@@ -65,7 +65,9 @@ typedef struct {
     float a_g, tau_g;   /* weight and truncation of the gradient term */
     int32_t border;     /* a label d > x (the match falls left of the image):
                            0 = both terms at their truncation (default),
-                           1 = compared with the row's first pixel */
+                           1 = compared with the row's first pixel;
+                           the entry points taking these parameters return
+                           HDP_EINVAL for any other value */
 } hdp_cost_params;
 
 /* Indices into hdp_forest.info (device int32 words written by hdp_build_tree). */
