@@ -352,6 +352,33 @@ def test_hdp_literal_end_to_end_small(H, orc):
         assert np.all(gap[mism & same_int] <= REL), f"layer {l}: unexplained mismatches"
 
 
+
+def test_hdp_border_clamp_end_to_end_small(H, orc):
+    """The whole loop with the clamped border (labels past the left edge
+    compared with the row's first pixel) on the GPU against the oracle's loop
+    with the same policy: labels identical except at near-ties or where an
+    interval upstream differs."""
+    pair = scenes.small_scene(641, 48, 80, 31)
+    prm = (0.89, 7.0, 0.11, 2.0, 1)
+    res = H.hdp_stereo(rgb_dev(pair.left), rgb_dev(pair.right), [(48, 80, 31)], S=2, L=2,
+                       window=2, params=H.cost_params(*prm))
+    ores = orc.hdp_stereo(pair.left, pair.right, 31, S=2, L=2, window=2, prm=prm)
+    for l in (2, 1, 0):
+        g = res[l].disp.cpu().numpy(); o = ores[l]["disp"].ravel()
+        gap = (ores[l]["c2"] - ores[l]["c1"]) / ores[l]["c1"]
+        mism = g != o
+        if l < 2:
+            same_int = ((res[l].pix_lo.cpu().numpy() == ores[l]["pix_lo"].ravel()) &
+                        (res[l].pix_hi.cpu().numpy() == ores[l]["pix_hi"].ravel()))
+        else:
+            same_int = np.ones_like(mism)
+        assert np.all(gap[mism & same_int] <= REL), f"layer {l}: unexplained mismatches"
+    # the policy changes the result: the saturated border gives other labels somewhere
+    sat = H.hdp_stereo(rgb_dev(pair.left), rgb_dev(pair.right), [(48, 80, 31)], S=2, L=2,
+                       window=2)
+    assert not np.array_equal(sat[0].disp.cpu().numpy(), res[0].disp.cpu().numpy())
+
+
 # --- cost, aggregation, WTA ------------------------------------------------------------
 
 @pytest.mark.parametrize("Hh,Ww,dmax,seed", [(120, 160, 15, 1001), (45, 70, 31, 7),
